@@ -1,0 +1,90 @@
+/*
+ * Test infrastructure: the CPU oracle of the auxiliary-space ("GAMG")
+ * preconditioned CG method of Lee, Leng and Zhang (arXiv:1204.2586).
+ *
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+ * call this code.  It is plain, single-threaded FP64 C with no blocking or
+ * fusion, written so that each step can be checked against the paper by eye.
+ * It shares no code with the GPU library.
+ */
+#ifndef ORC_H
+#define ORC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+/* compressed sparse rows: n rows, m columns */
+typedef struct {
+    int n, m;
+    int *ptr;     /* [n+1] */
+    int *col;     /* [nnz], sorted within each row */
+    double *val;  /* [nnz] */
+} ocsr;
+
+typedef struct {
+    ocsr A;        /* level operator */
+    double *dl1;   /* l1 row norms sum_j |a_ij| */
+    int *cf;       /* +1 coarse, -1 fine (not set on the coarsest level) */
+    ocsr P;        /* interpolation n x nc (not set on the coarsest level) */
+    ocsr R;        /* P transposed */
+    int nc;
+} olevel;
+
+#define ORC_MAX_LEVELS 32
+
+typedef struct {
+    /* mesh (copied) */
+    int k, nloc, nv, nt;
+    double *xyz;     /* [nv][3] */
+    int *tets;       /* [nt][4] */
+    double *kappa;   /* [nt] */
+
+    /* P^k nodes: global node g has key node_key[g*k .. g*k+k-1], a sorted
+       multiset of k vertex ids; nodes are numbered in lexicographic key order */
+    int nnode;
+    int *node_key;
+    int *tet_node;   /* [nt][nloc] global node of each local node */
+    int *node_dof;   /* [nnode] interior dof index or -1 (Dirichlet) */
+    int ndof;        /* n_h */
+
+    /* P^1 (auxiliary space) */
+    int *vert_dof;   /* [nv] interior vertex index or -1 */
+    int nH;          /* n_H */
+
+    ocsr A;          /* A_h on interior dofs */
+    double *dl1;     /* l1 row norms of A_h */
+    ocsr AH;         /* P1 stiffness on interior vertices */
+    ocsr IP;         /* n_h x n_H transfer, I_R = IP^T */
+    ocsr IR;
+
+    /* AMG hierarchy on AH */
+    int nlev;
+    olevel lev[ORC_MAX_LEVELS];
+    double *chol;    /* dense Cholesky factor of the coarsest operator (lower, row-major) */
+    int ncoarse;
+
+    /* options */
+    double theta;
+    int nu, coarse_max, max_levels;
+    uint64_t seed;
+} orc;
+
+/* fem */
+int orc_local_multi_indices(int k, int *alpha /* [nloc][4] */);
+double orc_basis(int k, const int *alpha, const double *lam);
+void orc_basis_dlam(int k, const int *alpha, const double *lam, double *d /* [4] */);
+int orc_gauss_jacobi(int m, int a, double *x, double *w);   /* on [0,1], weight (1-x)^a */
+int orc_tet_rule(int m, double *lam /* [m^3][4] */, double *w /* [m^3] */);
+int orc_build_mesh_dofs(orc *o);
+int orc_assemble(orc *o);
+
+/* sparse helpers */
+void ocsr_free(ocsr *a);
+int ocsr_transpose(const ocsr *a, ocsr *t);
+int ocsr_matmul(const ocsr *a, const ocsr *b, ocsr *c);
+int ocsr_from_triplets(int n, int m, size_t cnt, const int *ri, const int *ci, const double *v, ocsr *out);
+
+/* amg */
+int orc_amg_setup(orc *o);
+
+#endif
