@@ -1,0 +1,177 @@
+#!/usr/bin/env python
+"""Benchmark: P2/P3 Poisson time-to-1e-8 residual with the auxiliary-space
+preconditioned CG on one MI355X.
+
+A step is one complete solve (CG from u = 0 to ||r|| <= 1e-8 ||f||, every
+preconditioner application included) of the default workload: P2 elements
+on the unit cube cut into 48^3 cubes x 6 tets, interior vertices jittered by
++-0.2h (seed 0), kappa = 1, f from u = sin(pi x) sin(pi y) sin(pi z)
+(857,375 unknowns).  The headline value is the FP32-preconditioner form
+(FP64 CG); the all-FP64 form is measured beside it at the same tolerance.
+
+Prints one JSON line.  Inputs are resident in HBM before the timed region.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "P2/P3 Poisson time-to-1e-8 residual, DOF/s, precond HBM GB/s; mixed vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "p2_n48_jitter": dict(k=2, n=48, jitter=0.2, seed=0, kappa=None),
+    "p2_n8": dict(k=2, n=8, jitter=0.0, seed=0, kappa=None),
+    "p3_n32_grf": dict(k=3, n=32, jitter=0.0, seed=0, kappa=1),
+}
+
+
+def algorithmic_bytes(cat, n, nnz, s):
+    """Bytes a kernel must move at least once per launch (matrix, index and
+    vector arrays each counted once).  s = bytes of the preconditioner's
+    floating-point type, n rows, nnz entries of A_h."""
+    mat = (s + 4) * nnz + 4 * (n + 1)
+    if cat == "pk_sweep":      # z_in (gather), rhs, dinv, z_out
+        return mat + 4 * s * n
+    if cat == "pk_last":       # z_in, rhs (FP64), dinv, z_out (FP64)
+        return mat + 2 * s * n + 16 * n
+    if cat == "pk_first":      # r (FP64, gather), dinv, z_out, (FP32 copy of r)
+        return mat + 8 * n + 2 * s * n + (s * n if s == 4 else 0)
+    if cat == "pk_resid":      # rhs, z (gather), res
+        return mat + 3 * s * n
+    if cat == "cg_spmv":       # FP64 operator, x (gather), y
+        return 12 * nnz + 4 * (n + 1) + 16 * n
+    return None
+
+
+def run(args):
+    import numpy as np
+    import torch
+
+    import paper_1204_2586_amd as aux
+    import workloads as W
+
+    wl = WORKLOADS[args.workload]
+    xyz, tets = W.kuhn_mesh(wl["n"], jitter=wl["jitter"], seed=wl["seed"])
+    kappa = None
+    if wl["kappa"] is not None:
+        kappa = np.exp(W.grf_log_kappa(xyz, tets, seed=wl["kappa"]))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    s = aux.Solver(xyz, tets, wl["k"], kappa, precision="mixed", device=dev)
+    setup_s = time.time() - t0
+    b = s.load(W.manufactured_f)
+    f = torch.tensor(b, dtype=torch.float64, device=dev)
+    u = torch.zeros_like(f)
+    n, nnz = s.n, int(s.info.nnz_A)
+
+    def timed(mode, profile):
+        s.set_precision(mode)
+        for _ in range(args.warmup):
+            s.solve(f, tol=args.tol, out=u)
+        if profile:
+            s.profile(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its = []
+        for _ in range(args.steps):
+            _, info = s.solve(f, tol=args.tol, out=u)
+            its.append(info.iterations)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / args.steps
+        prof = s.profile_read() if profile else None
+        if profile:
+            s.profile(False)
+        sol = u.clone()
+        true_res = float(torch.linalg.norm(f - s.matvec(sol)) / torch.linalg.norm(f))
+        return dict(ms=ms, iterations=its, true_rel_residual=true_res, prof=prof, u=sol)
+
+    mixed = timed("mixed", True)
+    fp64 = timed("fp64", True)
+    diff = float(torch.linalg.norm(mixed["u"] - fp64["u"]) / torch.linalg.norm(fp64["u"]))
+
+    # roofline of the dominant kernel of the timed (mixed) solve
+    kernels = {}
+    for cat, (cnt, tot) in mixed["prof"].items():
+        ab = algorithmic_bytes(cat, n, nnz, 4)
+        if cnt and ab:
+            avg_ms = tot / cnt
+            kernels[cat] = dict(launches=cnt, total_ms=tot, avg_us=avg_ms * 1e3, bytes=ab,
+                                gbs=ab / (avg_ms * 1e-3) / 1e9)
+    dom = max(kernels, key=lambda c: kernels[c]["total_ms"])
+    kd = kernels[dom]
+    apply_cnt, apply_ms = mixed["prof"]["apply"]
+
+    out = {
+        "metric": METRIC,
+        "value": n / (mixed["ms"] * 1e-3),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 CG / f32 preconditioner",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "order": wl["k"], "cubes_per_side": wl["n"],
+                   "jitter": wl["jitter"], "n_h": n, "nnz_A": nnz, "tol": args.tol,
+                   "iterations": mixed["iterations"][-1], "true_rel_residual": mixed["true_rel_residual"],
+                   "amg_levels": int(s.info.levels), "op_complexity": round(float(s.info.op_complexity), 4),
+                   "setup_s": round(setup_s, 2)},
+        "fp64": {"value": n / (fp64["ms"] * 1e-3), "ms_per_step": fp64["ms"],
+                 "iterations": fp64["iterations"][-1], "true_rel_residual": fp64["true_rel_residual"],
+                 "mixed_vs_fp64_rel_diff": diff,
+                 "speedup_mixed_over_fp64": fp64["ms"] / mixed["ms"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": kd["bytes"], "avg_us": kd["avg_us"]},
+        "kernels_mixed": {c: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+                          for c, d in kernels.items()},
+        "precond_apply_us": {"mixed": apply_ms / max(apply_cnt, 1) * 1e3,
+                             "fp64": fp64["prof"]["apply"][1] / max(fp64["prof"]["apply"][0], 1) * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(xyz, tets, wl, kappa, b, args)
+    return out
+
+
+def cpu_baseline(xyz, tets, wl, kappa, b, args):
+    """The CPU oracle (single-threaded FP64 C) on the same system: one CG solve
+    to the same tolerance from u = 0, its setup excluded from the timing."""
+    import oracle
+    t0 = time.time()
+    P = oracle.Problem(xyz, tets, wl["k"], kappa).setup_amg()
+    setup = time.time() - t0
+    t0 = time.perf_counter()
+    x, it, rr, st = P.pcg(b, tol=args.tol)
+    dt = time.perf_counter() - t0
+    return {"value": P.n / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 CG solve of the full {args.workload} system (n_h={P.n}) to {args.tol:g}, "
+                      f"{it} iterations, {dt:.1f} s; oracle setup {setup:.1f} s not timed"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="p2_n48_jitter", choices=sorted(WORKLOADS))
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
+                                   "(the multi-GPU decomposition is described, not built)"}))
+        sys.exit(2)
+    print(json.dumps(run(args)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * aux.h -- C ABI of the MI355X auxiliary-space ("GAMG") preconditioned CG
+ * solver for P^k (k = 2, 3) Lagrange finite-element Poisson problems on
+ * tetrahedral meshes.
+ *
+ * Method: Lee, Leng and Zhang, "A scalable auxiliary space preconditioner for
+ * high-order finite element methods" (arXiv:1204.2586).
+ *   - problem: -div(kappa grad u) = f in Omega, u = 0 on the boundary, in the
+ *     weak form of Sec. 2, eq. (2.2)-(2.3) (the paper has kappa = 1; here kappa
+ *     is one positive value per tetrahedron);
+ *   - discrete system A_h u_h = f_h, (A_h)_ij = a(phi_j, phi_i),
+ *     f_i = <f, phi_i> (Sec. 2, eq. (2.5));
+ *   - preconditioner: Algorithm 2.1 with presmoothing (Remark 2.1): nu l1-Jacobi
+ *     sweeps on A_h, restriction with I_R = I_P^T, one AMG V(1,1) cycle on the
+ *     P^1 stiffness A_H, prolongation with I_P (eq. "Prol": (I_P)_ij =
+ *     psi_j(x_i^h)), nu l1-Jacobi sweeps;
+ *   - AMG setup (host, once): strength rule of Sec. 6.2, PMIS coarsening and
+ *     extended+i interpolation (the BoomerAMG options named in Sec. 1, 6.1).
+ *
+ * Degrees of freedom.  A P^k node is identified by the sorted multiset of k
+ * mesh vertex ids whose average is its position (vertex v: {v,..,v}; the P2
+ * edge midpoint of (a,b): {a,b}; the P3 node of edge (a,b) nearer a:
+ * {a,a,b}; the P3 face node: {a,b,c}).  Nodes on boundary faces (faces of a
+ * single tet) are eliminated.  The remaining n_h nodes are numbered in
+ * lexicographic order of their multisets; every vector of length n_h below
+ * uses that order (see aux_dof_keys).  P^1 unknowns are the n_H interior
+ * vertices in increasing vertex id.
+ *
+ * Memory.  "host" arguments are CPU memory borrowed for the call only.
+ * "device" arguments are GPU memory owned by the caller, contiguous, FP64,
+ * valid on the handle's device, and must not alias each other.  Device work
+ * is enqueued on the handle's stream (aux_set_stream); calls return after the
+ * work is enqueued unless stated otherwise.
+ *
+ * Errors.  Every entry point returns AUX_OK (0) or a negative AUX_E* code;
+ * aux_last_error() then returns a thread-local message.  On error no output
+ * is guaranteed except where stated.
+ */
+#ifndef AUX_H
+#define AUX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AUX_OK 0
+#define AUX_EINVAL -1        /* bad argument, mesh or coefficient */
+#define AUX_ENOMEM -2        /* host or device allocation failed */
+#define AUX_EHIP -3          /* a HIP runtime call failed */
+#define AUX_ENOTCONV -4      /* CG reached maxit; the solution holds the last iterate */
+#define AUX_EBREAKDOWN -5    /* CG breakdown: p.Ap <= 0 or r.z <= 0 */
+#define AUX_ENAN -6          /* a non-finite value appeared in CG */
+#define AUX_ESTATE -7        /* call not valid for this handle (e.g. host-only) */
+
+#define AUX_FP64 0           /* preconditioner in FP64 */
+#define AUX_MIXED 1          /* preconditioner in FP32 inside FP64 CG */
+
+typedef struct aux_handle aux_handle;
+
+typedef struct aux_mesh {
+    int32_t n_vertices;
+    const double *xyz;       /* host [n_vertices][3] */
+    int32_t n_tets;
+    const int32_t *tets;     /* host [n_tets][4] vertex ids, any orientation */
+} aux_mesh;
+
+typedef struct aux_options {
+    int nu;                  /* l1-Jacobi sweeps before and after the coarse correction (2) */
+    double theta;            /* AMG strength threshold, Sec. 6.2 (0.8) */
+    int coarse_max;          /* coarsest AMG level size, solved exactly (100) */
+    int max_levels;          /* AMG levels at most (25) */
+    uint64_t pmis_seed;      /* seed of the PMIS random measure (0) */
+    int precision;           /* AUX_FP64 or AUX_MIXED (AUX_FP64) */
+    int maxit;               /* CG iteration limit (1000) */
+    int host_only;           /* 1: run the host setup only, no device (for tests) */
+} aux_options;
+
+typedef struct aux_device {
+    void *stream;            /* hipStream_t to enqueue on (NULL: default stream) */
+    /* optional device allocator (e.g. a framework's caching allocator);
+       NULL alloc means hipMalloc/hipFree */
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} aux_device;
+
+typedef struct aux_info {
+    int64_t n_h, n_H, n_tets, nnz_A, nnz_AH, nnz_IP;
+    int32_t order, levels, ncoarse, precision;
+    double op_complexity;    /* sum_l nnz(A_l) / nnz(A_h), counting A_h and all P^1 levels */
+    double amg_complexity;   /* sum_l nnz(A_l) / nnz(A_H) over the P^1 levels */
+    int64_t level_rows[32];
+    int64_t level_nnz[32];
+    double setup_seconds;
+    int64_t device_bytes;    /* device memory held by the handle */
+} aux_info;
+
+typedef struct aux_solve_info {
+    int32_t iterations;      /* CG iterations (updates of u) performed */
+    int32_t status;          /* AUX_OK, AUX_ENOTCONV, AUX_EBREAKDOWN or AUX_ENAN */
+    double rel_residual;     /* ||r_k||_2 / ||f||_2 of the recursive residual at exit */
+    double seconds;          /* wall time of the solve (host clock, includes the final sync) */
+} aux_solve_info;
+
+/* Fill opt with the defaults listed above. */
+void aux_default_options(aux_options *opt);
+
+/* Build the discretisation, transfer and AMG hierarchy on the host and copy
+ * the solve-phase data to the device.  mesh: host arrays as described; order
+ * 2 or 3; kappa: host [n_tets] positive values, or NULL for kappa = 1;
+ * opt: NULL for defaults; dev: NULL for hipMalloc on the current device and
+ * the default stream.  On success *out owns all buffers; release it with
+ * aux_destroy.  Errors: AUX_EINVAL (order, empty or degenerate mesh, vertex id
+ * out of range, non-manifold face, kappa <= 0 or non-finite, coordinates not
+ * finite), AUX_ENOMEM, AUX_EHIP. */
+int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt,
+              const aux_device *dev, aux_handle **out);
+
+/* Release everything the handle owns (waits for its stream).  NULL is a no-op. */
+int aux_destroy(aux_handle *h);
+
+/* Change the stream later calls enqueue on. */
+int aux_set_stream(aux_handle *h, void *stream);
+
+/* Switch the preconditioner precision (AUX_FP64 or AUX_MIXED); the FP32
+ * copies are made on first use. */
+int aux_set_precision(aux_handle *h, int precision);
+
+/* Sizes, hierarchy shape and operator complexity (host struct). */
+int aux_get_info(const aux_handle *h, aux_info *info);
+
+/* Canonical key of each dof: host int32 [n_h][order], the sorted vertex
+ * multiset of the node (lexicographically increasing over the dofs). */
+int aux_dof_keys(const aux_handle *h, int32_t *keys);
+
+/* Load vector f_i = <f, phi_i> (Sec. 2) by a conical-product Gauss-Jacobi
+ * rule with (order+2)^3 points per tet.  The caller evaluates f at the points
+ * of tets [t0, t1) returned by aux_qpoints (host [(t1-t0)*npts][3], point q of
+ * tet t at row (t-t0)*npts+q, npts = aux_qpoints_per_tet) and accumulates
+ * with aux_load_accumulate (fq host [(t1-t0)*npts], b host [n_h], added to).
+ * Processing all tets in any chunking gives the load vector. */
+int aux_qpoints_per_tet(const aux_handle *h);
+int aux_qpoints(const aux_handle *h, int32_t t0, int32_t t1, double *xyzq);
+int aux_load_accumulate(const aux_handle *h, int32_t t0, int32_t t1, const double *fq, double *b);
+
+/* Export a host copy of a matrix for inspection.  which: 0 = A_h, 1 = A_H,
+ * 2 = I_P, 3 = AMG level operator A_level, 4 = AMG interpolation P_level.
+ * With ptr == NULL only shape[3] = {rows, cols, nnz} is written; otherwise
+ * ptr host int32 [rows+1], col int32 [nnz], val double [nnz] receive the CSR. */
+int aux_export_csr(const aux_handle *h, int which, int level, int64_t *shape, int32_t *ptr,
+                   int32_t *col, double *val);
+/* C/F splitting of an AMG level (host int32 [rows]: +1 coarse, -1 fine). */
+int aux_export_cf(const aux_handle *h, int level, int32_t *cf);
+
+/* z = B r, one application of the preconditioner (device r, z [n_h]). */
+int aux_apply(aux_handle *h, const double *r, double *z);
+
+/* Preconditioned CG on A_h u = f (Sec. 2, eq. (2.5)).  f: device [n_h] load
+ * vector; u: device [n_h], initial guess in, solution out.  Stops when
+ * ||f - A_h u_k||_2 (recursive residual) <= tol ||f||_2, or after maxit
+ * iterations (tol = 0 runs exactly maxit).  maxit <= 0 uses the handle's
+ * option.  Synchronises the stream; info (host, may be NULL) receives the
+ * iteration count and final relative residual.  Returns AUX_OK,
+ * AUX_ENOTCONV, AUX_EBREAKDOWN or AUX_ENAN (u then holds the last iterate). */
+int pcg_solve(aux_handle *h, const double *f, double *u, double tol, int maxit, aux_solve_info *info);
+
+/* nrhs independent CG solves in lock-step sharing every sparse-matrix pass.
+ * F, U: device row-major [n_h][nrhs] (column j is right-hand side j).  Each
+ * column follows exactly the single-right-hand-side algorithm and stops on
+ * its own criterion.  infos: host [nrhs] or NULL.  Returns the worst status. */
+int pcg_solve_batched(aux_handle *h, const double *F, double *U, int nrhs, double tol, int maxit,
+                      aux_solve_info *infos);
+
+/* y = A_h x (device x, y [n_h]), FP64. */
+int aux_matvec(aux_handle *h, const double *x, double *y);
+
+/* Per-tet derivative of a functional L(u(kappa)) with respect to log kappa,
+ * g_t = -lam_t^T K_t u_t, where A_h lam = dL/du (the adjoint solution), K_t
+ * the element stiffness of tet t and lam_t, u_t its local values (zero on
+ * the boundary).  u, lam: device [n_h]; g: device [n_tets]. */
+int aux_kappa_grad(aux_handle *h, const double *u, const double *lam, double *g);
+
+/* Kernel timing.  Categories of timed launches: */
+#define AUX_PROF_PK_FIRST 0   /* first two fused P^k l1-Jacobi sweeps from zero */
+#define AUX_PROF_PK_SWEEP 1   /* P^k l1-Jacobi sweep (preconditioner precision in and out) */
+#define AUX_PROF_PK_LAST 2    /* last P^k sweep, writes the FP64 result and reduces r.z */
+#define AUX_PROF_PK_RESID 3   /* P^k residual before restriction */
+#define AUX_PROF_COARSE 4     /* restriction + AMG V-cycle + prolongation */
+#define AUX_PROF_CG_SPMV 5    /* CG product q = A_h p with p.q */
+#define AUX_PROF_APPLY 6      /* one whole preconditioner application */
+#define AUX_PROF_NCAT 7
+/* With enable = 1, later preconditioner and CG calls record a HIP event pair
+ * on the handle's stream around each launch of the categories above (launches
+ * enqueued after convergence that returned at once are not counted).
+ * Resets the sums.  enable = 0 stops recording. */
+int aux_profile(aux_handle *h, int enable);
+/* Launch count and summed elapsed milliseconds of a category since the last
+ * aux_profile call (synchronises the stream). */
+int aux_profile_read(aux_handle *h, int category, int64_t *launches, double *ms);
+
+/* Message of the last error on this thread ("" if none). */
+const char *aux_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AUX_H */

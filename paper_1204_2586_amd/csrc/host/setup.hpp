@@ -1,0 +1,84 @@
+// Host-side setup of the auxiliary-space preconditioner: P^k degrees of
+// freedom, finite-element assembly, the P^k <- P^1 transfer and the AMG
+// hierarchy on the P^1 matrix.  Runs once per (mesh, order, kappa); the
+// solve phase on the GPU only consumes the arrays produced here.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace auxp {
+
+struct Csr {
+    int n = 0, m = 0;
+    std::vector<int> ptr{0};
+    std::vector<int> col;
+    std::vector<double> val;
+    int64_t nnz() const { return ptr.empty() ? 0 : ptr.back(); }
+};
+
+struct AmgLevel {
+    Csr A;                    // level operator
+    std::vector<double> l1;   // sum_j |a_ij|
+    std::vector<int> cf;      // +1 coarse / -1 fine (empty on the coarsest level)
+    Csr P;                    // interpolation n x nc
+    Csr R;                    // P^T
+};
+
+struct SetupOptions {
+    double theta = 0.8;
+    int coarse_max = 100;
+    int max_levels = 25;
+    uint64_t seed = 0;
+};
+
+struct Discretization {
+    int k = 0, nloc = 0, nv = 0, nt = 0;
+    std::vector<double> xyz;     // [nv][3]
+    std::vector<int> tets;       // [nt][4]
+    std::vector<double> kappa;   // [nt]
+
+    int ndof = 0;                // interior P^k nodes (n_h)
+    int nH = 0;                  // interior vertices (n_H)
+    std::vector<int32_t> keys;   // [ndof][k] sorted vertex multiset of each dof
+    std::vector<int> tet_dof;    // [nt][nloc] dof of each local node, -1 on the boundary
+    std::vector<int> vert_dof;   // [nv] P^1 index or -1
+
+    Csr A;                       // A_h
+    std::vector<double> l1;      // l1 row norms of A_h
+    Csr AH;                      // P^1 stiffness
+    Csr IP;                      // n_h x n_H
+    Csr IR;                      // I_P^T
+};
+
+struct Hierarchy {
+    std::vector<AmgLevel> levels;
+    std::vector<double> coarse_inv;   // dense inverse of the coarsest operator, row-major
+    int ncoarse = 0;
+};
+
+// local multi-indices of the P^k tet (|alpha| = k), lexicographic
+std::vector<int> multi_indices(int k);
+
+// Throws std::invalid_argument on bad input.
+void build_discretization(Discretization &d, int nv, const double *xyz, int nt, const int32_t *tets,
+                          int k, const double *kappa);
+void build_hierarchy(const Csr &AH, const SetupOptions &opt, Hierarchy &h);
+
+// reference tables M^pq_ab = (1/|T|) int dphi_a/dlam_p dphi_b/dlam_q, [4][4][nloc][nloc]
+const std::vector<double> &stiffness_tables(int k);
+// element stiffness of tet t (kappa included) = kappa * sum_pq G_pq M^pq
+void element_stiffness(const Discretization &d, int t, double *K);
+// gradient inner products |T| grad(lam_p).grad(lam_q) (4x4) of tet t, returns |det J|
+double tet_metric(const double *X0, const double *X1, const double *X2, const double *X3,
+                  double G[4][4]);
+
+// load vector by the conical-product rule with k+2 points per direction
+int load_rule_points(int k);                               // points per tet
+void quadrature_points(const Discretization &d, int t0, int t1, double *out);
+void accumulate_load(const Discretization &d, int t0, int t1, const double *fq, double *b);
+
+Csr transpose(const Csr &a);
+
+}  // namespace auxp

@@ -1,0 +1,155 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars (from the arithmetic):
+* FP64 preconditioner application: relative 2-norm <= 1e-12 (the operator is
+  a fixed composition of ~10^2 sparse passes; rounding-order differences stay
+  near machine precision times its norm);
+* CG in FP64 with the iteration count fixed to the oracle's: <= 1e-10; the
+  free-running iteration count within +-1 of the oracle's;
+* mixed mode (FP32 preconditioner): converged solution within 1e-7 of the
+  FP64 oracle, iteration count within +-1 of the oracle's FP32 mode;
+* determinism: repeated FP64 solves are bitwise identical.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1204_2586_amd as aux
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _case(k, n, jitter=0.0, kappa=None, seed=0):
+    xyz, tets = W.kuhn_mesh(n, jitter=jitter, seed=seed)
+    if kappa == "grf":
+        kappa = np.exp(W.grf_log_kappa(xyz, tets, seed=1))
+    elif kappa == "rand":
+        kappa = np.exp(np.random.default_rng(3).normal(size=len(tets)))
+    return xyz, tets, kappa
+
+
+CASES = {
+    "p2_n8": dict(k=2, n=8),                                   # the 8^3-cube P2 workload
+    "p2_n10_jitter_rand": dict(k=2, n=10, jitter=0.2, kappa="rand"),
+    "p3_n6_grf": dict(k=3, n=6, kappa="grf"),
+    "p3_n5_jitter": dict(k=3, n=5, jitter=0.15),
+    "p2_n3_single_level": dict(k=2, n=3),                      # n_H = 8: coarse solve only
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES), ids=list(CASES))
+def pair(request):
+    c = CASES[request.param]
+    xyz, tets, kappa = _case(c["k"], c["n"], c.get("jitter", 0.0), c.get("kappa"))
+    print(f"[case {request.param}]", flush=True)
+    lib = aux.Solver(xyz, tets, c["k"], kappa, device=DEV)
+    orc = oracle.Problem(xyz, tets, c["k"], kappa).setup_amg()
+    assert np.array_equal(lib.dof_keys(), orc.dof_keys())
+    b = orc.load(W.manufactured_f)
+    return lib, orc, b
+
+
+def _t(x):
+    return torch.tensor(np.asarray(x), dtype=torch.float64, device=DEV)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_matvec(pair):
+    lib, orc, b = pair
+    x = W.random_vector(lib.n, 5)
+    y = lib.matvec(_t(x)).cpu().numpy()
+    assert _rel(y, orc.csr("A") @ x) <= 1e-14
+
+
+def test_apply_fp64(pair):
+    lib, orc, b = pair
+    lib.set_precision("fp64")
+    for seed in (1, 2):
+        r = W.random_vector(lib.n, seed)
+        z = lib.apply(_t(r)).cpu().numpy()
+        assert _rel(z, orc.apply(r)) <= 1e-12
+
+
+def test_apply_mixed(pair):
+    lib, orc, b = pair
+    lib.set_precision("mixed")
+    r = W.random_vector(lib.n, 7)
+    z = lib.apply(_t(r)).cpu().numpy()
+    assert _rel(z, orc.apply(r, fp32=True)) <= 2e-6
+    assert _rel(z, orc.apply(r)) <= 2e-6
+    lib.set_precision("fp64")
+
+
+def test_pcg_fixed_iterations_fp64(pair):
+    lib, orc, b = pair
+    lib.set_precision("fp64")
+    x, it, rr, st = orc.pcg(b, tol=1e-8)
+    assert st == 0
+    u, info = lib.solve(_t(b), tol=0.0, maxit=it, check=False)
+    assert info.iterations == it and info.status == -4
+    assert _rel(u.cpu().numpy(), x) <= 1e-10
+    assert abs(info.rel_residual - rr) <= 1e-4 * rr
+
+
+def test_pcg_free_running_fp64(pair):
+    lib, orc, b = pair
+    lib.set_precision("fp64")
+    x, it, rr, st = orc.pcg(b, tol=1e-8)
+    u, info = lib.solve(_t(b), tol=1e-8)
+    assert info.converged and abs(info.iterations - it) <= 1
+    assert info.rel_residual <= 1e-8
+    assert _rel(u.cpu().numpy(), x) <= 1e-7
+
+
+def test_pcg_mixed(pair):
+    lib, orc, b = pair
+    lib.set_precision("mixed")
+    x64, it64, _, _ = orc.pcg(b, tol=1e-8)
+    x32, it32, _, _ = orc.pcg(b, tol=1e-8, fp32=True)
+    u, info = lib.solve(_t(b), tol=1e-8)
+    lib.set_precision("fp64")
+    assert info.converged and abs(info.iterations - it32) <= 1
+    assert _rel(u.cpu().numpy(), x64) <= 1e-7
+
+
+def test_deterministic(pair):
+    lib, orc, b = pair
+    lib.set_precision("fp64")
+    u1, i1 = lib.solve(_t(b), tol=1e-10)
+    u2, i2 = lib.solve(_t(b), tol=1e-10)
+    assert i1.iterations == i2.iterations
+    assert torch.equal(u1, u2)
+
+
+def test_kappa_grad(pair):
+    lib, orc, b = pair
+    u = W.random_vector(lib.n, 11)
+    lam = W.random_vector(lib.n, 12)
+    g = lib.kappa_grad(_t(u), _t(lam)).cpu().numpy()
+    assert _rel(g, orc.kappa_grad(u, lam)) <= 1e-12
+
+
+def test_status_codes():
+    xyz, tets, _ = _case(2, 4)
+    lib = aux.Solver(xyz, tets, 2, device=DEV)
+    orc = oracle.Problem(xyz, tets, 2).setup_amg()
+    b = orc.load(W.manufactured_f)
+    u, info = lib.solve(_t(np.zeros(lib.n)), tol=1e-8)
+    assert info.converged and info.iterations == 0 and not torch.any(u)
+    u, info = lib.solve(_t(b), tol=1e-12, maxit=1, check=False)
+    assert info.status == -4 and info.iterations == 1
+    bad = b.copy()
+    bad[2] = np.nan
+    u, info = lib.solve(_t(bad), tol=1e-8, check=False)
+    assert info.status == -6
+    # initial guess: starting from the converged solution needs no iteration
+    u, info = lib.solve(_t(b), tol=1e-8)
+    u2, info2 = lib.solve(_t(b), tol=1e-6, u0=u)
+    assert info2.iterations == 0 and torch.equal(u, u2)
