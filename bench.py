@@ -39,8 +39,8 @@ def algorithmic_bytes(cat, n, nnz, s):
         return mat + 4 * s * n
     if cat == "pk_last":       # z_in, rhs (FP64), dinv, z_out (FP64)
         return mat + 2 * s * n + 16 * n
-    if cat == "pk_first":      # r (FP64, gather), dinv, z_out, (FP32 copy of r)
-        return mat + 8 * n + 2 * s * n + (s * n if s == 4 else 0)
+    if cat == "pk_first":      # first sweep from zero, z = D^-1 r: r (FP64), dinv, z, (FP32 copy of r)
+        return 8 * n + 2 * s * n + (s * n if s == 4 else 0)
     if cat == "pk_resid":      # rhs, z (gather), res
         return mat + 3 * s * n
     if cat == "cg_spmv":       # FP64 operator, x (gather), y

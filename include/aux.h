@@ -58,6 +58,9 @@ extern "C" {
 #define AUX_FP64 0           /* preconditioner in FP64 */
 #define AUX_MIXED 1          /* preconditioner in FP32 inside FP64 CG */
 
+#define AUX_OP_ASSEMBLED 0   /* P^k smoother products with the assembled (sliced ELL) A_h */
+#define AUX_OP_MATFREE 1     /* ... with the matrix-free element operator on the matrix cores */
+
 typedef struct aux_handle aux_handle;
 
 typedef struct aux_mesh {
@@ -76,6 +79,9 @@ typedef struct aux_options {
     int precision;           /* AUX_FP64 or AUX_MIXED (AUX_FP64) */
     int maxit;               /* CG iteration limit (1000) */
     int host_only;           /* 1: run the host setup only, no device (for tests) */
+    int op;                  /* AUX_OP_ASSEMBLED or AUX_OP_MATFREE (AUX_OP_ASSEMBLED) */
+    int sell_window;         /* device A_h layout: rows sorted by length within windows of this
+                                many dofs (4096); 0 groups rows by node class instead */
 } aux_options;
 
 typedef struct aux_device {
@@ -96,6 +102,7 @@ typedef struct aux_info {
     int64_t level_nnz[32];
     double setup_seconds;
     int64_t device_bytes;    /* device memory held by the handle */
+    int64_t stored_A;        /* stored entries of the device P^k operator, slice padding included */
 } aux_info;
 
 typedef struct aux_solve_info {
@@ -128,6 +135,13 @@ int aux_set_stream(aux_handle *h, void *stream);
 /* Switch the preconditioner precision (AUX_FP64 or AUX_MIXED); the FP32
  * copies are made on first use. */
 int aux_set_precision(aux_handle *h, int precision);
+
+/* Choose how the preconditioner's P^k smoothing and residual products are
+ * computed: AUX_OP_ASSEMBLED (sliced-ELL A_h) or AUX_OP_MATFREE (element
+ * operator K_e = kappa_e sum_pq G^e_pq M^pq, Sec. 2 eq. (2.5), evaluated per
+ * tet with MFMA and summed per dof).  The CG product stays assembled FP64.
+ * The element data are built on first use. */
+int aux_set_operator(aux_handle *h, int op);
 
 /* Sizes, hierarchy shape and operator complexity (host struct). */
 int aux_get_info(const aux_handle *h, aux_info *info);

@@ -26,6 +26,7 @@ __all__ = ["Solver", "SolveInfo", "AuxSolveFn", "KappaSolve", "library_path", "l
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libauxprec.so")
 FP64, MIXED = 0, 1
+_OPS = {"assembled": 0, "matfree": 1}
 
 _ERRORS = {-1: "AUX_EINVAL", -2: "AUX_ENOMEM", -3: "AUX_EHIP", -4: "AUX_ENOTCONV", -5: "AUX_EBREAKDOWN",
            -6: "AUX_ENAN", -7: "AUX_ESTATE"}
@@ -45,7 +46,8 @@ class _Mesh(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_int), ("theta", ctypes.c_double), ("coarse_max", ctypes.c_int),
                 ("max_levels", ctypes.c_int), ("pmis_seed", ctypes.c_uint64), ("precision", ctypes.c_int),
-                ("maxit", ctypes.c_int), ("host_only", ctypes.c_int)]
+                ("maxit", ctypes.c_int), ("host_only", ctypes.c_int), ("op", ctypes.c_int),
+                ("sell_window", ctypes.c_int)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -63,7 +65,7 @@ class _Info(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("op_complexity", ctypes.c_double),
                 ("amg_complexity", ctypes.c_double), ("level_rows", ctypes.c_int64 * 32),
                 ("level_nnz", ctypes.c_int64 * 32), ("setup_seconds", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("stored_A", ctypes.c_int64)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -107,6 +109,7 @@ def load_library():
         "aux_destroy": (ctypes.c_int, [vp]),
         "aux_set_stream": (ctypes.c_int, [vp, vp]),
         "aux_set_precision": (ctypes.c_int, [vp, ctypes.c_int]),
+        "aux_set_operator": (ctypes.c_int, [vp, ctypes.c_int]),
         "aux_get_info": (ctypes.c_int, [vp, P(_Info)]),
         "aux_dof_keys": (ctypes.c_int, [vp, vp]),
         "aux_qpoints_per_tet": (ctypes.c_int, [vp]),
@@ -150,7 +153,8 @@ class Solver:
 
     def __init__(self, xyz, tets, order: int, kappa=None, *, nu: int = 2, theta: float = 0.8,
                  coarse_max: int = 100, max_levels: int = 25, seed: int = 0, precision: str = "fp64",
-                 maxit: int = 1000, host_only: bool = False, device=None, use_torch_allocator: bool = True):
+                 maxit: int = 1000, host_only: bool = False, device=None, use_torch_allocator: bool = True,
+                 operator: str = "assembled", sell_window: int = 4096):
         lib = load_library()
         self._h = ctypes.c_void_p()
         self.order = order
@@ -163,6 +167,8 @@ class Solver:
         opt.nu, opt.theta, opt.coarse_max, opt.max_levels = nu, theta, coarse_max, max_levels
         opt.pmis_seed, opt.maxit, opt.host_only = seed, maxit, int(host_only)
         opt.precision = {"fp64": FP64, "mixed": MIXED}[precision]
+        opt.op = _OPS[operator]
+        opt.sell_window = sell_window
         kap = None
         if kappa is not None:
             self._kappa = np.ascontiguousarray(kappa, dtype=np.float64)
@@ -224,6 +230,11 @@ class Solver:
     def set_precision(self, precision: str):
         _check(load_library().aux_set_precision(self._h, {"fp64": FP64, "mixed": MIXED}[precision]))
         self.info = self._info()
+
+    def set_operator(self, operator: str):
+        """'assembled' (sliced-ELL A_h) or 'matfree' (element operator on the matrix cores)
+        for the preconditioner's P^k products."""
+        _check(load_library().aux_set_operator(self._h, _OPS[operator]))
 
     @property
     def levels(self):
@@ -378,8 +389,7 @@ class KappaSolve:
     def solver_for(self, kappa: np.ndarray) -> Solver:
         key = hash(kappa.tobytes())
         if self._key != key:
-            if self._solver is not None:
-                self._solver.close()
+            # the previous solver stays alive while an autograd graph refers to it
             self._solver = Solver(self.xyz, self.tets, self.order, kappa, **self.options)
             self._key = key
         return self._solver
@@ -399,10 +409,11 @@ def _make_autograd():
 
         @staticmethod
         def forward(ctx, f, log_kappa, problem):
-            kappa = torch.exp(log_kappa.detach()).cpu().numpy()
+            kappa = torch.exp(log_kappa.detach().double()).cpu().numpy()
             s = problem.solver_for(kappa)
-            u, info = s.solve(f.detach().contiguous(), tol=problem.tol)
-            ctx.solver = s
+            u, info = s.solve(f.detach().double().contiguous(), tol=problem.tol)
+            ctx.solver, ctx.tol = s, problem.tol
+            ctx.kdtype, ctx.kdevice = log_kappa.dtype, log_kappa.device
             ctx.save_for_backward(u)
             return u
 
@@ -410,12 +421,9 @@ def _make_autograd():
         def backward(ctx, grad_u):
             (u,) = ctx.saved_tensors
             s = ctx.solver
-            lam, _ = s.solve(grad_u.contiguous(), tol=s_tol(ctx))
+            lam, _ = s.solve(grad_u.double().contiguous(), tol=ctx.tol)
             g = s.kappa_grad(u, lam)
-            return lam, g.to(grad_u.dtype), None
-
-    def s_tol(ctx):
-        return 1e-12
+            return lam, g.to(dtype=ctx.kdtype, device=ctx.kdevice), None
 
     return _AuxSolveFn
 

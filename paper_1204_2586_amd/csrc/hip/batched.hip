@@ -1,0 +1,508 @@
+// Batched solve phase: NR right-hand sides in lock-step.
+//
+// Block vectors are row-major [n][NR] (NR in {8, 16, 32, 64}); a row of a
+// sparse operator is handled by NR consecutive lanes, one per right-hand
+// side, so each matrix entry is read once per row and applied to all
+// columns (sparse matrix times dense block).  The gathered rows of the block
+// are NR contiguous words.  Every column follows the single right-hand-side
+// CG exactly: its own alpha, beta and stopping test; converged columns are
+// frozen while the others continue.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "batched.hpp"
+
+namespace auxp {
+
+namespace {
+
+__device__ __forceinline__ bool stop_all(const int *all_done) { return all_done != nullptr && *all_done != 0; }
+
+inline int grid_cap(long long need)
+{
+    if (need < 1) need = 1;
+    if (need > kMaxBlocks) need = kMaxBlocks;
+    return (int)need;
+}
+
+// rows handled by a block: kBlock / NR
+#define FOR_BROWS(NR, nrows)                                                                                 \
+    const int c_ = threadIdx.x % (NR);                                                                       \
+    for (int row = blockIdx.x * (kBlock / (NR)) + (int)threadIdx.x / (NR); row < (nrows);                    \
+         row += gridDim.x * (kBlock / (NR)))
+
+inline int brows_grid(int n, int NR) { return grid_cap(((long long)n * NR + kBlock - 1) / kBlock); }
+
+// per-column partial sums of a block: partials[blockIdx.x * NR + c]
+template <int NR>
+__device__ void write_col_partials(double *partials, double v)
+{
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x < NR) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < kBlock; i += NR) s += red[i];
+        partials[(size_t)blockIdx.x * NR + threadIdx.x] = s;
+    }
+}
+
+// ------------------------------------------------------------------ SELL
+
+// entries of one P^k row (internal row r: slice r/64, lane r%64)
+template <typename T, typename XF>
+__device__ __forceinline__ T bsell_row(const DevSellView &A, int row, XF x)
+{
+    const T *__restrict__ val = (const T *)A.val;
+    const int *__restrict__ col = A.col;
+    const int sl = row >> 6, lane = row & 63;
+    const int e1 = A.slice_off[sl + 1];
+    T s = T(0);
+#pragma unroll 4
+    for (int e = A.slice_off[sl] + lane; e < e1; e += kSlice) s += val[e] * x(col[e]);
+    return s;
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void kb_jacobi0(int n, const T *__restrict__ dinv, const double *__restrict__ R,
+                                                     T *__restrict__ Z, T *__restrict__ RT, const int *all_done)
+{
+    if (stop_all(all_done)) return;
+    FOR_BROWS(NR, n)
+    {
+        size_t o = (size_t)row * NR + c_;
+        T ri = (T)R[o];
+        Z[o] = dinv[row] * ri;
+        if (RT) RT[o] = ri;
+    }
+}
+
+template <typename T, typename TR, typename TZ, int NR, bool DOT>
+__global__ __launch_bounds__(kBlock) void kb_sweep(DevSellView A, const T *__restrict__ dinv,
+                                                   const TR *__restrict__ RHS, const T *__restrict__ Zin,
+                                                   TZ *__restrict__ Zout, const double *__restrict__ Rdot,
+                                                   double *partials, const int *all_done)
+{
+    if (stop_all(all_done)) return;
+    double acc = 0.0;
+    FOR_BROWS(NR, A.n)
+    {
+        T s = bsell_row<T>(A, row, [&](int j) { return Zin[(size_t)j * NR + c_]; });
+        size_t o = (size_t)row * NR + c_;
+        T zi = Zin[o] + dinv[row] * ((T)RHS[o] - s);
+        Zout[o] = (TZ)zi;
+        if (DOT) acc += Rdot[o] * (double)(TZ)zi;
+    }
+    if (DOT) write_col_partials<NR>(partials, acc);
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void kb_resid(DevSellView A, const T *__restrict__ RHS, const T *__restrict__ Z,
+                                                   T *__restrict__ Res, const int *all_done)
+{
+    if (stop_all(all_done)) return;
+    FOR_BROWS(NR, A.n)
+    {
+        T s = bsell_row<T>(A, row, [&](int j) { return Z[(size_t)j * NR + c_]; });
+        size_t o = (size_t)row * NR + c_;
+        Res[o] = RHS[o] - s;
+    }
+}
+
+template <int NR, bool DOT, bool RESID>
+__global__ __launch_bounds__(kBlock) void kb_spmv64(DevSellView A, const double *__restrict__ X,
+                                                    double *__restrict__ Y, const double *__restrict__ F,
+                                                    double *partials, const int *all_done)
+{
+    if (stop_all(all_done)) return;
+    double acc = 0.0;
+    FOR_BROWS(NR, A.n)
+    {
+        double s = bsell_row<double>(A, row, [&](int j) { return X[(size_t)j * NR + c_]; });
+        size_t o = (size_t)row * NR + c_;
+        if (RESID) {
+            Y[o] = F[o] - s;
+        } else {
+            Y[o] = s;
+            if (DOT) acc += X[o] * s;
+        }
+    }
+    if (DOT) write_col_partials<NR>(partials, acc);
+}
+
+// ------------------------------------------------------------------- CSR
+
+template <typename T, int NR, int MODE>   // MODE 0: y = Mx, 1: y += Mx
+__global__ __launch_bounds__(kBlock) void kb_csr_matvec(int n, const int *__restrict__ ptr, const int *__restrict__ col,
+                                                        const T *__restrict__ val, const T *__restrict__ X,
+                                                        T *__restrict__ Y, const int *all_done)
+{
+    if (stop_all(all_done)) return;
+    FOR_BROWS(NR, n)
+    {
+        T s = T(0);
+        for (int e = ptr[row]; e < ptr[row + 1]; e++) s += val[e] * X[(size_t)col[e] * NR + c_];
+        size_t o = (size_t)row * NR + c_;
+        Y[o] = MODE ? Y[o] + s : s;
+    }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void kb_csr_vpre(int n, const int *__restrict__ ptr, const int *__restrict__ col,
+                                                      const T *__restrict__ val, const T *__restrict__ dinv,
+                                                      const T *__restrict__ B, T *__restrict__ X, T *__restrict__ R,
+                                                      const int *all_done)
+{
+    if (stop_all(all_done)) return;
+    FOR_BROWS(NR, n)
+    {
+        T s = T(0);
+        for (int e = ptr[row]; e < ptr[row + 1]; e++) {
+            int j = col[e];
+            s += val[e] * (dinv[j] * B[(size_t)j * NR + c_]);
+        }
+        size_t o = (size_t)row * NR + c_;
+        X[o] = dinv[row] * B[o];
+        R[o] = B[o] - s;
+    }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void kb_csr_sweep(int n, const int *__restrict__ ptr, const int *__restrict__ col,
+                                                       const T *__restrict__ val, const T *__restrict__ dinv,
+                                                       const T *__restrict__ B, const T *__restrict__ X,
+                                                       T *__restrict__ Y, const int *all_done)
+{
+    if (stop_all(all_done)) return;
+    FOR_BROWS(NR, n)
+    {
+        T s = T(0);
+        for (int e = ptr[row]; e < ptr[row + 1]; e++) s += val[e] * X[(size_t)col[e] * NR + c_];
+        size_t o = (size_t)row * NR + c_;
+        Y[o] = X[o] + dinv[row] * (B[o] - s);
+    }
+}
+
+// X = Ainv B for the dense coarsest inverse (rows spread over the grid)
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void kb_dense(int n, const T *__restrict__ Ainv, const T *__restrict__ B,
+                                                   T *__restrict__ X, const int *all_done)
+{
+    if (stop_all(all_done)) return;
+    FOR_BROWS(NR, n)
+    {
+        T s = T(0);
+        for (int j = 0; j < n; j++) s += Ainv[(size_t)row * n + j] * B[(size_t)j * NR + c_];
+        X[(size_t)row * NR + c_] = s;
+    }
+}
+
+// ------------------------------------------------------------------- CG
+
+template <int NR>
+__global__ __launch_bounds__(kBlock) void kb_dot(int n, const double *__restrict__ a, const double *__restrict__ b,
+                                                 double *partials)
+{
+    double acc = 0.0;
+    FOR_BROWS(NR, n)
+    {
+        size_t o = (size_t)row * NR + c_;
+        acc += a[o] * b[o];
+    }
+    write_col_partials<NR>(partials, acc);
+}
+
+// sum the per-column partials and update the per-column CG state
+template <int NR>
+__global__ __launch_bounds__(kBlock) void kb_finish(const double *__restrict__ partials, int nparts, int mode,
+                                                    double *out, BCgState st)
+{
+    if (mode != FIN_PLAIN && *st.all_done) return;
+    __shared__ double red[kBlock];
+    const int c = threadIdx.x % NR;
+    double s = 0.0;
+    for (int b = threadIdx.x / NR; b < nparts; b += kBlock / NR) s += partials[(size_t)b * NR + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    __shared__ int active_left;
+    if (threadIdx.x == 0) active_left = 0;
+    __syncthreads();
+    if (threadIdx.x < NR) {
+        double t = 0.0;
+        for (int i = threadIdx.x; i < kBlock; i += NR) t += red[i];
+        const int k = *st.k;
+        if (mode == FIN_PLAIN) {
+            out[c] = t;
+        } else if (st.done[c] == 0) {
+            int d = 0;
+            if (mode == FIN_RR) {
+                st.rr[(size_t)(k + 1) * NR + c] = t;
+                st.iter[c] = k + 1;
+                if (!std::isfinite(t)) d = 4;
+                else if (t <= st.tol2ff[c]) d = 1;
+                else if (k + 1 >= st.maxit) d = 2;
+            } else {
+                (mode == FIN_PQ ? st.pq : st.rz)[(size_t)k * NR + c] = t;
+                if (!std::isfinite(t)) d = 4;
+                else if (!(t > 0.0)) d = 3;
+            }
+            if (d) st.done[c] = d;
+            else atomicAdd(&active_left, 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && mode != FIN_PLAIN) {
+        if (mode == FIN_RR) *st.k += 1;
+        if (active_left == 0) *st.all_done = 1;
+    }
+}
+
+template <int NR>
+__global__ void kb_cg_init(BCgState st, double tol2, const double *ff, const double *rr0)
+{
+    const int c = threadIdx.x;
+    if (c >= NR) return;
+    double f2 = ff[c], r2 = rr0[c];
+    st.rr[c] = r2;
+    st.tol2ff[c] = tol2 * f2;
+    st.iter[c] = 0;
+    int d = 0;
+    if (!std::isfinite(f2) || !std::isfinite(r2)) d = 4;
+    else if (r2 <= tol2 * f2) d = 1;
+    else if (st.maxit <= 0) d = 2;
+    st.done[c] = d;
+    __shared__ int any;
+    if (c == 0) any = 0;
+    __syncthreads();
+    if (d == 0) atomicAdd(&any, 1);
+    __syncthreads();
+    if (c == 0) {
+        *st.k = 0;
+        *st.all_done = any == 0;
+    }
+}
+
+template <int NR>
+__global__ __launch_bounds__(kBlock) void kb_cg_update(int n, double *__restrict__ X, double *__restrict__ R,
+                                                       const double *__restrict__ P, const double *__restrict__ Q,
+                                                       BCgState st, double *partials)
+{
+    if (*st.all_done) return;
+    const int k = *st.k;
+    const int c = threadIdx.x % NR;
+    const bool active = st.done[c] == 0;
+    const double alpha = active ? st.rz[(size_t)k * NR + c] / st.pq[(size_t)k * NR + c] : 0.0;
+    double acc = 0.0;
+    FOR_BROWS(NR, n)
+    {
+        size_t o = (size_t)row * NR + c_;
+        double ri = R[o];
+        if (active) {
+            X[o] += alpha * P[o];
+            ri -= alpha * Q[o];
+            R[o] = ri;
+        }
+        acc += ri * ri;
+    }
+    write_col_partials<NR>(partials, acc);
+}
+
+template <int NR>
+__global__ __launch_bounds__(kBlock) void kb_cg_direction(int n, const double *__restrict__ Z, double *__restrict__ P,
+                                                          BCgState st)
+{
+    if (*st.all_done) return;
+    const int k = *st.k;
+    const int c = threadIdx.x % NR;
+    if (st.done[c] != 0) return;
+    const double beta = k == 0 ? 0.0 : st.rz[(size_t)k * NR + c] / st.rz[(size_t)(k - 1) * NR + c];
+    FOR_BROWS(NR, n)
+    {
+        size_t o = (size_t)row * NR + c_;
+        P[o] = k == 0 ? Z[o] : Z[o] + beta * P[o];
+    }
+}
+
+// internal block row i = external row perm[i]; external leading dimension ld
+template <int NR>
+__global__ __launch_bounds__(kBlock) void kb_gather(int n, int ld, const int *__restrict__ perm,
+                                                    const double *__restrict__ x, double *__restrict__ y)
+{
+    FOR_BROWS(NR, n)
+    {
+        y[(size_t)row * NR + c_] = c_ < ld ? x[(size_t)perm[row] * ld + c_] : 0.0;
+    }
+}
+
+template <int NR>
+__global__ __launch_bounds__(kBlock) void kb_scatter(int n, int ld, const int *__restrict__ perm,
+                                                     const double *__restrict__ x, double *__restrict__ y)
+{
+    FOR_BROWS(NR, n)
+    {
+        if (c_ < ld) y[(size_t)perm[row] * ld + c_] = x[(size_t)row * NR + c_];
+    }
+}
+
+}  // namespace
+
+#define NR_SWITCH(nr, CALL)                            \
+    switch (nr) {                                      \
+    case 8: { constexpr int NR = 8; CALL; } break;     \
+    case 16: { constexpr int NR = 16; CALL; } break;   \
+    case 32: { constexpr int NR = 32; CALL; } break;   \
+    default: { constexpr int NR = 64; CALL; } break;   \
+    }
+
+template <typename T>
+void bjacobi0(hipStream_t s, int nr, int n, const T *dinv, const double *R, T *Z, T *RT, const int *all_done)
+{
+    int g = brows_grid(n, nr);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_jacobi0<T, NR>), dim3(g), dim3(kBlock), 0, s, n, dinv, R, Z, RT, all_done));
+}
+
+template <typename T, typename TR, typename TZ>
+int bsell_sweep(hipStream_t s, int nr, const DevSellView &A, const T *dinv, const TR *RHS, const T *Zin, TZ *Zout,
+                const double *Rdot, double *partials, const int *all_done)
+{
+    int g = brows_grid(A.n, nr);
+    if (partials) {
+        NR_SWITCH(nr, hipLaunchKernelGGL((kb_sweep<T, TR, TZ, NR, true>), dim3(g), dim3(kBlock), 0, s, A, dinv, RHS,
+                                         Zin, Zout, Rdot, partials, all_done));
+    } else {
+        NR_SWITCH(nr, hipLaunchKernelGGL((kb_sweep<T, TR, TZ, NR, false>), dim3(g), dim3(kBlock), 0, s, A, dinv, RHS,
+                                         Zin, Zout, Rdot, partials, all_done));
+    }
+    return g;
+}
+
+template <typename T>
+int bsell_resid(hipStream_t s, int nr, const DevSellView &A, const T *RHS, const T *Z, T *Res, const int *all_done)
+{
+    int g = brows_grid(A.n, nr);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_resid<T, NR>), dim3(g), dim3(kBlock), 0, s, A, RHS, Z, Res, all_done));
+    return g;
+}
+
+int bsell_spmv64(hipStream_t s, int nr, const DevSellView &A, const double *X, double *Y, double *partials,
+                 const int *all_done)
+{
+    int g = brows_grid(A.n, nr);
+    if (partials) {
+        NR_SWITCH(nr, hipLaunchKernelGGL((kb_spmv64<NR, true, false>), dim3(g), dim3(kBlock), 0, s, A, X, Y,
+                                         (const double *)nullptr, partials, all_done));
+    } else {
+        NR_SWITCH(nr, hipLaunchKernelGGL((kb_spmv64<NR, false, false>), dim3(g), dim3(kBlock), 0, s, A, X, Y,
+                                         (const double *)nullptr, partials, all_done));
+    }
+    return g;
+}
+
+int bsell_residual64(hipStream_t s, int nr, const DevSellView &A, const double *F, const double *U, double *R)
+{
+    int g = brows_grid(A.n, nr);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_spmv64<NR, false, true>), dim3(g), dim3(kBlock), 0, s, A, U, R, F,
+                                     (double *)nullptr, (const int *)nullptr));
+    return g;
+}
+
+template <typename T>
+void bcsr_matvec(hipStream_t s, int nr, const DevCsrView &M, const T *X, T *Y, bool add, const int *all_done)
+{
+    int g = brows_grid(M.n, nr);
+    if (add) {
+        NR_SWITCH(nr, hipLaunchKernelGGL((kb_csr_matvec<T, NR, 1>), dim3(g), dim3(kBlock), 0, s, M.n, M.ptr, M.col,
+                                         (const T *)M.val, X, Y, all_done));
+    } else {
+        NR_SWITCH(nr, hipLaunchKernelGGL((kb_csr_matvec<T, NR, 0>), dim3(g), dim3(kBlock), 0, s, M.n, M.ptr, M.col,
+                                         (const T *)M.val, X, Y, all_done));
+    }
+}
+
+template <typename T>
+void bcsr_vpre(hipStream_t s, int nr, const DevCsrView &A, const T *dinv, const T *B, T *X, T *R, const int *all_done)
+{
+    int g = brows_grid(A.n, nr);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_csr_vpre<T, NR>), dim3(g), dim3(kBlock), 0, s, A.n, A.ptr, A.col,
+                                     (const T *)A.val, dinv, B, X, R, all_done));
+}
+
+template <typename T>
+void bcsr_sweep(hipStream_t s, int nr, const DevCsrView &A, const T *dinv, const T *B, const T *X, T *Y,
+                const int *all_done)
+{
+    int g = brows_grid(A.n, nr);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_csr_sweep<T, NR>), dim3(g), dim3(kBlock), 0, s, A.n, A.ptr, A.col,
+                                     (const T *)A.val, dinv, B, X, Y, all_done));
+}
+
+template <typename T>
+void bdense(hipStream_t s, int nr, int n, const T *Ainv, const T *B, T *X, const int *all_done)
+{
+    int g = brows_grid(n, nr);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_dense<T, NR>), dim3(g), dim3(kBlock), 0, s, n, Ainv, B, X, all_done));
+}
+
+int bvec_dot(hipStream_t s, int nr, int n, const double *a, const double *b, double *partials)
+{
+    int g = brows_grid(n, nr);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_dot<NR>), dim3(g), dim3(kBlock), 0, s, n, a, b, partials));
+    return g;
+}
+
+void bfinish(hipStream_t s, int nr, const double *partials, int nparts, FinishMode mode, double *out,
+             const BCgState &st)
+{
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_finish<NR>), dim3(1), dim3(kBlock), 0, s, partials, nparts, (int)mode, out,
+                                     st));
+}
+
+void bcg_init(hipStream_t s, int nr, const BCgState &st, double tol2, const double *ff, const double *rr0)
+{
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_cg_init<NR>), dim3(1), dim3(64), 0, s, st, tol2, ff, rr0));
+}
+
+int bcg_update(hipStream_t s, int nr, int n, double *X, double *R, const double *P, const double *Q,
+               const BCgState &st, double *partials)
+{
+    int g = brows_grid(n, nr);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_cg_update<NR>), dim3(g), dim3(kBlock), 0, s, n, X, R, P, Q, st, partials));
+    return g;
+}
+
+void bcg_direction(hipStream_t s, int nr, int n, const double *Z, double *P, const BCgState &st)
+{
+    int g = brows_grid(n, nr);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_cg_direction<NR>), dim3(g), dim3(kBlock), 0, s, n, Z, P, st));
+}
+
+void bgather(hipStream_t s, int nr, int n, int ld, const int *perm, const double *x, double *y)
+{
+    int g = brows_grid(n, nr);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_gather<NR>), dim3(g), dim3(kBlock), 0, s, n, ld, perm, x, y));
+}
+
+void bscatter(hipStream_t s, int nr, int n, int ld, const int *perm, const double *x, double *y)
+{
+    int g = brows_grid(n, nr);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_scatter<NR>), dim3(g), dim3(kBlock), 0, s, n, ld, perm, x, y));
+}
+
+#define BINST(T)                                                                                                   \
+    template void bjacobi0<T>(hipStream_t, int, int, const T *, const double *, T *, T *, const int *);            \
+    template int bsell_sweep<T, T, T>(hipStream_t, int, const DevSellView &, const T *, const T *, const T *, T *, \
+                                      const double *, double *, const int *);                                      \
+    template int bsell_resid<T>(hipStream_t, int, const DevSellView &, const T *, const T *, T *, const int *);    \
+    template void bcsr_matvec<T>(hipStream_t, int, const DevCsrView &, const T *, T *, bool, const int *);         \
+    template void bcsr_vpre<T>(hipStream_t, int, const DevCsrView &, const T *, const T *, T *, T *, const int *); \
+    template void bcsr_sweep<T>(hipStream_t, int, const DevCsrView &, const T *, const T *, const T *, T *,        \
+                                const int *);                                                                      \
+    template void bdense<T>(hipStream_t, int, int, const T *, const T *, T *, const int *);
+
+BINST(double)
+BINST(float)
+template int bsell_sweep<float, double, double>(hipStream_t, int, const DevSellView &, const float *, const double *,
+                                                const float *, double *, const double *, double *, const int *);
+
+}  // namespace auxp

@@ -1,0 +1,50 @@
+// Batched (multi right-hand side) solve-phase kernels; see batched.hip.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace auxp {
+
+// Per-column CG state of a lock-step batched solve (NR columns).
+struct BCgState {
+    int *k;              // lock-step iteration index
+    int *iter;           // [NR] iterations performed by each column
+    int *done;           // [NR] 0 running, 1 converged, 2 maxit, 3 breakdown, 4 non-finite
+    int *all_done;       // 1 when no column is running
+    double *rz, *pq, *rr;  // [(maxit+2)][NR]
+    double *tol2ff;      // [NR] tol^2 f_c . f_c
+    int maxit;
+};
+
+template <typename T>
+void bjacobi0(hipStream_t s, int nr, int n, const T *dinv, const double *R, T *Z, T *RT, const int *all_done);
+template <typename T, typename TR, typename TZ>
+int bsell_sweep(hipStream_t s, int nr, const DevSellView &A, const T *dinv, const TR *RHS, const T *Zin, TZ *Zout,
+                const double *Rdot, double *partials, const int *all_done);
+template <typename T>
+int bsell_resid(hipStream_t s, int nr, const DevSellView &A, const T *RHS, const T *Z, T *Res, const int *all_done);
+int bsell_spmv64(hipStream_t s, int nr, const DevSellView &A, const double *X, double *Y, double *partials,
+                 const int *all_done);
+int bsell_residual64(hipStream_t s, int nr, const DevSellView &A, const double *F, const double *U, double *R);
+
+template <typename T>
+void bcsr_matvec(hipStream_t s, int nr, const DevCsrView &M, const T *X, T *Y, bool add, const int *all_done);
+template <typename T>
+void bcsr_vpre(hipStream_t s, int nr, const DevCsrView &A, const T *dinv, const T *B, T *X, T *R, const int *all_done);
+template <typename T>
+void bcsr_sweep(hipStream_t s, int nr, const DevCsrView &A, const T *dinv, const T *B, const T *X, T *Y,
+                const int *all_done);
+template <typename T>
+void bdense(hipStream_t s, int nr, int n, const T *Ainv, const T *B, T *X, const int *all_done);
+
+int bvec_dot(hipStream_t s, int nr, int n, const double *a, const double *b, double *partials);
+void bfinish(hipStream_t s, int nr, const double *partials, int nparts, FinishMode mode, double *out,
+             const BCgState &st);
+void bcg_init(hipStream_t s, int nr, const BCgState &st, double tol2, const double *ff, const double *rr0);
+int bcg_update(hipStream_t s, int nr, int n, double *X, double *R, const double *P, const double *Q,
+               const BCgState &st, double *partials);
+void bcg_direction(hipStream_t s, int nr, int n, const double *Z, double *P, const BCgState &st);
+void bgather(hipStream_t s, int nr, int n, int ld, const int *perm, const double *x, double *y);
+void bscatter(hipStream_t s, int nr, int n, int ld, const int *perm, const double *x, double *y);
+
+}  // namespace auxp

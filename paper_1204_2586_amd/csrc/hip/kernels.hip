@@ -1,8 +1,9 @@
 // Solve-phase kernels of the auxiliary-space preconditioned CG (gfx950).
 //
-// Memory-bound sparse work: every kernel streams its CSR operator once,
-// gathers the vector it multiplies, and fuses the elementwise smoother and
-// residual updates into the same pass (l1-Jacobi sweep = one pass over A).
+// All of this work is memory-bound sparse algebra: every kernel streams its
+// operator once, gathers the vector it multiplies, and fuses the elementwise
+// smoother / residual / CG updates into the same pass (one l1-Jacobi sweep is
+// one pass over A).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -23,22 +24,11 @@ __device__ __forceinline__ A group_sum(A v)
     return v;
 }
 
-// sum_j a_ij x(col_j) over the row, lanes sub, sub+LPR, ...
-template <int LPR, typename T, typename XF>
-__device__ __forceinline__ T row_dot(const int *__restrict__ ptr, const int *__restrict__ col,
-                                     const T *__restrict__ val, int row, int sub, XF x)
-{
-    T s = T(0);
-    const int e1 = ptr[row + 1];
-    for (int e = ptr[row] + sub; e < e1; e += LPR) s += val[e] * x(col[e]);
-    return group_sum<LPR>(s);
-}
-
+// sum over the block (kBlock threads) in a fixed order; valid in thread 0
 __device__ double block_sum(double v)
 {
     __shared__ double red[kBlock / 64];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    v = group_sum<64>(v);
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     __syncthreads();
     if (l == 0) red[w] = v;
@@ -46,52 +36,106 @@ __device__ double block_sum(double v)
     double s = 0.0;
     if (threadIdx.x == 0)
         for (int i = 0; i < kBlock / 64; i++) s += red[i];
-    return s;   // valid in thread 0
+    return s;
 }
 
-// Deterministic grid reduction: the partial of each workgroup is stored, and
-// the last workgroup to arrive sums all partials in index order.
-// Returns true in thread 0 of the last workgroup (which then holds *total).
-__device__ bool grid_reduce(double v, const Reduce &red, double *total)
+__device__ __forceinline__ void write_partial(double *partials, double v)
 {
-    __shared__ int is_last;
     double b = block_sum(v);
-    if (threadIdx.x == 0) {
-        red.partials[blockIdx.x] = b;
-        __threadfence();
-        unsigned int t = atomicAdd(red.counter, 1u);
-        is_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double s = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock)
-        s += __hip_atomic_load(&red.partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s = block_sum(s);
-    if (threadIdx.x == 0) {
-        *red.counter = 0u;
-        *total = s;
-        if (red.out) red.out[red.index ? *red.index : 0] = s;
-        return true;
-    }
-    return false;
+    if (threadIdx.x == 0) partials[blockIdx.x] = b;
 }
 
-inline int grid_for(int n, int rows_per_block)
+inline int grid_cap(long long need)
 {
-    long long g = ((long long)n + rows_per_block - 1) / rows_per_block;
-    if (g < 1) g = 1;
-    if (g > kMaxBlocks) g = kMaxBlocks;
-    return (int)g;
+    if (need < 1) need = 1;
+    if (need > kMaxBlocks) need = kMaxBlocks;
+    return (int)need;
 }
 
-#define FOR_ROWS(LPR, n)                                                               \
-    const int sub_ = threadIdx.x % (LPR);                                              \
-    for (int base_ = blockIdx.x * (kBlock / (LPR)); base_ < (n); base_ += gridDim.x * (kBlock / (LPR))) \
-        for (int row = base_ + threadIdx.x / (LPR), once_ = 1; once_; once_ = 0)
+// ------------------------------------------------------------------ SELL
 
-// ------------------------------------------------------------- smoothers
+// one wavefront per 64-row slice, one lane per row
+#define FOR_SLICES(A)                                                                                      \
+    const int lane_ = threadIdx.x & 63;                                                                    \
+    for (int sl_ = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6); sl_ < (A).nslices;                \
+         sl_ += gridDim.x * (kBlock / 64))
+
+template <typename T, typename XF>
+__device__ __forceinline__ T sell_row(const DevSellView &A, int slice, int lane, XF x)
+{
+    const T *__restrict__ val = (const T *)A.val;
+    const int *__restrict__ col = A.col;
+    const int e1 = A.slice_off[slice + 1];
+    T s = T(0);
+#pragma unroll 4
+    for (int e = A.slice_off[slice] + lane; e < e1; e += kSlice) s += val[e] * x(col[e]);
+    return s;
+}
+
+inline int sell_grid(const DevSellView &A) { return grid_cap(((long long)A.nslices + 3) / 4); }
+
+template <typename T, typename TR, typename TZ, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_sell_sweep(DevSellView A, const T *__restrict__ dinv,
+                                                       const TR *__restrict__ rhs, const T *__restrict__ zin,
+                                                       TZ *__restrict__ zout, const double *__restrict__ rdot,
+                                                       double *partials, const int *done)
+{
+    if (stop(done)) return;
+    double acc = 0.0;
+    FOR_SLICES(A)
+    {
+        const int row = sl_ * kSlice + lane_;
+        T s = sell_row<T>(A, sl_, lane_, [&](int j) { return zin[j]; });
+        if (row < A.n) {
+            T zi = zin[row] + dinv[row] * ((T)rhs[row] - s);
+            zout[row] = (TZ)zi;
+            if (DOT) acc += rdot[row] * (double)(TZ)zi;
+        }
+    }
+    if (DOT) write_partial(partials, acc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sell_resid(DevSellView A, const T *__restrict__ rhs,
+                                                       const T *__restrict__ z, T *__restrict__ res, const int *done)
+{
+    if (stop(done)) return;
+    FOR_SLICES(A)
+    {
+        const int row = sl_ * kSlice + lane_;
+        T s = sell_row<T>(A, sl_, lane_, [&](int j) { return z[j]; });
+        if (row < A.n) res[row] = rhs[row] - s;
+    }
+}
+
+template <bool DOT>
+__global__ __launch_bounds__(kBlock) void k_sell_spmv64(DevSellView A, const double *__restrict__ x,
+                                                        double *__restrict__ y, double *partials, const int *done)
+{
+    if (stop(done)) return;
+    double acc = 0.0;
+    FOR_SLICES(A)
+    {
+        const int row = sl_ * kSlice + lane_;
+        double s = sell_row<double>(A, sl_, lane_, [&](int j) { return x[j]; });
+        if (row < A.n) {
+            y[row] = s;
+            if (DOT) acc += x[row] * s;
+        }
+    }
+    if (DOT) write_partial(partials, acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sell_residual64(DevSellView A, const double *__restrict__ f,
+                                                            const double *__restrict__ u, double *__restrict__ r)
+{
+    FOR_SLICES(A)
+    {
+        const int row = sl_ * kSlice + lane_;
+        double s = sell_row<double>(A, sl_, lane_, [&](int j) { return u[j]; });
+        if (row < A.n) r[row] = f[row] - s;
+    }
+}
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_jacobi0(int n, const T *__restrict__ dinv, const double *__restrict__ r,
@@ -105,99 +149,69 @@ __global__ __launch_bounds__(kBlock) void k_jacobi0(int n, const T *__restrict__
     }
 }
 
-template <typename T, int LPR>
-__global__ __launch_bounds__(kBlock) void k_first2(int n, const int *__restrict__ ptr, const int *__restrict__ col,
-                                                   const T *__restrict__ val, const T *__restrict__ dinv,
-                                                   const double *__restrict__ r, T *__restrict__ z,
-                                                   T *__restrict__ rT, const int *done)
-{
-    if (stop(done)) return;
-    FOR_ROWS(LPR, n)
-    {
-        if (row < n) {
-            // A z1 with z1 = D^{-1} r formed on the fly
-            T s = row_dot<LPR>(ptr, col, val, row, sub_, [&](int j) { return dinv[j] * (T)r[j]; });
-            if (sub_ == 0) {
-                T ri = (T)r[row], di = dinv[row];
-                T z1 = di * ri;
-                z[row] = z1 + di * (ri - s);
-                if (rT) rT[row] = ri;
-            }
-        }
-    }
-}
+// ------------------------------------------------------------------- CSR
 
-template <typename T, typename TR, typename TZ, int LPR, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_sweep(int n, const int *__restrict__ ptr, const int *__restrict__ col,
-                                                  const T *__restrict__ val, const T *__restrict__ dinv,
-                                                  const TR *__restrict__ rhs, const T *__restrict__ zin,
-                                                  TZ *__restrict__ zout, const double *__restrict__ rdot,
-                                                  Reduce red, const int *done)
-{
-    if (stop(done)) return;
-    double acc = 0.0;
-    FOR_ROWS(LPR, n)
-    {
-        if (row < n) {
-            T s = row_dot<LPR>(ptr, col, val, row, sub_, [&](int j) { return zin[j]; });
-            if (sub_ == 0) {
-                T zi = zin[row] + dinv[row] * ((T)rhs[row] - s);
-                zout[row] = (TZ)zi;
-                if (DOT) acc += rdot[row] * (double)(TZ)zi;
-            }
-        }
-    }
-    if (DOT) {
-        double tot;
-        grid_reduce(acc, red, &tot);
-    }
-}
+#define FOR_ROWS(LPR, n)                                                                                    \
+    const int sub_ = threadIdx.x % (LPR);                                                                   \
+    for (int base_ = blockIdx.x * (kBlock / (LPR)); base_ < (n); base_ += gridDim.x * (kBlock / (LPR)))     \
+        for (int row = base_ + threadIdx.x / (LPR), once_ = 1; once_; once_ = 0)
 
-template <typename T, int LPR>
-__global__ __launch_bounds__(kBlock) void k_resid(int n, const int *__restrict__ ptr, const int *__restrict__ col,
-                                                  const T *__restrict__ val, const T *__restrict__ rhs,
-                                                  const T *__restrict__ z, T *__restrict__ res, const int *done)
+template <int LPR, typename T, typename XF>
+__device__ __forceinline__ T csr_row(const int *__restrict__ ptr, const int *__restrict__ col,
+                                     const T *__restrict__ val, int row, int sub, XF x)
 {
-    if (stop(done)) return;
-    FOR_ROWS(LPR, n)
-    {
-        if (row < n) {
-            T s = row_dot<LPR>(ptr, col, val, row, sub_, [&](int j) { return z[j]; });
-            if (sub_ == 0) res[row] = rhs[row] - s;
-        }
-    }
+    T s = T(0);
+    const int e1 = ptr[row + 1];
+    for (int e = ptr[row] + sub; e < e1; e += LPR) s += val[e] * x(col[e]);
+    return group_sum<LPR>(s);
 }
 
 template <typename T, int LPR, bool ADD>
-__global__ __launch_bounds__(kBlock) void k_matvec(int n, const int *__restrict__ ptr, const int *__restrict__ col,
-                                                   const T *__restrict__ val, const T *__restrict__ x,
-                                                   T *__restrict__ y, const int *done)
+__global__ __launch_bounds__(kBlock) void k_csr_matvec(int n, const int *__restrict__ ptr, const int *__restrict__ col,
+                                                       const T *__restrict__ val, const T *__restrict__ x,
+                                                       T *__restrict__ y, const int *done)
 {
     if (stop(done)) return;
     FOR_ROWS(LPR, n)
     {
         if (row < n) {
-            T s = row_dot<LPR>(ptr, col, val, row, sub_, [&](int j) { return x[j]; });
+            T s = csr_row<LPR>(ptr, col, val, row, sub_, [&](int j) { return x[j]; });
             if (sub_ == 0) y[row] = ADD ? y[row] + s : s;
         }
     }
 }
 
 template <typename T, int LPR>
-__global__ __launch_bounds__(kBlock) void k_vpre(int n, const int *__restrict__ ptr, const int *__restrict__ col,
-                                                 const T *__restrict__ val, const T *__restrict__ dinv,
-                                                 const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r,
-                                                 const int *done)
+__global__ __launch_bounds__(kBlock) void k_csr_vpre(int n, const int *__restrict__ ptr, const int *__restrict__ col,
+                                                     const T *__restrict__ val, const T *__restrict__ dinv,
+                                                     const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r,
+                                                     const int *done)
 {
     if (stop(done)) return;
     FOR_ROWS(LPR, n)
     {
         if (row < n) {
-            T s = row_dot<LPR>(ptr, col, val, row, sub_, [&](int j) { return dinv[j] * b[j]; });
+            T s = csr_row<LPR>(ptr, col, val, row, sub_, [&](int j) { return dinv[j] * b[j]; });
             if (sub_ == 0) {
                 x[row] = dinv[row] * b[row];
                 r[row] = b[row] - s;
             }
+        }
+    }
+}
+
+template <typename T, int LPR>
+__global__ __launch_bounds__(kBlock) void k_csr_sweep(int n, const int *__restrict__ ptr, const int *__restrict__ col,
+                                                      const T *__restrict__ val, const T *__restrict__ dinv,
+                                                      const T *__restrict__ b, const T *__restrict__ x,
+                                                      T *__restrict__ y, const int *done)
+{
+    if (stop(done)) return;
+    FOR_ROWS(LPR, n)
+    {
+        if (row < n) {
+            T s = csr_row<LPR>(ptr, col, val, row, sub_, [&](int j) { return x[j]; });
+            if (sub_ == 0) y[row] = x[row] + dinv[row] * (b[row] - s);
         }
     }
 }
@@ -216,70 +230,60 @@ __global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const T *__restric
     }
 }
 
-// ---------------------------------------------------------------- FP64 CG
+// ------------------------------------------------------------------ CG
 
-template <int LPR, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_spmv64(int n, const int *__restrict__ ptr, const int *__restrict__ col,
-                                                   const double *__restrict__ val, const double *__restrict__ x,
-                                                   double *__restrict__ y, Reduce red, const int *done)
-{
-    if (stop(done)) return;
-    double acc = 0.0;
-    FOR_ROWS(LPR, n)
-    {
-        if (row < n) {
-            double s = row_dot<LPR>(ptr, col, val, row, sub_, [&](int j) { return x[j]; });
-            if (sub_ == 0) {
-                y[row] = s;
-                if (DOT) acc += x[row] * s;
-            }
-        }
-    }
-    if (DOT) {
-        double tot;
-        grid_reduce(acc, red, &tot);
-    }
-}
-
-template <int LPR>
-__global__ __launch_bounds__(kBlock) void k_residual64(int n, const int *__restrict__ ptr, const int *__restrict__ col,
-                                                       const double *__restrict__ val, const double *__restrict__ f,
-                                                       const double *__restrict__ u, double *__restrict__ r)
-{
-    FOR_ROWS(LPR, n)
-    {
-        if (row < n) {
-            double s = row_dot<LPR>(ptr, col, val, row, sub_, [&](int j) { return u[j]; });
-            if (sub_ == 0) r[row] = f[row] - s;
-        }
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_dot64(int n, const double *__restrict__ a, const double *__restrict__ b,
-                                                  Reduce red)
+__global__ __launch_bounds__(kBlock) void k_dot(int n, const double *__restrict__ a, const double *__restrict__ b,
+                                                double *partials)
 {
     double acc = 0.0;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) acc += a[i] * b[i];
-    double tot;
-    grid_reduce(acc, red, &tot);
+    write_partial(partials, acc);
 }
 
-__global__ void k_cg_init(CgState st, double tol2, const double *ff, const double *rr0)
+__global__ __launch_bounds__(kBlock) void k_finish(const double *__restrict__ partials, int nparts, int mode,
+                                                   double *out, CgState st)
+{
+    if (mode != FIN_PLAIN && *st.done) return;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) s += partials[i];
+    s = block_sum(s);
+    if (threadIdx.x != 0) return;
+    if (mode == FIN_PLAIN) {
+        *out = s;
+        return;
+    }
+    const int k = *st.iter;
+    int d = 0;
+    if (mode == FIN_RR) {
+        st.rr[k + 1] = s;
+        *st.iter = k + 1;
+        if (!std::isfinite(s)) d = 4;
+        else if (s <= st.scal[2]) d = 1;
+        else if (k + 1 >= st.maxit) d = 2;
+    } else {
+        (mode == FIN_PQ ? st.pq : st.rz)[k] = s;
+        if (!std::isfinite(s)) d = 4;
+        else if (!(s > 0.0)) d = 3;
+    }
+    if (d) *st.done = d;
+}
+
+__global__ void k_cg_init(CgState st, double tol2)
 {
     *st.iter = 0;
-    double f2 = *ff, r2 = *rr0;
+    double f2 = st.scal[0], r2 = st.scal[1];
     st.rr[0] = r2;
-    *st.tol2bb = tol2 * f2;
+    st.scal[2] = tol2 * f2;
     int d = 0;
     if (!std::isfinite(f2) || !std::isfinite(r2)) d = 4;
-    else if (r2 <= tol2 * f2) d = 1;          // includes f = 0
+    else if (r2 <= tol2 * f2) d = 1;     // includes f = 0 with u = 0
     else if (st.maxit <= 0) d = 2;
     *st.done = d;
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_update(int n, double *__restrict__ x, double *__restrict__ r,
                                                       const double *__restrict__ p, const double *__restrict__ q,
-                                                      CgState st, Reduce red)
+                                                      CgState st, double *partials)
 {
     if (*st.done) return;
     const int k = *st.iter;
@@ -291,14 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int n, double *__restrict_
         r[i] = ri;
         acc += ri * ri;
     }
-    double tot;
-    if (grid_reduce(acc, red, &tot)) {
-        st.rr[k + 1] = tot;
-        *st.iter = k + 1;
-        if (!std::isfinite(tot)) *st.done = 4;
-        else if (tot <= *st.tol2bb) *st.done = 1;
-        else if (k + 1 >= st.maxit) *st.done = 2;
-    }
+    write_partial(partials, acc);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_direction(int n, const double *__restrict__ z, double *__restrict__ p,
@@ -314,20 +311,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(int n, const double *__
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i] + beta * p[i];
 }
 
-__global__ void k_cg_check_rz(CgState st)
+__global__ __launch_bounds__(kBlock) void k_gather(int n, const int *__restrict__ idx, const double *__restrict__ x,
+                                                   double *__restrict__ y)
 {
-    if (*st.done) return;
-    double v = st.rz[*st.iter];
-    if (!std::isfinite(v)) *st.done = 4;
-    else if (!(v > 0.0)) *st.done = 3;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) y[i] = x[idx[i]];
 }
 
-__global__ void k_cg_check_pq(CgState st)
+__global__ __launch_bounds__(kBlock) void k_scatter(int n, const int *__restrict__ idx, const double *__restrict__ x,
+                                                    double *__restrict__ y)
 {
-    if (*st.done) return;
-    double v = st.pq[*st.iter];
-    if (!std::isfinite(v)) *st.done = 4;
-    else if (!(v > 0.0)) *st.done = 3;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) y[idx[i]] = x[i];
 }
 
 // ------------------------------------------------------------- adjoint
@@ -359,12 +352,6 @@ __global__ __launch_bounds__(kBlock) void k_kappa_grad(int nt, int nloc, const i
     }
 }
 
-__global__ void k_cast(int64_t n, const double *__restrict__ x, float *__restrict__ y)
-{
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        y[i] = (float)x[i];
-}
-
 }  // namespace
 
 int pick_lpr(double avg)
@@ -377,155 +364,162 @@ int pick_lpr(double avg)
     return 32;
 }
 
-#define LPR_SWITCH(lpr, CALL)                              \
-    switch (lpr) {                                         \
-    case 1: { constexpr int L = 1; CALL; } break;          \
-    case 2: { constexpr int L = 2; CALL; } break;          \
-    case 4: { constexpr int L = 4; CALL; } break;          \
-    case 8: { constexpr int L = 8; CALL; } break;          \
-    case 16: { constexpr int L = 16; CALL; } break;        \
-    default: { constexpr int L = 32; CALL; } break;        \
+#define LPR_SWITCH(lpr, CALL)                         \
+    switch (lpr) {                                    \
+    case 1: { constexpr int L = 1; CALL; } break;     \
+    case 2: { constexpr int L = 2; CALL; } break;     \
+    case 4: { constexpr int L = 4; CALL; } break;     \
+    case 8: { constexpr int L = 8; CALL; } break;     \
+    case 16: { constexpr int L = 16; CALL; } break;   \
+    default: { constexpr int L = 32; CALL; } break;   \
     }
 
-template <typename T>
-void launch_jacobi0(hipStream_t s, int n, const T *dinv, const double *r, T *z, T *rT, const int *done)
-{
-    hipLaunchKernelGGL(k_jacobi0<T>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, dinv, r, z, rT, done);
-}
+static int vec_grid(long long n) { return grid_cap((n + kBlock - 1) / kBlock); }
+static int rows_grid(int n, int lpr) { return grid_cap(((long long)n * lpr + kBlock - 1) / kBlock); }
 
 template <typename T>
-void launch_first2(hipStream_t s, const DevCsrView &A, const T *dinv, const double *r, T *z, T *rT, const int *done)
+int vec_jacobi0(hipStream_t s, int n, const T *dinv, const double *r, T *z, T *rT, const int *done)
 {
-    LPR_SWITCH(A.lpr, hipLaunchKernelGGL((k_first2<T, L>), dim3(grid_for(A.n, kBlock / L)), dim3(kBlock), 0, s, A.n,
-                                         A.ptr, A.col, (const T *)A.val, dinv, r, z, rT, done));
+    int g = vec_grid(n);
+    hipLaunchKernelGGL(k_jacobi0<T>, dim3(g), dim3(kBlock), 0, s, n, dinv, r, z, rT, done);
+    return g;
 }
 
 template <typename T, typename TR, typename TZ>
-void launch_sweep(hipStream_t s, const DevCsrView &A, const T *dinv, const TR *rhs, const T *zin, TZ *zout,
-                  const double *rdot, const Reduce &red, const int *done)
+int sell_sweep(hipStream_t s, const DevSellView &A, const T *dinv, const TR *rhs, const T *zin, TZ *zout,
+               const double *rdot, double *partials, const int *done)
 {
-    if (red.out) {
-        LPR_SWITCH(A.lpr, hipLaunchKernelGGL((k_sweep<T, TR, TZ, L, true>), dim3(grid_for(A.n, kBlock / L)),
-                                             dim3(kBlock), 0, s, A.n, A.ptr, A.col, (const T *)A.val, dinv, rhs, zin,
-                                             zout, rdot, red, done));
-    } else {
-        LPR_SWITCH(A.lpr, hipLaunchKernelGGL((k_sweep<T, TR, TZ, L, false>), dim3(grid_for(A.n, kBlock / L)),
-                                             dim3(kBlock), 0, s, A.n, A.ptr, A.col, (const T *)A.val, dinv, rhs, zin,
-                                             zout, rdot, red, done));
-    }
+    int g = sell_grid(A);
+    if (partials)
+        hipLaunchKernelGGL((k_sell_sweep<T, TR, TZ, true>), dim3(g), dim3(kBlock), 0, s, A, dinv, rhs, zin, zout,
+                           rdot, partials, done);
+    else
+        hipLaunchKernelGGL((k_sell_sweep<T, TR, TZ, false>), dim3(g), dim3(kBlock), 0, s, A, dinv, rhs, zin, zout,
+                           rdot, partials, done);
+    return g;
 }
 
 template <typename T>
-void launch_resid(hipStream_t s, const DevCsrView &A, const T *rhs, const T *z, T *res, const int *done)
+int sell_resid(hipStream_t s, const DevSellView &A, const T *rhs, const T *z, T *res, const int *done)
 {
-    LPR_SWITCH(A.lpr, hipLaunchKernelGGL((k_resid<T, L>), dim3(grid_for(A.n, kBlock / L)), dim3(kBlock), 0, s, A.n,
-                                         A.ptr, A.col, (const T *)A.val, rhs, z, res, done));
+    int g = sell_grid(A);
+    hipLaunchKernelGGL(k_sell_resid<T>, dim3(g), dim3(kBlock), 0, s, A, rhs, z, res, done);
+    return g;
+}
+
+int sell_spmv64(hipStream_t s, const DevSellView &A, const double *x, double *y, double *partials, const int *done)
+{
+    int g = sell_grid(A);
+    if (partials)
+        hipLaunchKernelGGL(k_sell_spmv64<true>, dim3(g), dim3(kBlock), 0, s, A, x, y, partials, done);
+    else
+        hipLaunchKernelGGL(k_sell_spmv64<false>, dim3(g), dim3(kBlock), 0, s, A, x, y, partials, done);
+    return g;
+}
+
+int sell_residual64(hipStream_t s, const DevSellView &A, const double *f, const double *u, double *r)
+{
+    int g = sell_grid(A);
+    hipLaunchKernelGGL(k_sell_residual64, dim3(g), dim3(kBlock), 0, s, A, f, u, r);
+    return g;
 }
 
 template <typename T>
-void launch_matvec(hipStream_t s, const DevCsrView &M, const T *x, T *y, const int *done)
+void csr_matvec(hipStream_t s, const DevCsrView &M, const T *x, T *y, const int *done)
 {
-    LPR_SWITCH(M.lpr, hipLaunchKernelGGL((k_matvec<T, L, false>), dim3(grid_for(M.n, kBlock / L)), dim3(kBlock), 0, s,
+    LPR_SWITCH(M.lpr, hipLaunchKernelGGL((k_csr_matvec<T, L, false>), dim3(rows_grid(M.n, L)), dim3(kBlock), 0, s,
                                          M.n, M.ptr, M.col, (const T *)M.val, x, y, done));
 }
 
 template <typename T>
-void launch_matvec_add(hipStream_t s, const DevCsrView &M, const T *e, T *x, const int *done)
+void csr_matvec_add(hipStream_t s, const DevCsrView &M, const T *e, T *x, const int *done)
 {
-    LPR_SWITCH(M.lpr, hipLaunchKernelGGL((k_matvec<T, L, true>), dim3(grid_for(M.n, kBlock / L)), dim3(kBlock), 0, s,
+    LPR_SWITCH(M.lpr, hipLaunchKernelGGL((k_csr_matvec<T, L, true>), dim3(rows_grid(M.n, L)), dim3(kBlock), 0, s,
                                          M.n, M.ptr, M.col, (const T *)M.val, e, x, done));
 }
 
 template <typename T>
-void launch_vpre(hipStream_t s, const DevCsrView &A, const T *dinv, const T *b, T *x, T *r, const int *done)
+void csr_vpre(hipStream_t s, const DevCsrView &A, const T *dinv, const T *b, T *x, T *r, const int *done)
 {
-    LPR_SWITCH(A.lpr, hipLaunchKernelGGL((k_vpre<T, L>), dim3(grid_for(A.n, kBlock / L)), dim3(kBlock), 0, s, A.n,
-                                         A.ptr, A.col, (const T *)A.val, dinv, b, x, r, done));
+    LPR_SWITCH(A.lpr, hipLaunchKernelGGL((k_csr_vpre<T, L>), dim3(rows_grid(A.n, L)), dim3(kBlock), 0, s, A.n, A.ptr,
+                                         A.col, (const T *)A.val, dinv, b, x, r, done));
 }
 
 template <typename T>
-void launch_dense_gemv(hipStream_t s, int n, const T *Ainv, const T *b, T *x, const int *done)
+void csr_sweep(hipStream_t s, const DevCsrView &A, const T *dinv, const T *b, const T *x, T *y, const int *done)
+{
+    LPR_SWITCH(A.lpr, hipLaunchKernelGGL((k_csr_sweep<T, L>), dim3(rows_grid(A.n, L)), dim3(kBlock), 0, s, A.n,
+                                         A.ptr, A.col, (const T *)A.val, dinv, b, x, y, done));
+}
+
+template <typename T>
+void dense_gemv(hipStream_t s, int n, const T *Ainv, const T *b, T *x, const int *done)
 {
     hipLaunchKernelGGL(k_dense_gemv<T>, dim3(1), dim3(kBlock), 0, s, n, Ainv, b, x, done);
 }
 
-void launch_spmv64(hipStream_t s, const DevCsrView &A, const double *x, double *y, const Reduce &red, const int *done)
+int vec_dot(hipStream_t s, int n, const double *a, const double *b, double *partials)
 {
-    if (red.out) {
-        LPR_SWITCH(A.lpr, hipLaunchKernelGGL((k_spmv64<L, true>), dim3(grid_for(A.n, kBlock / L)), dim3(kBlock), 0, s,
-                                             A.n, A.ptr, A.col, (const double *)A.val, x, y, red, done));
-    } else {
-        LPR_SWITCH(A.lpr, hipLaunchKernelGGL((k_spmv64<L, false>), dim3(grid_for(A.n, kBlock / L)), dim3(kBlock), 0,
-                                             s, A.n, A.ptr, A.col, (const double *)A.val, x, y, red, done));
-    }
+    int g = vec_grid(n);
+    hipLaunchKernelGGL(k_dot, dim3(g), dim3(kBlock), 0, s, n, a, b, partials);
+    return g;
 }
 
-void launch_residual64(hipStream_t s, const DevCsrView &A, const double *f, const double *u, double *r)
+void finish(hipStream_t s, const double *partials, int nparts, FinishMode mode, double *out, const CgState &st)
 {
-    LPR_SWITCH(A.lpr, hipLaunchKernelGGL((k_residual64<L>), dim3(grid_for(A.n, kBlock / L)), dim3(kBlock), 0, s, A.n,
-                                         A.ptr, A.col, (const double *)A.val, f, u, r));
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nparts, (int)mode, out, st);
 }
 
-void launch_dot64(hipStream_t s, int n, const double *a, const double *b, const Reduce &red)
+void cg_init(hipStream_t s, const CgState &st, double tol2)
 {
-    hipLaunchKernelGGL(k_dot64, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, a, b, red);
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(1), 0, s, st, tol2);
 }
 
-void launch_cg_init(hipStream_t s, const CgState &st, double tol2, const double *ff, const double *rr0)
+int cg_update(hipStream_t s, int n, double *x, double *r, const double *p, const double *q, const CgState &st,
+              double *partials)
 {
-    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(1), 0, s, st, tol2, ff, rr0);
+    int g = vec_grid(n);
+    hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kBlock), 0, s, n, x, r, p, q, st, partials);
+    return g;
 }
 
-void launch_cg_update(hipStream_t s, int n, double *x, double *r, const double *p, const double *q, const CgState &st,
-                      const Reduce &red)
+void cg_direction(hipStream_t s, int n, const double *z, double *p, const CgState &st)
 {
-    hipLaunchKernelGGL(k_cg_update, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, x, r, p, q, st, red);
+    hipLaunchKernelGGL(k_cg_direction, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, z, p, st);
 }
 
-void launch_cg_direction(hipStream_t s, int n, const double *z, double *p, const CgState &st)
+void vec_gather(hipStream_t s, int n, const int *idx, const double *x, double *y)
 {
-    hipLaunchKernelGGL(k_cg_direction, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, z, p, st);
+    hipLaunchKernelGGL(k_gather, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, idx, x, y);
 }
 
-void launch_cg_check_rz(hipStream_t s, const CgState &st)
+void vec_scatter(hipStream_t s, int n, const int *idx, const double *x, double *y)
 {
-    hipLaunchKernelGGL(k_cg_check_rz, dim3(1), dim3(1), 0, s, st);
+    hipLaunchKernelGGL(k_scatter, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, idx, x, y);
 }
 
-void launch_cg_check_pq(hipStream_t s, const CgState &st)
+void kappa_grad(hipStream_t s, int nt, int nloc, const int *tet_dof, const double *G, const double *kappa,
+                const double *M, const double *u, const double *lam, double *g)
 {
-    hipLaunchKernelGGL(k_cg_check_pq, dim3(1), dim3(1), 0, s, st);
-}
-
-void launch_kappa_grad(hipStream_t s, int nt, int nloc, const int *tet_dof, const double *G, const double *kappa,
-                       const double *M, const double *u, const double *lam, double *g)
-{
-    hipLaunchKernelGGL(k_kappa_grad, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, nt, nloc, tet_dof, G, kappa, M,
-                       u, lam, g);
-}
-
-void launch_cast(hipStream_t s, int64_t n, const double *x, float *y)
-{
-    int g = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, kMaxBlocks);
-    hipLaunchKernelGGL(k_cast, dim3(g < 1 ? 1 : g), dim3(kBlock), 0, s, n, x, y);
+    hipLaunchKernelGGL(k_kappa_grad, dim3(vec_grid(nt)), dim3(kBlock), 0, s, nt, nloc, tet_dof, G, kappa, M, u, lam,
+                       g);
 }
 
 #define INST(T)                                                                                              \
-    template void launch_jacobi0<T>(hipStream_t, int, const T *, const double *, T *, T *, const int *);     \
-    template void launch_first2<T>(hipStream_t, const DevCsrView &, const T *, const double *, T *, T *,     \
-                                   const int *);                                                             \
-    template void launch_resid<T>(hipStream_t, const DevCsrView &, const T *, const T *, T *, const int *);  \
-    template void launch_matvec<T>(hipStream_t, const DevCsrView &, const T *, T *, const int *);            \
-    template void launch_matvec_add<T>(hipStream_t, const DevCsrView &, const T *, T *, const int *);        \
-    template void launch_vpre<T>(hipStream_t, const DevCsrView &, const T *, const T *, T *, T *, const int *); \
-    template void launch_dense_gemv<T>(hipStream_t, int, const T *, const T *, T *, const int *);            \
-    template void launch_sweep<T, T, T>(hipStream_t, const DevCsrView &, const T *, const T *, const T *, T *, \
-                                        const double *, const Reduce &, const int *);
+    template int vec_jacobi0<T>(hipStream_t, int, const T *, const double *, T *, T *, const int *);         \
+    template int sell_resid<T>(hipStream_t, const DevSellView &, const T *, const T *, T *, const int *);    \
+    template int sell_sweep<T, T, T>(hipStream_t, const DevSellView &, const T *, const T *, const T *, T *, \
+                                     const double *, double *, const int *);                                 \
+    template void csr_matvec<T>(hipStream_t, const DevCsrView &, const T *, T *, const int *);               \
+    template void csr_matvec_add<T>(hipStream_t, const DevCsrView &, const T *, T *, const int *);           \
+    template void csr_vpre<T>(hipStream_t, const DevCsrView &, const T *, const T *, T *, T *, const int *); \
+    template void csr_sweep<T>(hipStream_t, const DevCsrView &, const T *, const T *, const T *, T *,        \
+                               const int *);                                                                 \
+    template void dense_gemv<T>(hipStream_t, int, const T *, const T *, T *, const int *);
 
 INST(double)
 INST(float)
-template void launch_sweep<float, double, double>(hipStream_t, const DevCsrView &, const float *, const double *,
-                                                  const float *, double *, const double *, const Reduce &,
-                                                  const int *);
+template int sell_sweep<float, double, double>(hipStream_t, const DevSellView &, const float *, const double *,
+                                               const float *, double *, const double *, double *, const int *);
 
 }  // namespace auxp

@@ -1,11 +1,18 @@
-// Solve-phase kernels for gfx950 (CDNA4, wave64).  All sparse operators are
-// CSR with int32 indices; each row is handled by LPR consecutive lanes of a
-// wavefront (LPR in {1,2,4,8,16,32,64}) that stride over the row and combine
-// with cross-lane shuffles.  Dot products are reduced deterministically: one
-// partial per workgroup, and the last workgroup to finish sums the partials
-// in a fixed order.  Kernels that belong to a CG iteration return at once when
-// the device "done" flag is set, so iterations can be enqueued ahead of the
-// convergence test.
+// Solve-phase kernels for gfx950 (CDNA4, wave64).
+//
+// The P^k operator A_h is stored as sliced ELLPACK with 64-row slices
+// (one wavefront per slice, one lane per row, entries of a slice stored
+// column-major so every load of a wavefront is 64 consecutive words).  Its
+// rows are numbered in an internal order: within windows of consecutive dofs
+// the rows are sorted by length, which keeps the padding of each slice small
+// while the window keeps the gathered vector entries local.  The small AMG
+// operators and the transfers are CSR with LPR lanes per row.
+//
+// Dot products are reduced deterministically without atomics: every
+// workgroup writes one partial, and a one-workgroup "finish" kernel that
+// follows in the stream sums them in a fixed order.  Kernels that belong to a
+// CG iteration return at once when the device "done" flag is set, so
+// iterations can be enqueued ahead of the convergence test.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,7 +22,8 @@
 namespace auxp {
 
 constexpr int kBlock = 256;
-constexpr int kMaxBlocks = 2048;
+constexpr int kMaxBlocks = 4096;       // partial sums per reduction at most
+constexpr int kSlice = 64;             // rows per ELL slice (one wavefront)
 
 struct DevCsrView {
     int n;
@@ -25,13 +33,12 @@ struct DevCsrView {
     int lpr;
 };
 
-// Reduction target: partials[kMaxBlocks], an arrival counter, and the
-// output slot.
-struct Reduce {
-    double *partials;
-    unsigned int *counter;
-    double *out;         // result slot base (null: no reduction)
-    const int *index;    // if set, the result goes to out[*index] (the CG iteration)
+struct DevSellView {
+    int n;               // rows
+    int nslices;
+    const int *slice_off;  // [nslices+1] first entry of each slice (multiple of 64)
+    const int *col;      // [slice_off[nslices]], padding entries point at column 0
+    const void *val;     // double or float, padding entries are 0
 };
 
 // State of a CG solve in device memory.
@@ -41,75 +48,65 @@ struct CgState {
     double *rz;          // rz[k] = r_k . z_k
     double *pq;          // pq[k] = p_k . A p_k
     double *rr;          // rr[k] = r_k . r_k
-    double *tol2bb;      // tol^2 ||f||^2
+    double *scal;        // [0] f.f, [1] r_0.r_0, [2] tol^2 f.f
     int maxit;
 };
 
-// ---- launchers (T = double or float is the preconditioner precision)
+enum FinishMode { FIN_PLAIN = 0, FIN_PQ = 1, FIN_RZ = 2, FIN_RR = 3 };
 
-// z = D^{-1} r  (one sweep from zero); optionally writes rT = (T) r
+// ---- P^k level (SELL).  Kernels that reduce write one partial per
+// workgroup to `partials` (if non-null) and return the grid size used.
+
+// z = D^{-1} r (one sweep from zero); rT = (T) r if rT
 template <typename T>
-void launch_jacobi0(hipStream_t s, int n, const T *dinv, const double *r, T *z, T *rT, const int *done);
-
-// z = D^{-1} r + D^{-1} (r - A D^{-1} r)   (two sweeps from zero); optionally rT = (T) r
-template <typename T>
-void launch_first2(hipStream_t s, const DevCsrView &A, const T *dinv, const double *r, T *z, T *rT,
-                   const int *done);
-
-// zout = zin + D^{-1} (rhs - A zin); RHS type TR, output type TZ.  With red.out,
-// also reduces dot(rdot, zout) in double (rdot: double rhs of the dot).
+int vec_jacobi0(hipStream_t s, int n, const T *dinv, const double *r, T *z, T *rT, const int *done);
+// zout = zin + D^{-1} (rhs - A zin); with partials, also sum_i rdot_i zout_i
 template <typename T, typename TR, typename TZ>
-void launch_sweep(hipStream_t s, const DevCsrView &A, const T *dinv, const TR *rhs, const T *zin, TZ *zout,
-                  const double *rdot, const Reduce &red, const int *done);
-
+int sell_sweep(hipStream_t s, const DevSellView &A, const T *dinv, const TR *rhs, const T *zin, TZ *zout,
+               const double *rdot, double *partials, const int *done);
 // res = rhs - A z
 template <typename T>
-void launch_resid(hipStream_t s, const DevCsrView &A, const T *rhs, const T *z, T *res, const int *done);
-
-// y = M x (rectangular CSR)
-template <typename T>
-void launch_matvec(hipStream_t s, const DevCsrView &M, const T *x, T *y, const int *done);
-
-// x += M e
-template <typename T>
-void launch_matvec_add(hipStream_t s, const DevCsrView &M, const T *e, T *x, const int *done);
-
-// V-cycle presmoothing from zero fused with the residual: x = D^{-1} b, r = b - A x
-template <typename T>
-void launch_vpre(hipStream_t s, const DevCsrView &A, const T *dinv, const T *b, T *x, T *r, const int *done);
-
-// x = Ainv b for a dense row-major n x n inverse (one workgroup)
-template <typename T>
-void launch_dense_gemv(hipStream_t s, int n, const T *Ainv, const T *b, T *x, const int *done);
-
-// ---- FP64 CG kernels
-
-// y = A x; with red.out also dot(x, y)
-void launch_spmv64(hipStream_t s, const DevCsrView &A, const double *x, double *y, const Reduce &red,
-                   const int *done);
-// r = f - A u, rr[0] = r.r, tol2bb = tol^2 f.f ; two reductions, host-ordered
-void launch_dot64(hipStream_t s, int n, const double *a, const double *b, const Reduce &red);
-// the CG "init" bookkeeping kernel (single thread)
-void launch_cg_init(hipStream_t s, const CgState &st, double tol2, const double *ff, const double *rr0);
-// x += alpha p ; r -= alpha q ; rr[k+1] = r.r ; convergence test ; iter++
-void launch_cg_update(hipStream_t s, int n, double *x, double *r, const double *p, const double *q,
-                      const CgState &st, const Reduce &red);
-// p = z + beta p  (beta = rz[k]/rz[k-1]); with first = true, p = z
-void launch_cg_direction(hipStream_t s, int n, const double *z, double *p, const CgState &st);
-// check r.z > 0 after the preconditioner: sets done = 3/4 (single thread)
-void launch_cg_check_rz(hipStream_t s, const CgState &st);
-// check p.Ap > 0 (single thread)
-void launch_cg_check_pq(hipStream_t s, const CgState &st);
-
+int sell_resid(hipStream_t s, const DevSellView &A, const T *rhs, const T *z, T *res, const int *done);
+// y = A x (FP64); with partials also x.y
+int sell_spmv64(hipStream_t s, const DevSellView &A, const double *x, double *y, double *partials, const int *done);
 // r = f - A u (FP64)
-void launch_residual64(hipStream_t s, const DevCsrView &A, const double *f, const double *u, double *r);
+int sell_residual64(hipStream_t s, const DevSellView &A, const double *f, const double *u, double *r);
 
-// g_t = -lam_t^T K_t u_t for every tet (FP64): K_t = kappa_t sum_pq G_pq M^pq,
-// G per tet [nt][16], M^pq tables [16][nloc][nloc], tet_dof [nt][nloc]
-void launch_kappa_grad(hipStream_t s, int nt, int nloc, const int *tet_dof, const double *G,
-                       const double *kappa, const double *M, const double *u, const double *lam, double *g);
+// ---- CSR (AMG levels, transfers)
+template <typename T>
+void csr_matvec(hipStream_t s, const DevCsrView &M, const T *x, T *y, const int *done);
+template <typename T>
+void csr_matvec_add(hipStream_t s, const DevCsrView &M, const T *e, T *x, const int *done);
+// x = D^{-1} b, r = b - A x (V-cycle presmoothing from zero fused with the residual)
+template <typename T>
+void csr_vpre(hipStream_t s, const DevCsrView &A, const T *dinv, const T *b, T *x, T *r, const int *done);
+// y = x + D^{-1} (b - A x)
+template <typename T>
+void csr_sweep(hipStream_t s, const DevCsrView &A, const T *dinv, const T *b, const T *x, T *y, const int *done);
+// x = Ainv b, dense row-major n x n (one workgroup)
+template <typename T>
+void dense_gemv(hipStream_t s, int n, const T *Ainv, const T *b, T *x, const int *done);
 
-void launch_cast(hipStream_t s, int64_t n, const double *x, float *y);
+// ---- vectors and CG bookkeeping (FP64)
+int vec_dot(hipStream_t s, int n, const double *a, const double *b, double *partials);
+// sum nparts partials; FIN_PLAIN writes out[0]; the others write the CG slot of
+// the current iteration and update the state (see kernels.hip)
+void finish(hipStream_t s, const double *partials, int nparts, FinishMode mode, double *out, const CgState &st);
+void cg_init(hipStream_t s, const CgState &st, double tol2);
+// x += alpha p ; r -= alpha q ; partial r.r
+int cg_update(hipStream_t s, int n, double *x, double *r, const double *p, const double *q, const CgState &st,
+              double *partials);
+// p = z + beta p, beta = rz[k]/rz[k-1] (p = z at k = 0)
+void cg_direction(hipStream_t s, int n, const double *z, double *p, const CgState &st);
+// y[i] = x[idx[i]]
+void vec_gather(hipStream_t s, int n, const int *idx, const double *x, double *y);
+// y[idx[i]] = x[i]
+void vec_scatter(hipStream_t s, int n, const int *idx, const double *x, double *y);
+
+// g_t = -kappa_t sum_pq G_pq lam_t^T M^pq u_t per tet (FP64); tet_dof holds
+// internal dof numbers (-1 on the boundary)
+void kappa_grad(hipStream_t s, int nt, int nloc, const int *tet_dof, const double *G, const double *kappa,
+                const double *M, const double *u, const double *lam, double *g);
 
 int pick_lpr(double avg_row_nnz);
 

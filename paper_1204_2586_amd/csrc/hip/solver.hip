@@ -1,6 +1,10 @@
 // Device side of the solver: upload of the setup data, the preconditioner
 // B (Algorithm 2.1 with presmoothing, Remark 2.1) and preconditioned CG,
 // behind the C ABI declared in include/aux.h.
+//
+// The P^k level runs in an internal dof order (rows sorted by length within
+// windows, see formats.cpp); vectors are permuted once on entry to and exit
+// from aux_apply / pcg_solve / aux_matvec.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,7 +18,9 @@
 
 #include "../host/setup.hpp"
 #include "aux.h"
+#include "batched.hpp"
 #include "kernels.hpp"
+#include "mfree.hpp"
 
 using namespace auxp;
 
@@ -34,7 +40,7 @@ struct AuxError : std::runtime_error {
             throw AuxError(AUX_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));                \
     } while (0)
 
-struct DevOp {
+struct DevOp {   // CSR with values in both precisions
     int n = 0, m = 0;
     int64_t nnz = 0;
     int *ptr = nullptr, *col = nullptr;
@@ -45,6 +51,19 @@ struct DevOp {
     DevCsrView view() const
     {
         return {n, ptr, col, std::is_same<T, float>::value ? (const void *)v32 : (const void *)v64, lpr};
+    }
+};
+
+struct DevSell {
+    int n = 0, nslices = 0;
+    int64_t stored = 0;
+    int *slice_off = nullptr, *col = nullptr;
+    double *v64 = nullptr;
+    float *v32 = nullptr;
+    template <typename T>
+    DevSellView view() const
+    {
+        return {n, nslices, slice_off, col, std::is_same<T, float>::value ? (const void *)v32 : (const void *)v64};
     }
 };
 
@@ -60,11 +79,14 @@ double seconds_since(std::chrono::steady_clock::time_point t0)
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+constexpr int kSellWindow = 4096;
+
 }  // namespace
 
 struct aux_handle {
     Discretization disc;
     Hierarchy hier;
+    Sell sell;                       // host copy of the P^k operator format (internal order)
     aux_options opt{};
     aux_device dev{};
     bool host_only = false;
@@ -74,7 +96,9 @@ struct aux_handle {
     int64_t device_bytes = 0;
     std::vector<void *> allocs;
 
-    DevOp A, IP, IR;
+    DevSell A;                       // A_h, internal order
+    int *perm = nullptr;             // internal -> external dof
+    DevOp IP, IR;                    // I_P rows and I_R columns in internal order
     double *dinv64 = nullptr;
     float *dinv32 = nullptr;
     struct Lev {
@@ -90,20 +114,113 @@ struct aux_handle {
     Work<double> w64;
     Work<float> w32;
 
-    // CG buffers
-    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    // CG buffers (internal order)
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *xi = nullptr, *fi = nullptr;
     double *partials = nullptr;
-    unsigned int *counter = nullptr;
-    double *scal = nullptr;      // [0] f.f, [1] r0.r0, [2] tol2bb
-    int *istate = nullptr;       // [0] iter, [1] done
-    double *hist = nullptr;      // rz, pq, rr each [hist_cap]
+    double *scal = nullptr;          // [0] f.f, [1] r0.r0, [2] tol^2 f.f
+    int *istate = nullptr;           // [0] iter, [1] done
+    double *hist = nullptr;          // rz, pq, rr each [hist_cap]
     int hist_cap = 0;
-    int *host_state = nullptr;   // pinned: iter, done
-    double *host_scal = nullptr; // pinned
+    int *host_state = nullptr;       // pinned: iter, done
+    std::vector<void *> host_bufs;   // other pinned buffers
 
-    // adjoint data
+    // adjoint data (external dof numbering)
     double *G = nullptr, *kappa_d = nullptr, *Mtab = nullptr;
     int *tet_dof_d = nullptr;
+
+    // matrix-free element operator (internal dof numbering)
+    bool mf_ready = false;
+    int *mf_emap = nullptr, *mf_inc_ptr = nullptr, *mf_inc = nullptr;
+    double *mf_w64 = nullptr, *mf_S64 = nullptr, *mf_Y64 = nullptr;
+    float *mf_w32 = nullptr, *mf_S32 = nullptr, *mf_Y32 = nullptr;
+
+    void ensure_mf()
+    {
+        if (mf_ready) return;
+        const int nt = disc.nt, nl = disc.nloc, n = disc.ndof;
+        static const int pairs[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+        const std::vector<double> &M = stiffness_tables(disc.k);
+        auto Mat = [&](int p, int q, int a, int b) { return M[(((size_t)p * 4 + q) * nl + a) * nl + b]; };
+        std::vector<double> S((size_t)nl * 6 * nl);
+        for (int k = 0; k < 6; k++) {
+            int p = pairs[k][0], q = pairs[k][1];
+            for (int a = 0; a < nl; a++)
+                for (int b = 0; b < nl; b++)
+                    S[(size_t)a * 6 * nl + k * nl + b] = Mat(p, p, a, b) + Mat(q, q, a, b) - Mat(p, q, a, b) - Mat(q, p, a, b);
+        }
+        std::vector<double> w((size_t)nt * 6);
+        std::vector<int> emap((size_t)nt * nl), cnt((size_t)n + 1, 0);
+        for (int t = 0; t < nt; t++) {
+            const int *v = &disc.tets[4 * (size_t)t];
+            double Gt[4][4];
+            tet_metric(&disc.xyz[3 * (size_t)v[0]], &disc.xyz[3 * (size_t)v[1]], &disc.xyz[3 * (size_t)v[2]],
+                       &disc.xyz[3 * (size_t)v[3]], Gt);
+            for (int k = 0; k < 6; k++) w[(size_t)t * 6 + k] = -disc.kappa[t] * Gt[pairs[k][0]][pairs[k][1]];
+            for (int a = 0; a < nl; a++) {
+                int d = disc.tet_dof[(size_t)t * nl + a];
+                emap[(size_t)t * nl + a] = d >= 0 ? sell.iperm[d] : -1;
+                if (d >= 0) cnt[sell.iperm[d] + 1]++;
+            }
+        }
+        for (int i = 0; i < n; i++) cnt[i + 1] += cnt[i];
+        std::vector<int> inc(cnt.back()), fill(cnt.begin(), cnt.end() - 1);
+        for (size_t s = 0; s < emap.size(); s++)
+            if (emap[s] >= 0) inc[fill[emap[s]]++] = (int)s;
+        mf_emap = upload(emap);
+        mf_inc_ptr = upload(cnt);
+        mf_inc = upload(inc);
+        mf_w64 = upload(w);
+        mf_S64 = upload(S);
+        mf_w32 = upload(to_f32(w));
+        mf_S32 = upload(to_f32(S));
+        mf_Y64 = dnew<double>((size_t)nt * nl);
+        mf_Y32 = dnew<float>((size_t)nt * nl);
+        mf_ready = true;
+    }
+    template <typename T>
+    MfView<T> mf_view() const
+    {
+        MfView<T> v{disc.ndof, disc.nt, disc.nloc, mf_emap, nullptr, nullptr, mf_inc_ptr, mf_inc};
+        if constexpr (std::is_same<T, float>::value) {
+            v.w = mf_w32;
+            v.S = mf_S32;
+        } else {
+            v.w = mf_w64;
+            v.S = mf_S64;
+        }
+        return v;
+    }
+    template <typename T>
+    T *mf_Y() const
+    {
+        if constexpr (std::is_same<T, float>::value) return mf_Y32;
+        else return mf_Y64;
+    }
+    bool use_mf() const { return opt.op == AUX_OP_MATFREE; }
+
+    // P^k smoothing sweep zout = zin + D^{-1}(rhs - A zin) with the configured operator
+    template <typename T, typename TR, typename TZ>
+    int pk_sweep(const T *d, const TR *rhs, const T *zin, TZ *zout, const double *rdot, double *partials,
+                 const int *done)
+    {
+        if (use_mf()) {
+            MfView<T> v = mf_view<T>();
+            mf_apply<T>(stream, v, zin, mf_Y<T>(), done);
+            return mf_sweep<T, TR, TZ>(stream, v, mf_Y<T>(), zin, d, rhs, zout, rdot, partials, done);
+        }
+        return sell_sweep<T, TR, TZ>(stream, A.view<T>(), d, rhs, zin, zout, rdot, partials, done);
+    }
+    template <typename T>
+    void pk_resid(const T *rhs, const T *z, T *res, const int *done)
+    {
+        if (use_mf()) {
+            MfView<T> v = mf_view<T>();
+            mf_apply<T>(stream, v, z, mf_Y<T>(), done);
+            mf_resid<T>(stream, v, mf_Y<T>(), rhs, res, done);
+            return;
+        }
+        sell_resid<T>(stream, A.view<T>(), rhs, z, res, done);
+    }
 
     // kernel timing with HIP events on the handle's stream
     struct ProfRec {
@@ -118,46 +235,7 @@ struct aux_handle {
     double prof_ms[AUX_PROF_NCAT] = {};
     int64_t prof_n[AUX_PROF_NCAT] = {};
 
-    hipEvent_t take_event()
-    {
-        if (ev_used == ev_pool.size()) {
-            hipEvent_t e;
-            HIPCHECK(hipEventCreate(&e));
-            ev_pool.push_back(e);
-        }
-        return ev_pool[ev_used++];
-    }
-    int pbeg(int cat)
-    {
-        if (!prof_on) return -1;
-        ProfRec r{take_event(), take_event(), cat, prof_tag};
-        HIPCHECK(hipEventRecord(r.a, stream));
-        prof.push_back(r);
-        return (int)prof.size() - 1;
-    }
-    void pend(int idx)
-    {
-        if (idx >= 0) HIPCHECK(hipEventRecord(prof[idx].b, stream));
-    }
-    // fold the recorded events into the per-category sums; launches of CG
-    // iteration tags that never ran (enqueued after convergence) are dropped
-    void prof_collect(int final_iter)
-    {
-        if (prof.empty()) return;
-        HIPCHECK(hipStreamSynchronize(stream));
-        for (const ProfRec &r : prof) {
-            bool ran = r.tag < 0 || r.tag == 0 ||
-                       (r.cat == AUX_PROF_CG_SPMV ? r.tag <= final_iter : r.tag < final_iter);
-            if (!ran) continue;
-            float ms = 0.f;
-            HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
-            prof_ms[r.cat] += ms;
-            prof_n[r.cat] += 1;
-        }
-        prof.clear();
-        ev_used = 0;
-    }
-
+    // ------------------------------------------------------------ memory
     void *dalloc(size_t bytes)
     {
         if (bytes == 0) bytes = 16;
@@ -190,17 +268,13 @@ struct aux_handle {
     {
         return upload(v.data(), v.size());
     }
-    static std::vector<float> to_f32(const std::vector<double> &v)
-    {
-        return std::vector<float>(v.begin(), v.end());
-    }
+    static std::vector<float> to_f32(const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); }
     static std::vector<double> inverse(const std::vector<double> &v)
     {
         std::vector<double> o(v.size());
         for (size_t i = 0; i < v.size(); i++) o[i] = 1.0 / v[i];
         return o;
     }
-
     DevOp upload_op(const Csr &c)
     {
         DevOp d;
@@ -213,14 +287,44 @@ struct aux_handle {
         d.lpr = pick_lpr(c.n ? (double)c.nnz() / c.n : 1.0);
         return d;
     }
-    void op_fp32(DevOp &d, const Csr &c) { d.v32 = upload(to_f32(c.val)); }
+
+    Csr IPi, IRi;                    // internal-order transfers (host, for the FP32 copies)
+    std::vector<double> l1i;         // l1 norms in internal order
 
     void upload_all()
     {
-        A = upload_op(disc.A);
-        dinv64 = upload(inverse(disc.l1));
-        IP = upload_op(disc.IP);
-        IR = upload_op(disc.IR);
+        if (opt.sell_window > 0) {
+            build_sell(disc.A, kSlice, opt.sell_window, nullptr, sell);
+        } else {
+            // group rows by node class: row length, then the gaps between the
+            // vertex ids of the node's multiset (on a structured mesh these
+            // identify the node's type and direction); the dof order within a
+            // class keeps neighbouring rows' j-th columns close in memory
+            std::vector<uint64_t> cls(disc.ndof);
+            const int k = disc.k;
+            for (int i = 0; i < disc.ndof; i++) {
+                const int32_t *key = &disc.keys[(size_t)i * k];
+                uint64_t len = (uint64_t)(disc.A.ptr[i + 1] - disc.A.ptr[i]);
+                uint64_t d1 = k > 1 ? (uint64_t)std::min(key[1] - key[0], (1 << 21) - 1) : 0;
+                uint64_t d2 = k > 2 ? (uint64_t)std::min(key[2] - key[1], (1 << 21) - 1) : 0;
+                cls[i] = ((uint64_t)(0xfffff - std::min<uint64_t>(len, 0xfffff)) << 42) | (d1 << 21) | d2;
+            }
+            build_sell(disc.A, kSlice, disc.ndof > 0 ? disc.ndof : 1, &cls, sell);
+        }
+        A.n = sell.n;
+        A.nslices = sell.nslices;
+        A.stored = (int64_t)sell.val.size();
+        A.slice_off = upload(sell.slice_off);
+        A.col = upload(sell.col);
+        A.v64 = upload(sell.val);
+        perm = upload(sell.perm);
+        l1i.resize(disc.ndof);
+        for (int i = 0; i < disc.ndof; i++) l1i[i] = disc.l1[sell.perm[i]];
+        dinv64 = upload(inverse(l1i));
+        IPi = permute_rows(disc.IP, sell.perm);
+        IRi = transpose(IPi);
+        IP = upload_op(IPi);
+        IR = upload_op(IRi);
         lev.resize(hier.levels.size());
         for (size_t l = 0; l < hier.levels.size(); l++) {
             const AmgLevel &hl = hier.levels[l];
@@ -237,13 +341,12 @@ struct aux_handle {
         z = dnew<double>(n);
         p = dnew<double>(n);
         q = dnew<double>(n);
+        xi = dnew<double>(n);
+        fi = dnew<double>(n);
         partials = dnew<double>(kMaxBlocks);
-        counter = dnew<unsigned int>(4);
-        HIPCHECK(hipMemset(counter, 0, 4 * sizeof(unsigned int)));
         scal = dnew<double>(8);
         istate = dnew<int>(4);
         HIPCHECK(hipHostMalloc((void **)&host_state, 4 * sizeof(int), hipHostMallocDefault));
-        HIPCHECK(hipHostMalloc((void **)&host_scal, 8 * sizeof(double), hipHostMallocDefault));
         ensure_hist(std::max(opt.maxit, 16));
     }
 
@@ -257,17 +360,17 @@ struct aux_handle {
     void ensure_fp32()
     {
         if (fp32_ready) return;
-        op_fp32(A, disc.A);
-        dinv32 = upload(to_f32(inverse(disc.l1)));
-        op_fp32(IP, disc.IP);
-        op_fp32(IR, disc.IR);
+        A.v32 = upload(to_f32(sell.val));
+        dinv32 = upload(to_f32(inverse(l1i)));
+        IP.v32 = upload(to_f32(IPi.val));
+        IR.v32 = upload(to_f32(IRi.val));
         for (size_t l = 0; l < hier.levels.size(); l++) {
             const AmgLevel &hl = hier.levels[l];
-            op_fp32(lev[l].A, hl.A);
+            lev[l].A.v32 = upload(to_f32(hl.A.val));
             lev[l].dinv32 = upload(to_f32(inverse(hl.l1)));
             if (l + 1 < hier.levels.size()) {
-                op_fp32(lev[l].P, hl.P);
-                op_fp32(lev[l].R, hl.R);
+                lev[l].P.v32 = upload(to_f32(hl.P.val));
+                lev[l].R.v32 = upload(to_f32(hl.R.val));
             }
         }
         cinv32 = upload(to_f32(hier.coarse_inv));
@@ -316,6 +419,48 @@ struct aux_handle {
         else return cinv64;
     }
 
+    // ------------------------------------------------------------ timing
+    hipEvent_t take_event()
+    {
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t e;
+            HIPCHECK(hipEventCreate(&e));
+            ev_pool.push_back(e);
+        }
+        return ev_pool[ev_used++];
+    }
+    int pbeg(int cat)
+    {
+        if (!prof_on) return -1;
+        ProfRec rec{take_event(), take_event(), cat, prof_tag};
+        HIPCHECK(hipEventRecord(rec.a, stream));
+        prof.push_back(rec);
+        return (int)prof.size() - 1;
+    }
+    void pend(int idx)
+    {
+        if (idx >= 0) HIPCHECK(hipEventRecord(prof[idx].b, stream));
+    }
+    // Fold recorded events into per-category sums.  In a CG solve, launch tag
+    // j belongs to iteration j; launches of iterations enqueued after the
+    // solve finished returned at once and are dropped.
+    void prof_collect(int final_iter)
+    {
+        if (prof.empty()) return;
+        HIPCHECK(hipStreamSynchronize(stream));
+        for (const ProfRec &rec : prof) {
+            bool ran = rec.tag <= 0 || (rec.cat == AUX_PROF_CG_SPMV ? rec.tag <= final_iter : rec.tag < final_iter);
+            if (!ran) continue;
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, rec.a, rec.b));
+            prof_ms[rec.cat] += ms;
+            prof_n[rec.cat] += 1;
+        }
+        prof.clear();
+        ev_used = 0;
+    }
+
+    // ------------------------------------------------------------ preconditioner
     // one V(1,1) cycle from zero on level l; returns the device vector holding the result
     template <typename T>
     const T *vcycle(size_t l, const int *done)
@@ -324,81 +469,98 @@ struct aux_handle {
         hipStream_t s = stream;
         const Lev &L = lev[l];
         if (l + 1 == lev.size()) {
-            launch_dense_gemv<T>(s, L.A.n, cinv<T>(), w.b[l], w.x[l], done);
+            dense_gemv<T>(s, L.A.n, cinv<T>(), w.b[l], w.x[l], done);
             return w.x[l];
         }
         DevCsrView Av = L.A.view<T>();
-        launch_vpre<T>(s, Av, ldinv<T>(l), w.b[l], w.x[l], w.r[l], done);
-        launch_matvec<T>(s, L.R.view<T>(), w.r[l], w.b[l + 1], done);
+        csr_vpre<T>(s, Av, ldinv<T>(l), w.b[l], w.x[l], w.r[l], done);
+        csr_matvec<T>(s, L.R.view<T>(), w.r[l], w.b[l + 1], done);
         const T *e = vcycle<T>(l + 1, done);
-        launch_matvec_add<T>(s, L.P.view<T>(), e, w.x[l], done);
-        Reduce none{nullptr, nullptr, nullptr, nullptr};
-        launch_sweep<T, T, T>(s, Av, ldinv<T>(l), w.b[l], w.x[l], w.y[l], nullptr, none, done);
+        csr_matvec_add<T>(s, L.P.view<T>(), e, w.x[l], done);
+        csr_sweep<T>(s, Av, ldinv<T>(l), w.b[l], w.x[l], w.y[l], done);
         return w.y[l];
     }
 
-    // zout = B r; with red.out, also r.zout into red.out[*red.index]
+    // zout = B rin (internal order).  With rz_partials, the last sweep also
+    // writes the partial sums of rin . zout and the number of partials is
+    // returned.
     template <typename T>
-    void apply_B(const double *rin, double *zout, const Reduce &red, const int *done)
+    int apply_B(const double *rin, double *zout, double *rz_partials, const int *done)
     {
         Work<T> &w = work<T>();
         hipStream_t s = stream;
-        DevCsrView Av = A.view<T>();
         const T *d = dinv<T>();
         const int nu = opt.nu;
         T *rTbuf = std::is_same<T, float>::value ? w.rT : nullptr;
         T *zc = w.za, *zn = w.zb;
-        Reduce none{nullptr, nullptr, nullptr, nullptr};
-        // presmoothing: nu l1-Jacobi sweeps from z = 0 (the first two fused)
         int pb = pbeg(AUX_PROF_APPLY);
+        // presmoothing: nu l1-Jacobi sweeps from z = 0 (the first is z = D^{-1} r)
         int pk = pbeg(AUX_PROF_PK_FIRST);
-        if (nu >= 2) launch_first2<T>(s, Av, d, rin, zc, rTbuf, done);
-        else launch_jacobi0<T>(s, disc.ndof, d, rin, zc, rTbuf, done);
+        vec_jacobi0<T>(s, disc.ndof, d, rin, zc, rTbuf, done);
         pend(pk);
         const T *rT = rTbuf ? (const T *)rTbuf : (const T *)(const void *)rin;
-        for (int k = 2; k < nu; k++) {
+        for (int k = 1; k < nu; k++) {
             pk = pbeg(AUX_PROF_PK_SWEEP);
-            launch_sweep<T, T, T>(s, Av, d, rT, zc, zn, nullptr, none, done);
+            pk_sweep<T, T, T>(d, rT, zc, zn, nullptr, nullptr, done);
             pend(pk);
             std::swap(zc, zn);
         }
         // Step 1: r_H = I_R (r - A z), one AMG V-cycle; Step 2: z += I_P e_H
         if (!lev.empty()) {
             pk = pbeg(AUX_PROF_PK_RESID);
-            launch_resid<T>(s, Av, rT, zc, w.res, done);
+            pk_resid<T>(rT, zc, w.res, done);
             pend(pk);
             pk = pbeg(AUX_PROF_COARSE);
-            launch_matvec<T>(s, IR.view<T>(), w.res, w.b[0], done);
+            csr_matvec<T>(s, IR.view<T>(), w.res, w.b[0], done);
             const T *e0 = vcycle<T>(0, done);
-            launch_matvec_add<T>(s, IP.view<T>(), e0, zc, done);
+            csr_matvec_add<T>(s, IP.view<T>(), e0, zc, done);
             pend(pk);
         }
         // Step 3: nu postsmoothing sweeps; the last one writes the FP64 result
         for (int k = 1; k < nu; k++) {
             pk = pbeg(AUX_PROF_PK_SWEEP);
-            launch_sweep<T, T, T>(s, Av, d, rT, zc, zn, nullptr, none, done);
+            pk_sweep<T, T, T>(d, rT, zc, zn, nullptr, nullptr, done);
             pend(pk);
             std::swap(zc, zn);
         }
         pk = pbeg(AUX_PROF_PK_LAST);
-        launch_sweep<T, double, double>(s, Av, d, rin, zc, zout, rin, red, done);
+        int g = pk_sweep<T, double, double>(d, rin, zc, zout, rin, rz_partials, done);
         pend(pk);
         pend(pb);
+        return g;
     }
 
-    void apply(const double *rin, double *zout, const Reduce &red, const int *done)
+    int apply(const double *rin, double *zout, double *rz_partials, const int *done)
     {
+        if (use_mf()) ensure_mf();
         if (opt.precision == AUX_MIXED) {
             ensure_fp32();
-            apply_B<float>(rin, zout, red, done);
-        } else {
-            apply_B<double>(rin, zout, red, done);
+            return apply_B<float>(rin, zout, rz_partials, done);
         }
+        return apply_B<double>(rin, zout, rz_partials, done);
     }
 
-    CgState cg_state()
+    // ------------------------------------------------------------ CG
+    CgState cg_state(int maxit)
     {
-        return {istate, istate + 1, hist, hist + hist_cap, hist + 2 * hist_cap, scal + 2, 0};
+        return {istate, istate + 1, hist, hist + hist_cap, hist + 2 * hist_cap, scal, maxit};
+    }
+
+    // one CG iteration: q = A p, alpha, x/r update, z = B r, beta, p update
+    void cg_iteration(const CgState &st)
+    {
+        hipStream_t s = stream;
+        int n = disc.ndof;
+        DevSellView A64 = A.view<double>();
+        int pk = pbeg(AUX_PROF_CG_SPMV);
+        int g = sell_spmv64(s, A64, p, q, partials, st.done);
+        pend(pk);
+        finish(s, partials, g, FIN_PQ, nullptr, st);
+        g = cg_update(s, n, xi, r, p, q, st, partials);
+        finish(s, partials, g, FIN_RR, nullptr, st);
+        g = apply(r, z, partials, st.done);
+        finish(s, partials, g, FIN_RZ, nullptr, st);
+        cg_direction(s, n, z, p, st);
     }
 
     int pcg(const double *f, double *u, double tol, int maxit, aux_solve_info *info)
@@ -408,36 +570,25 @@ struct aux_handle {
         ensure_hist(maxit);
         hipStream_t s = stream;
         int n = disc.ndof;
-        CgState st = cg_state();
-        st.maxit = maxit;
-        Reduce rf{partials, counter, scal, nullptr};
-        DevCsrView A64 = A.view<double>();
-        launch_residual64(s, A64, f, u, r);
-        launch_dot64(s, n, f, f, Reduce{partials, counter, scal + 0, nullptr});
-        launch_dot64(s, n, r, r, Reduce{partials, counter, scal + 1, nullptr});
-        launch_cg_init(s, st, tol * tol, scal + 0, scal + 1);
-        Reduce rz{partials, counter, st.rz, st.iter};
-        Reduce pq{partials, counter, st.pq, st.iter};
+        CgState st = cg_state(maxit);
+        vec_gather(s, n, perm, f, fi);
+        vec_gather(s, n, perm, u, xi);
+        sell_residual64(s, A.view<double>(), fi, xi, r);
+        int g = vec_dot(s, n, fi, fi, partials);
+        finish(s, partials, g, FIN_PLAIN, scal + 0, st);
+        g = vec_dot(s, n, r, r, partials);
+        finish(s, partials, g, FIN_PLAIN, scal + 1, st);
+        cg_init(s, st, tol * tol);
         prof_tag = 0;
-        apply(r, z, rz, st.done);
-        launch_cg_check_rz(s, st);
-        launch_cg_direction(s, n, z, p, st);
-        (void)rf;
+        g = apply(r, z, partials, st.done);
+        finish(s, partials, g, FIN_RZ, nullptr, st);
+        cg_direction(s, n, z, p, st);
 
-        int issued = 0, iter = 0, done = 0;
-        int chunk = 2;
-        std::vector<double> rr_host;
+        int issued = 0, iter = 0, done = 0, chunk = 2;
         while (true) {
             for (int c = 0; c < chunk && issued < maxit; c++, issued++) {
                 prof_tag = issued + 1;
-                int pk = pbeg(AUX_PROF_CG_SPMV);
-                launch_spmv64(s, A64, p, q, pq, st.done);
-                pend(pk);
-                launch_cg_check_pq(s, st);
-                launch_cg_update(s, n, u, r, p, q, st, Reduce{partials, counter, nullptr, nullptr});
-                apply(r, z, rz, st.done);
-                launch_cg_check_rz(s, st);
-                launch_cg_direction(s, n, z, p, st);
+                cg_iteration(st);
             }
             HIPCHECK(hipMemcpyAsync(host_state, istate, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
@@ -445,17 +596,19 @@ struct aux_handle {
             done = host_state[1];
             if (done || issued >= maxit) break;
             // predict the remaining iterations from the observed contraction
-            std::vector<double> rr(iter + 1);
-            HIPCHECK(hipMemcpy(rr.data(), st.rr, (iter + 1) * sizeof(double), hipMemcpyDeviceToHost));
-            double target = 0.0;
-            HIPCHECK(hipMemcpy(&target, st.tol2bb, sizeof(double), hipMemcpyDeviceToHost));
             chunk = 2;
-            if (iter >= 2 && rr[iter] > 0 && rr[iter - 2] > rr[iter] && target > 0) {
-                double rate = std::sqrt(rr[iter] / rr[iter - 2]);          // per iteration, squared norm
-                double need = std::log(target / rr[iter]) / std::log(rate);
-                chunk = (int)std::ceil(std::max(1.0, std::min(need, 16.0)));
+            if (iter >= 2) {
+                double rr[3], target = 0.0;
+                HIPCHECK(hipMemcpy(rr, st.rr + iter - 2, 3 * sizeof(double), hipMemcpyDeviceToHost));
+                HIPCHECK(hipMemcpy(&target, st.scal + 2, sizeof(double), hipMemcpyDeviceToHost));
+                if (rr[2] > 0 && rr[0] > rr[2] && target > 0) {
+                    double rate = std::sqrt(rr[2] / rr[0]);
+                    double need = std::log(target / rr[2]) / std::log(rate);
+                    chunk = (int)std::ceil(std::max(1.0, std::min(need, 16.0)));
+                }
             }
         }
+        vec_scatter(s, n, perm, xi, u);
         prof_tag = -1;
         prof_collect(iter);
         double rrv = 0.0, ffv = 0.0;
@@ -472,6 +625,221 @@ struct aux_handle {
             info->seconds = seconds_since(t0);
         }
         return status;
+    }
+
+    // ------------------------------------------------------------ batched CG
+    struct Batch {
+        int nr = 0, hist_cap = 0;
+        double *X = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr, *F = nullptr;
+        double *partials = nullptr, *ff = nullptr, *rr0 = nullptr, *tol2ff = nullptr, *hist = nullptr;
+        int *ist = nullptr;            // k, all_done, iter[nr], done[nr]
+        int *host = nullptr;           // pinned copy of ist
+        Work<double> w64;
+        Work<float> w32;
+    } bt;
+
+    void ensure_batch(int nr, int maxit)
+    {
+        int n = disc.ndof;
+        if (bt.nr != nr) {
+            bt = Batch();
+            bt.nr = nr;
+            size_t blk = (size_t)n * nr;
+            bt.X = dnew<double>(blk);
+            bt.R = dnew<double>(blk);
+            bt.Z = dnew<double>(blk);
+            bt.P = dnew<double>(blk);
+            bt.Q = dnew<double>(blk);
+            bt.F = dnew<double>(blk);
+            bt.partials = dnew<double>((size_t)kMaxBlocks * nr);
+            bt.ff = dnew<double>(nr);
+            bt.rr0 = dnew<double>(nr);
+            bt.tol2ff = dnew<double>(nr);
+            bt.ist = dnew<int>(2 + 2 * (size_t)nr);
+            HIPCHECK(hipHostMalloc((void **)&bt.host, (2 + 2 * (size_t)nr) * sizeof(int), hipHostMallocDefault));
+            host_bufs.push_back(bt.host);
+        }
+        if (maxit + 2 > bt.hist_cap) {
+            bt.hist_cap = maxit + 2;
+            bt.hist = dnew<double>((size_t)3 * bt.hist_cap * nr);
+        }
+    }
+
+    template <typename T>
+    Work<T> &bwork()
+    {
+        Work<T> *w;
+        if constexpr (std::is_same<T, float>::value) w = &bt.w32;
+        else w = &bt.w64;
+        if (!w->ready) {
+            size_t n = (size_t)disc.ndof * bt.nr;
+            w->za = dnew<T>(n);
+            w->zb = dnew<T>(n);
+            w->res = dnew<T>(n);
+            if (std::is_same<T, float>::value) w->rT = dnew<T>(n);
+            for (auto &L : lev) {
+                size_t m = (size_t)L.A.n * bt.nr;
+                w->b.push_back(dnew<T>(m));
+                w->x.push_back(dnew<T>(m));
+                w->r.push_back(dnew<T>(m));
+                w->y.push_back(dnew<T>(m));
+            }
+            w->ready = true;
+        }
+        return *w;
+    }
+
+    BCgState bstate(int maxit)
+    {
+        int nr = bt.nr;
+        return {bt.ist, bt.ist + 2, bt.ist + 2 + nr, bt.ist + 1, bt.hist, bt.hist + (size_t)bt.hist_cap * nr,
+                bt.hist + (size_t)2 * bt.hist_cap * nr, bt.tol2ff, maxit};
+    }
+
+    template <typename T>
+    const T *bvcycle(size_t l, const int *all_done)
+    {
+        Work<T> &w = bwork<T>();
+        hipStream_t s = stream;
+        const int nr = bt.nr;
+        const Lev &L = lev[l];
+        if (l + 1 == lev.size()) {
+            bdense<T>(s, nr, L.A.n, cinv<T>(), w.b[l], w.x[l], all_done);
+            return w.x[l];
+        }
+        DevCsrView Av = L.A.view<T>();
+        bcsr_vpre<T>(s, nr, Av, ldinv<T>(l), w.b[l], w.x[l], w.r[l], all_done);
+        bcsr_matvec<T>(s, nr, L.R.view<T>(), w.r[l], w.b[l + 1], false, all_done);
+        const T *e = bvcycle<T>(l + 1, all_done);
+        bcsr_matvec<T>(s, nr, L.P.view<T>(), e, w.x[l], true, all_done);
+        bcsr_sweep<T>(s, nr, Av, ldinv<T>(l), w.b[l], w.x[l], w.y[l], all_done);
+        return w.y[l];
+    }
+
+    // Zout = B Rin for the nr columns of a block (internal order)
+    template <typename T>
+    int bapply_B(const double *Rin, double *Zout, double *rz_partials, const int *all_done)
+    {
+        Work<T> &w = bwork<T>();
+        hipStream_t s = stream;
+        const int nr = bt.nr;
+        DevSellView Av = A.view<T>();
+        const T *d = dinv<T>();
+        const int nu = opt.nu;
+        T *rTbuf = std::is_same<T, float>::value ? w.rT : nullptr;
+        T *zc = w.za, *zn = w.zb;
+        int pb = pbeg(AUX_PROF_APPLY);
+        bjacobi0<T>(s, nr, disc.ndof, d, Rin, zc, rTbuf, all_done);
+        const T *rT = rTbuf ? (const T *)rTbuf : (const T *)(const void *)Rin;
+        for (int k = 1; k < nu; k++) {
+            bsell_sweep<T, T, T>(s, nr, Av, d, rT, zc, zn, nullptr, nullptr, all_done);
+            std::swap(zc, zn);
+        }
+        if (!lev.empty()) {
+            bsell_resid<T>(s, nr, Av, rT, zc, w.res, all_done);
+            bcsr_matvec<T>(s, nr, IR.view<T>(), w.res, w.b[0], false, all_done);
+            const T *e0 = bvcycle<T>(0, all_done);
+            bcsr_matvec<T>(s, nr, IP.view<T>(), e0, zc, true, all_done);
+        }
+        for (int k = 1; k < nu; k++) {
+            bsell_sweep<T, T, T>(s, nr, Av, d, rT, zc, zn, nullptr, nullptr, all_done);
+            std::swap(zc, zn);
+        }
+        int g = bsell_sweep<T, double, double>(s, nr, Av, d, Rin, zc, Zout, Rin, rz_partials, all_done);
+        pend(pb);
+        return g;
+    }
+
+    int bapply(const double *Rin, double *Zout, double *rz_partials, const int *all_done)
+    {
+        if (opt.precision == AUX_MIXED) {
+            ensure_fp32();
+            return bapply_B<float>(Rin, Zout, rz_partials, all_done);
+        }
+        return bapply_B<double>(Rin, Zout, rz_partials, all_done);
+    }
+
+    int pcg_batched(const double *Fext, double *Uext, int nrhs, double tol, int maxit, aux_solve_info *infos)
+    {
+        auto t0 = std::chrono::steady_clock::now();
+        if (maxit <= 0) maxit = opt.maxit;
+        int nr = 8;
+        while (nr < nrhs) nr *= 2;
+        ensure_batch(nr, maxit);
+        hipStream_t s = stream;
+        const int n = disc.ndof;
+        BCgState st = bstate(maxit);
+        const int *all_done = st.all_done;
+        DevSellView A64 = A.view<double>();
+        bgather(s, nr, n, nrhs, perm, Fext, bt.F);
+        bgather(s, nr, n, nrhs, perm, Uext, bt.X);
+        bsell_residual64(s, nr, A64, bt.F, bt.X, bt.R);
+        int g = bvec_dot(s, nr, n, bt.F, bt.F, bt.partials);
+        bfinish(s, nr, bt.partials, g, FIN_PLAIN, bt.ff, st);
+        g = bvec_dot(s, nr, n, bt.R, bt.R, bt.partials);
+        bfinish(s, nr, bt.partials, g, FIN_PLAIN, bt.rr0, st);
+        bcg_init(s, nr, st, tol * tol, bt.ff, bt.rr0);
+        g = bapply(bt.R, bt.Z, bt.partials, all_done);
+        bfinish(s, nr, bt.partials, g, FIN_RZ, nullptr, st);
+        bcg_direction(s, nr, n, bt.Z, bt.P, st);
+        int issued = 0, chunk = 2;
+        int *h = bt.host;
+        while (true) {
+            for (int c = 0; c < chunk && issued < maxit; c++, issued++) {
+                int pk = pbeg(AUX_PROF_CG_SPMV);
+                g = bsell_spmv64(s, nr, A64, bt.P, bt.Q, bt.partials, all_done);
+                pend(pk);
+                bfinish(s, nr, bt.partials, g, FIN_PQ, nullptr, st);
+                g = bcg_update(s, nr, n, bt.X, bt.R, bt.P, bt.Q, st, bt.partials);
+                bfinish(s, nr, bt.partials, g, FIN_RR, nullptr, st);
+                g = bapply(bt.R, bt.Z, bt.partials, all_done);
+                bfinish(s, nr, bt.partials, g, FIN_RZ, nullptr, st);
+                bcg_direction(s, nr, n, bt.Z, bt.P, st);
+            }
+            HIPCHECK(hipMemcpyAsync(h, bt.ist, (2 + 2 * (size_t)nr) * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipStreamSynchronize(s));
+            if (h[1] || issued >= maxit) break;
+            chunk = 4;
+        }
+        bscatter(s, nr, n, nrhs, perm, bt.X, Uext);
+        prof_collect(1 << 30);
+        std::vector<double> ff(nr), rr((size_t)bt.hist_cap * nr);
+        HIPCHECK(hipMemcpy(ff.data(), bt.ff, nr * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(rr.data(), st.rr, rr.size() * sizeof(double), hipMemcpyDeviceToHost));
+        int worst = AUX_OK;
+        double secs = seconds_since(t0);
+        for (int c = 0; c < nrhs; c++) {
+            int it = h[2 + c], d = h[2 + nr + c];
+            int status = AUX_OK;
+            if (d == 2 || d == 0) status = AUX_ENOTCONV;
+            else if (d == 3) status = AUX_EBREAKDOWN;
+            else if (d == 4) status = AUX_ENAN;
+            if (status != AUX_OK && (worst == AUX_OK || status < worst)) worst = status;
+            if (infos) {
+                infos[c].iterations = it;
+                infos[c].status = status;
+                double r2 = rr[(size_t)it * nr + c];
+                infos[c].rel_residual = ff[c] > 0 ? std::sqrt(r2 / ff[c]) : 0.0;
+                infos[c].seconds = secs;
+            }
+        }
+        return worst;
+    }
+
+    void apply_external(const double *rext, double *zext)
+    {
+        int n = disc.ndof;
+        vec_gather(stream, n, perm, rext, fi);
+        apply(fi, z, nullptr, nullptr);
+        vec_scatter(stream, n, perm, z, zext);
+    }
+
+    void matvec_external(const double *x, double *y)
+    {
+        int n = disc.ndof;
+        vec_gather(stream, n, perm, x, fi);
+        sell_spmv64(stream, A.view<double>(), fi, q, nullptr, nullptr);
+        vec_scatter(stream, n, perm, q, y);
     }
 
     void ensure_adjoint()
@@ -506,9 +874,9 @@ struct aux_handle {
         for (hipEvent_t e : ev_pool) hipEventDestroy(e);
         ev_pool.clear();
         if (host_state) hipHostFree(host_state);
-        if (host_scal) hipHostFree(host_scal);
         host_state = nullptr;
-        host_scal = nullptr;
+        for (void *ptr : host_bufs) hipHostFree(ptr);
+        host_bufs.clear();
     }
 };
 
@@ -558,6 +926,8 @@ void aux_default_options(aux_options *o)
     o->precision = AUX_FP64;
     o->maxit = 1000;
     o->host_only = 0;
+    o->op = AUX_OP_ASSEMBLED;
+    o->sell_window = 4096;
 }
 
 int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt, const aux_device *dev,
@@ -575,6 +945,7 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
         if (o.coarse_max < 1 || o.max_levels < 1 || o.max_levels > 32)
             throw AuxError(AUX_EINVAL, "bad coarse_max or max_levels");
         if (o.precision != AUX_FP64 && o.precision != AUX_MIXED) throw AuxError(AUX_EINVAL, "bad precision");
+        if (o.op != AUX_OP_ASSEMBLED && o.op != AUX_OP_MATFREE) throw AuxError(AUX_EINVAL, "bad operator kind");
         if (o.maxit < 1) o.maxit = 1000;
         auto *h = new aux_handle();
         try {
@@ -583,6 +954,7 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
             if (dev) h->dev = *dev;
             h->stream = (hipStream_t)h->dev.stream;
             build_discretization(h->disc, mesh->n_vertices, mesh->xyz, mesh->n_tets, mesh->tets, order, kappa);
+            if (h->disc.ndof == 0) throw AuxError(AUX_EINVAL, "mesh has no interior degrees of freedom");
             SetupOptions so;
             so.theta = o.theta;
             so.coarse_max = o.coarse_max;
@@ -643,6 +1015,18 @@ int aux_set_precision(aux_handle *h, int precision)
     });
 }
 
+int aux_set_operator(aux_handle *h, int op)
+{
+    return guarded([&]() {
+        need_device(h);
+        if (op != AUX_OP_ASSEMBLED && op != AUX_OP_MATFREE) throw AuxError(AUX_EINVAL, "bad operator kind");
+        set_dev(h);
+        h->opt.op = op;
+        if (op == AUX_OP_MATFREE) h->ensure_mf();
+        return AUX_OK;
+    });
+}
+
 int aux_get_info(const aux_handle *h, aux_info *info)
 {
     return guarded([&]() {
@@ -669,6 +1053,7 @@ int aux_get_info(const aux_handle *h, aux_info *info)
         info->amg_complexity = d.AH.nnz() ? tot / (double)d.AH.nnz() : 0.0;
         info->setup_seconds = h->setup_seconds;
         info->device_bytes = h->device_bytes;
+        info->stored_A = h->A.stored;
         return AUX_OK;
     });
 }
@@ -746,7 +1131,7 @@ int aux_apply(aux_handle *h, const double *r, double *z)
         need_device(h);
         if (!r || !z) throw AuxError(AUX_EINVAL, "null vector");
         set_dev(h);
-        h->apply(r, z, Reduce{nullptr, nullptr, nullptr, nullptr}, nullptr);
+        h->apply_external(r, z);
         HIPCHECK(hipGetLastError());
         return AUX_OK;
     });
@@ -770,8 +1155,13 @@ int pcg_solve_batched(aux_handle *h, const double *F, double *U, int nrhs, doubl
 {
     return guarded([&]() -> int {
         need_device(h);
-        (void)F; (void)U; (void)nrhs; (void)tol; (void)maxit; (void)infos;
-        throw AuxError(AUX_ESTATE, "batched solve not built yet");
+        if (!F || !U) throw AuxError(AUX_EINVAL, "null block");
+        if (nrhs < 1 || nrhs > 64) throw AuxError(AUX_EINVAL, "nrhs must be in [1, 64]");
+        if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
+        set_dev(h);
+        int st = h->pcg_batched(F, U, nrhs, tol, maxit, infos);
+        HIPCHECK(hipGetLastError());
+        return st;
     });
 }
 
@@ -781,7 +1171,7 @@ int aux_matvec(aux_handle *h, const double *x, double *y)
         need_device(h);
         if (!x || !y) throw AuxError(AUX_EINVAL, "null vector");
         set_dev(h);
-        launch_spmv64(h->stream, h->A.view<double>(), x, y, Reduce{nullptr, nullptr, nullptr, nullptr}, nullptr);
+        h->matvec_external(x, y);
         HIPCHECK(hipGetLastError());
         return AUX_OK;
     });
@@ -794,7 +1184,7 @@ int aux_kappa_grad(aux_handle *h, const double *u, const double *lam, double *g)
         if (!u || !lam || !g) throw AuxError(AUX_EINVAL, "null vector");
         set_dev(h);
         h->ensure_adjoint();
-        launch_kappa_grad(h->stream, h->disc.nt, h->disc.nloc, h->tet_dof_d, h->G, h->kappa_d, h->Mtab, u, lam, g);
+        kappa_grad(h->stream, h->disc.nt, h->disc.nloc, h->tet_dof_d, h->G, h->kappa_d, h->Mtab, u, lam, g);
         HIPCHECK(hipGetLastError());
         return AUX_OK;
     });

@@ -82,3 +82,22 @@ void accumulate_load(const Discretization &d, int t0, int t1, const double *fq, 
 Csr transpose(const Csr &a);
 
 }  // namespace auxp
+
+namespace auxp {
+
+// Sliced ELLPACK in an internal row order (see formats.cpp).
+struct Sell {
+    int n = 0, slice = 64, nslices = 0;
+    std::vector<int> perm;        // internal row -> original row
+    std::vector<int> iperm;       // original row -> internal row
+    std::vector<int> slice_off;   // [nslices+1]
+    std::vector<int> col;         // internal column numbers
+    std::vector<double> val;
+};
+
+// cls (optional): rows are first grouped by this key (stable)
+void build_sell(const Csr &A, int slice, int window, const std::vector<uint64_t> *cls, Sell &out);
+// rows of A in the order perm (row r of the result is row perm[r] of A)
+Csr permute_rows(const Csr &A, const std::vector<int> &perm);
+
+}  // namespace auxp

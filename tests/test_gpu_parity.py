@@ -153,3 +153,57 @@ def test_status_codes():
     u, info = lib.solve(_t(b), tol=1e-8)
     u2, info2 = lib.solve(_t(b), tol=1e-6, u0=u)
     assert info2.iterations == 0 and torch.equal(u, u2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_columns_match_single_solves(precision):
+    xyz, tets, kappa = _case(2, 8, jitter=0.2, kappa="rand")
+    lib = aux.Solver(xyz, tets, 2, kappa, device=DEV, precision=precision)
+    orc = oracle.Problem(xyz, tets, 2, kappa).setup_amg()
+    nrhs = 12                                   # padded to 16 lanes internally
+    F = np.stack([orc.load(W.fourier_f(r)) for r in range(nrhs)], axis=1)
+    U, infos = lib.solve_batched(_t(F), tol=1e-8)
+    for j in range(nrhs):
+        u, info = lib.solve(_t(F[:, j]), tol=1e-8)
+        assert infos[j].converged and abs(infos[j].iterations - info.iterations) <= 1
+        assert _rel(U[:, j].cpu().numpy(), u.cpu().numpy()) <= 1e-8
+        x, it, rr, st = orc.pcg(F[:, j], tol=1e-8, fp32=(precision == "mixed"))
+        assert abs(infos[j].iterations - it) <= 1
+        assert _rel(U[:, j].cpu().numpy(), x) <= 1e-7
+
+
+def test_batched_fixed_iterations_fp64():
+    xyz, tets, _ = _case(3, 5, jitter=0.1)
+    lib = aux.Solver(xyz, tets, 3, device=DEV)
+    orc = oracle.Problem(xyz, tets, 3).setup_amg()
+    F = np.stack([orc.load(W.fourier_f(r)) for r in range(8)], axis=1)
+    its = [orc.pcg(F[:, j], tol=1e-8)[1] for j in range(8)]
+    m = min(its)
+    U, infos = lib.solve_batched(_t(F), tol=0.0, maxit=m, check=False)
+    for j in range(8):
+        x, it, rr, st = orc.pcg(F[:, j], tol=0.0, maxit=m)
+        assert infos[j].iterations == m
+        assert _rel(U[:, j].cpu().numpy(), x) <= 1e-10
+
+
+@pytest.mark.parametrize("k,n,jit,kap", [(3, 6, 0.0, "grf"), (2, 7, 0.2, "rand"), (3, 5, 0.15, None)])
+def test_matfree_operator(k, n, jit, kap):
+    """The matrix-free element operator (MFMA) inside the preconditioner equals
+    the assembled one: FP64 to rounding, FP32 to single precision."""
+    xyz, tets, kappa = _case(k, n, jitter=jit, kappa=kap)
+    lib = aux.Solver(xyz, tets, k, kappa, device=DEV)
+    orc = oracle.Problem(xyz, tets, k, kappa).setup_amg()
+    r = W.random_vector(lib.n, 3)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 2e-6)):
+        lib.set_precision(prec)
+        lib.set_operator("assembled")
+        z_asm = lib.apply(_t(r)).cpu().numpy()
+        lib.set_operator("matfree")
+        z_mf = lib.apply(_t(r)).cpu().numpy()
+        assert _rel(z_mf, z_asm) <= tol, prec
+        assert _rel(z_mf, orc.apply(r, fp32=(prec == "mixed"))) <= tol, prec
+    b = orc.load(W.manufactured_f)
+    x, it, rr, st = orc.pcg(b, tol=1e-8, fp32=True)
+    u, info = lib.solve(_t(b), tol=1e-8)
+    assert info.converged and abs(info.iterations - it) <= 1
+    assert _rel(u.cpu().numpy(), orc.pcg(b, tol=1e-8)[0]) <= 1e-7
