@@ -48,6 +48,33 @@ def algorithmic_bytes(cat, n, nnz, s):
     return None
 
 
+def apply_bytes(info, s, nu):
+    """Algorithmic bytes of one preconditioner application z = B r with the
+    assembled operator, summed over its kernels (each matrix, index and
+    vector byte counted once per kernel that needs it).  s = bytes of the
+    preconditioner's floating-point type."""
+    n, N, nH, NP = info.n_h, info.nnz_A, info.n_H, info.nnz_IP
+    total = algorithmic_bytes("pk_first", n, N, s)
+    total += 2 * (nu - 1) * algorithmic_bytes("pk_sweep", n, N, s)
+    total += algorithmic_bytes("pk_resid", n, N, s)
+    total += algorithmic_bytes("pk_last", n, N, s)
+    total += (s + 4) * NP + 4 * (nH + 1) + s * n + s * nH          # r_H = I_R res
+    total += (s + 4) * NP + 4 * (n + 1) + s * nH + 2 * s * n      # z += I_P e_H
+    L = info.levels
+    for l in range(L):
+        nl, Nl = info.level_rows[l], info.level_nnz[l]
+        if l + 1 == L:                                               # dense coarse inverse
+            total += s * nl * nl + 2 * s * nl
+            continue
+        nc, Pl = info.level_rows[l + 1], info.level_nnz_P[l]
+        mat = (s + 4) * Nl + 4 * (nl + 1)
+        total += mat + 4 * s * nl                                    # x = D^-1 b, r = b - A x
+        total += (s + 4) * Pl + 4 * (nc + 1) + s * nl + s * nc       # b_{l+1} = P^T r
+        total += (s + 4) * Pl + 4 * (nl + 1) + s * nc + 2 * s * nl   # x += P e
+        total += mat + 4 * s * nl                                    # post-sweep
+    return total
+
+
 def run(args):
     import numpy as np
     import torch
@@ -63,19 +90,19 @@ def run(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
-    s = aux.Solver(xyz, tets, wl["k"], kappa, precision="mixed", device=dev)
+    s = aux.Solver(xyz, tets, wl["k"], kappa, precision="mixed", device=dev, operator=args.operator)
     setup_s = time.time() - t0
     b = s.load(W.manufactured_f)
     f = torch.tensor(b, dtype=torch.float64, device=dev)
     u = torch.zeros_like(f)
     n, nnz = s.n, int(s.info.nnz_A)
 
-    def timed(mode, profile):
+    def timed(mode):
+        """K unprofiled solves (each CG iteration replayed as a HIP graph):
+        the throughput figures come from these."""
         s.set_precision(mode)
         for _ in range(args.warmup):
             s.solve(f, tol=args.tol, out=u)
-        if profile:
-            s.profile(True)
         torch.cuda.synchronize()
         t = time.perf_counter()
         its = []
@@ -84,15 +111,23 @@ def run(args):
             its.append(info.iterations)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t) * 1e3 / args.steps
-        prof = s.profile_read() if profile else None
-        if profile:
-            s.profile(False)
         sol = u.clone()
         true_res = float(torch.linalg.norm(f - s.matvec(sol)) / torch.linalg.norm(f))
-        return dict(ms=ms, iterations=its, true_rel_residual=true_res, prof=prof, u=sol)
+        # the same K solves again with HIP events around every launch (eager
+        # launches): per-kernel durations for the roofline
+        s.profile(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            s.solve(f, tol=args.tol, out=u)
+        torch.cuda.synchronize()
+        ms_prof = (time.perf_counter() - t) * 1e3 / args.steps
+        prof = s.profile_read()
+        s.profile(False)
+        return dict(ms=ms, ms_profiled=ms_prof, iterations=its, true_rel_residual=true_res, prof=prof, u=sol)
 
-    mixed = timed("mixed", True)
-    fp64 = timed("fp64", True)
+    mixed = timed("mixed")
+    fp64 = timed("fp64")
     diff = float(torch.linalg.norm(mixed["u"] - fp64["u"]) / torch.linalg.norm(fp64["u"]))
 
     # roofline of the dominant kernel of the timed (mixed) solve
@@ -105,7 +140,16 @@ def run(args):
                                 gbs=ab / (avg_ms * 1e-3) / 1e9)
     dom = max(kernels, key=lambda c: kernels[c]["total_ms"])
     kd = kernels[dom]
-    apply_cnt, apply_ms = mixed["prof"]["apply"]
+    # whole preconditioner application: algorithmic bytes over its measured time
+    precond = {}
+    for name, res, sz in (("mixed", mixed, 4), ("fp64", fp64, 8)):
+        cnt, tot = res["prof"]["apply"]
+        us = tot / max(cnt, 1) * 1e3
+        entry = {"us": us}
+        if args.operator == "assembled":
+            ab = apply_bytes(s.info, sz, 2)
+            entry.update(bytes=ab, gbs=ab / (us * 1e-6) / 1e9, frac=ab / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+        precond[name] = entry
 
     out = {
         "metric": METRIC,
@@ -120,11 +164,12 @@ def run(args):
         "vs_baseline": None,
         "dtype": "f64 CG / f32 preconditioner",
         "data": "synthetic",
-        "config": {"workload": args.workload, "order": wl["k"], "cubes_per_side": wl["n"],
+        "config": {"workload": args.workload, "operator": args.operator, "order": wl["k"], "cubes_per_side": wl["n"],
                    "jitter": wl["jitter"], "n_h": n, "nnz_A": nnz, "tol": args.tol,
                    "iterations": mixed["iterations"][-1], "true_rel_residual": mixed["true_rel_residual"],
                    "amg_levels": int(s.info.levels), "op_complexity": round(float(s.info.op_complexity), 4),
-                   "setup_s": round(setup_s, 2)},
+                   "setup_s": round(setup_s, 2), "sell_window": int(s.info.sell_window),
+                   "ms_per_step_profiled": round(mixed["ms_profiled"], 3)},
         "fp64": {"value": n / (fp64["ms"] * 1e-3), "ms_per_step": fp64["ms"],
                  "iterations": fp64["iterations"][-1], "true_rel_residual": fp64["true_rel_residual"],
                  "mixed_vs_fp64_rel_diff": diff,
@@ -134,8 +179,7 @@ def run(args):
                      "bytes_per_launch": kd["bytes"], "avg_us": kd["avg_us"]},
         "kernels_mixed": {c: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
                           for c, d in kernels.items()},
-        "precond_apply_us": {"mixed": apply_ms / max(apply_cnt, 1) * 1e3,
-                             "fp64": fp64["prof"]["apply"][1] / max(fp64["prof"]["apply"][0], 1) * 1e3},
+        "precond_apply": precond,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xyz, tets, wl, kappa, b, args)
@@ -164,6 +208,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="p2_n48_jitter", choices=sorted(WORKLOADS))
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--operator", default="assembled", choices=["assembled", "matfree"],
+                    help="P^k products inside the preconditioner: sliced-ELL A_h or the MFMA element operator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -81,7 +81,12 @@ typedef struct aux_options {
     int host_only;           /* 1: run the host setup only, no device (for tests) */
     int op;                  /* AUX_OP_ASSEMBLED or AUX_OP_MATFREE (AUX_OP_ASSEMBLED) */
     int sell_window;         /* device A_h layout: rows sorted by length within windows of this
-                                many dofs (4096); 0 groups rows by node class instead */
+                                many dofs; 0 (default) lets the setup time the candidate
+                                layouts on the device and keep the fastest.  The layout
+                                fixes the internal dof order and so the summation order
+                                of inner products: two handles agree bitwise only if
+                                they use the same window (aux_info.sell_window) */
+    int graph;               /* 1: replay each CG iteration as a captured HIP graph (1) */
 } aux_options;
 
 typedef struct aux_device {
@@ -103,6 +108,9 @@ typedef struct aux_info {
     double setup_seconds;
     int64_t device_bytes;    /* device memory held by the handle */
     int64_t stored_A;        /* stored entries of the device P^k operator, slice padding included */
+    int64_t sell_window;     /* length-sorting window of the device A_h layout in use */
+    int64_t level_nnz_P[32]; /* entries of the interpolation P_l from level l+1 to level l
+                                (0 on the coarsest level) */
 } aux_info;
 
 typedef struct aux_solve_info {

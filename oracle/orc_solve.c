@@ -157,7 +157,7 @@ static void apply_B(const orc *o, const bops *B, const double *rin, double *z)
 {
     rfun R = B->R;
     int n = o->ndof, nH = o->nH;
-    double *r = malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *r = calloc((size_t)(n > 0 ? n : 1), sizeof(double));
     double *t = malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     double *bH = malloc((size_t)(nH > 0 ? nH : 1) * sizeof(double));
     double *eH = malloc((size_t)(nH > 0 ? nH : 1) * sizeof(double));

@@ -47,7 +47,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_int), ("theta", ctypes.c_double), ("coarse_max", ctypes.c_int),
                 ("max_levels", ctypes.c_int), ("pmis_seed", ctypes.c_uint64), ("precision", ctypes.c_int),
                 ("maxit", ctypes.c_int), ("host_only", ctypes.c_int), ("op", ctypes.c_int),
-                ("sell_window", ctypes.c_int)]
+                ("sell_window", ctypes.c_int), ("graph", ctypes.c_int)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -65,7 +65,8 @@ class _Info(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("op_complexity", ctypes.c_double),
                 ("amg_complexity", ctypes.c_double), ("level_rows", ctypes.c_int64 * 32),
                 ("level_nnz", ctypes.c_int64 * 32), ("setup_seconds", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64), ("stored_A", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("stored_A", ctypes.c_int64), ("sell_window", ctypes.c_int64),
+                ("level_nnz_P", ctypes.c_int64 * 32)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -154,7 +155,7 @@ class Solver:
     def __init__(self, xyz, tets, order: int, kappa=None, *, nu: int = 2, theta: float = 0.8,
                  coarse_max: int = 100, max_levels: int = 25, seed: int = 0, precision: str = "fp64",
                  maxit: int = 1000, host_only: bool = False, device=None, use_torch_allocator: bool = True,
-                 operator: str = "assembled", sell_window: int = 4096):
+                 operator: str = "assembled", sell_window: int = 0, graph: bool = True):
         lib = load_library()
         self._h = ctypes.c_void_p()
         self.order = order
@@ -169,6 +170,7 @@ class Solver:
         opt.precision = {"fp64": FP64, "mixed": MIXED}[precision]
         opt.op = _OPS[operator]
         opt.sell_window = sell_window
+        opt.graph = int(graph)
         kap = None
         if kappa is not None:
             self._kappa = np.ascontiguousarray(kappa, dtype=np.float64)

@@ -11,11 +11,13 @@
 // evaluated with v_mfma_*_16x16x4 (A operand = the reference tables, held in
 // registers for the whole kernel; B operand = Z built from LDS).
 //
-// The element results Y (one row of nloc values per tet) are then summed per
-// dof over its (tet, local node) incidences in a fixed order -- no atomics,
-// so the result is deterministic -- and the smoother or residual update is
-// fused into that gather-sum pass.
+// Each element result (K_t x_t)_a is written to the slot of (t, a) in an
+// array ordered by dof, so the contributions to one dof are contiguous; a
+// second pass sums each dof's range in a fixed order -- no atomics, so the
+// result is deterministic -- with the smoother or residual update fused in.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "kernels.hpp"
 #include "mfree.hpp"
@@ -29,6 +31,9 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct Acc;
+// Operand layouts (both 16x16x4 forms): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16].  Result register v of lane l holds D[row][l % 16] with
+// row = 4 (l / 16) + v for FP32 and row = (l / 16) + 4 v for FP64.
 template <>
 struct Acc<float> {
     using V = f32x4;
@@ -36,6 +41,7 @@ struct Acc<float> {
     {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int grp, int v) { return 4 * grp + v; }
 };
 template <>
 struct Acc<double> {
@@ -44,6 +50,7 @@ struct Acc<double> {
     {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int grp, int v) { return grp + 4 * v; }
 };
 
 __device__ __forceinline__ bool stop(const int *done) { return done != nullptr && *done != 0; }
@@ -51,66 +58,73 @@ __device__ __forceinline__ bool stop(const int *done) { return done != nullptr &
 constexpr int kTetsPerWave = 16;
 constexpr int kWaves = kBlock / 64;
 
-// Yel[t] = K_t x_t for all tets
+// Y[slot(t, a)] = (K_t x_t)_a for all tets.
+//
+// Contraction order: the 6 nloc terms (k, b) are split into steps of four,
+// step s covering k = s / NB and b = 4 (s % NB) + g for the four lane groups
+// g = lane / 16 (NB = ceil(nloc / 4); b >= nloc is padding).  So lane (g, c)
+// of a wave needs only the six weights of its tet c and its NB gathered
+// values b = g, g+4, ..., held in registers -- no shared memory and no
+// barriers -- and every register index below is a compile-time constant.
 template <typename T, int NLOC>
 __global__ __launch_bounds__(kBlock) void k_mf_element(MfView<T> op, const T *__restrict__ X, T *__restrict__ Yel,
                                                        const int *done)
 {
     if (stop(done)) return;
-    constexpr int KK = 6 * NLOC;                 // contraction length
-    constexpr int KS = KK / 4;                   // MFMA steps (4 per step)
+    constexpr int NB = (NLOC + 3) / 4;           // gathered values per lane
+    constexpr int KS = 6 * NB;                   // MFMA steps
     constexpr int MT = (NLOC + 15) / 16;         // 16-row output tiles
-    __shared__ T xs[kWaves][NLOC][kTetsPerWave];
-    __shared__ T ws[kWaves][6][kTetsPerWave];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int col = lane & 15, grp = lane >> 4;
 
-    // A operand: lane (row i = lane % 16, k = lane / 16) of step s holds S[16 mt + i][4 s + k]
+    // A operand: lane (i = lane % 16, g) of step s holds S[16 mt + i][k nloc + b]
     T areg[MT][KS];
 #pragma unroll
     for (int mt = 0; mt < MT; mt++)
 #pragma unroll
         for (int s = 0; s < KS; s++) {
-            const int row = 16 * mt + col;
-            areg[mt][s] = row < NLOC ? op.S[row * KK + 4 * s + grp] : T(0);
+            const int row = 16 * mt + col, k = s / NB, b = 4 * (s % NB) + grp;
+            areg[mt][s] = (row < NLOC && b < NLOC) ? op.S[row * 6 * NLOC + k * NLOC + b] : T(0);
         }
 
-    const long long ntiles = ((long long)op.nt + kTetsPerWave * kWaves - 1) / (kTetsPerWave * kWaves);
-    for (long long bt = blockIdx.x; bt < ntiles; bt += gridDim.x) {
-        const int t = (int)(bt * (kTetsPerWave * kWaves)) + wave * kTetsPerWave + col;
+    const int nwaves = gridDim.x * kWaves;
+    const int ntiles = (op.nt + kTetsPerWave - 1) / kTetsPerWave;
+    for (int tile = blockIdx.x * kWaves + (int)(threadIdx.x >> 6); tile < ntiles; tile += nwaves) {
+        const int t = tile * kTetsPerWave + col;
         const bool tv = t < op.nt;
-        for (int b = grp; b < NLOC; b += 4) {
-            T v = T(0);
-            if (tv) {
-                const int d = op.emap[(size_t)t * NLOC + b];
-                if (d >= 0) v = X[d];
-            }
-            xs[wave][b][col] = v;
+        T wv[6], xv[NB];
+#pragma unroll
+        for (int k = 0; k < 6; k++) wv[k] = tv ? op.w[(size_t)t * 6 + k] : T(0);
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+            const int b = 4 * j + grp;
+            int d = -1;
+            if (tv && b < NLOC) d = op.emap[(size_t)t * NLOC + b];
+            xv[j] = d >= 0 ? X[d] : T(0);
         }
-        for (int k = grp; k < 6; k += 4) ws[wave][k][col] = tv ? op.w[(size_t)t * 6 + k] : T(0);
-        __syncthreads();
         typename Acc<T>::V acc[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; mt++) acc[mt] = typename Acc<T>::V{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < KS; s++) {
-            // B operand: lane (k = lane / 16, column = lane % 16) holds Z[4 s + k][column]
-            const int kk = 4 * s + grp;
-            const T bv = ws[wave][kk / NLOC][col] * xs[wave][kk % NLOC][col];
+            // B operand: lane (g, c) holds Z[(k, b)][c] = w_c,k x_c,b
+            const T bv = wv[s / NB] * xv[s % NB];
 #pragma unroll
             for (int mt = 0; mt < MT; mt++) acc[mt] = Acc<T>::mfma(areg[mt][s], bv, acc[mt]);
         }
-        // D: lane holds rows 4 (lane / 16) + v, v = 0..3, of column lane % 16
+        // D: register v of this lane holds row Acc<T>::row(grp, v) of column c
         if (tv) {
 #pragma unroll
             for (int mt = 0; mt < MT; mt++)
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
-                    const int a = 16 * mt + 4 * grp + v;
-                    if (a < NLOC) Yel[(size_t)t * NLOC + a] = acc[mt][v];
+                    const int a = 16 * mt + Acc<T>::row(grp, v);
+                    if (a < NLOC) {
+                        const int p = op.slot[(size_t)t * NLOC + a];
+                        if (p >= 0) Yel[p] = acc[mt][v];
+                    }
                 }
         }
-        __syncthreads();
     }
 }
 
@@ -129,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_gather(MfView<T> op, const T *__r
     double acc = 0.0;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < op.n; i += gridDim.x * kBlock) {
         T s = T(0);
-        for (int p = op.inc_ptr[i]; p < op.inc_ptr[i + 1]; p++) s += Yel[op.inc[p]];
+        for (int p = op.inc_ptr[i]; p < op.inc_ptr[i + 1]; p++) s += Yel[p];
         T v;
         if (MODE == MF_RESID) v = (T)rhs[i] - s;
         else v = xin[i] + dinv[i] * ((T)rhs[i] - s);
@@ -161,7 +175,10 @@ inline int cap_grid(long long need)
 template <typename T>
 void mf_apply(hipStream_t s, const MfView<T> &op, const T *x, T *Yel, const int *done)
 {
-    int g = cap_grid(((long long)op.nt + kTetsPerWave * kWaves - 1) / (kTetsPerWave * kWaves));
+    // persistent waves: a few tiles each, so the operand tables are loaded once per wave
+    const long long tiles = ((long long)op.nt + kTetsPerWave - 1) / kTetsPerWave;
+    int g = (int)std::min<long long>((tiles + kWaves - 1) / kWaves, 1024);
+    if (g < 1) g = 1;
     if (op.nloc == 10)
         hipLaunchKernelGGL((k_mf_element<T, 10>), dim3(g), dim3(kBlock), 0, s, op, x, Yel, done);
     else

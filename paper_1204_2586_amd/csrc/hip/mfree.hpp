@@ -13,11 +13,11 @@ struct MfView {
     const int *emap;     // [nt][nloc] internal dof of each local node, -1 on the boundary
     const T *w;          // [nt][6] edge weights -kappa_e G^e_pq, pairs (01,02,03,12,13,23)
     const T *S;          // [nloc][6 nloc] reference tables S[a][k nloc + b] = S^k_ab
-    const int *inc_ptr;  // [n+1] incidences of each dof
-    const int *inc;      // entries t*nloc + a of the element results
+    const int *inc_ptr;  // [n+1] incidence range of each dof in the element-result array
+    const int *slot;     // [nt][nloc] position of (t, a) in that array, -1 on the boundary
 };
 
-// Yel[t][a] = (K_t x_t)_a for every tet
+// Y[slot[t][a]] = (K_t x_t)_a for every tet (the results of a dof are contiguous)
 template <typename T>
 void mf_apply(hipStream_t s, const MfView<T> &op, const T *x, T *Yel, const int *done);
 // res = rhs - (sum of element results)

@@ -95,6 +95,8 @@ struct aux_handle {
     double setup_seconds = 0.0;
     int64_t device_bytes = 0;
     std::vector<void *> allocs;
+    std::vector<size_t> alloc_size;
+    int sell_window_used = 0;        // layout window the setup chose
 
     DevSell A;                       // A_h, internal order
     int *perm = nullptr;             // internal -> external dof
@@ -130,7 +132,7 @@ struct aux_handle {
 
     // matrix-free element operator (internal dof numbering)
     bool mf_ready = false;
-    int *mf_emap = nullptr, *mf_inc_ptr = nullptr, *mf_inc = nullptr;
+    int *mf_emap = nullptr, *mf_inc_ptr = nullptr, *mf_inc = nullptr;   // mf_inc: slot of each (tet, node)
     double *mf_w64 = nullptr, *mf_S64 = nullptr, *mf_Y64 = nullptr;
     float *mf_w32 = nullptr, *mf_S32 = nullptr, *mf_Y32 = nullptr;
 
@@ -163,12 +165,13 @@ struct aux_handle {
             }
         }
         for (int i = 0; i < n; i++) cnt[i + 1] += cnt[i];
-        std::vector<int> inc(cnt.back()), fill(cnt.begin(), cnt.end() - 1);
+        // slot of each (tet, local node) in the dof-ordered result array
+        std::vector<int> slot(emap.size(), -1), fill(cnt.begin(), cnt.end() - 1);
         for (size_t s = 0; s < emap.size(); s++)
-            if (emap[s] >= 0) inc[fill[emap[s]]++] = (int)s;
+            if (emap[s] >= 0) slot[s] = fill[emap[s]]++;
         mf_emap = upload(emap);
         mf_inc_ptr = upload(cnt);
-        mf_inc = upload(inc);
+        mf_inc = upload(slot);
         mf_w64 = upload(w);
         mf_S64 = upload(S);
         mf_w32 = upload(to_f32(w));
@@ -248,8 +251,22 @@ struct aux_handle {
             if (e != hipSuccess) throw AuxError(AUX_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         }
         allocs.push_back(ptr);
+        alloc_size.push_back(bytes);
         device_bytes += (int64_t)bytes;
         return ptr;
+    }
+    void dfree(void *ptr)
+    {
+        for (size_t i = 0; i < allocs.size(); i++)
+            if (allocs[i] == ptr) {
+                HIPCHECK(hipStreamSynchronize(stream));
+                if (dev.free) dev.free(ptr, dev.ctx);
+                else HIPCHECK(hipFree(ptr));
+                device_bytes -= (int64_t)alloc_size[i];
+                allocs.erase(allocs.begin() + i);
+                alloc_size.erase(alloc_size.begin() + i);
+                return;
+            }
     }
     template <typename T>
     T *dnew(size_t n)
@@ -291,32 +308,70 @@ struct aux_handle {
     Csr IPi, IRi;                    // internal-order transfers (host, for the FP32 copies)
     std::vector<double> l1i;         // l1 norms in internal order
 
+    DevSell upload_sell(const Sell &sl)
+    {
+        DevSell d;
+        d.n = sl.n;
+        d.nslices = sl.nslices;
+        d.stored = (int64_t)sl.val.size();
+        d.slice_off = upload(sl.slice_off);
+        d.col = upload(sl.col);
+        d.v64 = upload(sl.val);
+        return d;
+    }
+
+    // mean time of a few FP64 products with a device layout (the autotuner's measure)
+    double time_sell(const DevSell &d)
+    {
+        double *x = dnew<double>(disc.ndof), *y = dnew<double>(disc.ndof);
+        HIPCHECK(hipMemsetAsync(x, 0, (size_t)disc.ndof * sizeof(double), stream));
+        hipEvent_t a = take_event(), b = take_event();
+        sell_spmv64(stream, d.view<double>(), x, y, nullptr, nullptr);
+        HIPCHECK(hipEventRecord(a, stream));
+        for (int i = 0; i < 5; i++) sell_spmv64(stream, d.view<double>(), x, y, nullptr, nullptr);
+        HIPCHECK(hipEventRecord(b, stream));
+        HIPCHECK(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, a, b));
+        ev_used -= 2;
+        dfree(x);
+        dfree(y);
+        return ms / 5.0;
+    }
+
     void upload_all()
     {
-        if (opt.sell_window > 0) {
-            build_sell(disc.A, kSlice, opt.sell_window, nullptr, sell);
-        } else {
-            // group rows by node class: row length, then the gaps between the
-            // vertex ids of the node's multiset (on a structured mesh these
-            // identify the node's type and direction); the dof order within a
-            // class keeps neighbouring rows' j-th columns close in memory
-            std::vector<uint64_t> cls(disc.ndof);
-            const int k = disc.k;
-            for (int i = 0; i < disc.ndof; i++) {
-                const int32_t *key = &disc.keys[(size_t)i * k];
-                uint64_t len = (uint64_t)(disc.A.ptr[i + 1] - disc.A.ptr[i]);
-                uint64_t d1 = k > 1 ? (uint64_t)std::min(key[1] - key[0], (1 << 21) - 1) : 0;
-                uint64_t d2 = k > 2 ? (uint64_t)std::min(key[2] - key[1], (1 << 21) - 1) : 0;
-                cls[i] = ((uint64_t)(0xfffff - std::min<uint64_t>(len, 0xfffff)) << 42) | (d1 << 21) | d2;
+        // Device layout of A_h.  A fixed window if one is given; otherwise the
+        // autotuner builds the candidates (rows sorted by length over the whole
+        // operator, which on lattice-structured meshes groups nodes of one
+        // type so a slice gathers nearly contiguous entries; and a 4096-row
+        // window, which keeps locality on unstructured meshes), times a few
+        // products with each on the device and keeps the faster.
+        std::vector<int> windows;
+        if (opt.sell_window > 0) windows.push_back(opt.sell_window);
+        else windows = {std::max(disc.ndof, 1), kSellWindow};
+        double best = 1e300;
+        for (int win : windows) {
+            Sell cand;
+            build_sell(disc.A, kSlice, win, cand);
+            DevSell d = upload_sell(cand);
+            double ms = windows.size() > 1 ? time_sell(d) : 0.0;
+            if (ms < best) {
+                if (A.v64) {
+                    dfree(A.slice_off);
+                    dfree(A.col);
+                    dfree(A.v64);
+                }
+                best = ms;
+                A = d;
+                sell = std::move(cand);
+                sell_window_used = win;
+            } else {
+                dfree(d.slice_off);
+                dfree(d.col);
+                dfree(d.v64);
             }
-            build_sell(disc.A, kSlice, disc.ndof > 0 ? disc.ndof : 1, &cls, sell);
         }
-        A.n = sell.n;
-        A.nslices = sell.nslices;
-        A.stored = (int64_t)sell.val.size();
-        A.slice_off = upload(sell.slice_off);
-        A.col = upload(sell.col);
-        A.v64 = upload(sell.val);
         perm = upload(sell.perm);
         l1i.resize(disc.ndof);
         for (int i = 0; i < disc.ndof; i++) l1i[i] = disc.l1[sell.perm[i]];
@@ -563,6 +618,47 @@ struct aux_handle {
         cg_direction(s, n, z, p, st);
     }
 
+    // cached graph of one CG iteration; recaptured when anything its kernels
+    // depend on by value changes (precision, operator, iteration limit)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_key[3] = {-1, -1, -1};
+
+    hipGraphExec_t iteration_graph(const CgState &st)
+    {
+        const int key[3] = {opt.precision, opt.op, st.maxit};
+        if (graph_exec && std::equal(key, key + 3, graph_key)) return graph_exec;
+        drop_graph();
+        if (!cap_stream) HIPCHECK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        // make every buffer the iteration touches exist before capture
+        if (use_mf()) ensure_mf();
+        if (opt.precision == AUX_MIXED) {
+            ensure_fp32();
+            work<float>();
+        } else {
+            work<double>();
+        }
+        hipStream_t keep = stream;
+        stream = cap_stream;
+        HIPCHECK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+        cg_iteration(st);
+        hipError_t e = hipStreamEndCapture(cap_stream, &graph);
+        stream = keep;
+        HIPCHECK(e);
+        HIPCHECK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+        std::copy(key, key + 3, graph_key);
+        return graph_exec;
+    }
+
+    void drop_graph()
+    {
+        if (graph_exec) hipGraphExecDestroy(graph_exec);
+        if (graph) hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+    }
+
     int pcg(const double *f, double *u, double tol, int maxit, aux_solve_info *info)
     {
         auto t0 = std::chrono::steady_clock::now();
@@ -584,11 +680,16 @@ struct aux_handle {
         finish(s, partials, g, FIN_RZ, nullptr, st);
         cg_direction(s, n, z, p, st);
 
+        // one CG iteration as a HIP graph (its kernels have fixed arguments:
+        // the iteration index and the stopping state live in device memory);
+        // not used while kernel timing records events
+        hipGraphExec_t gexec = opt.graph && !prof_on ? iteration_graph(st) : nullptr;
         int issued = 0, iter = 0, done = 0, chunk = 2;
         while (true) {
             for (int c = 0; c < chunk && issued < maxit; c++, issued++) {
                 prof_tag = issued + 1;
-                cg_iteration(st);
+                if (gexec) HIPCHECK(hipGraphLaunch(gexec, s));
+                else cg_iteration(st);
             }
             HIPCHECK(hipMemcpyAsync(host_state, istate, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
@@ -866,11 +967,15 @@ struct aux_handle {
             if (stream) hipStreamSynchronize(stream);
             else hipDeviceSynchronize();
         }
+        drop_graph();
+        if (cap_stream) hipStreamDestroy(cap_stream);
+        cap_stream = nullptr;
         for (void *ptr : allocs) {
             if (dev.free) dev.free(ptr, dev.ctx);
             else hipFree(ptr);
         }
         allocs.clear();
+        alloc_size.clear();
         for (hipEvent_t e : ev_pool) hipEventDestroy(e);
         ev_pool.clear();
         if (host_state) hipHostFree(host_state);
@@ -927,7 +1032,8 @@ void aux_default_options(aux_options *o)
     o->maxit = 1000;
     o->host_only = 0;
     o->op = AUX_OP_ASSEMBLED;
-    o->sell_window = 4096;
+    o->sell_window = 0;
+    o->graph = 1;
 }
 
 int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt, const aux_device *dev,
@@ -1047,6 +1153,7 @@ int aux_get_info(const aux_handle *h, aux_info *info)
         for (size_t l = 0; l < h->hier.levels.size() && l < 32; l++) {
             info->level_rows[l] = h->hier.levels[l].A.n;
             info->level_nnz[l] = h->hier.levels[l].A.nnz();
+            info->level_nnz_P[l] = l + 1 < h->hier.levels.size() ? h->hier.levels[l].P.nnz() : 0;
             tot += (double)h->hier.levels[l].A.nnz();
         }
         info->op_complexity = d.A.nnz() ? (d.A.nnz() + tot) / (double)d.A.nnz() : 0.0;
@@ -1054,6 +1161,7 @@ int aux_get_info(const aux_handle *h, aux_info *info)
         info->setup_seconds = h->setup_seconds;
         info->device_bytes = h->device_bytes;
         info->stored_A = h->A.stored;
+        info->sell_window = h->sell_window_used;
         return AUX_OK;
     });
 }

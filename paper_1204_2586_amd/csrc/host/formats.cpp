@@ -2,9 +2,9 @@
 //
 // Sliced ELLPACK for the P^k operator.  Rows keep the dof order (which is
 // lexicographic in the vertex multisets, so neighbours along one mesh axis
-// are adjacent in memory), optionally grouped first by a class key (stable),
-// and within each window of `window` consecutive rows longer rows come first
-// (stable): the rows of a slice then have nearly equal lengths.  Consecutive groups of `slice` rows form slices
+// are adjacent in memory) except that within each window of `window`
+// consecutive rows longer rows come first (stable): the rows of a slice then
+// have nearly equal lengths.  Consecutive groups of `slice` rows form slices
 // whose entries are stored column-major (entry j of the slice's rows is
 // contiguous), padded to the slice's longest row with zero values pointing at
 // column 0.
@@ -16,14 +16,13 @@
 
 namespace auxp {
 
-void build_sell(const Csr &A, int slice, int window, const std::vector<uint64_t> *cls, Sell &out)
+void build_sell(const Csr &A, int slice, int window, Sell &out)
 {
     const int n = A.n;
     out.n = n;
     out.slice = slice;
     out.perm.resize(n);
     std::iota(out.perm.begin(), out.perm.end(), 0);
-    if (cls) std::stable_sort(out.perm.begin(), out.perm.end(), [&](int a, int b) { return (*cls)[a] < (*cls)[b]; });
     auto len = [&](int i) { return A.ptr[i + 1] - A.ptr[i]; };
     for (int w0 = 0; w0 < n; w0 += window) {
         int w1 = std::min(n, w0 + window);

@@ -95,8 +95,7 @@ struct Sell {
     std::vector<double> val;
 };
 
-// cls (optional): rows are first grouped by this key (stable)
-void build_sell(const Csr &A, int slice, int window, const std::vector<uint64_t> *cls, Sell &out);
+void build_sell(const Csr &A, int slice, int window, Sell &out);
 // rows of A in the order perm (row r of the result is row perm[r] of A)
 Csr permute_rows(const Csr &A, const std::vector<int> &perm);
 

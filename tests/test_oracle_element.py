@@ -182,3 +182,30 @@ def test_element_matrix_invariants(k):
         uq = nodes[:, 0] ** 2
         exact = 4 * kappa[t] * vol / 20 * (np.sum(X[:, 0] ** 2) + np.sum(X[:, 0]) ** 2)
         assert abs(uq @ K @ uq - exact) < 1e-12 * exact
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_six_term_edge_form_of_element_stiffness(k):
+    """The form the matrix-free operator uses: since the barycentric gradients
+    sum to zero, K_e = sum_{p<q} (-kappa G_pq) (M^pp + M^qq - M^pq - M^qp) with
+    G_pq = |T| grad lam_p . grad lam_q and M^pq the reference tables."""
+    al = oracle.multi_indices(k)
+    nl = len(al)
+    lam, w = oracle.tet_rule(k + 1)
+    d = np.array([[oracle.basis_dlam(k, al[a], l) for a in range(nl)] for l in lam])   # [q][a][p]
+    M = 6.0 * np.einsum("q,qap,qbr->prab", w, d, d)       # (1/|T|) int dphi_a/dlam_p dphi_b/dlam_r
+    xyz, tets = W.kuhn_mesh(2, jitter=0.2, seed=3)
+    kappa = np.exp(np.random.default_rng(4).normal(size=len(tets)))
+    P = oracle.Problem(xyz, tets, k, kappa)
+    for t in (0, 7, 30):
+        X = xyz[tets[t]]
+        J = (X[1:] - X[0]).T
+        g = np.linalg.inv(J)                              # rows: grad lam_1..3
+        grads = np.vstack([-g.sum(0), g])
+        vol = abs(np.linalg.det(J)) / 6
+        G = vol * grads @ grads.T
+        assert np.max(np.abs(G.sum(1))) < 1e-14 * np.abs(G).max()
+        K6 = sum(-kappa[t] * G[p, q] * (M[p, p] + M[q, q] - M[p, q] - M[q, p])
+                 for p in range(4) for q in range(p + 1, 4))
+        K = P.element_matrix(t)
+        assert np.max(np.abs(K6 - K)) < 1e-12 * np.max(np.abs(K))
