@@ -27,14 +27,24 @@ WORKLOADS = {
     "p2_n48_jitter": dict(k=2, n=48, jitter=0.2, seed=0, kappa=None),
     "p2_n8": dict(k=2, n=8, jitter=0.0, seed=0, kappa=None),
     "p3_n32_grf": dict(k=3, n=32, jitter=0.0, seed=0, kappa=1),
+    # 32 right-hand sides solved in lock-step (sources fourier_f(0..31))
+    "p2_n64_32rhs": dict(k=2, n=64, jitter=0.0, seed=0, kappa=None, nrhs=32),
 }
 
 
-def algorithmic_bytes(cat, n, nnz, s):
-    """Bytes a kernel must move at least once per launch (matrix, index and
-    vector arrays each counted once).  s = bytes of the preconditioner's
-    floating-point type, n rows, nnz entries of A_h."""
-    mat = (s + 4) * nnz + 4 * (n + 1)
+def index_bytes_per_entry(info):
+    """Column-stream bytes per entry of the device A_h layout (16-bit offsets
+    in some slices, 32-bit columns in the others), and the per-slice
+    metadata bytes (offset and mode words)."""
+    return info.sell_index_bytes / max(info.stored_A, 1), 8 * info.sell_slices
+
+
+def algorithmic_bytes(cat, n, nnz, s, fmt):
+    """Bytes a kernel must move at least once per launch (matrix values and
+    column stream over the nnz entries, each vector array once).  s = bytes
+    of the floating-point type, fmt = index_bytes_per_entry(info)."""
+    idx, meta = fmt
+    mat = (s + idx) * nnz + meta
     if cat == "pk_sweep":      # z_in (gather), rhs, dinv, z_out
         return mat + 4 * s * n
     if cat == "pk_last":       # z_in, rhs (FP64), dinv, z_out (FP64)
@@ -44,8 +54,15 @@ def algorithmic_bytes(cat, n, nnz, s):
     if cat == "pk_resid":      # rhs, z (gather), res
         return mat + 3 * s * n
     if cat == "cg_spmv":       # FP64 operator, x (gather), y
-        return 12 * nnz + 4 * (n + 1) + 16 * n
+        return (8 + idx) * nnz + meta + 16 * n
     return None
+
+
+def restrict_bytes(info, s):
+    """The fused restricted residual r_H = [I_R, -I_R A_h] [r; z]: CSR
+    operator, both gathered vectors, the P^1 result."""
+    n, nH = info.n_h, info.n_H
+    return (s + 4) * info.nnz_restrict + 4 * (nH + 1) + 2 * s * n + s * nH
 
 
 def apply_bytes(info, s, nu):
@@ -54,11 +71,16 @@ def apply_bytes(info, s, nu):
     vector byte counted once per kernel that needs it).  s = bytes of the
     preconditioner's floating-point type."""
     n, N, nH, NP = info.n_h, info.nnz_A, info.n_H, info.nnz_IP
-    total = algorithmic_bytes("pk_first", n, N, s)
-    total += 2 * (nu - 1) * algorithmic_bytes("pk_sweep", n, N, s)
-    total += algorithmic_bytes("pk_resid", n, N, s)
-    total += algorithmic_bytes("pk_last", n, N, s)
-    total += (s + 4) * NP + 4 * (nH + 1) + s * n + s * nH          # r_H = I_R res
+    fmt = index_bytes_per_entry(info)
+    fused = info.nnz_restrict > 0
+    total = algorithmic_bytes("pk_first", n, N, s, fmt)
+    total += 2 * (nu - 1) * algorithmic_bytes("pk_sweep", n, N, s, fmt)
+    total += algorithmic_bytes("pk_last", n, N, s, fmt)
+    if fused:
+        total += restrict_bytes(info, s)                             # r_H = [I_R, -I_R A_h][r; z]
+    else:
+        total += algorithmic_bytes("pk_resid", n, N, s, fmt)
+        total += (s + 4) * NP + 4 * (nH + 1) + s * n + s * nH      # r_H = I_R res
     total += (s + 4) * NP + 4 * (n + 1) + s * nH + 2 * s * n      # z += I_P e_H
     L = info.levels
     for l in range(L):
@@ -67,6 +89,10 @@ def apply_bytes(info, s, nu):
             total += s * nl * nl + 2 * s * nl
             continue
         nc, Pl = info.level_rows[l + 1], info.level_nnz_P[l]
+        if fused:
+            total += (s + 4) * info.level_nnz_down[l] + 4 * (nc + 1) + s * nl + s * nc   # b' = down b
+            total += (s + 4) * info.level_nnz_up[l] + 4 * (nl + 1) + 2 * s * nl + s * nc  # y = up [b; e]
+            continue
         mat = (s + 4) * Nl + 4 * (nl + 1)
         total += mat + 4 * s * nl                                    # x = D^-1 b, r = b - A x
         total += (s + 4) * Pl + 4 * (nc + 1) + s * nl + s * nc       # b_{l+1} = P^T r
@@ -133,7 +159,9 @@ def run(args):
     # roofline of the dominant kernel of the timed (mixed) solve
     kernels = {}
     for cat, (cnt, tot) in mixed["prof"].items():
-        ab = algorithmic_bytes(cat, n, nnz, 4)
+        ab = algorithmic_bytes(cat, n, nnz, 4, index_bytes_per_entry(s.info))
+        if cat == "pk_resid" and s.info.nnz_restrict > 0:
+            ab = restrict_bytes(s.info, 4)
         if cnt and ab:
             avg_ms = tot / cnt
             kernels[cat] = dict(launches=cnt, total_ms=tot, avg_us=avg_ms * 1e3, bytes=ab,
@@ -169,6 +197,8 @@ def run(args):
                    "iterations": mixed["iterations"][-1], "true_rel_residual": mixed["true_rel_residual"],
                    "amg_levels": int(s.info.levels), "op_complexity": round(float(s.info.op_complexity), 4),
                    "setup_s": round(setup_s, 2), "sell_window": int(s.info.sell_window),
+                   "sell_16bit_slices": f"{int(s.info.sell_narrow_slices)}/{int(s.info.sell_slices)}",
+                   "sell_tune_ms": [round(v, 4) for v in s.info.sell_tune_ms],
                    "ms_per_step_profiled": round(mixed["ms_profiled"], 3)},
         "fp64": {"value": n / (fp64["ms"] * 1e-3), "ms_per_step": fp64["ms"],
                  "iterations": fp64["iterations"][-1], "true_rel_residual": fp64["true_rel_residual"],
@@ -182,17 +212,185 @@ def run(args):
         "precond_apply": precond,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(xyz, tets, wl, kappa, b, args)
+        out["cpu_baseline"] = cpu_baseline(xyz, tets, wl, kappa, args)
     return out
 
 
-def cpu_baseline(xyz, tets, wl, kappa, b, args):
-    """The CPU oracle (single-threaded FP64 C) on the same system: one CG solve
-    to the same tolerance from u = 0, its setup excluded from the timing."""
+def batched_bytes(cat, n, nnz, s, nr, fmt):
+    """Algorithmic bytes of one launch of a block kernel over nr columns
+    (block vectors [n][nr]; matrix, index and vector bytes counted once)."""
+    idx, meta = fmt
+    mat = (s + idx) * nnz + meta
+    if cat == "pk_sweep":      # Z_in (gather), RHS, Z_out; dinv
+        return mat + 3 * s * n * nr + s * n
+    if cat == "pk_last":       # Z_in, RHS (FP64), Z_out (FP64); dinv
+        return mat + s * n * nr + 16 * n * nr + s * n
+    if cat == "pk_first":      # R (FP64), dinv, Z, (FP32 copy of R)
+        return 8 * n * nr + s * n + s * n * nr + (s * n * nr if s == 4 else 0)
+    if cat == "pk_resid":      # RHS, Z (gather), RES
+        return mat + 3 * s * n * nr
+    if cat == "cg_spmv":       # FP64 operator, P (gather), Q
+        return (8 + idx) * nnz + meta + 16 * n * nr
+    return None
+
+
+def run_batched(args):
+    import numpy as np
+    import torch
+
+    import paper_1204_2586_amd as aux
+    import workloads as W
+
+    wl = WORKLOADS[args.workload]
+    nrhs = wl["nrhs"]
+    xyz, tets = W.kuhn_mesh(wl["n"], jitter=wl["jitter"], seed=wl["seed"])
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    s = aux.Solver(xyz, tets, wl["k"], None, precision="mixed", device=dev)
+    setup_s = time.time() - t0
+    t0 = time.time()
+    B = s.load_many(W.fourier_fields(range(nrhs)), nrhs, threads=args.threads)
+    load_s = time.time() - t0
+    F = torch.tensor(B, dtype=torch.float64, device=dev)
+    n, nnz = s.n, int(s.info.nnz_A)
+
+    def timed(mode):
+        s.set_precision(mode)
+        for _ in range(args.warmup):
+            s.solve_batched(F, tol=args.tol)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            U, infos = s.solve_batched(F, tol=args.tol)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / args.steps
+        res = torch.stack([torch.linalg.norm(F[:, c] - s.matvec(U[:, c].contiguous())) / torch.linalg.norm(F[:, c])
+                           for c in range(nrhs)])
+        s.profile(True)
+        s.solve_batched(F, tol=args.tol)
+        prof = s.profile_read()
+        s.profile(False)
+        return dict(ms=ms, its=[i.iterations for i in infos], true_res=float(res.max()), prof=prof, U=U)
+
+    mixed = timed("mixed")
+    fp64 = timed("fp64")
+    # the same sources one at a time (mixed), for the lock-step gain
+    s.set_precision("mixed")
+    u = torch.zeros(n, dtype=torch.float64, device=dev)
+    cols = [F[:, c].contiguous() for c in range(nrhs)]
+    s.solve(cols[0], tol=args.tol, out=u)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    single_its = []
+    for c in range(nrhs):
+        _, info = s.solve(cols[c], tol=args.tol, out=u)
+        single_its.append(info.iterations)
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - t) * 1e3
+    diff = float(torch.linalg.norm(mixed["U"] - fp64["U"]) / torch.linalg.norm(fp64["U"]))
+
+    nr = 8
+    while nr < nrhs:
+        nr *= 2
+    kernels = {}
+    for cat, (cnt, tot) in mixed["prof"].items():
+        ab = batched_bytes(cat, n, nnz, 4, nr, index_bytes_per_entry(s.info))
+        if cat == "pk_resid" and s.info.nnz_restrict > 0:    # fused restricted residual, block vectors
+            ab = (4 + 4) * s.info.nnz_restrict + 8 * s.info.n_H + (2 * n + s.info.n_H) * 4 * nr
+        if cnt and ab:
+            avg_ms = tot / cnt
+            kernels[cat] = dict(launches=cnt, total_ms=round(tot, 3), avg_us=round(avg_ms * 1e3, 2), bytes=ab,
+                                gbs=round(ab / (avg_ms * 1e-3) / 1e9, 1))
+    dom = max(kernels, key=lambda c: kernels[c]["total_ms"])
+    kd = kernels[dom]
+    cnt, tot = mixed["prof"]["apply"]
+    out = {
+        "metric": METRIC,
+        "value": nrhs * n / (mixed["ms"] * 1e-3),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 CG / f32 preconditioner",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "order": wl["k"], "cubes_per_side": wl["n"], "nrhs": nrhs,
+                   "n_h": n, "nnz_A": nnz, "tol": args.tol, "iterations_max": max(mixed["its"]),
+                   "iterations_min": min(mixed["its"]), "true_rel_residual_max": mixed["true_res"],
+                   "setup_s": round(setup_s, 2), "load_s": round(load_s, 1), "sell_window": int(s.info.sell_window),
+                   "sell_16bit_slices": f"{int(s.info.sell_narrow_slices)}/{int(s.info.sell_slices)}"},
+        "fp64": {"value": nrhs * n / (fp64["ms"] * 1e-3), "ms_per_step": fp64["ms"],
+                 "iterations_max": max(fp64["its"]), "true_rel_residual_max": fp64["true_res"],
+                 "mixed_vs_fp64_rel_diff": diff, "speedup_mixed_over_fp64": fp64["ms"] / mixed["ms"]},
+        "single_rhs_sequential": {"ms_for_all": single_ms, "value": nrhs * n / (single_ms * 1e-3),
+                                  "iterations_max": max(single_its),
+                                  "speedup_batched_over_sequential": single_ms / mixed["ms"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": kd["bytes"], "avg_us": kd["avg_us"]},
+        "kernels_mixed": kernels,
+        "precond_apply_us": {"mixed": tot / max(cnt, 1) * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_single(xyz, tets, wl, args)
+    return out
+
+
+def calibrate_copy(nbytes=1 << 30, reps=3):
+    """Plain device copies of a known size: what a hardware byte counter
+    reads for them scales the counters of the solver's kernels."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps,
+            "copy_gbs": 2 * nbytes / dt / 1e9}
+
+
+def cpu_baseline_single(xyz, tets, wl, args):
+    """The CPU oracle on one of the batched sources (column 0): one FP64 CG
+    solve at full size; the oracle's own setup and load vector are not timed."""
+    import numpy as np
+
     import oracle
+    import workloads as W
+    P = oracle.Problem(xyz, tets, wl["k"], None).setup_amg()
+    src = W.fourier_fields([0])
+
+    def f(p):                                # evaluated in slices to bound memory
+        out = np.empty(p.shape[0])
+        for i in range(0, p.shape[0], 1 << 22):
+            out[i:i + (1 << 22)] = src(p[i:i + (1 << 22)])[0]
+        return out
+
+    b = P.load(f)
+    t0 = time.perf_counter()
+    x, it, rr, st = P.pcg(b, tol=args.tol)
+    dt = time.perf_counter() - t0
+    return {"value": P.n / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 CG solve of source 0 of {args.workload} (n_h={P.n}) to {args.tol:g}, "
+                      f"{it} iterations, {dt:.1f} s; the 32-source batch would take {32 * dt:.0f} s"}
+
+
+def cpu_baseline(xyz, tets, wl, kappa, args):
+    """The CPU oracle (single-threaded FP64 C) on the same system: one CG solve
+    to the same tolerance from u = 0; its setup and its own load vector are
+    not timed."""
+    import oracle
+    import workloads as W
     t0 = time.time()
     P = oracle.Problem(xyz, tets, wl["k"], kappa).setup_amg()
     setup = time.time() - t0
+    b = P.load(W.manufactured_f)
     t0 = time.perf_counter()
     x, it, rr, st = P.pcg(b, tol=args.tol)
     dt = time.perf_counter() - t0
@@ -211,12 +409,19 @@ def main():
     ap.add_argument("--operator", default="assembled", choices=["assembled", "matfree"],
                     help="P^k products inside the preconditioner: sliced-ELL A_h or the MFMA element operator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--threads", type=int, default=16, help="host threads for the load vectors of the batch")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run plain 1 GiB device-to-device copies (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
                                    "(the multi-GPU decomposition is described, not built)"}))
         sys.exit(2)
-    print(json.dumps(run(args)), flush=True)
+    if args.calibrate_copy:
+        print(json.dumps(calibrate_copy()), flush=True)
+        return
+    fn = run_batched if "nrhs" in WORKLOADS[args.workload] else run
+    print(json.dumps(fn(args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -87,6 +87,16 @@ typedef struct aux_options {
                                 of inner products: two handles agree bitwise only if
                                 they use the same window (aux_info.sell_window) */
     int graph;               /* 1: replay each CG iteration as a captured HIP graph (1) */
+    int sell_index16;        /* 1 (default): A_h's column indices may be stored as 16-bit offsets
+                                from a base per group of 64 entries, in every 64-row slice whose
+                                groups each span less than 2^16 (with sell_window 0 the setup
+                                times the layout with and without and keeps the faster);
+                                0: 32-bit columns.  Results are identical either way */
+    int fuse_cycle;          /* 1 (default): evaluate the V-cycle with composite level operators
+                                (two passes per level: b' = P^T (I - A D^-1) b and
+                                y = (2 D^-1 - D^-1 A D^-1) b + (P - D^-1 A P) e) and the
+                                restricted residual as I_R r - (I_R A_h) z; the same linear
+                                operator B as the step-by-step cycle (0), up to rounding */
 } aux_options;
 
 typedef struct aux_device {
@@ -111,6 +121,18 @@ typedef struct aux_info {
     int64_t sell_window;     /* length-sorting window of the device A_h layout in use */
     int64_t level_nnz_P[32]; /* entries of the interpolation P_l from level l+1 to level l
                                 (0 on the coarsest level) */
+    int64_t sell_slices;     /* 64-row slices of the device A_h */
+    int64_t sell_narrow_slices; /* of which store 16-bit column offsets */
+    int64_t sell_index_bytes; /* bytes of the column stream one product reads: 2 per stored
+                                entry of a 16-bit slice plus 4 per slot base, 4 per stored
+                                entry of a 32-bit slice */
+    int64_t nnz_restrict;    /* entries of the fused restriction [I_R, -I_R A_h] (0 if not fused) */
+    int64_t level_nnz_down[32]; /* entries of the fused down operator of level l */
+    int64_t level_nnz_up[32];   /* entries of the fused up operator of level l */
+    double sell_tune_ms[4];  /* autotuner's time (one FP64 plus one FP32 product, ms) of the
+                                candidate layouts: global sort with 16-bit offsets, global
+                                sort 32-bit, 4096-row windows 16-bit, windows 32-bit; 0 for a
+                                candidate not timed */
 } aux_info;
 
 typedef struct aux_solve_info {

@@ -47,7 +47,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_int), ("theta", ctypes.c_double), ("coarse_max", ctypes.c_int),
                 ("max_levels", ctypes.c_int), ("pmis_seed", ctypes.c_uint64), ("precision", ctypes.c_int),
                 ("maxit", ctypes.c_int), ("host_only", ctypes.c_int), ("op", ctypes.c_int),
-                ("sell_window", ctypes.c_int), ("graph", ctypes.c_int)]
+                ("sell_window", ctypes.c_int), ("graph", ctypes.c_int),
+                ("sell_index16", ctypes.c_int), ("fuse_cycle", ctypes.c_int)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -66,7 +67,10 @@ class _Info(ctypes.Structure):
                 ("amg_complexity", ctypes.c_double), ("level_rows", ctypes.c_int64 * 32),
                 ("level_nnz", ctypes.c_int64 * 32), ("setup_seconds", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("stored_A", ctypes.c_int64), ("sell_window", ctypes.c_int64),
-                ("level_nnz_P", ctypes.c_int64 * 32)]
+                ("level_nnz_P", ctypes.c_int64 * 32), ("sell_slices", ctypes.c_int64),
+                ("sell_narrow_slices", ctypes.c_int64), ("sell_index_bytes", ctypes.c_int64),
+                ("nnz_restrict", ctypes.c_int64), ("level_nnz_down", ctypes.c_int64 * 32),
+                ("level_nnz_up", ctypes.c_int64 * 32), ("sell_tune_ms", ctypes.c_double * 4)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -155,7 +159,8 @@ class Solver:
     def __init__(self, xyz, tets, order: int, kappa=None, *, nu: int = 2, theta: float = 0.8,
                  coarse_max: int = 100, max_levels: int = 25, seed: int = 0, precision: str = "fp64",
                  maxit: int = 1000, host_only: bool = False, device=None, use_torch_allocator: bool = True,
-                 operator: str = "assembled", sell_window: int = 0, graph: bool = True):
+                 operator: str = "assembled", sell_window: int = 0, graph: bool = True, sell_index16: bool = True,
+                 fuse_cycle: bool = True):
         lib = load_library()
         self._h = ctypes.c_void_p()
         self.order = order
@@ -171,6 +176,8 @@ class Solver:
         opt.op = _OPS[operator]
         opt.sell_window = sell_window
         opt.graph = int(graph)
+        opt.sell_index16 = int(sell_index16)
+        opt.fuse_cycle = int(fuse_cycle)
         kap = None
         if kappa is not None:
             self._kappa = np.ascontiguousarray(kappa, dtype=np.float64)
@@ -263,6 +270,37 @@ class Solver:
             fq = np.ascontiguousarray(f(self.qpoints(t0, t1)), dtype=np.float64)
             _check(load_library().aux_load_accumulate(self._h, t0, t1, _np_ptr(fq), _np_ptr(b)))
         return b
+
+    def load_many(self, f, ncols: int, chunk: int = 65536, threads: int = 8) -> np.ndarray:
+        """Load vectors of ncols sources at once: f(points[npts, 3]) returns
+        [ncols, npts].  Returns a host [n_h, ncols] array.  Each chunk of
+        tets is split into `threads` tet ranges whose sources are evaluated
+        in parallel; the accumulation then runs in parallel over columns
+        (numpy and the library release the GIL)."""
+        from concurrent.futures import ThreadPoolExecutor
+        lib = load_library()
+        threads = max(1, threads)
+        B = np.zeros((ncols, self.n))
+
+        def evaluate(rng):
+            ta, tb = rng
+            F = np.ascontiguousarray(f(self.qpoints(ta, tb)), dtype=np.float64)
+            if F.shape[0] != ncols:
+                raise ValueError(f"f returned {F.shape[0]} sources, expected {ncols}")
+            return ta, tb, F
+
+        with ThreadPoolExecutor(threads) as ex:
+            for t0 in range(0, self.n_tets, chunk):
+                t1 = min(self.n_tets, t0 + chunk)
+                cuts = np.linspace(t0, t1, threads + 1).astype(int)
+                parts = list(ex.map(evaluate, [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]))
+
+                def accumulate(c):
+                    for ta, tb, F in parts:
+                        _check(lib.aux_load_accumulate(self._h, ta, tb, _np_ptr(F[c]), _np_ptr(B[c])))
+
+                list(ex.map(accumulate, range(ncols)))
+        return np.ascontiguousarray(B.T)
 
     def export_csr(self, which: str, level: int = 0):
         import scipy.sparse as sp

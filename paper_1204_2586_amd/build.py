@@ -10,7 +10,7 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libauxprec.so")
 
-HOST_SOURCES = ["host/fem.cpp", "host/amg.cpp", "host/formats.cpp"]
+HOST_SOURCES = ["host/fem.cpp", "host/amg.cpp", "host/formats.cpp", "host/fuse.cpp"]
 HIP_SOURCES = ["hip/kernels.hip", "hip/batched.hip", "hip/mfree.hip", "hip/solver.hip"]
 ARCH = os.environ.get("AUXPREC_ARCH", "gfx950")
 

@@ -50,19 +50,64 @@ __device__ void write_col_partials(double *partials, double v)
 
 // ------------------------------------------------------------------ SELL
 
-// entries of one P^k row (internal row r: slice r/64, lane r%64)
-template <typename T, typename XF>
-__device__ __forceinline__ T bsell_row(const DevSellView &A, int row, XF x)
+// One block per 64-row slice.  The slice's values and decoded columns are
+// staged in LDS in chunks of kChunk slots (coalesced, once per block), then
+// every (row, column) pair of the slice is accumulated by the lane that owns
+// it: kBlock / NR rows per pass, kSlice / (kBlock / NR) passes.  Blocks never
+// share a slice, so no two XCDs fetch the same matrix lines.
+constexpr int kChunk = 32;
+
+__device__ __forceinline__ int sell_col_at(const DevSellView &A, int slice, int e0, int mode, int e)
 {
-    const T *__restrict__ val = (const T *)A.val;
-    const int *__restrict__ col = A.col;
-    const int sl = row >> 6, lane = row & 63;
-    const int e1 = A.slice_off[sl + 1];
-    T s = T(0);
-#pragma unroll 4
-    for (int e = A.slice_off[sl] + lane; e < e1; e += kSlice) s += val[e] * x(col[e]);
-    return s;
+    return mode == 0 ? A.base[e / kSlice] + (int)A.off[e] : A.wide[~mode + (e - e0)];
 }
+
+template <typename T, int NR, typename XL, typename BODY>
+__device__ __forceinline__ void bsell_slices(const DevSellView &A, XL xload, BODY body)
+{
+    constexpr int RP = kBlock / NR, NP = kSlice / RP;
+    __shared__ T vs[kChunk * kSlice];
+    __shared__ int cs[kChunk * kSlice];
+    const T *__restrict__ val = (const T *)A.val;
+    const int c = threadIdx.x % NR, rl0 = threadIdx.x / NR;
+    for (int sl = blockIdx.x; sl < A.nslices; sl += gridDim.x) {
+        const int e0 = A.slice_off[sl], width = (A.slice_off[sl + 1] - e0) / kSlice;
+        const int mode = A.mode[sl];
+        T acc[NP];
+#pragma unroll
+        for (int p = 0; p < NP; p++) acc[p] = T(0);
+        for (int j0 = 0; j0 < width; j0 += kChunk) {
+            const int jn = min(kChunk, width - j0);
+            __syncthreads();
+            for (int k = threadIdx.x; k < jn * kSlice; k += kBlock) {
+                const int e = e0 + j0 * kSlice + k;
+                vs[k] = val[e];
+                cs[k] = sell_col_at(A, sl, e0, mode, e);
+            }
+            __syncthreads();
+            // the NP rows of a lane are independent: their gathers are in
+            // flight together
+            for (int jj = 0; jj < jn; jj++) {
+                T xv[NP], vv[NP];
+#pragma unroll
+                for (int p = 0; p < NP; p++) {
+                    const int k = jj * kSlice + p * RP + rl0;
+                    vv[p] = vs[k];
+                    xv[p] = xload(cs[k], c);
+                }
+#pragma unroll
+                for (int p = 0; p < NP; p++) acc[p] += vv[p] * xv[p];
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < NP; p++) {
+            const int row = sl * kSlice + p * RP + rl0;
+            if (row < A.n) body(row, c, acc[p]);
+        }
+    }
+}
+
+inline int bsell_grid(const DevSellView &A) { return grid_cap(A.nslices); }
 
 template <typename T, int NR>
 __global__ __launch_bounds__(kBlock) void kb_jacobi0(int n, const T *__restrict__ dinv, const double *__restrict__ R,
@@ -86,14 +131,12 @@ __global__ __launch_bounds__(kBlock) void kb_sweep(DevSellView A, const T *__res
 {
     if (stop_all(all_done)) return;
     double acc = 0.0;
-    FOR_BROWS(NR, A.n)
-    {
-        T s = bsell_row<T>(A, row, [&](int j) { return Zin[(size_t)j * NR + c_]; });
-        size_t o = (size_t)row * NR + c_;
+    bsell_slices<T, NR>(A, [&](int j, int c) { return Zin[(size_t)j * NR + c]; }, [&](int row, int c, T s) {
+        size_t o = (size_t)row * NR + c;
         T zi = Zin[o] + dinv[row] * ((T)RHS[o] - s);
         Zout[o] = (TZ)zi;
         if (DOT) acc += Rdot[o] * (double)(TZ)zi;
-    }
+    });
     if (DOT) write_col_partials<NR>(partials, acc);
 }
 
@@ -102,12 +145,10 @@ __global__ __launch_bounds__(kBlock) void kb_resid(DevSellView A, const T *__res
                                                    T *__restrict__ Res, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    FOR_BROWS(NR, A.n)
-    {
-        T s = bsell_row<T>(A, row, [&](int j) { return Z[(size_t)j * NR + c_]; });
-        size_t o = (size_t)row * NR + c_;
+    bsell_slices<T, NR>(A, [&](int j, int c) { return Z[(size_t)j * NR + c]; }, [&](int row, int c, T s) {
+        size_t o = (size_t)row * NR + c;
         Res[o] = RHS[o] - s;
-    }
+    });
 }
 
 template <int NR, bool DOT, bool RESID>
@@ -117,71 +158,74 @@ __global__ __launch_bounds__(kBlock) void kb_spmv64(DevSellView A, const double 
 {
     if (stop_all(all_done)) return;
     double acc = 0.0;
-    FOR_BROWS(NR, A.n)
-    {
-        double s = bsell_row<double>(A, row, [&](int j) { return X[(size_t)j * NR + c_]; });
-        size_t o = (size_t)row * NR + c_;
+    bsell_slices<double, NR>(A, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int row, int c, double s) {
+        size_t o = (size_t)row * NR + c;
         if (RESID) {
             Y[o] = F[o] - s;
         } else {
             Y[o] = s;
             if (DOT) acc += X[o] * s;
         }
-    }
+    });
     if (DOT) write_col_partials<NR>(partials, acc);
 }
 
-// ------------------------------------------------------------------- CSR
+// ------------------------------------------------------- AMG levels, transfers
+// Row-permuted sliced ELL: internal row r of M is row perm[r] of the
+// operator; columns are not renumbered.
 
-template <typename T, int NR, int MODE>   // MODE 0: y = Mx, 1: y += Mx
-__global__ __launch_bounds__(kBlock) void kb_csr_matvec(int n, const int *__restrict__ ptr, const int *__restrict__ col,
-                                                        const T *__restrict__ val, const T *__restrict__ X,
-                                                        T *__restrict__ Y, const int *all_done)
+template <typename T, int NR, int MODE>   // MODE 0: Y = M X, 1: Y += M X
+__global__ __launch_bounds__(kBlock) void kb_lmatvec(DevSellView M, const int *__restrict__ perm,
+                                                     const T *__restrict__ X, T *__restrict__ Y, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    FOR_BROWS(NR, n)
-    {
-        T s = T(0);
-        for (int e = ptr[row]; e < ptr[row + 1]; e++) s += val[e] * X[(size_t)col[e] * NR + c_];
-        size_t o = (size_t)row * NR + c_;
-        Y[o] = MODE ? Y[o] + s : s;
-    }
+    bsell_slices<T, NR>(M, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
+        size_t o = (size_t)perm[r] * NR + c;
+        if (MODE) Y[o] += s;
+        else Y[o] = s;
+    });
 }
 
+// Y = M [X1; X2] (columns below split index X1, the others X2)
 template <typename T, int NR>
-__global__ __launch_bounds__(kBlock) void kb_csr_vpre(int n, const int *__restrict__ ptr, const int *__restrict__ col,
-                                                      const T *__restrict__ val, const T *__restrict__ dinv,
-                                                      const T *__restrict__ B, T *__restrict__ X, T *__restrict__ R,
-                                                      const int *all_done)
+__global__ __launch_bounds__(kBlock) void kb_lmatvec2(DevSellView M, const int *__restrict__ perm,
+                                                      const T *__restrict__ X1, const T *__restrict__ X2, int split,
+                                                      T *__restrict__ Y, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    FOR_BROWS(NR, n)
-    {
-        T s = T(0);
-        for (int e = ptr[row]; e < ptr[row + 1]; e++) {
-            int j = col[e];
-            s += val[e] * (dinv[j] * B[(size_t)j * NR + c_]);
-        }
-        size_t o = (size_t)row * NR + c_;
-        X[o] = dinv[row] * B[o];
-        R[o] = B[o] - s;
-    }
+    bsell_slices<T, NR>(
+        M, [&](int j, int c) { return j < split ? X1[(size_t)j * NR + c] : X2[(size_t)(j - split) * NR + c]; },
+        [&](int r, int c, T s) { Y[(size_t)perm[r] * NR + c] = s; });
 }
 
+// X = D^-1 B, R = B - A X: the product gathers D^-1 B directly
 template <typename T, int NR>
-__global__ __launch_bounds__(kBlock) void kb_csr_sweep(int n, const int *__restrict__ ptr, const int *__restrict__ col,
-                                                       const T *__restrict__ val, const T *__restrict__ dinv,
-                                                       const T *__restrict__ B, const T *__restrict__ X,
-                                                       T *__restrict__ Y, const int *all_done)
+__global__ __launch_bounds__(kBlock) void kb_lvpre(DevSellView A, const int *__restrict__ perm,
+                                                   const T *__restrict__ dinv, const T *__restrict__ B,
+                                                   T *__restrict__ X, T *__restrict__ R, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    FOR_BROWS(NR, n)
-    {
-        T s = T(0);
-        for (int e = ptr[row]; e < ptr[row + 1]; e++) s += val[e] * X[(size_t)col[e] * NR + c_];
-        size_t o = (size_t)row * NR + c_;
-        Y[o] = X[o] + dinv[row] * (B[o] - s);
-    }
+    bsell_slices<T, NR>(A, [&](int j, int c) { return dinv[j] * B[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
+        const int i = perm[r];
+        size_t o = (size_t)i * NR + c;
+        T b = B[o];
+        X[o] = dinv[i] * b;
+        R[o] = b - s;
+    });
+}
+
+// Y = X + D^-1 (B - A X)
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void kb_lsweep(DevSellView A, const int *__restrict__ perm,
+                                                    const T *__restrict__ dinv, const T *__restrict__ B,
+                                                    const T *__restrict__ X, T *__restrict__ Y, const int *all_done)
+{
+    if (stop_all(all_done)) return;
+    bsell_slices<T, NR>(A, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
+        const int i = perm[r];
+        size_t o = (size_t)i * NR + c;
+        Y[o] = X[o] + dinv[i] * (B[o] - s);
+    });
 }
 
 // X = Ainv B for the dense coarsest inverse (rows spread over the grid)
@@ -193,6 +237,7 @@ __global__ __launch_bounds__(kBlock) void kb_dense(int n, const T *__restrict__ 
     FOR_BROWS(NR, n)
     {
         T s = T(0);
+#pragma unroll 4
         for (int j = 0; j < n; j++) s += Ainv[(size_t)row * n + j] * B[(size_t)j * NR + c_];
         X[(size_t)row * NR + c_] = s;
     }
@@ -214,23 +259,34 @@ __global__ __launch_bounds__(kBlock) void kb_dot(int n, const double *__restrict
 }
 
 // sum the per-column partials and update the per-column CG state
+constexpr int kFinishBlock = 1024;
+
 template <int NR>
-__global__ __launch_bounds__(kBlock) void kb_finish(const double *__restrict__ partials, int nparts, int mode,
-                                                    double *out, BCgState st)
+__global__ __launch_bounds__(kFinishBlock) void kb_finish(const double *__restrict__ partials, int nparts, int mode,
+                                                          double *out, BCgState st)
 {
     if (mode != FIN_PLAIN && *st.all_done) return;
-    __shared__ double red[kBlock];
-    const int c = threadIdx.x % NR;
-    double s = 0.0;
-    for (int b = threadIdx.x / NR; b < nparts; b += kBlock / NR) s += partials[(size_t)b * NR + c];
-    red[threadIdx.x] = s;
+    __shared__ double red[kFinishBlock];
+    constexpr int G = kFinishBlock / NR;           // partial rows summed side by side
+    const int c = threadIdx.x % NR, g = threadIdx.x / NR;
+    // four independent accumulators keep several loads in flight
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = g;
+    for (; b + 3 * G < nparts; b += 4 * G) {
+        s0 += partials[(size_t)b * NR + c];
+        s1 += partials[(size_t)(b + G) * NR + c];
+        s2 += partials[(size_t)(b + 2 * G) * NR + c];
+        s3 += partials[(size_t)(b + 3 * G) * NR + c];
+    }
+    for (; b < nparts; b += G) s0 += partials[(size_t)b * NR + c];
+    red[threadIdx.x] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     __shared__ int active_left;
     if (threadIdx.x == 0) active_left = 0;
     __syncthreads();
     if (threadIdx.x < NR) {
         double t = 0.0;
-        for (int i = threadIdx.x; i < kBlock; i += NR) t += red[i];
+        for (int i = threadIdx.x; i < kFinishBlock; i += NR) t += red[i];
         const int k = *st.k;
         if (mode == FIN_PLAIN) {
             out[c] = t;
@@ -366,7 +422,7 @@ template <typename T, typename TR, typename TZ>
 int bsell_sweep(hipStream_t s, int nr, const DevSellView &A, const T *dinv, const TR *RHS, const T *Zin, TZ *Zout,
                 const double *Rdot, double *partials, const int *all_done)
 {
-    int g = brows_grid(A.n, nr);
+    int g = bsell_grid(A);
     if (partials) {
         NR_SWITCH(nr, hipLaunchKernelGGL((kb_sweep<T, TR, TZ, NR, true>), dim3(g), dim3(kBlock), 0, s, A, dinv, RHS,
                                          Zin, Zout, Rdot, partials, all_done));
@@ -380,7 +436,7 @@ int bsell_sweep(hipStream_t s, int nr, const DevSellView &A, const T *dinv, cons
 template <typename T>
 int bsell_resid(hipStream_t s, int nr, const DevSellView &A, const T *RHS, const T *Z, T *Res, const int *all_done)
 {
-    int g = brows_grid(A.n, nr);
+    int g = bsell_grid(A);
     NR_SWITCH(nr, hipLaunchKernelGGL((kb_resid<T, NR>), dim3(g), dim3(kBlock), 0, s, A, RHS, Z, Res, all_done));
     return g;
 }
@@ -388,7 +444,7 @@ int bsell_resid(hipStream_t s, int nr, const DevSellView &A, const T *RHS, const
 int bsell_spmv64(hipStream_t s, int nr, const DevSellView &A, const double *X, double *Y, double *partials,
                  const int *all_done)
 {
-    int g = brows_grid(A.n, nr);
+    int g = bsell_grid(A);
     if (partials) {
         NR_SWITCH(nr, hipLaunchKernelGGL((kb_spmv64<NR, true, false>), dim3(g), dim3(kBlock), 0, s, A, X, Y,
                                          (const double *)nullptr, partials, all_done));
@@ -401,41 +457,51 @@ int bsell_spmv64(hipStream_t s, int nr, const DevSellView &A, const double *X, d
 
 int bsell_residual64(hipStream_t s, int nr, const DevSellView &A, const double *F, const double *U, double *R)
 {
-    int g = brows_grid(A.n, nr);
+    int g = bsell_grid(A);
     NR_SWITCH(nr, hipLaunchKernelGGL((kb_spmv64<NR, false, true>), dim3(g), dim3(kBlock), 0, s, A, U, R, F,
                                      (double *)nullptr, (const int *)nullptr));
     return g;
 }
 
 template <typename T>
-void bcsr_matvec(hipStream_t s, int nr, const DevCsrView &M, const T *X, T *Y, bool add, const int *all_done)
+void blevel_matvec(hipStream_t s, int nr, const DevSellView &M, const int *perm, const T *X, T *Y, bool add,
+                   const int *all_done)
 {
-    int g = brows_grid(M.n, nr);
+    int g = bsell_grid(M);
     if (add) {
-        NR_SWITCH(nr, hipLaunchKernelGGL((kb_csr_matvec<T, NR, 1>), dim3(g), dim3(kBlock), 0, s, M.n, M.ptr, M.col,
-                                         (const T *)M.val, X, Y, all_done));
+        NR_SWITCH(nr, hipLaunchKernelGGL((kb_lmatvec<T, NR, 1>), dim3(g), dim3(kBlock), 0, s, M, perm, X, Y, all_done));
     } else {
-        NR_SWITCH(nr, hipLaunchKernelGGL((kb_csr_matvec<T, NR, 0>), dim3(g), dim3(kBlock), 0, s, M.n, M.ptr, M.col,
-                                         (const T *)M.val, X, Y, all_done));
+        NR_SWITCH(nr, hipLaunchKernelGGL((kb_lmatvec<T, NR, 0>), dim3(g), dim3(kBlock), 0, s, M, perm, X, Y, all_done));
     }
 }
 
 template <typename T>
-void bcsr_vpre(hipStream_t s, int nr, const DevCsrView &A, const T *dinv, const T *B, T *X, T *R, const int *all_done)
+void blevel_matvec2(hipStream_t s, int nr, const DevSellView &M, const int *perm, const T *X1, const T *X2, int split,
+                    T *Y, const int *all_done)
 {
-    int g = brows_grid(A.n, nr);
-    NR_SWITCH(nr, hipLaunchKernelGGL((kb_csr_vpre<T, NR>), dim3(g), dim3(kBlock), 0, s, A.n, A.ptr, A.col,
-                                     (const T *)A.val, dinv, B, X, R, all_done));
+    int g = bsell_grid(M);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_lmatvec2<T, NR>), dim3(g), dim3(kBlock), 0, s, M, perm, X1, X2, split, Y,
+                                     all_done));
 }
 
 template <typename T>
-void bcsr_sweep(hipStream_t s, int nr, const DevCsrView &A, const T *dinv, const T *B, const T *X, T *Y,
-                const int *all_done)
+void blevel_vpre(hipStream_t s, int nr, const DevSellView &A, const int *perm, const T *dinv, const T *B, T *X, T *R,
+                 const int *all_done)
 {
-    int g = brows_grid(A.n, nr);
-    NR_SWITCH(nr, hipLaunchKernelGGL((kb_csr_sweep<T, NR>), dim3(g), dim3(kBlock), 0, s, A.n, A.ptr, A.col,
-                                     (const T *)A.val, dinv, B, X, Y, all_done));
+    int g = bsell_grid(A);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_lvpre<T, NR>), dim3(g), dim3(kBlock), 0, s, A, perm, dinv, B, X, R, all_done));
 }
+
+template <typename T>
+void blevel_sweep(hipStream_t s, int nr, const DevSellView &A, const int *perm, const T *dinv, const T *B, const T *X,
+                  T *Y, const int *all_done)
+{
+    int g = bsell_grid(A);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_lsweep<T, NR>), dim3(g), dim3(kBlock), 0, s, A, perm, dinv, B, X, Y, all_done));
+}
+
+
+
 
 template <typename T>
 void bdense(hipStream_t s, int nr, int n, const T *Ainv, const T *B, T *X, const int *all_done)
@@ -454,8 +520,8 @@ int bvec_dot(hipStream_t s, int nr, int n, const double *a, const double *b, dou
 void bfinish(hipStream_t s, int nr, const double *partials, int nparts, FinishMode mode, double *out,
              const BCgState &st)
 {
-    NR_SWITCH(nr, hipLaunchKernelGGL((kb_finish<NR>), dim3(1), dim3(kBlock), 0, s, partials, nparts, (int)mode, out,
-                                     st));
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_finish<NR>), dim3(1), dim3(kFinishBlock), 0, s, partials, nparts, (int)mode,
+                                     out, st));
 }
 
 void bcg_init(hipStream_t s, int nr, const BCgState &st, double tol2, const double *ff, const double *rr0)
@@ -494,10 +560,14 @@ void bscatter(hipStream_t s, int nr, int n, int ld, const int *perm, const doubl
     template int bsell_sweep<T, T, T>(hipStream_t, int, const DevSellView &, const T *, const T *, const T *, T *, \
                                       const double *, double *, const int *);                                      \
     template int bsell_resid<T>(hipStream_t, int, const DevSellView &, const T *, const T *, T *, const int *);    \
-    template void bcsr_matvec<T>(hipStream_t, int, const DevCsrView &, const T *, T *, bool, const int *);         \
-    template void bcsr_vpre<T>(hipStream_t, int, const DevCsrView &, const T *, const T *, T *, T *, const int *); \
-    template void bcsr_sweep<T>(hipStream_t, int, const DevCsrView &, const T *, const T *, const T *, T *,        \
-                                const int *);                                                                      \
+    template void blevel_matvec<T>(hipStream_t, int, const DevSellView &, const int *, const T *, T *, bool,      \
+                                   const int *);                                                                   \
+    template void blevel_matvec2<T>(hipStream_t, int, const DevSellView &, const int *, const T *, const T *, int, \
+                                    T *, const int *);                                                             \
+    template void blevel_vpre<T>(hipStream_t, int, const DevSellView &, const int *, const T *, const T *, T *,     \
+                                 T *, const int *);                                                                \
+    template void blevel_sweep<T>(hipStream_t, int, const DevSellView &, const int *, const T *, const T *,         \
+                                  const T *, T *, const int *);                                                    \
     template void bdense<T>(hipStream_t, int, int, const T *, const T *, T *, const int *);
 
 BINST(double)

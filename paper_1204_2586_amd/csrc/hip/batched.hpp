@@ -27,13 +27,23 @@ int bsell_spmv64(hipStream_t s, int nr, const DevSellView &A, const double *X, d
                  const int *all_done);
 int bsell_residual64(hipStream_t s, int nr, const DevSellView &A, const double *F, const double *U, double *R);
 
+// AMG levels and transfers as row-permuted sliced ELL (row r of M is row
+// perm[r] of the operator, columns not renumbered)
 template <typename T>
-void bcsr_matvec(hipStream_t s, int nr, const DevCsrView &M, const T *X, T *Y, bool add, const int *all_done);
+void blevel_matvec(hipStream_t s, int nr, const DevSellView &M, const int *perm, const T *X, T *Y, bool add,
+                   const int *all_done);
+// Y = M [X1; X2] (columns below split index X1, the others X2)
 template <typename T>
-void bcsr_vpre(hipStream_t s, int nr, const DevCsrView &A, const T *dinv, const T *B, T *X, T *R, const int *all_done);
+void blevel_matvec2(hipStream_t s, int nr, const DevSellView &M, const int *perm, const T *X1, const T *X2, int split,
+                    T *Y, const int *all_done);
+// X = D^-1 B, R = B - A X
 template <typename T>
-void bcsr_sweep(hipStream_t s, int nr, const DevCsrView &A, const T *dinv, const T *B, const T *X, T *Y,
-                const int *all_done);
+void blevel_vpre(hipStream_t s, int nr, const DevSellView &A, const int *perm, const T *dinv, const T *B, T *X, T *R,
+                 const int *all_done);
+// Y = X + D^-1 (B - A X)
+template <typename T>
+void blevel_sweep(hipStream_t s, int nr, const DevSellView &A, const int *perm, const T *dinv, const T *B, const T *X,
+                  T *Y, const int *all_done);
 template <typename T>
 void bdense(hipStream_t s, int nr, int n, const T *Ainv, const T *B, T *X, const int *all_done);
 

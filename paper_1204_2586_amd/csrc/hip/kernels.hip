@@ -54,7 +54,11 @@ inline int grid_cap(long long need)
 
 // ------------------------------------------------------------------ SELL
 
-// one wavefront per 64-row slice, one lane per row
+// One wavefront per 64-row slice, one lane per row; consecutive slices go to
+// consecutive workgroups, which the dispatcher spreads round-robin over the
+// dies, so at any moment all dies gather from the same neighbourhood of the
+// vector and share it through the last-level cache (giving each die its own
+// contiguous range of slices measured twice as slow).
 #define FOR_SLICES(A)                                                                                      \
     const int lane_ = threadIdx.x & 63;                                                                    \
     for (int sl_ = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6); sl_ < (A).nslices;                \
@@ -64,11 +68,29 @@ template <typename T, typename XF>
 __device__ __forceinline__ T sell_row(const DevSellView &A, int slice, int lane, XF x)
 {
     const T *__restrict__ val = (const T *)A.val;
-    const int *__restrict__ col = A.col;
-    const int e1 = A.slice_off[slice + 1];
+    slice = __builtin_amdgcn_readfirstlane(slice);      // one slice per wavefront
+    const int e0 = A.slice_off[slice], e1 = A.slice_off[slice + 1];
+    const int mode = A.mode[slice];
     T s = T(0);
+    if (mode == 0) {
+        // 16-bit offsets: the bases of 64 slots come in one vector load and
+        // are broadcast from their lanes
+        const int t0 = e0 / kSlice, width = (e1 - e0) / kSlice;
+        for (int jc = 0; jc < width; jc += kSlice) {
+            const int jn = min(kSlice, width - jc);
+            const int bl = lane < jn ? A.base[t0 + jc + lane] : 0;
+            const int eb = e0 + jc * kSlice + lane;
 #pragma unroll 4
-    for (int e = A.slice_off[slice] + lane; e < e1; e += kSlice) s += val[e] * x(col[e]);
+            for (int jj = 0; jj < jn; jj++) {
+                const int e = eb + jj * kSlice;
+                s += val[e] * x(__builtin_amdgcn_readlane(bl, jj) + (int)A.off[e]);
+            }
+        }
+    } else {
+        const int *__restrict__ w = A.wide + ~mode;
+#pragma unroll 4
+        for (int k = lane; k < e1 - e0; k += kSlice) s += val[e0 + k] * x(w[k]);
+    }
     return s;
 }
 
@@ -181,6 +203,23 @@ __global__ __launch_bounds__(kBlock) void k_csr_matvec(int n, const int *__restr
     }
 }
 
+// y = M [x1; x2]: columns below `split` index x1, the others x2
+template <typename T, int LPR>
+__global__ __launch_bounds__(kBlock) void k_csr_matvec2(int n, const int *__restrict__ ptr, const int *__restrict__ col,
+                                                        const T *__restrict__ val, const T *__restrict__ x1,
+                                                        const T *__restrict__ x2, int split, T *__restrict__ y,
+                                                        const int *done)
+{
+    if (stop(done)) return;
+    FOR_ROWS(LPR, n)
+    {
+        if (row < n) {
+            T s = csr_row<LPR>(ptr, col, val, row, sub_, [&](int j) { return j < split ? x1[j] : x2[j - split]; });
+            if (sub_ == 0) y[row] = s;
+        }
+    }
+}
+
 template <typename T, int LPR>
 __global__ __launch_bounds__(kBlock) void k_csr_vpre(int n, const int *__restrict__ ptr, const int *__restrict__ col,
                                                      const T *__restrict__ val, const T *__restrict__ dinv,
@@ -222,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const T *__restric
 {
     if (stop(done)) return;
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-    for (int i = w; i < n; i += kBlock / 64) {
+    for (int i = blockIdx.x * (kBlock / 64) + w; i < n; i += gridDim.x * (kBlock / 64)) {
         T s = T(0);
         for (int j = l; j < n; j += 64) s += Ainv[(size_t)i * n + j] * b[j];
         s = group_sum<64>(s);
@@ -439,6 +478,13 @@ void csr_matvec_add(hipStream_t s, const DevCsrView &M, const T *e, T *x, const 
 }
 
 template <typename T>
+void csr_matvec2(hipStream_t s, const DevCsrView &M, const T *x1, const T *x2, int split, T *y, const int *done)
+{
+    LPR_SWITCH(M.lpr, hipLaunchKernelGGL((k_csr_matvec2<T, L>), dim3(rows_grid(M.n, L)), dim3(kBlock), 0, s, M.n,
+                                         M.ptr, M.col, (const T *)M.val, x1, x2, split, y, done));
+}
+
+template <typename T>
 void csr_vpre(hipStream_t s, const DevCsrView &A, const T *dinv, const T *b, T *x, T *r, const int *done)
 {
     LPR_SWITCH(A.lpr, hipLaunchKernelGGL((k_csr_vpre<T, L>), dim3(rows_grid(A.n, L)), dim3(kBlock), 0, s, A.n, A.ptr,
@@ -455,7 +501,9 @@ void csr_sweep(hipStream_t s, const DevCsrView &A, const T *dinv, const T *b, co
 template <typename T>
 void dense_gemv(hipStream_t s, int n, const T *Ainv, const T *b, T *x, const int *done)
 {
-    hipLaunchKernelGGL(k_dense_gemv<T>, dim3(1), dim3(kBlock), 0, s, n, Ainv, b, x, done);
+    // one wavefront per row
+    hipLaunchKernelGGL(k_dense_gemv<T>, dim3(grid_cap((n + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, s, n,
+                       Ainv, b, x, done);
 }
 
 int vec_dot(hipStream_t s, int n, const double *a, const double *b, double *partials)
@@ -512,6 +560,7 @@ void kappa_grad(hipStream_t s, int nt, int nloc, const int *tet_dof, const doubl
                                      const double *, double *, const int *);                                 \
     template void csr_matvec<T>(hipStream_t, const DevCsrView &, const T *, T *, const int *);               \
     template void csr_matvec_add<T>(hipStream_t, const DevCsrView &, const T *, T *, const int *);           \
+    template void csr_matvec2<T>(hipStream_t, const DevCsrView &, const T *, const T *, int, T *, const int *); \
     template void csr_vpre<T>(hipStream_t, const DevCsrView &, const T *, const T *, T *, T *, const int *); \
     template void csr_sweep<T>(hipStream_t, const DevCsrView &, const T *, const T *, const T *, T *,        \
                                const int *);                                                                 \

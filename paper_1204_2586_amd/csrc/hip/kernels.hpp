@@ -36,8 +36,14 @@ struct DevCsrView {
 struct DevSellView {
     int n;               // rows
     int nslices;
+    int max_width;       // longest slice, in slots of 64 entries
     const int *slice_off;  // [nslices+1] first entry of each slice (multiple of 64)
-    const int *col;      // [slice_off[nslices]], padding entries point at column 0
+    // Columns.  mode[s] == 0: entry e of slot t = e / 64 has column
+    // base[t] + off[e]; mode[s] = ~w < 0: column wide[w + e - slice_off[s]].
+    const int *mode;
+    const int *base;
+    const unsigned short *off;
+    const int *wide;
     const void *val;     // double or float, padding entries are 0
 };
 
@@ -77,6 +83,9 @@ template <typename T>
 void csr_matvec(hipStream_t s, const DevCsrView &M, const T *x, T *y, const int *done);
 template <typename T>
 void csr_matvec_add(hipStream_t s, const DevCsrView &M, const T *e, T *x, const int *done);
+// y = M [x1; x2] (columns below split index x1, the rest x2)
+template <typename T>
+void csr_matvec2(hipStream_t s, const DevCsrView &M, const T *x1, const T *x2, int split, T *y, const int *done);
 // x = D^{-1} b, r = b - A x (V-cycle presmoothing from zero fused with the residual)
 template <typename T>
 void csr_vpre(hipStream_t s, const DevCsrView &A, const T *dinv, const T *b, T *x, T *r, const int *done);

@@ -55,15 +55,17 @@ struct DevOp {   // CSR with values in both precisions
 };
 
 struct DevSell {
-    int n = 0, nslices = 0;
-    int64_t stored = 0;
-    int *slice_off = nullptr, *col = nullptr;
+    int n = 0, nslices = 0, max_width = 0;
+    int64_t stored = 0, narrow_slices = 0, index_bytes = 0;
+    int *slice_off = nullptr, *mode = nullptr, *base = nullptr, *wide = nullptr;
+    unsigned short *off = nullptr;
     double *v64 = nullptr;
     float *v32 = nullptr;
     template <typename T>
     DevSellView view() const
     {
-        return {n, nslices, slice_off, col, std::is_same<T, float>::value ? (const void *)v32 : (const void *)v64};
+        return {n, nslices, max_width, slice_off, mode, base, off, wide,
+                std::is_same<T, float>::value ? (const void *)v32 : (const void *)v64};
     }
 };
 
@@ -97,6 +99,7 @@ struct aux_handle {
     std::vector<void *> allocs;
     std::vector<size_t> alloc_size;
     int sell_window_used = 0;        // layout window the setup chose
+    double tune_ms[4] = {0, 0, 0, 0};
 
     DevSell A;                       // A_h, internal order
     int *perm = nullptr;             // internal -> external dof
@@ -105,9 +108,13 @@ struct aux_handle {
     float *dinv32 = nullptr;
     struct Lev {
         DevOp A, P, R;
+        DevOp down, up;              // composite operators (fuse_cycle)
         double *dinv64 = nullptr;
         float *dinv32 = nullptr;
     };
+    DevOp RF;                        // composite restriction [I_R, -I_R A_h] (fuse_cycle)
+    std::vector<FusedLevel> fused_host;
+    Csr RF_host;
     std::vector<Lev> lev;
     double *cinv64 = nullptr;
     float *cinv32 = nullptr;
@@ -292,6 +299,14 @@ struct aux_handle {
         for (size_t i = 0; i < v.size(); i++) o[i] = 1.0 / v[i];
         return o;
     }
+    // CSR with both precisions uploaded at once (composite operators)
+    DevOp upload_op2(const Csr &c)
+    {
+        DevOp d = upload_op(c);
+        d.v32 = upload(to_f32(c.val));
+        return d;
+    }
+
     DevOp upload_op(const Csr &c)
     {
         DevOp d;
@@ -313,29 +328,56 @@ struct aux_handle {
         DevSell d;
         d.n = sl.n;
         d.nslices = sl.nslices;
+        d.max_width = sl.max_width;
         d.stored = (int64_t)sl.val.size();
+        for (int s = 0; s < sl.nslices; s++) {
+            const int64_t entries = sl.slice_off[s + 1] - sl.slice_off[s];
+            d.narrow_slices += sl.mode[s] == 0;
+            d.index_bytes += sl.mode[s] == 0 ? 2 * entries + 4 * (entries / sl.slice) : 4 * entries;
+        }
         d.slice_off = upload(sl.slice_off);
-        d.col = upload(sl.col);
+        d.mode = upload(sl.mode);
+        d.base = upload(sl.base);
+        d.off = upload(sl.off);
+        d.wide = upload(sl.wide);
         d.v64 = upload(sl.val);
         return d;
     }
 
-    // mean time of a few FP64 products with a device layout (the autotuner's measure)
-    double time_sell(const DevSell &d)
+    void free_sell(DevSell &d)
     {
-        double *x = dnew<double>(disc.ndof), *y = dnew<double>(disc.ndof);
-        HIPCHECK(hipMemsetAsync(x, 0, (size_t)disc.ndof * sizeof(double), stream));
+        for (void *b : {(void *)d.slice_off, (void *)d.mode, (void *)d.base, (void *)d.off, (void *)d.wide,
+                        (void *)d.v64, (void *)d.v32})
+            dfree(b);
+        d = DevSell();
+    }
+
+    // mean time of a few products with a device layout, FP64 plus FP32 (the
+    // autotuner's measure: the CG product and the preconditioner's passes)
+    double time_sell(DevSell &d, const Sell &sl)
+    {
+        const int n = disc.ndof;
+        d.v32 = upload(to_f32(sl.val));
+        double *x = dnew<double>(n), *y = dnew<double>(n);
+        float *xf = dnew<float>(n), *yf = dnew<float>(n), *bf = dnew<float>(n);
+        HIPCHECK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), stream));
+        HIPCHECK(hipMemsetAsync(xf, 0, (size_t)n * sizeof(float), stream));
+        HIPCHECK(hipMemsetAsync(bf, 0, (size_t)n * sizeof(float), stream));
         hipEvent_t a = take_event(), b = take_event();
         sell_spmv64(stream, d.view<double>(), x, y, nullptr, nullptr);
+        sell_resid<float>(stream, d.view<float>(), bf, xf, yf, nullptr);
         HIPCHECK(hipEventRecord(a, stream));
-        for (int i = 0; i < 5; i++) sell_spmv64(stream, d.view<double>(), x, y, nullptr, nullptr);
+        for (int i = 0; i < 5; i++) {
+            sell_spmv64(stream, d.view<double>(), x, y, nullptr, nullptr);
+            sell_resid<float>(stream, d.view<float>(), bf, xf, yf, nullptr);
+        }
         HIPCHECK(hipEventRecord(b, stream));
         HIPCHECK(hipEventSynchronize(b));
         float ms = 0.f;
         HIPCHECK(hipEventElapsedTime(&ms, a, b));
         ev_used -= 2;
-        dfree(x);
-        dfree(y);
+        for (void *p : {(void *)x, (void *)y, (void *)xf, (void *)yf, (void *)bf, (void *)d.v32}) dfree(p);
+        d.v32 = nullptr;
         return ms / 5.0;
     }
 
@@ -347,29 +389,29 @@ struct aux_handle {
         // type so a slice gathers nearly contiguous entries; and a 4096-row
         // window, which keeps locality on unstructured meshes), times a few
         // products with each on the device and keeps the faster.
+        std::vector<std::pair<int, bool>> cands;
         std::vector<int> windows;
         if (opt.sell_window > 0) windows.push_back(opt.sell_window);
         else windows = {std::max(disc.ndof, 1), kSellWindow};
-        double best = 1e300;
         for (int win : windows) {
+            if (opt.sell_index16) cands.push_back({win, true});
+            if (!opt.sell_index16 || opt.sell_window <= 0) cands.push_back({win, false});
+        }
+        double best = 1e300;
+        for (auto [win, idx16] : cands) {
             Sell cand;
-            build_sell(disc.A, kSlice, win, cand);
+            build_sell(disc.A, kSlice, win, idx16, cand);
             DevSell d = upload_sell(cand);
-            double ms = windows.size() > 1 ? time_sell(d) : 0.0;
+            double ms = cands.size() > 1 ? time_sell(d, cand) : 0.0;
+            tune_ms[(win == kSellWindow ? 2 : 0) + (idx16 ? 0 : 1)] = ms;
             if (ms < best) {
-                if (A.v64) {
-                    dfree(A.slice_off);
-                    dfree(A.col);
-                    dfree(A.v64);
-                }
+                if (A.v64) free_sell(A);
                 best = ms;
                 A = d;
                 sell = std::move(cand);
                 sell_window_used = win;
             } else {
-                dfree(d.slice_off);
-                dfree(d.col);
-                dfree(d.v64);
+                free_sell(d);
             }
         }
         perm = upload(sell.perm);
@@ -391,6 +433,16 @@ struct aux_handle {
             }
         }
         cinv64 = upload(hier.coarse_inv);
+        if (opt.fuse_cycle && !hier.levels.empty()) {
+            fused_host.resize(hier.levels.size());
+            for (size_t l = 0; l + 1 < hier.levels.size(); l++) {
+                fused_host[l] = fuse_level(hier.levels[l]);
+                lev[l].down = upload_op2(fused_host[l].down);
+                lev[l].up = upload_op2(fused_host[l].up);
+            }
+            RF_host = fuse_restriction(IRi, permute_symmetric(disc.A, sell.perm, sell.iperm));
+            RF = upload_op2(RF_host);
+        }
         int n = disc.ndof;
         r = dnew<double>(n);
         z = dnew<double>(n);
@@ -527,6 +579,13 @@ struct aux_handle {
             dense_gemv<T>(s, L.A.n, cinv<T>(), w.b[l], w.x[l], done);
             return w.x[l];
         }
+        if (opt.fuse_cycle) {
+            // b' = P^T (I - A D^-1) b; recurse; y = (2 D^-1 - D^-1 A D^-1) b + (P - D^-1 A P) e
+            csr_matvec<T>(s, L.down.view<T>(), w.b[l], w.b[l + 1], done);
+            const T *e = vcycle<T>(l + 1, done);
+            csr_matvec2<T>(s, L.up.view<T>(), w.b[l], e, L.A.n, w.y[l], done);
+            return w.y[l];
+        }
         DevCsrView Av = L.A.view<T>();
         csr_vpre<T>(s, Av, ldinv<T>(l), w.b[l], w.x[l], w.r[l], done);
         csr_matvec<T>(s, L.R.view<T>(), w.r[l], w.b[l + 1], done);
@@ -563,10 +622,17 @@ struct aux_handle {
         // Step 1: r_H = I_R (r - A z), one AMG V-cycle; Step 2: z += I_P e_H
         if (!lev.empty()) {
             pk = pbeg(AUX_PROF_PK_RESID);
-            pk_resid<T>(rT, zc, w.res, done);
-            pend(pk);
-            pk = pbeg(AUX_PROF_COARSE);
-            csr_matvec<T>(s, IR.view<T>(), w.res, w.b[0], done);
+            if (opt.fuse_cycle) {
+                // r_H = I_R r - (I_R A_h) z in one pass
+                csr_matvec2<T>(s, RF.view<T>(), rT, zc, disc.ndof, w.b[0], done);
+                pend(pk);
+                pk = pbeg(AUX_PROF_COARSE);
+            } else {
+                pk_resid<T>(rT, zc, w.res, done);
+                pend(pk);
+                pk = pbeg(AUX_PROF_COARSE);
+                csr_matvec<T>(s, IR.view<T>(), w.res, w.b[0], done);
+            }
             const T *e0 = vcycle<T>(0, done);
             csr_matvec_add<T>(s, IP.view<T>(), e0, zc, done);
             pend(pk);
@@ -618,19 +684,44 @@ struct aux_handle {
         cg_direction(s, n, z, p, st);
     }
 
-    // cached graph of one CG iteration; recaptured when anything its kernels
-    // depend on by value changes (precision, operator, iteration limit)
+    // Cached graph of one CG iteration; recaptured when anything its kernels
+    // depend on by value changes (precision, operator, iteration limit, block
+    // width).  Capture runs on a private stream of default priority.
+    struct GraphCache {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        int key[4] = {-1, -1, -1, -1};
+        void drop()
+        {
+            if (exec) hipGraphExecDestroy(exec);
+            if (graph) hipGraphDestroy(graph);
+            exec = nullptr;
+            graph = nullptr;
+        }
+    };
     hipStream_t cap_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    int graph_key[3] = {-1, -1, -1};
+    GraphCache g_single, g_batch;
+
+    template <typename Body>
+    hipGraphExec_t captured(GraphCache &gc, const int key[4], Body body)
+    {
+        if (gc.exec && std::equal(key, key + 4, gc.key)) return gc.exec;
+        gc.drop();
+        if (!cap_stream) HIPCHECK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        hipStream_t keep = stream;
+        stream = cap_stream;
+        HIPCHECK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+        body();
+        hipError_t e = hipStreamEndCapture(cap_stream, &gc.graph);
+        stream = keep;
+        HIPCHECK(e);
+        HIPCHECK(hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0));
+        std::copy(key, key + 4, gc.key);
+        return gc.exec;
+    }
 
     hipGraphExec_t iteration_graph(const CgState &st)
     {
-        const int key[3] = {opt.precision, opt.op, st.maxit};
-        if (graph_exec && std::equal(key, key + 3, graph_key)) return graph_exec;
-        drop_graph();
-        if (!cap_stream) HIPCHECK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
         // make every buffer the iteration touches exist before capture
         if (use_mf()) ensure_mf();
         if (opt.precision == AUX_MIXED) {
@@ -639,24 +730,14 @@ struct aux_handle {
         } else {
             work<double>();
         }
-        hipStream_t keep = stream;
-        stream = cap_stream;
-        HIPCHECK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-        cg_iteration(st);
-        hipError_t e = hipStreamEndCapture(cap_stream, &graph);
-        stream = keep;
-        HIPCHECK(e);
-        HIPCHECK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
-        std::copy(key, key + 3, graph_key);
-        return graph_exec;
+        const int key[4] = {opt.precision, opt.op, st.maxit, 1};
+        return captured(g_single, key, [&]() { cg_iteration(st); });
     }
 
     void drop_graph()
     {
-        if (graph_exec) hipGraphExecDestroy(graph_exec);
-        if (graph) hipGraphDestroy(graph);
-        graph_exec = nullptr;
-        graph = nullptr;
+        g_single.drop();
+        g_batch.drop();
     }
 
     int pcg(const double *f, double *u, double tol, int maxit, aux_solve_info *info)
@@ -743,7 +824,7 @@ struct aux_handle {
     {
         int n = disc.ndof;
         if (bt.nr != nr) {
-            bt = Batch();
+            release_batch();
             bt.nr = nr;
             size_t blk = (size_t)n * nr;
             bt.X = dnew<double>(blk);
@@ -761,9 +842,32 @@ struct aux_handle {
             host_bufs.push_back(bt.host);
         }
         if (maxit + 2 > bt.hist_cap) {
+            dfree(bt.hist);
             bt.hist_cap = maxit + 2;
             bt.hist = dnew<double>((size_t)3 * bt.hist_cap * nr);
         }
+    }
+
+    // device buffers of the current block width (the pinned status copy
+    // stays with the handle)
+    void release_batch()
+    {
+        g_batch.drop();
+        for (double *b : {bt.X, bt.R, bt.Z, bt.P, bt.Q, bt.F, bt.partials, bt.ff, bt.rr0, bt.tol2ff, bt.hist})
+            dfree(b);
+        dfree(bt.ist);
+        release_work(bt.w64);
+        release_work(bt.w32);
+        bt = Batch();
+    }
+
+    template <typename T>
+    void release_work(Work<T> &w)
+    {
+        for (T *b : {w.za, w.zb, w.res, w.rT}) dfree(b);
+        for (auto *v : {&w.b, &w.x, &w.r, &w.y})
+            for (T *b : *v) dfree(b);
+        w = Work<T>();
     }
 
     template <typename T>
@@ -797,6 +901,56 @@ struct aux_handle {
                 bt.hist + (size_t)2 * bt.hist_cap * nr, bt.tol2ff, maxit};
     }
 
+    // Operators of the V-cycle and the transfers for the block kernels:
+    // row-permuted sliced ELL (rows sorted by length within 4096-row windows,
+    // results written back to the original rows), FP64 and FP32 values.
+    struct BOp {
+        DevSell m;
+        int *perm = nullptr;
+        template <typename T>
+        DevSellView view() const { return m.view<T>(); }
+    };
+    std::vector<BOp> bA, bP, bR;
+    BOp bIP, bIR, bRF;
+    bool bops_ready = false;
+
+    BOp upload_bop(const Csr &op)
+    {
+        Sell sl;
+        build_sell(op, kSlice, kSellWindow, false, sl, false);
+        BOp b;
+        b.m = upload_sell(sl);
+        b.m.v32 = upload(to_f32(sl.val));
+        b.perm = upload(sl.perm);
+        return b;
+    }
+
+    void ensure_bops()
+    {
+        if (bops_ready) return;
+        const size_t L = hier.levels.size();
+        bA.resize(L);
+        bP.resize(L);
+        bR.resize(L);
+        // The block kernels are bound by the bytes gathered per entry
+        // (NR words each), where the composite level operators' scattered
+        // coarse-row gathers cost more than the two extra passes save; they
+        // keep the four-pass cycle and fuse only the restricted residual.
+        for (size_t l = 0; l < L; l++) {
+            const AmgLevel &hl = hier.levels[l];
+            if (l + 1 == L) continue;                 // coarsest: dense inverse
+            bA[l] = upload_bop(hl.A);
+            bP[l] = upload_bop(hl.P);
+            bR[l] = upload_bop(hl.R);
+        }
+        if (L) {
+            bIP = upload_bop(IPi);
+            if (opt.fuse_cycle) bRF = upload_bop(RF_host);
+            else bIR = upload_bop(IRi);
+        }
+        bops_ready = true;
+    }
+
     template <typename T>
     const T *bvcycle(size_t l, const int *all_done)
     {
@@ -808,12 +962,12 @@ struct aux_handle {
             bdense<T>(s, nr, L.A.n, cinv<T>(), w.b[l], w.x[l], all_done);
             return w.x[l];
         }
-        DevCsrView Av = L.A.view<T>();
-        bcsr_vpre<T>(s, nr, Av, ldinv<T>(l), w.b[l], w.x[l], w.r[l], all_done);
-        bcsr_matvec<T>(s, nr, L.R.view<T>(), w.r[l], w.b[l + 1], false, all_done);
+        const BOp &A_ = bA[l], &P_ = bP[l], &R_ = bR[l];
+        blevel_vpre<T>(s, nr, A_.view<T>(), A_.perm, ldinv<T>(l), w.b[l], w.x[l], w.r[l], all_done);
+        blevel_matvec<T>(s, nr, R_.view<T>(), R_.perm, w.r[l], w.b[l + 1], false, all_done);
         const T *e = bvcycle<T>(l + 1, all_done);
-        bcsr_matvec<T>(s, nr, L.P.view<T>(), e, w.x[l], true, all_done);
-        bcsr_sweep<T>(s, nr, Av, ldinv<T>(l), w.b[l], w.x[l], w.y[l], all_done);
+        blevel_matvec<T>(s, nr, P_.view<T>(), P_.perm, e, w.x[l], true, all_done);
+        blevel_sweep<T>(s, nr, A_.view<T>(), A_.perm, ldinv<T>(l), w.b[l], w.x[l], w.y[l], all_done);
         return w.y[l];
     }
 
@@ -830,34 +984,71 @@ struct aux_handle {
         T *rTbuf = std::is_same<T, float>::value ? w.rT : nullptr;
         T *zc = w.za, *zn = w.zb;
         int pb = pbeg(AUX_PROF_APPLY);
+        int pk = pbeg(AUX_PROF_PK_FIRST);
         bjacobi0<T>(s, nr, disc.ndof, d, Rin, zc, rTbuf, all_done);
+        pend(pk);
         const T *rT = rTbuf ? (const T *)rTbuf : (const T *)(const void *)Rin;
         for (int k = 1; k < nu; k++) {
+            pk = pbeg(AUX_PROF_PK_SWEEP);
             bsell_sweep<T, T, T>(s, nr, Av, d, rT, zc, zn, nullptr, nullptr, all_done);
+            pend(pk);
             std::swap(zc, zn);
         }
         if (!lev.empty()) {
-            bsell_resid<T>(s, nr, Av, rT, zc, w.res, all_done);
-            bcsr_matvec<T>(s, nr, IR.view<T>(), w.res, w.b[0], false, all_done);
+            pk = pbeg(AUX_PROF_PK_RESID);
+            if (opt.fuse_cycle) {
+                blevel_matvec2<T>(s, nr, bRF.view<T>(), bRF.perm, rT, zc, disc.ndof, w.b[0], all_done);
+                pend(pk);
+                pk = pbeg(AUX_PROF_COARSE);
+            } else {
+                bsell_resid<T>(s, nr, Av, rT, zc, w.res, all_done);
+                pend(pk);
+                pk = pbeg(AUX_PROF_COARSE);
+                blevel_matvec<T>(s, nr, bIR.view<T>(), bIR.perm, w.res, w.b[0], false, all_done);
+            }
             const T *e0 = bvcycle<T>(0, all_done);
-            bcsr_matvec<T>(s, nr, IP.view<T>(), e0, zc, true, all_done);
+            blevel_matvec<T>(s, nr, bIP.view<T>(), bIP.perm, e0, zc, true, all_done);
+            pend(pk);
         }
         for (int k = 1; k < nu; k++) {
+            pk = pbeg(AUX_PROF_PK_SWEEP);
             bsell_sweep<T, T, T>(s, nr, Av, d, rT, zc, zn, nullptr, nullptr, all_done);
+            pend(pk);
             std::swap(zc, zn);
         }
+        pk = pbeg(AUX_PROF_PK_LAST);
         int g = bsell_sweep<T, double, double>(s, nr, Av, d, Rin, zc, Zout, Rin, rz_partials, all_done);
+        pend(pk);
         pend(pb);
         return g;
     }
 
     int bapply(const double *Rin, double *Zout, double *rz_partials, const int *all_done)
     {
+        ensure_bops();
         if (opt.precision == AUX_MIXED) {
             ensure_fp32();
             return bapply_B<float>(Rin, Zout, rz_partials, all_done);
         }
         return bapply_B<double>(Rin, Zout, rz_partials, all_done);
+    }
+
+    // one lock-step iteration of every column: Q = A P, alpha, X/R update,
+    // Z = B R, beta, P update (columns that stopped are left unchanged)
+    void bcg_iteration(const BCgState &st)
+    {
+        hipStream_t s = stream;
+        const int nr = bt.nr, n = disc.ndof;
+        DevSellView A64 = A.view<double>();
+        int pk = pbeg(AUX_PROF_CG_SPMV);
+        int g = bsell_spmv64(s, nr, A64, bt.P, bt.Q, bt.partials, st.all_done);
+        pend(pk);
+        bfinish(s, nr, bt.partials, g, FIN_PQ, nullptr, st);
+        g = bcg_update(s, nr, n, bt.X, bt.R, bt.P, bt.Q, st, bt.partials);
+        bfinish(s, nr, bt.partials, g, FIN_RR, nullptr, st);
+        g = bapply(bt.R, bt.Z, bt.partials, st.all_done);
+        bfinish(s, nr, bt.partials, g, FIN_RZ, nullptr, st);
+        bcg_direction(s, nr, n, bt.Z, bt.P, st);
     }
 
     int pcg_batched(const double *Fext, double *Uext, int nrhs, double tol, int maxit, aux_solve_info *infos)
@@ -880,22 +1071,30 @@ struct aux_handle {
         g = bvec_dot(s, nr, n, bt.R, bt.R, bt.partials);
         bfinish(s, nr, bt.partials, g, FIN_PLAIN, bt.rr0, st);
         bcg_init(s, nr, st, tol * tol, bt.ff, bt.rr0);
+        prof_tag = 0;
         g = bapply(bt.R, bt.Z, bt.partials, all_done);
         bfinish(s, nr, bt.partials, g, FIN_RZ, nullptr, st);
         bcg_direction(s, nr, n, bt.Z, bt.P, st);
+        // lock-step iterations, replayed as a HIP graph when not profiling
+        hipGraphExec_t gexec = nullptr;
+        if (opt.graph && !prof_on) {
+            ensure_bops();
+            if (opt.precision == AUX_MIXED) {
+                ensure_fp32();
+                bwork<float>();
+            } else {
+                bwork<double>();
+            }
+            const int key[4] = {opt.precision, 0, maxit, nr};
+            gexec = captured(g_batch, key, [&]() { bcg_iteration(st); });
+        }
         int issued = 0, chunk = 2;
         int *h = bt.host;
         while (true) {
             for (int c = 0; c < chunk && issued < maxit; c++, issued++) {
-                int pk = pbeg(AUX_PROF_CG_SPMV);
-                g = bsell_spmv64(s, nr, A64, bt.P, bt.Q, bt.partials, all_done);
-                pend(pk);
-                bfinish(s, nr, bt.partials, g, FIN_PQ, nullptr, st);
-                g = bcg_update(s, nr, n, bt.X, bt.R, bt.P, bt.Q, st, bt.partials);
-                bfinish(s, nr, bt.partials, g, FIN_RR, nullptr, st);
-                g = bapply(bt.R, bt.Z, bt.partials, all_done);
-                bfinish(s, nr, bt.partials, g, FIN_RZ, nullptr, st);
-                bcg_direction(s, nr, n, bt.Z, bt.P, st);
+                prof_tag = issued + 1;
+                if (gexec) HIPCHECK(hipGraphLaunch(gexec, s));
+                else bcg_iteration(st);
             }
             HIPCHECK(hipMemcpyAsync(h, bt.ist, (2 + 2 * (size_t)nr) * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
@@ -903,7 +1102,10 @@ struct aux_handle {
             chunk = 4;
         }
         bscatter(s, nr, n, nrhs, perm, bt.X, Uext);
-        prof_collect(1 << 30);
+        int last = 0;
+        for (int c = 0; c < nrhs; c++) last = std::max(last, h[2 + c]);
+        prof_tag = -1;
+        prof_collect(last);
         std::vector<double> ff(nr), rr((size_t)bt.hist_cap * nr);
         HIPCHECK(hipMemcpy(ff.data(), bt.ff, nr * sizeof(double), hipMemcpyDeviceToHost));
         HIPCHECK(hipMemcpy(rr.data(), st.rr, rr.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -1034,6 +1236,8 @@ void aux_default_options(aux_options *o)
     o->op = AUX_OP_ASSEMBLED;
     o->sell_window = 0;
     o->graph = 1;
+    o->sell_index16 = 1;
+    o->fuse_cycle = 1;
 }
 
 int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt, const aux_device *dev,
@@ -1162,6 +1366,15 @@ int aux_get_info(const aux_handle *h, aux_info *info)
         info->device_bytes = h->device_bytes;
         info->stored_A = h->A.stored;
         info->sell_window = h->sell_window_used;
+        info->sell_slices = h->A.nslices;
+        info->sell_narrow_slices = h->A.narrow_slices;
+        info->sell_index_bytes = h->A.index_bytes;
+        for (int c = 0; c < 4; c++) info->sell_tune_ms[c] = h->tune_ms[c];
+        info->nnz_restrict = h->RF_host.nnz();
+        for (size_t l = 0; l < h->fused_host.size() && l < 32; l++) {
+            info->level_nnz_down[l] = h->fused_host[l].down.nnz();
+            info->level_nnz_up[l] = h->fused_host[l].up.nnz();
+        }
         return AUX_OK;
     });
 }

@@ -6,8 +6,11 @@
 // consecutive rows longer rows come first (stable): the rows of a slice then
 // have nearly equal lengths.  Consecutive groups of `slice` rows form slices
 // whose entries are stored column-major (entry j of the slice's rows is
-// contiguous), padded to the slice's longest row with zero values pointing at
-// column 0.
+// contiguous), padded to the slice's longest row with zero values.  Each
+// such group of `slice` entries (a slot) stores its columns as 16-bit
+// offsets from a per-slot base when they span less than 2^16, which cuts
+// the index stream from 4 to 2 bytes per entry; other slots keep 32-bit
+// columns in a side array.
 #include <algorithm>
 #include <numeric>
 #include <stdexcept>
@@ -16,7 +19,7 @@
 
 namespace auxp {
 
-void build_sell(const Csr &A, int slice, int window, Sell &out)
+void build_sell(const Csr &A, int slice, int window, bool index16, Sell &out, bool permute_cols)
 {
     const int n = A.n;
     out.n = n;
@@ -46,10 +49,66 @@ void build_sell(const Csr &A, int slice, int window, Sell &out)
         int s = r / slice, lane = r % slice, i = out.perm[r];
         for (int e = A.ptr[i], j = 0; e < A.ptr[i + 1]; e++, j++) {
             size_t pos = (size_t)out.slice_off[s] + (size_t)j * slice + lane;
-            out.col[pos] = out.iperm[A.col[e]];
+            out.col[pos] = permute_cols ? out.iperm[A.col[e]] : A.col[e];
             out.val[pos] = A.val[e];
         }
     }
+    // compressed columns; padding entries (value 0) take the slot's base
+    const size_t nslots = total / (size_t)slice;
+    out.mode.assign(out.nslices, 0);
+    out.base.assign(index16 ? nslots : 0, 0);
+    out.off.assign(index16 ? total : 0, 0);
+    out.wide.clear();
+    out.max_width = 0;
+    for (int s = 0; s < out.nslices; s++) {
+        const int r0 = s * slice, r1 = std::min(n, r0 + slice);
+        const int width = (out.slice_off[s + 1] - out.slice_off[s]) / slice;
+        const size_t e0 = (size_t)out.slice_off[s];
+        out.max_width = std::max(out.max_width, width);
+        bool narrow = index16;
+        for (int j = 0; j < width; j++) {
+            const size_t t = e0 / slice + j, ej = t * slice;
+            int lo = INT32_MAX, hi = INT32_MIN;
+            for (int r = r0; r < r1; r++)
+                if (len(out.perm[r]) > j) {
+                    lo = std::min(lo, out.col[ej + (r - r0)]);
+                    hi = std::max(hi, out.col[ej + (r - r0)]);
+                }
+            if (index16) out.base[t] = lo;
+            if ((int64_t)hi - lo >= 65536) narrow = false;
+            for (int l = 0; l < slice; l++) {
+                const bool valid = r0 + l < r1 && len(out.perm[r0 + l]) > j;
+                if (!valid) out.col[ej + l] = lo;     // padding points at a column of the slot
+                else if (index16 && (int64_t)hi - lo < 65536) out.off[ej + l] = (uint16_t)(out.col[ej + l] - lo);
+            }
+        }
+        if (!narrow) {
+            if (out.wide.size() + (size_t)width * slice > 0x7fffffffu) throw std::invalid_argument("operator too large");
+            out.mode[s] = ~(int)out.wide.size();
+            out.wide.insert(out.wide.end(), out.col.begin() + e0, out.col.begin() + e0 + (size_t)width * slice);
+        }
+    }
+}
+
+Csr permute_symmetric(const Csr &A, const std::vector<int> &perm, const std::vector<int> &iperm)
+{
+    Csr B;
+    B.n = A.n;
+    B.m = A.m;
+    B.ptr.assign((size_t)A.n + 1, 0);
+    std::vector<std::pair<int, double>> row;
+    for (int r = 0; r < A.n; r++) {
+        const int i = perm[r];
+        row.clear();
+        for (int e = A.ptr[i]; e < A.ptr[i + 1]; e++) row.push_back({iperm[A.col[e]], A.val[e]});
+        std::sort(row.begin(), row.end());
+        for (auto &cv : row) {
+            B.col.push_back(cv.first);
+            B.val.push_back(cv.second);
+        }
+        B.ptr[r + 1] = (int)B.col.size();
+    }
+    return B;
 }
 
 Csr permute_rows(const Csr &A, const std::vector<int> &perm)

@@ -81,6 +81,17 @@ void accumulate_load(const Discretization &d, int t0, int t1, const double *fq, 
 
 Csr transpose(const Csr &a);
 
+// Composite operators of the preconditioner (fuse.cpp).  For an AMG level
+// with D = diag(l1):  down = P^T (I - A D^-1)  (n_{l+1} x n_l);
+// up = [2 D^-1 - D^-1 A D^-1,  P - D^-1 A P]  (n_l x (n_l + n_{l+1})), so
+// that one V(1,1) cycle from zero is  b' = down b,  y = up [b; e].
+struct FusedLevel {
+    Csr down, up;
+};
+FusedLevel fuse_level(const AmgLevel &L);
+// [I_R, -I_R A] (n_H x 2 n_h): the restricted residual I_R (r - A z) of [r; z]
+Csr fuse_restriction(const Csr &IR, const Csr &A);
+
 }  // namespace auxp
 
 namespace auxp {
@@ -93,10 +104,27 @@ struct Sell {
     std::vector<int> slice_off;   // [nslices+1]
     std::vector<int> col;         // internal column numbers
     std::vector<double> val;
+    // Column indices as stored on the device.  A slice is narrow when, for
+    // every slot t of it (the t-th group of `slice` consecutive entries), the
+    // columns of the slot span less than 2^16: then entry e has column
+    // base[t] + off[e] and mode[s] = 0.  Otherwise mode[s] = ~w and the
+    // slice's entries have 32-bit columns wide[w + (e - slice_off[s])].
+    std::vector<int> mode;        // [nslices]
+    std::vector<int> base;        // [slice_off[nslices] / slice]
+    std::vector<uint16_t> off;    // [slice_off[nslices]]
+    std::vector<int> wide;        // columns of the wide slices
+    int max_width = 0;            // longest slice, in slots
 };
 
-void build_sell(const Csr &A, int slice, int window, Sell &out);
+// Rows sorted by decreasing length (stably) within windows of `window` rows;
+// index16 = false stores every slice with plain 32-bit columns.  With
+// permute_cols the columns are renumbered like the rows (a square operator
+// acting on vectors in the internal order); otherwise only the rows move
+// (results go to row perm[r]).
+void build_sell(const Csr &A, int slice, int window, bool index16, Sell &out, bool permute_cols = true);
 // rows of A in the order perm (row r of the result is row perm[r] of A)
 Csr permute_rows(const Csr &A, const std::vector<int> &perm);
+// rows and columns renumbered: entry (r, iperm[j]) of the result is a_{perm[r], j}
+Csr permute_symmetric(const Csr &A, const std::vector<int> &perm, const std::vector<int> &iperm);
 
 }  // namespace auxp

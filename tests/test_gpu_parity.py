@@ -231,3 +231,92 @@ def test_graph_replay_matches_eager(precision, operator):
         assert ig.iterations == ie.iterations
         assert torch.equal(ug, ue)
         assert torch.equal(z, e.apply(_t(b)))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_graph_replay_matches_eager(precision):
+    """Lock-step iterations replayed as a HIP graph give bitwise the eager
+    result, also after the block width changes (buffers reallocated, graph
+    recaptured) and changes back."""
+    xyz, tets, kappa = _case(2, 7, jitter=0.2, kappa="rand")
+    kw = dict(device=DEV, precision=precision, sell_window=4096)
+    g = aux.Solver(xyz, tets, 2, kappa, graph=True, **kw)
+    e = aux.Solver(xyz, tets, 2, kappa, graph=False, **kw)
+    orc = oracle.Problem(xyz, tets, 2, kappa).setup_amg()
+    F = np.stack([orc.load(W.fourier_f(r)) for r in range(12)], axis=1)
+    for cols in (5, 12, 5):
+        Fc = _t(np.ascontiguousarray(F[:, :cols]))
+        Ug, ig = g.solve_batched(Fc, tol=1e-9)
+        Ue, ie = e.solve_batched(Fc, tol=1e-9)
+        torch.cuda.synchronize()
+        assert [i.iterations for i in ig] == [i.iterations for i in ie]
+        assert all(i.converged for i in ig)
+        assert torch.equal(Ug, Ue)
+
+
+@pytest.mark.parametrize("window", [0, 4096, 10 ** 9])
+def test_index16_layout_equals_int32(window):
+    """16-bit column offsets (narrow slots) and 32-bit side columns (wide
+    slots) give bitwise the results of plain 32-bit columns."""
+    xyz, tets, kappa = _case(2, 24, jitter=0.2, kappa="rand")     # 103,823 unknowns > 2^16
+    kw = dict(device=DEV, sell_window=window)
+    a = aux.Solver(xyz, tets, 2, kappa, sell_index16=True, **kw)
+    b = aux.Solver(xyz, tets, 2, kappa, sell_index16=False, **kw)
+    if window:
+        assert a.info.sell_window == b.info.sell_window == window
+    else:                                     # autotuned: the same windows for both
+        a = aux.Solver(xyz, tets, 2, kappa, sell_index16=True, device=DEV, sell_window=int(a.info.sell_window))
+        b = aux.Solver(xyz, tets, 2, kappa, sell_index16=False, device=DEV, sell_window=int(a.info.sell_window))
+    if window == 4096:                        # every slice spans less than 2^16 columns
+        assert a.info.sell_narrow_slices == a.info.sell_slices
+    if window == 10 ** 9:                     # global length sort: both kinds of slices
+        assert 0 < a.info.sell_narrow_slices < a.info.sell_slices
+    assert b.info.sell_narrow_slices == 0
+    orc = oracle.Problem(xyz, tets, 2, kappa).setup_amg()
+    f = _t(orc.load(W.manufactured_f))
+    r = _t(W.random_vector(a.n, 5))
+    assert torch.equal(a.matvec(r), b.matvec(r))
+    for prec in ("fp64", "mixed"):
+        a.set_precision(prec)
+        b.set_precision(prec)
+        assert torch.equal(a.apply(r), b.apply(r))
+        ua, ia = a.solve(f, tol=1e-9)
+        ub, ib = b.solve(f, tol=1e-9)
+        assert ia.iterations == ib.iterations and torch.equal(ua, ub)
+    F = torch.stack([f, r], dim=1).contiguous()
+    Ua, _ = a.solve_batched(F, tol=1e-9)
+    Ub, _ = b.solve_batched(F, tol=1e-9)
+    assert torch.equal(Ua, Ub)
+
+
+@pytest.mark.parametrize("k,n,jit,kap", [(2, 10, 0.2, "rand"), (3, 6, 0.0, "grf")])
+def test_fused_cycle_matches_stepwise(k, n, jit, kap):
+    """The composite level operators (two passes per level) and the fused
+    restricted residual give the step-by-step preconditioner up to rounding."""
+    xyz, tets, kappa = _case(k, n, jitter=jit, kappa=kap)
+    kw = dict(device=DEV, sell_window=4096)
+    f_ = aux.Solver(xyz, tets, k, kappa, fuse_cycle=True, **kw)
+    s_ = aux.Solver(xyz, tets, k, kappa, fuse_cycle=False, **kw)
+    assert f_.info.nnz_restrict > 0 and s_.info.nnz_restrict == 0
+    orc = oracle.Problem(xyz, tets, k, kappa).setup_amg()
+    r = W.random_vector(f_.n, 11)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 2e-6)):
+        f_.set_precision(prec)
+        s_.set_precision(prec)
+        zf = f_.apply(_t(r)).cpu().numpy()
+        assert _rel(zf, s_.apply(_t(r)).cpu().numpy()) <= tol
+        assert _rel(zf, orc.apply(r, fp32=(prec == "mixed"))) <= tol
+    b = orc.load(W.manufactured_f)
+    f_.set_precision("fp64")
+    x, it, _, _ = orc.pcg(b, tol=1e-8)
+    u, info = f_.solve(_t(b), tol=0.0, maxit=it, check=False)
+    assert _rel(u.cpu().numpy(), x) <= 1e-10
+    F = np.stack([b, r], axis=1)
+    for prec in ("fp64", "mixed"):
+        f_.set_precision(prec)
+        s_.set_precision(prec)
+        Uf, inf_ = f_.solve_batched(_t(F), tol=1e-9)
+        Us, ins_ = s_.solve_batched(_t(F), tol=1e-9)
+        for j in range(2):
+            assert abs(inf_[j].iterations - ins_[j].iterations) <= 1
+            assert _rel(Uf[:, j].cpu().numpy(), Us[:, j].cpu().numpy()) <= 1e-8

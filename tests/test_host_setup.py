@@ -50,6 +50,16 @@ def test_load_vector(pair):
     assert np.max(np.abs(b1 - b2)) < 1e-13 * np.max(np.abs(b2))
 
 
+def test_load_many_matches_oracle_per_column(pair):
+    lib, orc = pair
+    rs = [0, 5, 9]
+    B = lib.load_many(W.fourier_fields(rs), len(rs), chunk=37, threads=3)
+    assert B.shape == (lib.n, 3)
+    for c, r in enumerate(rs):
+        b = orc.load(W.fourier_f(r))
+        assert np.max(np.abs(B[:, c] - b)) < 1e-13 * np.max(np.abs(b))
+
+
 def test_amg_hierarchy_identical(pair):
     lib, orc = pair
     assert lib.info.levels == orc.nlev and lib.info.ncoarse == orc.ncoarse

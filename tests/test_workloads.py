@@ -47,3 +47,13 @@ def test_sources():
     assert np.array_equal(f0(p), W.fourier_f(0)(p)) and not np.array_equal(f0(p), W.fourier_f(1)(p))
     edge = np.array([[0.0, 0.3, 0.4], [0.2, 1.0, 0.5]])
     assert np.allclose(f0(edge), 0.0)
+
+
+def test_fourier_fields_equal_single_sources():
+    p = np.random.default_rng(1).uniform(size=(2000, 3))
+    rs = [0, 3, 7, 31]
+    F = W.fourier_fields(rs)(p)
+    assert F.shape == (4, 2000)
+    for c, r in enumerate(rs):
+        ref = W.fourier_f(r)(p)
+        assert np.max(np.abs(F[c] - ref)) < 1e-13 * np.max(np.abs(ref))

@@ -146,6 +146,40 @@ def fourier_f(r: int, n_modes: int = 16, kmax: int = 4):
     return f
 
 
+def fourier_fields(rs, n_modes: int = 16, kmax: int = 4):
+    """The sources fourier_f(r) for every r in rs, evaluated together.
+
+    Returns f(p) -> array [len(rs), ...] (one row per source).  Every mode is a product
+    sin(pi k1 x) sin(pi k2 y) sin(pi k3 z) with k in 1..kmax, so all sources
+    are combinations of the same kmax^3 products: those are formed once per
+    call and combined by one matrix product with the [kmax^3, len(rs)]
+    amplitude table (equal to fourier_f up to rounding order).
+    """
+    rs = list(rs)
+    amp = np.zeros((kmax ** 3, len(rs)))
+    for c, r in enumerate(rs):
+        rng = np.random.default_rng(1000 + r)
+        a = rng.normal(size=n_modes)
+        k = rng.integers(1, kmax + 1, size=(n_modes, 3))
+        for m in range(n_modes):
+            amp[((k[m, 0] - 1) * kmax + k[m, 1] - 1) * kmax + k[m, 2] - 1, c] += a[m]
+    used = np.flatnonzero(np.any(amp != 0.0, axis=1))
+
+    def f(p):
+        p = np.asarray(p, dtype=np.float64)
+        flat = p.reshape(-1, 3)
+        tab = [np.sin(np.pi * np.arange(1, kmax + 1)[:, None] * flat[None, :, ax]) for ax in range(3)]
+        prod = np.empty((len(used), flat.shape[0]))
+        for j, idx in enumerate(used):
+            k1, rem = divmod(int(idx), kmax * kmax)
+            k2, k3 = divmod(rem, kmax)
+            np.multiply(tab[0][k1], tab[1][k2], out=prod[j])
+            prod[j] *= tab[2][k3]
+        return (amp[used].T @ prod).reshape((len(rs),) + p.shape[:-1])
+
+    return f
+
+
 def random_vector(n: int, seed: int, dtype=np.float64):
     """Seeded N(0,1) vector (used as a residual to precondition)."""
     return np.random.default_rng(seed).standard_normal(n).astype(dtype)
