@@ -32,6 +32,31 @@ WORKLOADS = {
 }
 
 
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "hbm_traffic_sell_sweep.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1204_2586_amd", "csrc", "hip", "kernels.hip")
+
+
+def measured_traffic(workload, operator, category, precision):
+    """HBM bytes per launch of a kernel category as measured by the
+    FETCH_SIZE and WRITE_SIZE counters (scaled by a plain copy of known
+    size), from the committed summary table; None when the table has no
+    row for this case or the kernel source changed since the counters were
+    taken (its sha1 differs)."""
+    import hashlib
+    import re
+    if not os.path.exists(TRAFFIC_TABLE):
+        return None
+    with open(KERNEL_SOURCE, "rb") as fh:
+        sha = hashlib.sha1(fh.read()).hexdigest()
+    for line in open(TRAFFIC_TABLE):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 6 and cells[:4] == [workload, operator, category, precision]:
+            if cells[4] != sha or not re.fullmatch(r"\d+", cells[5]):
+                return None
+            return int(cells[5])
+    return None
+
+
 def index_bytes_per_entry(info):
     """Column-stream bytes per entry of the device A_h layout (16-bit offsets
     in some slices, 32-bit columns in the others), and the per-slice
@@ -205,7 +230,8 @@ def run(args):
                  "mixed_vs_fp64_rel_diff": diff,
                  "speedup_mixed_over_fp64": fp64["ms"] / mixed["ms"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": kd["gbs"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, args.operator, dom, "mixed"),
                      "bytes_per_launch": kd["bytes"], "avg_us": kd["avg_us"]},
         "kernels_mixed": {c: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
                           for c, d in kernels.items()},
@@ -322,6 +348,7 @@ def run_batched(args):
                    "n_h": n, "nnz_A": nnz, "tol": args.tol, "iterations_max": max(mixed["its"]),
                    "iterations_min": min(mixed["its"]), "true_rel_residual_max": mixed["true_res"],
                    "setup_s": round(setup_s, 2), "load_s": round(load_s, 1), "sell_window": int(s.info.sell_window),
+                   "batch_tile_rows": {"fp32": int(s.info.batch_tile_rows[0]), "fp64": int(s.info.batch_tile_rows[1])},
                    "sell_16bit_slices": f"{int(s.info.sell_narrow_slices)}/{int(s.info.sell_slices)}"},
         "fp64": {"value": nrhs * n / (fp64["ms"] * 1e-3), "ms_per_step": fp64["ms"],
                  "iterations_max": max(fp64["its"]), "true_rel_residual_max": fp64["true_res"],

@@ -82,10 +82,12 @@ typedef struct aux_options {
     int op;                  /* AUX_OP_ASSEMBLED or AUX_OP_MATFREE (AUX_OP_ASSEMBLED) */
     int sell_window;         /* device A_h layout: rows sorted by length within windows of this
                                 many dofs; 0 (default) lets the setup time the candidate
-                                layouts on the device and keep the fastest.  The layout
-                                fixes the internal dof order and so the summation order
-                                of inner products: two handles agree bitwise only if
-                                they use the same window (aux_info.sell_window) */
+                                layouts (and the lanes per row of the large CSR passes) on
+                                the device and keep the fastest.  These choices fix the
+                                internal dof order and the summation order: two handles
+                                agree bitwise only if neither times its choices, i.e. both
+                                are given the same window > 0 (then every choice is
+                                rule-based) */
     int graph;               /* 1: replay each CG iteration as a captured HIP graph (1) */
     int sell_index16;        /* 1 (default): A_h's column indices may be stored as 16-bit offsets
                                 from a base per group of 64 entries, in every 64-row slice whose
@@ -97,6 +99,13 @@ typedef struct aux_options {
                                 y = (2 D^-1 - D^-1 A D^-1) b + (P - D^-1 A P) e) and the
                                 restricted residual as I_R r - (I_R A_h) z; the same linear
                                 operator B as the step-by-step cycle (0), up to rounding */
+    int batch_tiles;         /* block products of A_h in the batched solve: 0 one workgroup per
+                                64-row slice; 2 tiles of 16/32/64 consecutive rows whose
+                                gathered block rows are staged in LDS (the largest that fits);
+                                1 (default) the faster of the two, timed per block width and
+                                precision (slices when sell_window > 0).  The products are
+                                identical; the inner products' partial sums are grouped
+                                differently (results agree to rounding) */
 } aux_options;
 
 typedef struct aux_device {
@@ -129,6 +138,8 @@ typedef struct aux_info {
     int64_t nnz_restrict;    /* entries of the fused restriction [I_R, -I_R A_h] (0 if not fused) */
     int64_t level_nnz_down[32]; /* entries of the fused down operator of level l */
     int64_t level_nnz_up[32];   /* entries of the fused up operator of level l */
+    int32_t batch_tile_rows[2]; /* block products of the last batch width, FP32 and FP64: rows
+                                per LDS tile the batched autotuner chose, 0 = 64-row slices */
     double sell_tune_ms[4];  /* autotuner's time (one FP64 plus one FP32 product, ms) of the
                                 candidate layouts: global sort with 16-bit offsets, global
                                 sort 32-bit, 4096-row windows 16-bit, windows 32-bit; 0 for a
@@ -179,6 +190,11 @@ int aux_get_info(const aux_handle *h, aux_info *info);
 /* Canonical key of each dof: host int32 [n_h][order], the sorted vertex
  * multiset of the node (lexicographically increasing over the dofs). */
 int aux_dof_keys(const aux_handle *h, int32_t *keys);
+
+/* Position of each dof's node (Sec. 2: the nodes of the P^k Lagrange space):
+ * host double [n_h][3], the mean of the vertices of its key, i.e.
+ * sum_p alpha_p v_p / k for the node with barycentric multi-index alpha. */
+int aux_dof_xyz(const aux_handle *h, double *xyz);
 
 /* Load vector f_i = <f, phi_i> (Sec. 2) by a conical-product Gauss-Jacobi
  * rule with (order+2)^3 points per tet.  The caller evaluates f at the points

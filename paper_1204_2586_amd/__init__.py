@@ -48,7 +48,8 @@ class _Options(ctypes.Structure):
                 ("max_levels", ctypes.c_int), ("pmis_seed", ctypes.c_uint64), ("precision", ctypes.c_int),
                 ("maxit", ctypes.c_int), ("host_only", ctypes.c_int), ("op", ctypes.c_int),
                 ("sell_window", ctypes.c_int), ("graph", ctypes.c_int),
-                ("sell_index16", ctypes.c_int), ("fuse_cycle", ctypes.c_int)]
+                ("sell_index16", ctypes.c_int), ("fuse_cycle", ctypes.c_int),
+                ("batch_tiles", ctypes.c_int)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -70,7 +71,8 @@ class _Info(ctypes.Structure):
                 ("level_nnz_P", ctypes.c_int64 * 32), ("sell_slices", ctypes.c_int64),
                 ("sell_narrow_slices", ctypes.c_int64), ("sell_index_bytes", ctypes.c_int64),
                 ("nnz_restrict", ctypes.c_int64), ("level_nnz_down", ctypes.c_int64 * 32),
-                ("level_nnz_up", ctypes.c_int64 * 32), ("sell_tune_ms", ctypes.c_double * 4)]
+                ("level_nnz_up", ctypes.c_int64 * 32), ("batch_tile_rows", ctypes.c_int32 * 2),
+                ("sell_tune_ms", ctypes.c_double * 4)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -116,6 +118,7 @@ def load_library():
         "aux_set_precision": (ctypes.c_int, [vp, ctypes.c_int]),
         "aux_set_operator": (ctypes.c_int, [vp, ctypes.c_int]),
         "aux_get_info": (ctypes.c_int, [vp, P(_Info)]),
+        "aux_dof_xyz": (ctypes.c_int, [vp, vp]),
         "aux_dof_keys": (ctypes.c_int, [vp, vp]),
         "aux_qpoints_per_tet": (ctypes.c_int, [vp]),
         "aux_qpoints": (ctypes.c_int, [vp, i32, i32, vp]),
@@ -160,7 +163,7 @@ class Solver:
                  coarse_max: int = 100, max_levels: int = 25, seed: int = 0, precision: str = "fp64",
                  maxit: int = 1000, host_only: bool = False, device=None, use_torch_allocator: bool = True,
                  operator: str = "assembled", sell_window: int = 0, graph: bool = True, sell_index16: bool = True,
-                 fuse_cycle: bool = True):
+                 fuse_cycle: bool = True, batch_tiles: int = 1):
         lib = load_library()
         self._h = ctypes.c_void_p()
         self.order = order
@@ -178,6 +181,7 @@ class Solver:
         opt.graph = int(graph)
         opt.sell_index16 = int(sell_index16)
         opt.fuse_cycle = int(fuse_cycle)
+        opt.batch_tiles = int(batch_tiles)
         kap = None
         if kappa is not None:
             self._kappa = np.ascontiguousarray(kappa, dtype=np.float64)
@@ -255,6 +259,12 @@ class Solver:
         k = np.zeros((self.n, self.order), dtype=np.int32)
         _check(load_library().aux_dof_keys(self._h, _np_ptr(k)))
         return k
+
+    def dof_xyz(self) -> np.ndarray:
+        """Node position of each dof (host [n_h, 3])."""
+        out = np.zeros((self.n, 3))
+        _check(load_library().aux_dof_xyz(self._h, _np_ptr(out)))
+        return out
 
     def qpoints(self, t0: int, t1: int) -> np.ndarray:
         m = load_library().aux_qpoints_per_tet(self._h)
@@ -383,6 +393,7 @@ class Solver:
         self._sync_stream()
         rc = load_library().pcg_solve_batched(self._h, ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(U.data_ptr()),
                                               nrhs, tol, int(maxit), infos)
+        self.info = self._info()                  # the layout chosen for this block width
         if check:
             _check(rc)
         return U, [SolveInfo(i.iterations, i.status, i.rel_residual, i.seconds) for i in infos]

@@ -34,16 +34,16 @@ inline int grid_cap(long long need)
 
 inline int brows_grid(int n, int NR) { return grid_cap(((long long)n * NR + kBlock - 1) / kBlock); }
 
-// per-column partial sums of a block: partials[blockIdx.x * NR + c]
-template <int NR>
+// per-column partial sums of a block of BS threads: partials[blockIdx.x * NR + c]
+template <int NR, int BS = kBlock>
 __device__ void write_col_partials(double *partials, double v)
 {
-    __shared__ double red[kBlock];
+    __shared__ double red[BS];
     red[threadIdx.x] = v;
     __syncthreads();
     if (threadIdx.x < NR) {
         double s = 0.0;
-        for (int i = threadIdx.x; i < kBlock; i += NR) s += red[i];
+        for (int i = threadIdx.x; i < BS; i += NR) s += red[i];
         partials[(size_t)blockIdx.x * NR + threadIdx.x] = s;
     }
 }
@@ -168,6 +168,115 @@ __global__ __launch_bounds__(kBlock) void kb_spmv64(DevSellView A, const double 
         }
     });
     if (DOT) write_col_partials<NR>(partials, acc);
+}
+
+// ------------------------------------------------------------------ tiles
+// One workgroup per tile of consecutive (original-order) rows: the tile's
+// distinct gathered block rows (NR words each), its values, column
+// positions and row offsets are staged in LDS with coalesced loads, then
+// each group of NR lanes accumulates its rows from LDS.  A gathered block
+// row crosses L2 once per tile instead of once per entry (5x fewer for P2,
+// 8x for P3 at 64-row tiles).
+
+constexpr int kTileBlock = 512;
+
+template <typename T>
+__host__ __device__ inline size_t tile_lds_bytes(int max_cols, int max_entries, int tile, int nr)
+{
+    size_t b = (size_t)max_cols * nr * sizeof(T) + (size_t)max_entries * sizeof(T);
+    b += (size_t)(tile + 1) * sizeof(int) + (size_t)max_cols * sizeof(int);
+    b += (size_t)max_entries * sizeof(unsigned short);
+    return (b + 15) & ~(size_t)15;
+}
+
+// Staging happens in two steps so that no load waits on another global
+// load: the tile's column list, values, positions and row offsets first
+// (coalesced), then the gathered block rows, whose addresses now come from
+// LDS, unrolled so that many rows are in flight per thread.
+template <typename T, int NR, typename XT, typename BODY>
+__device__ __forceinline__ void btile_rows(const DevTilesView &A, const XT *__restrict__ X, BODY body)
+{
+    constexpr int BS = kTileBlock, RG = BS / NR;   // row groups of NR lanes
+    extern __shared__ __align__(16) unsigned char lds_[];
+    T *Xs = (T *)lds_;
+    T *Vs = Xs + (size_t)A.max_cols * NR;
+    int *Rp = (int *)(Vs + A.max_entries);
+    int *Us = Rp + A.tile + 1;
+    unsigned short *Ls = (unsigned short *)(Us + A.max_cols);
+    const T *__restrict__ val = (const T *)A.val;
+    const int c = threadIdx.x % NR, g = threadIdx.x / NR;
+    for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+        const int c0 = A.col_off[t], nc = A.col_off[t + 1] - c0;
+        const int e0 = A.row_ptr[(size_t)t * A.tile], ne = A.row_ptr[(size_t)(t + 1) * A.tile] - e0;
+        __syncthreads();                               // the previous tile is consumed
+        for (int k = threadIdx.x; k < nc; k += BS) Us[k] = A.ucols[c0 + k];
+        for (int k = threadIdx.x; k < ne; k += BS) {
+            Vs[k] = val[e0 + k];
+            Ls[k] = A.lidx[e0 + k];
+        }
+        for (int k = threadIdx.x; k <= A.tile; k += BS) Rp[k] = A.row_ptr[(size_t)t * A.tile + k] - e0;
+        __syncthreads();
+#pragma unroll 8
+        for (int u = g; u < nc; u += RG) Xs[u * NR + c] = (T)X[(size_t)Us[u] * NR + c];
+        __syncthreads();
+        for (int i = g; i < A.tile; i += RG) {
+            const int row = A.rows[(size_t)t * A.tile + i];
+            if (row < 0) continue;
+            T s = T(0);
+            const int k1 = Rp[i + 1];
+#pragma unroll 4
+            for (int k = Rp[i]; k < k1; k++) s += Vs[k] * Xs[(int)Ls[k] * NR + c];
+            body(row, c, s);
+        }
+    }
+}
+
+template <typename T, typename TR, typename TZ, int NR, bool DOT>
+__global__ __launch_bounds__(kTileBlock) void kt_sweep(DevTilesView A, const T *__restrict__ dinv,
+                                                       const TR *__restrict__ RHS, const T *__restrict__ Zin,
+                                                       TZ *__restrict__ Zout, const double *__restrict__ Rdot,
+                                                       double *partials, const int *all_done)
+{
+    if (stop_all(all_done)) return;
+    double acc = 0.0;
+    btile_rows<T, NR>(A, Zin, [&](int row, int c, T s) {
+        size_t o = (size_t)row * NR + c;
+        T zi = Zin[o] + dinv[row] * ((T)RHS[o] - s);
+        Zout[o] = (TZ)zi;
+        if (DOT) acc += Rdot[o] * (double)(TZ)zi;
+    });
+    if (DOT) write_col_partials<NR, kTileBlock>(partials, acc);
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kTileBlock) void kt_resid(DevTilesView A, const T *__restrict__ RHS,
+                                                       const T *__restrict__ Z, T *__restrict__ Res,
+                                                       const int *all_done)
+{
+    if (stop_all(all_done)) return;
+    btile_rows<T, NR>(A, Z, [&](int row, int c, T s) {
+        size_t o = (size_t)row * NR + c;
+        Res[o] = RHS[o] - s;
+    });
+}
+
+template <int NR, bool DOT, bool RESID>
+__global__ __launch_bounds__(kTileBlock) void kt_spmv64(DevTilesView A, const double *__restrict__ X,
+                                                        double *__restrict__ Y, const double *__restrict__ F,
+                                                        double *partials, const int *all_done)
+{
+    if (stop_all(all_done)) return;
+    double acc = 0.0;
+    btile_rows<double, NR>(A, X, [&](int row, int c, double s) {
+        size_t o = (size_t)row * NR + c;
+        if (RESID) {
+            Y[o] = F[o] - s;
+        } else {
+            Y[o] = s;
+            if (DOT) acc += X[o] * s;
+        }
+    });
+    if (DOT) write_col_partials<NR, kTileBlock>(partials, acc);
 }
 
 // ------------------------------------------------------- AMG levels, transfers
@@ -411,6 +520,66 @@ __global__ __launch_bounds__(kBlock) void kb_scatter(int n, int ld, const int *_
     default: { constexpr int NR = 64; CALL; } break;   \
     }
 
+constexpr size_t kTileLdsMax = 40 * 1024;   // leaves room for several workgroups per CU
+
+size_t btile_lds(const DevTilesView &A, int nr, int s)
+{
+    size_t b = s == 8 ? tile_lds_bytes<double>(A.max_cols, A.max_entries, A.tile, nr)
+                      : tile_lds_bytes<float>(A.max_cols, A.max_entries, A.tile, nr);
+    return b <= kTileLdsMax ? b : 0;
+}
+
+inline int btile_grid(const DevTilesView &A) { return grid_cap(A.ntiles); }
+
+template <typename T, typename TR, typename TZ>
+int btile_sweep(hipStream_t s, int nr, const DevTilesView &A, const T *dinv, const TR *RHS, const T *Zin, TZ *Zout,
+                const double *Rdot, double *partials, const int *all_done)
+{
+    const int g = btile_grid(A);
+    const size_t lds = btile_lds(A, nr, sizeof(T));
+    if (partials) {
+        NR_SWITCH(nr, hipLaunchKernelGGL((kt_sweep<T, TR, TZ, NR, true>), dim3(g), dim3(kTileBlock), lds, s, A, dinv, RHS,
+                                         Zin, Zout, Rdot, partials, all_done));
+    } else {
+        NR_SWITCH(nr, hipLaunchKernelGGL((kt_sweep<T, TR, TZ, NR, false>), dim3(g), dim3(kTileBlock), lds, s, A, dinv,
+                                         RHS, Zin, Zout, Rdot, partials, all_done));
+    }
+    return g;
+}
+
+template <typename T>
+int btile_resid(hipStream_t s, int nr, const DevTilesView &A, const T *RHS, const T *Z, T *Res, const int *all_done)
+{
+    const int g = btile_grid(A);
+    const size_t lds = btile_lds(A, nr, sizeof(T));
+    NR_SWITCH(nr, hipLaunchKernelGGL((kt_resid<T, NR>), dim3(g), dim3(kTileBlock), lds, s, A, RHS, Z, Res, all_done));
+    return g;
+}
+
+int btile_spmv64(hipStream_t s, int nr, const DevTilesView &A, const double *X, double *Y, double *partials,
+                 const int *all_done)
+{
+    const int g = btile_grid(A);
+    const size_t lds = btile_lds(A, nr, 8);
+    if (partials) {
+        NR_SWITCH(nr, hipLaunchKernelGGL((kt_spmv64<NR, true, false>), dim3(g), dim3(kTileBlock), lds, s, A, X, Y,
+                                         (const double *)nullptr, partials, all_done));
+    } else {
+        NR_SWITCH(nr, hipLaunchKernelGGL((kt_spmv64<NR, false, false>), dim3(g), dim3(kTileBlock), lds, s, A, X, Y,
+                                         (const double *)nullptr, partials, all_done));
+    }
+    return g;
+}
+
+int btile_residual64(hipStream_t s, int nr, const DevTilesView &A, const double *F, const double *U, double *R)
+{
+    const int g = btile_grid(A);
+    const size_t lds = btile_lds(A, nr, 8);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kt_spmv64<NR, false, true>), dim3(g), dim3(kTileBlock), lds, s, A, U, R, F,
+                                     (double *)nullptr, (const int *)nullptr));
+    return g;
+}
+
 template <typename T>
 void bjacobi0(hipStream_t s, int nr, int n, const T *dinv, const double *R, T *Z, T *RT, const int *all_done)
 {
@@ -556,6 +725,9 @@ void bscatter(hipStream_t s, int nr, int n, int ld, const int *perm, const doubl
 }
 
 #define BINST(T)                                                                                                   \
+    template int btile_sweep<T, T, T>(hipStream_t, int, const DevTilesView &, const T *, const T *, const T *, T *, \
+                                      const double *, double *, const int *);                                      \
+    template int btile_resid<T>(hipStream_t, int, const DevTilesView &, const T *, const T *, T *, const int *);    \
     template void bjacobi0<T>(hipStream_t, int, int, const T *, const double *, T *, T *, const int *);            \
     template int bsell_sweep<T, T, T>(hipStream_t, int, const DevSellView &, const T *, const T *, const T *, T *, \
                                       const double *, double *, const int *);                                      \
@@ -573,6 +745,8 @@ void bscatter(hipStream_t s, int nr, int n, int ld, const int *perm, const doubl
 BINST(double)
 BINST(float)
 template int bsell_sweep<float, double, double>(hipStream_t, int, const DevSellView &, const float *, const double *,
+                                                const float *, double *, const double *, double *, const int *);
+template int btile_sweep<float, double, double>(hipStream_t, int, const DevTilesView &, const float *, const double *,
                                                 const float *, double *, const double *, double *, const int *);
 
 }  // namespace auxp

@@ -16,6 +16,27 @@ struct BCgState {
     int maxit;
 };
 
+// Row tiles of the P^k operator for block products (see Tiles in the host
+// setup): per tile the distinct gathered block rows are staged in LDS.
+struct DevTilesView {
+    int n, tile, ntiles, max_cols, max_entries;
+    const int *rows, *row_ptr, *col_off, *ucols;
+    const unsigned short *lidx;
+    const void *val;     // double or float
+};
+// LDS bytes a tile kernel needs for nr columns of type size s (0 if the
+// tiles cannot be used: more than 64 KiB)
+size_t btile_lds(const DevTilesView &A, int nr, int s);
+
+template <typename T, typename TR, typename TZ>
+int btile_sweep(hipStream_t s, int nr, const DevTilesView &A, const T *dinv, const TR *RHS, const T *Zin, TZ *Zout,
+                const double *Rdot, double *partials, const int *all_done);
+template <typename T>
+int btile_resid(hipStream_t s, int nr, const DevTilesView &A, const T *RHS, const T *Z, T *Res, const int *all_done);
+int btile_spmv64(hipStream_t s, int nr, const DevTilesView &A, const double *X, double *Y, double *partials,
+                 const int *all_done);
+int btile_residual64(hipStream_t s, int nr, const DevTilesView &A, const double *F, const double *U, double *R);
+
 template <typename T>
 void bjacobi0(hipStream_t s, int nr, int n, const T *dinv, const double *R, T *Z, T *RT, const int *all_done);
 template <typename T, typename TR, typename TZ>

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <stdexcept>
 
 #include "kernels.hpp"
 
@@ -64,14 +65,22 @@ inline int grid_cap(long long need)
     for (int sl_ = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6); sl_ < (A).nslices;                \
          sl_ += gridDim.x * (kBlock / 64))
 
-template <typename T, typename XF>
+// MIXED = false: every slice has 32-bit columns, stored in entry order
+// (wide[e]); MIXED = true: a 16-bit or 32-bit choice per slice.
+template <typename T, bool MIXED, typename XF>
 __device__ __forceinline__ T sell_row(const DevSellView &A, int slice, int lane, XF x)
 {
     const T *__restrict__ val = (const T *)A.val;
     slice = __builtin_amdgcn_readfirstlane(slice);      // one slice per wavefront
     const int e0 = A.slice_off[slice], e1 = A.slice_off[slice + 1];
-    const int mode = A.mode[slice];
     T s = T(0);
+    if (!MIXED) {
+        const int *__restrict__ col = A.wide;
+#pragma unroll 4
+        for (int e = e0 + lane; e < e1; e += kSlice) s += val[e] * x(col[e]);
+        return s;
+    }
+    const int mode = A.mode[slice];
     if (mode == 0) {
         // 16-bit offsets: the bases of 64 slots come in one vector load and
         // are broadcast from their lanes
@@ -94,9 +103,20 @@ __device__ __forceinline__ T sell_row(const DevSellView &A, int slice, int lane,
     return s;
 }
 
+#define MIXED_SWITCH(A, CALL)        \
+    do {                             \
+        if ((A).mixed) {             \
+            constexpr bool M = true; \
+            CALL;                    \
+        } else {                     \
+            constexpr bool M = false; \
+            CALL;                    \
+        }                            \
+    } while (0)
+
 inline int sell_grid(const DevSellView &A) { return grid_cap(((long long)A.nslices + 3) / 4); }
 
-template <typename T, typename TR, typename TZ, bool DOT>
+template <typename T, typename TR, typename TZ, bool DOT, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_sell_sweep(DevSellView A, const T *__restrict__ dinv,
                                                        const TR *__restrict__ rhs, const T *__restrict__ zin,
                                                        TZ *__restrict__ zout, const double *__restrict__ rdot,
@@ -107,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_sweep(DevSellView A, const T *_
     FOR_SLICES(A)
     {
         const int row = sl_ * kSlice + lane_;
-        T s = sell_row<T>(A, sl_, lane_, [&](int j) { return zin[j]; });
+        T s = sell_row<T, MIXED>(A, sl_, lane_, [&](int j) { return zin[j]; });
         if (row < A.n) {
             T zi = zin[row] + dinv[row] * ((T)rhs[row] - s);
             zout[row] = (TZ)zi;
@@ -117,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_sweep(DevSellView A, const T *_
     if (DOT) write_partial(partials, acc);
 }
 
-template <typename T>
+template <typename T, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_sell_resid(DevSellView A, const T *__restrict__ rhs,
                                                        const T *__restrict__ z, T *__restrict__ res, const int *done)
 {
@@ -125,12 +145,12 @@ __global__ __launch_bounds__(kBlock) void k_sell_resid(DevSellView A, const T *_
     FOR_SLICES(A)
     {
         const int row = sl_ * kSlice + lane_;
-        T s = sell_row<T>(A, sl_, lane_, [&](int j) { return z[j]; });
+        T s = sell_row<T, MIXED>(A, sl_, lane_, [&](int j) { return z[j]; });
         if (row < A.n) res[row] = rhs[row] - s;
     }
 }
 
-template <bool DOT>
+template <bool DOT, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_sell_spmv64(DevSellView A, const double *__restrict__ x,
                                                         double *__restrict__ y, double *partials, const int *done)
 {
@@ -139,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv64(DevSellView A, const dou
     FOR_SLICES(A)
     {
         const int row = sl_ * kSlice + lane_;
-        double s = sell_row<double>(A, sl_, lane_, [&](int j) { return x[j]; });
+        double s = sell_row<double, MIXED>(A, sl_, lane_, [&](int j) { return x[j]; });
         if (row < A.n) {
             y[row] = s;
             if (DOT) acc += x[row] * s;
@@ -148,13 +168,14 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv64(DevSellView A, const dou
     if (DOT) write_partial(partials, acc);
 }
 
+template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_sell_residual64(DevSellView A, const double *__restrict__ f,
                                                             const double *__restrict__ u, double *__restrict__ r)
 {
     FOR_SLICES(A)
     {
         const int row = sl_ * kSlice + lane_;
-        double s = sell_row<double>(A, sl_, lane_, [&](int j) { return u[j]; });
+        double s = sell_row<double, MIXED>(A, sl_, lane_, [&](int j) { return u[j]; });
         if (row < A.n) r[row] = f[row] - s;
     }
 }
@@ -429,12 +450,10 @@ int sell_sweep(hipStream_t s, const DevSellView &A, const T *dinv, const TR *rhs
                const double *rdot, double *partials, const int *done)
 {
     int g = sell_grid(A);
-    if (partials)
-        hipLaunchKernelGGL((k_sell_sweep<T, TR, TZ, true>), dim3(g), dim3(kBlock), 0, s, A, dinv, rhs, zin, zout,
-                           rdot, partials, done);
-    else
-        hipLaunchKernelGGL((k_sell_sweep<T, TR, TZ, false>), dim3(g), dim3(kBlock), 0, s, A, dinv, rhs, zin, zout,
-                           rdot, partials, done);
+    MIXED_SWITCH(A, if (partials) hipLaunchKernelGGL((k_sell_sweep<T, TR, TZ, true, M>), dim3(g), dim3(kBlock), 0, s, A,
+                                                     dinv, rhs, zin, zout, rdot, partials, done);
+                 else hipLaunchKernelGGL((k_sell_sweep<T, TR, TZ, false, M>), dim3(g), dim3(kBlock), 0, s, A, dinv,
+                                         rhs, zin, zout, rdot, partials, done));
     return g;
 }
 
@@ -442,7 +461,7 @@ template <typename T>
 int sell_resid(hipStream_t s, const DevSellView &A, const T *rhs, const T *z, T *res, const int *done)
 {
     int g = sell_grid(A);
-    hipLaunchKernelGGL(k_sell_resid<T>, dim3(g), dim3(kBlock), 0, s, A, rhs, z, res, done);
+    MIXED_SWITCH(A, hipLaunchKernelGGL((k_sell_resid<T, M>), dim3(g), dim3(kBlock), 0, s, A, rhs, z, res, done));
     return g;
 }
 
@@ -450,16 +469,18 @@ int sell_spmv64(hipStream_t s, const DevSellView &A, const double *x, double *y,
 {
     int g = sell_grid(A);
     if (partials)
-        hipLaunchKernelGGL(k_sell_spmv64<true>, dim3(g), dim3(kBlock), 0, s, A, x, y, partials, done);
+        MIXED_SWITCH(A, hipLaunchKernelGGL((k_sell_spmv64<true, M>), dim3(g), dim3(kBlock), 0, s, A, x, y, partials,
+                                           done));
     else
-        hipLaunchKernelGGL(k_sell_spmv64<false>, dim3(g), dim3(kBlock), 0, s, A, x, y, partials, done);
+        MIXED_SWITCH(A, hipLaunchKernelGGL((k_sell_spmv64<false, M>), dim3(g), dim3(kBlock), 0, s, A, x, y, partials,
+                                           done));
     return g;
 }
 
 int sell_residual64(hipStream_t s, const DevSellView &A, const double *f, const double *u, double *r)
 {
     int g = sell_grid(A);
-    hipLaunchKernelGGL(k_sell_residual64, dim3(g), dim3(kBlock), 0, s, A, f, u, r);
+    MIXED_SWITCH(A, hipLaunchKernelGGL((k_sell_residual64<M>), dim3(g), dim3(kBlock), 0, s, A, f, u, r));
     return g;
 }
 

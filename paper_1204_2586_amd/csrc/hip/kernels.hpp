@@ -37,6 +37,7 @@ struct DevSellView {
     int n;               // rows
     int nslices;
     int max_width;       // longest slice, in slots of 64 entries
+    int mixed;           // 0: every slice 32-bit with wide[e] the column of entry e
     const int *slice_off;  // [nslices+1] first entry of each slice (multiple of 64)
     // Columns.  mode[s] == 0: entry e of slot t = e / 64 has column
     // base[t] + off[e]; mode[s] = ~w < 0: column wide[w + e - slice_off[s]].
@@ -86,6 +87,7 @@ void csr_matvec_add(hipStream_t s, const DevCsrView &M, const T *e, T *x, const 
 // y = M [x1; x2] (columns below split index x1, the rest x2)
 template <typename T>
 void csr_matvec2(hipStream_t s, const DevCsrView &M, const T *x1, const T *x2, int split, T *y, const int *done);
+
 // x = D^{-1} b, r = b - A x (V-cycle presmoothing from zero fused with the residual)
 template <typename T>
 void csr_vpre(hipStream_t s, const DevCsrView &A, const T *dinv, const T *b, T *x, T *r, const int *done);

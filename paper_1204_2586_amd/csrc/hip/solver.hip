@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <functional>
 #include <cmath>
 #include <cstring>
 #include <stdexcept>
@@ -64,7 +65,21 @@ struct DevSell {
     template <typename T>
     DevSellView view() const
     {
-        return {n, nslices, max_width, slice_off, mode, base, off, wide,
+        return {n, nslices, max_width, narrow_slices > 0 ? 1 : 0, slice_off, mode, base, off, wide,
+                std::is_same<T, float>::value ? (const void *)v32 : (const void *)v64};
+    }
+};
+
+struct DevTiles {
+    int n = 0, tile = 0, ntiles = 0, max_cols = 0, max_entries = 0;
+    int *rows = nullptr, *row_ptr = nullptr, *col_off = nullptr, *ucols = nullptr;
+    unsigned short *lidx = nullptr;
+    double *v64 = nullptr;
+    float *v32 = nullptr;
+    template <typename T>
+    DevTilesView view() const
+    {
+        return {n, tile, ntiles, max_cols, max_entries, rows, row_ptr, col_off, ucols, lidx,
                 std::is_same<T, float>::value ? (const void *)v32 : (const void *)v64};
     }
 };
@@ -299,6 +314,42 @@ struct aux_handle {
         for (size_t i = 0; i < v.size(); i++) o[i] = 1.0 / v[i];
         return o;
     }
+    // Lanes per row of a CSR operator: time one FP32 product (two-source
+    // form when split > 0) for each candidate and keep the fastest.
+    void tune_lpr(DevOp &op, int split)
+    {
+        if (!op.v32 || op.n == 0) return;
+        float *x = dnew<float>(std::max(op.m, 1)), *y = dnew<float>(op.n);
+        HIPCHECK(hipMemsetAsync(x, 0, (size_t)std::max(op.m, 1) * sizeof(float), stream));
+        const double avg = (double)op.nnz / op.n;
+        double best = 1e300;
+        int pick = op.lpr;
+        hipEvent_t a = take_event(), b = take_event();
+        for (int lpr : {2, 4, 8, 16, 32}) {
+            if (lpr > 4 * avg + 4) break;
+            op.lpr = lpr;
+            auto run = [&]() {
+                if (split > 0) csr_matvec2<float>(stream, op.view<float>(), x, x + split, split, y, nullptr);
+                else csr_matvec<float>(stream, op.view<float>(), x, y, nullptr);
+            };
+            run();
+            HIPCHECK(hipEventRecord(a, stream));
+            for (int i = 0; i < 3; i++) run();
+            HIPCHECK(hipEventRecord(b, stream));
+            HIPCHECK(hipEventSynchronize(b));
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, a, b));
+            if (ms < best) {
+                best = ms;
+                pick = lpr;
+            }
+        }
+        ev_used -= 2;
+        op.lpr = pick;
+        dfree(x);
+        dfree(y);
+    }
+
     // CSR with both precisions uploaded at once (composite operators)
     DevOp upload_op2(const Csr &c)
     {
@@ -420,7 +471,7 @@ struct aux_handle {
         dinv64 = upload(inverse(l1i));
         IPi = permute_rows(disc.IP, sell.perm);
         IRi = transpose(IPi);
-        IP = upload_op(IPi);
+        IP = upload_op2(IPi);
         IR = upload_op(IRi);
         lev.resize(hier.levels.size());
         for (size_t l = 0; l < hier.levels.size(); l++) {
@@ -442,6 +493,17 @@ struct aux_handle {
             }
             RF_host = fuse_restriction(IRi, permute_symmetric(disc.A, sell.perm, sell.iperm));
             RF = upload_op2(RF_host);
+            // lanes per row of the large CSR passes, timed on the device
+            // (with a fixed layout window every choice is rule-based)
+            if (opt.sell_window <= 0) {
+                tune_lpr(RF, disc.ndof);
+                tune_lpr(IP, 0);
+                for (size_t l = 0; l + 1 < lev.size(); l++) {
+                    if (lev[l].A.n < 8192) break;
+                    tune_lpr(lev[l].down, 0);
+                    tune_lpr(lev[l].up, lev[l].A.n);
+                }
+            }
         }
         int n = disc.ndof;
         r = dnew<double>(n);
@@ -469,7 +531,7 @@ struct aux_handle {
         if (fp32_ready) return;
         A.v32 = upload(to_f32(sell.val));
         dinv32 = upload(to_f32(inverse(l1i)));
-        IP.v32 = upload(to_f32(IPi.val));
+        if (!IP.v32) IP.v32 = upload(to_f32(IPi.val));
         IR.v32 = upload(to_f32(IRi.val));
         for (size_t l = 0; l < hier.levels.size(); l++) {
             const AmgLevel &hl = hier.levels[l];
@@ -815,6 +877,7 @@ struct aux_handle {
         double *X = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr, *F = nullptr;
         double *partials = nullptr, *ff = nullptr, *rr0 = nullptr, *tol2ff = nullptr, *hist = nullptr;
         int *ist = nullptr;            // k, all_done, iter[nr], done[nr]
+        int layout32 = -1, layout64 = -1;   // tile size index of the block products, -1 slices
         int *host = nullptr;           // pinned copy of ist
         Work<double> w64;
         Work<float> w32;
@@ -840,12 +903,80 @@ struct aux_handle {
             bt.ist = dnew<int>(2 + 2 * (size_t)nr);
             HIPCHECK(hipHostMalloc((void **)&bt.host, (2 + 2 * (size_t)nr) * sizeof(int), hipHostMallocDefault));
             host_bufs.push_back(bt.host);
+            tune_batch_layout();
         }
         if (maxit + 2 > bt.hist_cap) {
             dfree(bt.hist);
             bt.hist_cap = maxit + 2;
             bt.hist = dnew<double>((size_t)3 * bt.hist_cap * nr);
         }
+    }
+
+    // The batched autotuner: for the current block width, time the block
+    // products of A_h with 64-row slices and with each tile size whose LDS
+    // fits (an FP32 sweep for the preconditioner, an FP64 product for CG) and
+    // keep the fastest per precision.
+    double time_block(const std::function<void()> &f)
+    {
+        hipEvent_t a = take_event(), b = take_event();
+        f();
+        HIPCHECK(hipEventRecord(a, stream));
+        for (int i = 0; i < 3; i++) f();
+        HIPCHECK(hipEventRecord(b, stream));
+        HIPCHECK(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, a, b));
+        ev_used -= 2;
+        return ms;
+    }
+
+    void tune_batch_layout()
+    {
+        bt.layout32 = bt.layout64 = -1;
+        // 0: slices; with a fixed layout window every choice is rule-based (slices)
+        if (!opt.batch_tiles || (opt.batch_tiles == 1 && opt.sell_window > 0)) return;
+        ensure_tiles();
+        if (opt.batch_tiles == 2) {                    // the largest tile whose LDS fits
+            for (int k = 0; k < kTileSizes; k++) {
+                if (btile_lds(tiles[k].view<float>(), bt.nr, 4)) bt.layout32 = k;
+                if (btile_lds(tiles[k].view<double>(), bt.nr, 8)) bt.layout64 = k;
+            }
+            return;
+        }
+        ensure_fp32();
+        const int nr = bt.nr;
+        const size_t blk = (size_t)disc.ndof * nr;
+        float *z0 = dnew<float>(blk), *z1 = dnew<float>(blk), *rh = dnew<float>(blk);
+        HIPCHECK(hipMemsetAsync(z0, 0, blk * sizeof(float), stream));
+        HIPCHECK(hipMemsetAsync(rh, 0, blk * sizeof(float), stream));
+        HIPCHECK(hipMemsetAsync(bt.P, 0, blk * sizeof(double), stream));
+        double best32 = time_block([&]() {
+            bsell_sweep<float, float, float>(stream, nr, A.view<float>(), dinv32, rh, z0, z1, nullptr, nullptr, nullptr);
+        });
+        double best64 = time_block([&]() { bsell_spmv64(stream, nr, A.view<double>(), bt.P, bt.Q, nullptr, nullptr); });
+        for (int k = 0; k < kTileSizes; k++) {
+            if (btile_lds(tiles[k].view<float>(), nr, 4)) {
+                double ms = time_block([&]() {
+                    btile_sweep<float, float, float>(stream, nr, tiles[k].view<float>(), dinv32, rh, z0, z1, nullptr,
+                                                     nullptr, nullptr);
+                });
+                if (ms < best32) {
+                    best32 = ms;
+                    bt.layout32 = k;
+                }
+            }
+            if (btile_lds(tiles[k].view<double>(), nr, 8)) {
+                double ms = time_block(
+                    [&]() { btile_spmv64(stream, nr, tiles[k].view<double>(), bt.P, bt.Q, nullptr, nullptr); });
+                if (ms < best64) {
+                    best64 = ms;
+                    bt.layout64 = k;
+                }
+            }
+        }
+        dfree(z0);
+        dfree(z1);
+        dfree(rh);
     }
 
     // device buffers of the current block width (the pinned status copy
@@ -914,6 +1045,46 @@ struct aux_handle {
     BOp bIP, bIR, bRF;
     bool bops_ready = false;
 
+    // A_h as row tiles (16, 32 and 64 consecutive original rows) for the
+    // block products; a launch uses the largest tile whose LDS fits
+    static constexpr int kTileSizes = 3;
+    DevTiles tiles[kTileSizes];
+    bool tiles_ready = false;
+
+    void ensure_tiles()
+    {
+        if (tiles_ready || !opt.batch_tiles) return;
+        const int sizes[kTileSizes] = {16, 32, 64};
+        for (int k = 0; k < kTileSizes; k++) {
+            Tiles h;
+            build_tiles(disc.A, sell.iperm, sizes[k], h);
+            DevTiles &d = tiles[k];
+            d.n = h.n;
+            d.tile = h.tile;
+            d.ntiles = h.ntiles;
+            d.max_cols = h.max_cols;
+            d.max_entries = h.max_entries;
+            d.rows = upload(h.rows);
+            d.row_ptr = upload(h.row_ptr);
+            d.col_off = upload(h.col_off);
+            d.ucols = upload(h.ucols);
+            d.lidx = upload(h.lidx);
+            d.v64 = upload(h.val);
+            d.v32 = upload(to_f32(h.val));
+        }
+        tiles_ready = true;
+    }
+
+    // tile layout the batched autotuner chose for values of type T at the
+    // current block width, or null (slice kernels)
+    template <typename T>
+    const DevTiles *tiles_for(int nr) const
+    {
+        const int k = std::is_same<T, float>::value ? bt.layout32 : bt.layout64;
+        if (!tiles_ready || k < 0 || bt.nr != nr) return nullptr;
+        return &tiles[k];
+    }
+
     BOp upload_bop(const Csr &op)
     {
         Sell sl;
@@ -979,6 +1150,7 @@ struct aux_handle {
         hipStream_t s = stream;
         const int nr = bt.nr;
         DevSellView Av = A.view<T>();
+        const DevTiles *tl = tiles_for<T>(nr);
         const T *d = dinv<T>();
         const int nu = opt.nu;
         T *rTbuf = std::is_same<T, float>::value ? w.rT : nullptr;
@@ -990,7 +1162,8 @@ struct aux_handle {
         const T *rT = rTbuf ? (const T *)rTbuf : (const T *)(const void *)Rin;
         for (int k = 1; k < nu; k++) {
             pk = pbeg(AUX_PROF_PK_SWEEP);
-            bsell_sweep<T, T, T>(s, nr, Av, d, rT, zc, zn, nullptr, nullptr, all_done);
+            if (tl) btile_sweep<T, T, T>(s, nr, tl->view<T>(), d, rT, zc, zn, nullptr, nullptr, all_done);
+            else bsell_sweep<T, T, T>(s, nr, Av, d, rT, zc, zn, nullptr, nullptr, all_done);
             pend(pk);
             std::swap(zc, zn);
         }
@@ -1001,7 +1174,8 @@ struct aux_handle {
                 pend(pk);
                 pk = pbeg(AUX_PROF_COARSE);
             } else {
-                bsell_resid<T>(s, nr, Av, rT, zc, w.res, all_done);
+                if (tl) btile_resid<T>(s, nr, tl->view<T>(), rT, zc, w.res, all_done);
+                else bsell_resid<T>(s, nr, Av, rT, zc, w.res, all_done);
                 pend(pk);
                 pk = pbeg(AUX_PROF_COARSE);
                 blevel_matvec<T>(s, nr, bIR.view<T>(), bIR.perm, w.res, w.b[0], false, all_done);
@@ -1012,12 +1186,14 @@ struct aux_handle {
         }
         for (int k = 1; k < nu; k++) {
             pk = pbeg(AUX_PROF_PK_SWEEP);
-            bsell_sweep<T, T, T>(s, nr, Av, d, rT, zc, zn, nullptr, nullptr, all_done);
+            if (tl) btile_sweep<T, T, T>(s, nr, tl->view<T>(), d, rT, zc, zn, nullptr, nullptr, all_done);
+            else bsell_sweep<T, T, T>(s, nr, Av, d, rT, zc, zn, nullptr, nullptr, all_done);
             pend(pk);
             std::swap(zc, zn);
         }
         pk = pbeg(AUX_PROF_PK_LAST);
-        int g = bsell_sweep<T, double, double>(s, nr, Av, d, Rin, zc, Zout, Rin, rz_partials, all_done);
+        int g = tl ? btile_sweep<T, double, double>(s, nr, tl->view<T>(), d, Rin, zc, Zout, Rin, rz_partials, all_done)
+                   : bsell_sweep<T, double, double>(s, nr, Av, d, Rin, zc, Zout, Rin, rz_partials, all_done);
         pend(pk);
         pend(pb);
         return g;
@@ -1041,7 +1217,9 @@ struct aux_handle {
         const int nr = bt.nr, n = disc.ndof;
         DevSellView A64 = A.view<double>();
         int pk = pbeg(AUX_PROF_CG_SPMV);
-        int g = bsell_spmv64(s, nr, A64, bt.P, bt.Q, bt.partials, st.all_done);
+        const DevTiles *tl = tiles_for<double>(nr);
+        int g = tl ? btile_spmv64(s, nr, tl->view<double>(), bt.P, bt.Q, bt.partials, st.all_done)
+                   : bsell_spmv64(s, nr, A64, bt.P, bt.Q, bt.partials, st.all_done);
         pend(pk);
         bfinish(s, nr, bt.partials, g, FIN_PQ, nullptr, st);
         g = bcg_update(s, nr, n, bt.X, bt.R, bt.P, bt.Q, st, bt.partials);
@@ -1065,7 +1243,8 @@ struct aux_handle {
         DevSellView A64 = A.view<double>();
         bgather(s, nr, n, nrhs, perm, Fext, bt.F);
         bgather(s, nr, n, nrhs, perm, Uext, bt.X);
-        bsell_residual64(s, nr, A64, bt.F, bt.X, bt.R);
+        if (const DevTiles *tl = tiles_for<double>(nr)) btile_residual64(s, nr, tl->view<double>(), bt.F, bt.X, bt.R);
+        else bsell_residual64(s, nr, A64, bt.F, bt.X, bt.R);
         int g = bvec_dot(s, nr, n, bt.F, bt.F, bt.partials);
         bfinish(s, nr, bt.partials, g, FIN_PLAIN, bt.ff, st);
         g = bvec_dot(s, nr, n, bt.R, bt.R, bt.partials);
@@ -1238,6 +1417,7 @@ void aux_default_options(aux_options *o)
     o->graph = 1;
     o->sell_index16 = 1;
     o->fuse_cycle = 1;
+    o->batch_tiles = 1;
 }
 
 int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt, const aux_device *dev,
@@ -1371,6 +1551,8 @@ int aux_get_info(const aux_handle *h, aux_info *info)
         info->sell_index_bytes = h->A.index_bytes;
         for (int c = 0; c < 4; c++) info->sell_tune_ms[c] = h->tune_ms[c];
         info->nnz_restrict = h->RF_host.nnz();
+        info->batch_tile_rows[0] = h->bt.layout32 >= 0 ? h->tiles[h->bt.layout32].tile : 0;
+        info->batch_tile_rows[1] = h->bt.layout64 >= 0 ? h->tiles[h->bt.layout64].tile : 0;
         for (size_t l = 0; l < h->fused_host.size() && l < 32; l++) {
             info->level_nnz_down[l] = h->fused_host[l].down.nnz();
             info->level_nnz_up[l] = h->fused_host[l].up.nnz();
@@ -1384,6 +1566,21 @@ int aux_dof_keys(const aux_handle *h, int32_t *keys)
     return guarded([&]() {
         if (!h || !keys) throw AuxError(AUX_EINVAL, "null argument");
         std::memcpy(keys, h->disc.keys.data(), h->disc.keys.size() * sizeof(int32_t));
+        return AUX_OK;
+    });
+}
+
+int aux_dof_xyz(const aux_handle *h, double *xyz)
+{
+    return guarded([&]() {
+        if (!h || !xyz) throw AuxError(AUX_EINVAL, "null argument");
+        const Discretization &d = h->disc;
+        for (int i = 0; i < d.ndof; i++)
+            for (int c = 0; c < 3; c++) {
+                double s = 0.0;
+                for (int p = 0; p < d.k; p++) s += d.xyz[3 * (size_t)d.keys[(size_t)i * d.k + p] + c];
+                xyz[3 * (size_t)i + c] = s / d.k;
+            }
         return AUX_OK;
     });
 }

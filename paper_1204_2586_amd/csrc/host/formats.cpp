@@ -90,6 +90,46 @@ void build_sell(const Csr &A, int slice, int window, bool index16, Sell &out, bo
     }
 }
 
+void build_tiles(const Csr &A, const std::vector<int> &iperm, int tile, Tiles &out)
+{
+    const int n = A.n;
+    out = Tiles();
+    out.n = n;
+    out.tile = tile;
+    out.ntiles = (n + tile - 1) / tile;
+    out.rows.assign((size_t)out.ntiles * tile, -1);
+    out.row_ptr.assign((size_t)out.ntiles * tile + 1, 0);
+    out.col_off.assign((size_t)out.ntiles + 1, 0);
+    std::vector<int> cols;
+    for (int t = 0; t < out.ntiles; t++) {
+        const int r0 = t * tile, r1 = std::min(n, r0 + tile);
+        cols.clear();
+        for (int r = r0; r < r1; r++)
+            for (int e = A.ptr[r]; e < A.ptr[r + 1]; e++) cols.push_back(iperm[A.col[e]]);
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        if (cols.size() > 65535) throw std::invalid_argument("build_tiles: tile too wide for 16-bit positions");
+        out.ucols.insert(out.ucols.end(), cols.begin(), cols.end());
+        out.col_off[t + 1] = (int)out.ucols.size();
+        out.max_cols = std::max(out.max_cols, (int)cols.size());
+        const size_t first = out.val.size();
+        for (int i = 0; i < tile; i++) {
+            const int r = r0 + i;
+            if (r < r1) {
+                out.rows[(size_t)t * tile + i] = iperm[r];
+                for (int e = A.ptr[r]; e < A.ptr[r + 1]; e++) {
+                    const int c = iperm[A.col[e]];
+                    out.lidx.push_back((uint16_t)(std::lower_bound(cols.begin(), cols.end(), c) - cols.begin()));
+                    out.val.push_back(A.val[e]);
+                }
+            }
+            if (out.val.size() > 0x7fffffffu) throw std::invalid_argument("build_tiles: operator too large");
+            out.row_ptr[(size_t)t * tile + i + 1] = (int)out.val.size();
+        }
+        out.max_entries = std::max(out.max_entries, (int)(out.val.size() - first));
+    }
+}
+
 Csr permute_symmetric(const Csr &A, const std::vector<int> &perm, const std::vector<int> &iperm)
 {
     Csr B;

@@ -116,6 +116,24 @@ struct Sell {
     int max_width = 0;            // longest slice, in slots
 };
 
+// Row tiles for products with a block of vectors (batched solve).  Tile t
+// holds `tile` consecutive rows of A in the original order (neighbouring
+// dofs, which share most of their columns); ucols lists the distinct columns
+// of the tile (in the internal numbering), and each entry stores the 16-bit
+// position of its column in that list, so a workgroup can stage the gathered
+// block rows once per tile.  Rows and columns are renumbered with iperm.
+struct Tiles {
+    int n = 0, tile = 0, ntiles = 0;
+    std::vector<int> rows;        // [ntiles*tile] internal row of each tile row, -1 past the end
+    std::vector<int> row_ptr;     // [ntiles*tile + 1] entry offsets, tile rows in order
+    std::vector<uint16_t> lidx;   // per entry: position of its column in the tile's list
+    std::vector<double> val;
+    std::vector<int> col_off;     // [ntiles+1] offsets into ucols
+    std::vector<int> ucols;       // distinct internal columns of each tile, sorted
+    int max_cols = 0, max_entries = 0;
+};
+void build_tiles(const Csr &A, const std::vector<int> &iperm, int tile, Tiles &out);
+
 // Rows sorted by decreasing length (stably) within windows of `window` rows;
 // index16 = false stores every slice with plain 32-bit columns.  With
 // permute_cols the columns are renumbered like the rows (a square operator

@@ -320,3 +320,25 @@ def test_fused_cycle_matches_stepwise(k, n, jit, kap):
         for j in range(2):
             assert abs(inf_[j].iterations - ins_[j].iterations) <= 1
             assert _rel(Uf[:, j].cpu().numpy(), Us[:, j].cpu().numpy()) <= 1e-8
+
+
+@pytest.mark.parametrize("nrhs", [5, 12, 32])
+def test_batched_tiles_equal_slices(nrhs):
+    """Block products from LDS-staged row tiles and from 64-row slices sum each
+    row in the same order; only the grouping of the inner products' partial
+    sums differs, so the lock-step solves agree to rounding."""
+    xyz, tets, kappa = _case(2, 9, jitter=0.2, kappa="rand")
+    kw = dict(device=DEV, sell_window=4096)
+    a = aux.Solver(xyz, tets, 2, kappa, batch_tiles=2, **kw)
+    b = aux.Solver(xyz, tets, 2, kappa, batch_tiles=0, **kw)
+    orc = oracle.Problem(xyz, tets, 2, kappa).setup_amg()
+    F = np.stack([orc.load(W.fourier_f(r)) for r in range(nrhs)], axis=1)
+    for prec in ("fp64", "mixed"):
+        a.set_precision(prec)
+        b.set_precision(prec)
+        Ua, ia = a.solve_batched(_t(F), tol=1e-9)
+        Ub, ib = b.solve_batched(_t(F), tol=1e-9)
+        assert min(a.info.batch_tile_rows) > 0 and max(b.info.batch_tile_rows) == 0
+        for j in range(nrhs):
+            assert ia[j].converged and abs(ia[j].iterations - ib[j].iterations) <= 1
+            assert _rel(Ua[:, j].cpu().numpy(), Ub[:, j].cpu().numpy()) <= 1e-8

@@ -44,6 +44,25 @@ def test_dofs_and_operators(pair):
     assert _rel(lib.export_csr("IP"), orc.csr("IP")) == 0.0
 
 
+def test_dof_xyz_reproduced_by_linear_transfer(pair):
+    """Node positions: I_P carries a linear function at the P^1 vertices to its
+    values at the P^k nodes (Sec. 2), so rows whose vertices are all interior
+    reproduce g(x_i) for g linear."""
+    lib, orc = pair
+    X = lib.dof_xyz()
+    assert X.shape == (lib.n, 3)
+    interior = np.flatnonzero(np.all((orc.xyz > 1e-12) & (orc.xyz < 1 - 1e-12), axis=1))
+    assert len(interior) == lib.nH
+    coef = np.array([0.3, -1.7, 2.2])
+    g = orc.xyz[interior] @ coef + 0.5
+    IP = orc.csr("IP")
+    full = np.isclose(np.asarray(IP.sum(axis=1)).ravel(), 1.0)
+    assert full.sum() > lib.n // 4
+    assert np.max(np.abs((IP @ g)[full] - (X[full] @ coef + 0.5))) < 1e-12
+    # nodes lie inside the cube, vertices of the key averaged
+    assert np.all((X > 0) & (X < 1))
+
+
 def test_load_vector(pair):
     lib, orc = pair
     b1, b2 = lib.load(W.manufactured_f), orc.load(W.manufactured_f)
