@@ -342,3 +342,27 @@ def test_batched_tiles_equal_slices(nrhs):
         for j in range(nrhs):
             assert ia[j].converged and abs(ia[j].iterations - ib[j].iterations) <= 1
             assert _rel(Ua[:, j].cpu().numpy(), Ub[:, j].cpu().numpy()) <= 1e-8
+
+
+@pytest.mark.parametrize("k,n", [(2, 1), (3, 1), (2, 2), (3, 2)])
+def test_degenerate_meshes(k, n):
+    """One cube (no interior P^1 vertex: B is the P^k smoother alone) and two
+    cubes per side (a single P^1 unknown, the coarse solve only)."""
+    xyz, tets = W.kuhn_mesh(n)
+    lib = aux.Solver(xyz, tets, k, device=DEV)
+    orc = oracle.Problem(xyz, tets, k).setup_amg()
+    assert lib.n == orc.n and lib.nH == orc.nH == (n - 1) ** 3
+    r = W.random_vector(lib.n, 4)
+    assert _rel(lib.apply(_t(r)).cpu().numpy(), orc.apply(r)) <= 1e-12
+    b = orc.load(W.manufactured_f)
+    x, it, _, st = orc.pcg(b, tol=1e-10)
+    assert st == 0
+    u, info = lib.solve(_t(b), tol=1e-10)
+    assert info.converged and abs(info.iterations - it) <= 1
+    assert _rel(u.cpu().numpy(), x) <= 1e-9
+    lib.set_precision("mixed")
+    u, info = lib.solve(_t(b), tol=1e-8)
+    assert info.converged and _rel(u.cpu().numpy(), x) <= 1e-7
+    U, infos = lib.solve_batched(_t(np.stack([b, 2 * b, r], axis=1)), tol=1e-8)
+    assert all(i.converged for i in infos)
+    assert _rel(U[:, 1].cpu().numpy(), 2 * x) <= 1e-7
