@@ -358,6 +358,31 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int n, double *__restrict_
     write_partial(partials, acc);
 }
 
+// the update fused with the preconditioner's first sweep from zero:
+// z0 = D^-1 r in the preconditioner's type (and its copy of r), with the
+// expressions of k_jacobi0
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update_prep(int n, double *__restrict__ x, double *__restrict__ r,
+                                                           const double *__restrict__ p, const double *__restrict__ q,
+                                                           CgState st, double *partials, const T *__restrict__ dinv,
+                                                           T *__restrict__ z0, T *__restrict__ rT)
+{
+    if (*st.done) return;
+    const int k = *st.iter;
+    const double alpha = st.rz[k] / st.pq[k];
+    double acc = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        x[i] += alpha * p[i];
+        double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        acc += ri * ri;
+        T rt = (T)ri;
+        z0[i] = dinv[i] * rt;
+        if (rT) rT[i] = rt;
+    }
+    write_partial(partials, acc);
+}
+
 __global__ __launch_bounds__(kBlock) void k_cg_direction(int n, const double *__restrict__ z, double *__restrict__ p,
                                                          CgState st)
 {
@@ -551,6 +576,19 @@ int cg_update(hipStream_t s, int n, double *x, double *r, const double *p, const
     hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kBlock), 0, s, n, x, r, p, q, st, partials);
     return g;
 }
+
+template <typename T>
+int cg_update_prep(hipStream_t s, int n, double *x, double *r, const double *p, const double *q, const CgState &st,
+                   double *partials, const T *dinv, T *z0, T *rT)
+{
+    int g = vec_grid(n);
+    hipLaunchKernelGGL(k_cg_update_prep<T>, dim3(g), dim3(kBlock), 0, s, n, x, r, p, q, st, partials, dinv, z0, rT);
+    return g;
+}
+template int cg_update_prep<float>(hipStream_t, int, double *, double *, const double *, const double *,
+                                   const CgState &, double *, const float *, float *, float *);
+template int cg_update_prep<double>(hipStream_t, int, double *, double *, const double *, const double *,
+                                    const CgState &, double *, const double *, double *, double *);
 
 void cg_direction(hipStream_t s, int n, const double *z, double *p, const CgState &st)
 {

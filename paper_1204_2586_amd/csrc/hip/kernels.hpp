@@ -107,6 +107,11 @@ void cg_init(hipStream_t s, const CgState &st, double tol2);
 // x += alpha p ; r -= alpha q ; partial r.r
 int cg_update(hipStream_t s, int n, double *x, double *r, const double *p, const double *q, const CgState &st,
               double *partials);
+// the same, also writing the preconditioner's first sweep from zero,
+// z0 = D^-1 r, and (rT non-null) r in the preconditioner's type
+template <typename T>
+int cg_update_prep(hipStream_t s, int n, double *x, double *r, const double *p, const double *q, const CgState &st,
+                   double *partials, const T *dinv, T *z0, T *rT);
 // p = z + beta p, beta = rz[k]/rz[k-1] (p = z at k = 0)
 void cg_direction(hipStream_t s, int n, const double *z, double *p, const CgState &st);
 // y[i] = x[idx[i]]

@@ -495,9 +495,10 @@ struct aux_handle {
             RF = upload_op2(RF_host);
             // lanes per row of the large CSR passes, timed on the device
             // (with a fixed layout window every choice is rule-based)
+            // (I_P has one or two entries per row: its rule-based two lanes
+            // per row measured best in the solve)
             if (opt.sell_window <= 0) {
                 tune_lpr(RF, disc.ndof);
-                tune_lpr(IP, 0);
                 for (size_t l = 0; l + 1 < lev.size(); l++) {
                     if (lev[l].A.n < 8192) break;
                     tune_lpr(lev[l].down, 0);
@@ -660,8 +661,9 @@ struct aux_handle {
     // zout = B rin (internal order).  With rz_partials, the last sweep also
     // writes the partial sums of rin . zout and the number of partials is
     // returned.
+    // prepped: z = D^-1 r (and the FP32 copy of r) are already in w.za / w.rT
     template <typename T>
-    int apply_B(const double *rin, double *zout, double *rz_partials, const int *done)
+    int apply_B(const double *rin, double *zout, double *rz_partials, const int *done, bool prepped = false)
     {
         Work<T> &w = work<T>();
         hipStream_t s = stream;
@@ -671,9 +673,12 @@ struct aux_handle {
         T *zc = w.za, *zn = w.zb;
         int pb = pbeg(AUX_PROF_APPLY);
         // presmoothing: nu l1-Jacobi sweeps from z = 0 (the first is z = D^{-1} r)
-        int pk = pbeg(AUX_PROF_PK_FIRST);
-        vec_jacobi0<T>(s, disc.ndof, d, rin, zc, rTbuf, done);
-        pend(pk);
+        int pk = -1;
+        if (!prepped) {
+            pk = pbeg(AUX_PROF_PK_FIRST);
+            vec_jacobi0<T>(s, disc.ndof, d, rin, zc, rTbuf, done);
+            pend(pk);
+        }
         const T *rT = rTbuf ? (const T *)rTbuf : (const T *)(const void *)rin;
         for (int k = 1; k < nu; k++) {
             pk = pbeg(AUX_PROF_PK_SWEEP);
@@ -713,14 +718,14 @@ struct aux_handle {
         return g;
     }
 
-    int apply(const double *rin, double *zout, double *rz_partials, const int *done)
+    int apply(const double *rin, double *zout, double *rz_partials, const int *done, bool prepped = false)
     {
         if (use_mf()) ensure_mf();
         if (opt.precision == AUX_MIXED) {
             ensure_fp32();
-            return apply_B<float>(rin, zout, rz_partials, done);
+            return apply_B<float>(rin, zout, rz_partials, done, prepped);
         }
-        return apply_B<double>(rin, zout, rz_partials, done);
+        return apply_B<double>(rin, zout, rz_partials, done, prepped);
     }
 
     // ------------------------------------------------------------ CG
@@ -739,9 +744,18 @@ struct aux_handle {
         int g = sell_spmv64(s, A64, p, q, partials, st.done);
         pend(pk);
         finish(s, partials, g, FIN_PQ, nullptr, st);
-        g = cg_update(s, n, xi, r, p, q, st, partials);
+        // the update also starts the preconditioner: z = D^-1 r
+        if (use_mf()) ensure_mf();
+        if (opt.precision == AUX_MIXED) {
+            ensure_fp32();
+            Work<float> &w = work<float>();
+            g = cg_update_prep<float>(s, n, xi, r, p, q, st, partials, dinv32, w.za, w.rT);
+        } else {
+            Work<double> &w = work<double>();
+            g = cg_update_prep<double>(s, n, xi, r, p, q, st, partials, dinv64, w.za, nullptr);
+        }
         finish(s, partials, g, FIN_RR, nullptr, st);
-        g = apply(r, z, partials, st.done);
+        g = apply(r, z, partials, st.done, true);
         finish(s, partials, g, FIN_RZ, nullptr, st);
         cg_direction(s, n, z, p, st);
     }
