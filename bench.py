@@ -238,6 +238,8 @@ def run(args):
                           for c, d in kernels.items()},
         "precond_apply": precond,
     }
+    # achievable HBM bandwidth on this device: plain 1 GiB device copies
+    out["hbm_copy_gbs"] = round(calibrate_copy(reps=5)["copy_gbs"], 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xyz, tets, wl, kappa, args)
     return out
@@ -374,6 +376,7 @@ def calibrate_copy(nbytes=1 << 30, reps=3):
     import torch
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
     dst = torch.empty_like(src)
+    dst.copy_(src)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(reps):

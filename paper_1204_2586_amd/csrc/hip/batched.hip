@@ -57,10 +57,6 @@ __device__ void write_col_partials(double *partials, double v)
 // share a slice, so no two XCDs fetch the same matrix lines.
 constexpr int kChunk = 32;
 
-__device__ __forceinline__ int sell_col_at(const DevSellView &A, int slice, int e0, int mode, int e)
-{
-    return mode == 0 ? A.base[e / kSlice] + (int)A.off[e] : A.wide[~mode + (e - e0)];
-}
 
 template <typename T, int NR, typename XL, typename BODY>
 __device__ __forceinline__ void bsell_slices(const DevSellView &A, XL xload, BODY body)
@@ -78,11 +74,36 @@ __device__ __forceinline__ void bsell_slices(const DevSellView &A, XL xload, BOD
         for (int p = 0; p < NP; p++) acc[p] = T(0);
         for (int j0 = 0; j0 < width; j0 += kChunk) {
             const int jn = min(kChunk, width - j0);
-            __syncthreads();
-            for (int k = threadIdx.x; k < jn * kSlice; k += kBlock) {
-                const int e = e0 + j0 * kSlice + k;
-                vs[k] = val[e];
-                cs[k] = sell_col_at(A, sl, e0, mode, e);
+            const int cnt = jn * kSlice, eb = e0 + j0 * kSlice;
+            // every load of the chunk is issued before any is waited on
+            // (indices clamped into the chunk, stores predicated)
+            constexpr int PER = kChunk * kSlice / kBlock;
+            T vt[PER];
+            int ct[PER];
+            if (mode == 0) {
+#pragma unroll
+                for (int i = 0; i < PER; i++) {
+                    const int e = eb + min(threadIdx.x + i * kBlock, cnt - 1);
+                    vt[i] = val[e];
+                    ct[i] = A.base[e / kSlice] + (int)A.off[e];
+                }
+            } else {
+                const int *__restrict__ w = A.wide + (~mode) + (eb - e0);
+#pragma unroll
+                for (int i = 0; i < PER; i++) {
+                    const int k = min(threadIdx.x + i * kBlock, cnt - 1);
+                    vt[i] = val[eb + k];
+                    ct[i] = w[k];
+                }
+            }
+            __syncthreads();                           // the previous chunk is consumed
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const int k = threadIdx.x + i * kBlock;
+                if (k < cnt) {
+                    vs[k] = vt[i];
+                    cs[k] = ct[i];
+                }
             }
             __syncthreads();
             // the NP rows of a lane are independent: their gathers are in

@@ -76,7 +76,7 @@ __device__ __forceinline__ T sell_row(const DevSellView &A, int slice, int lane,
     T s = T(0);
     if (!MIXED) {
         const int *__restrict__ col = A.wide;
-#pragma unroll 4
+#pragma unroll 8
         for (int e = e0 + lane; e < e1; e += kSlice) s += val[e] * x(col[e]);
         return s;
     }
@@ -205,6 +205,7 @@ __device__ __forceinline__ T csr_row(const int *__restrict__ ptr, const int *__r
 {
     T s = T(0);
     const int e1 = ptr[row + 1];
+#pragma unroll 8
     for (int e = ptr[row] + sub; e < e1; e += LPR) s += val[e] * x(col[e]);
     return group_sum<LPR>(s);
 }
@@ -304,9 +305,17 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double *__restrict__ pa
                                                    double *out, CgState st)
 {
     if (mode != FIN_PLAIN && *st.done) return;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += kBlock) s += partials[i];
-    s = block_sum(s);
+    // four accumulators, loads unrolled: all of a thread's partials in flight
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * kBlock < nparts; i += 4 * kBlock) {
+        s0 += partials[i];
+        s1 += partials[i + kBlock];
+        s2 += partials[i + 2 * kBlock];
+        s3 += partials[i + 3 * kBlock];
+    }
+    for (; i < nparts; i += kBlock) s0 += partials[i];
+    double s = block_sum((s0 + s1) + (s2 + s3));
     if (threadIdx.x != 0) return;
     if (mode == FIN_PLAIN) {
         *out = s;

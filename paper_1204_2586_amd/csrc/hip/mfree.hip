@@ -56,6 +56,7 @@ struct Acc<double> {
 __device__ __forceinline__ bool stop(const int *done) { return done != nullptr && *done != 0; }
 
 constexpr int kTetsPerWave = 16;
+constexpr int kDies = 8;
 constexpr int kWaves = kBlock / 64;
 
 // Y[slot(t, a)] = (K_t x_t)_a for all tets.
@@ -87,44 +88,86 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(MfView<T> op, const T *__
             areg[mt][s] = (row < NLOC && b < NLOC) ? op.S[row * 6 * NLOC + k * NLOC + b] : T(0);
         }
 
-    const int nwaves = gridDim.x * kWaves;
+    // Each die (workgroups are dispatched round-robin over kDies dies, b to
+    // b % kDies) takes a contiguous range of tiles, so the slots of a dof,
+    // written by neighbouring tets, fill their cache lines in one L2 instead
+    // of being written back in pieces from every die.  Any grid visits every
+    // tile exactly once; placement affects only speed.
     const int ntiles = (op.nt + kTetsPerWave - 1) / kTetsPerWave;
-    for (int tile = blockIdx.x * kWaves + (int)(threadIdx.x >> 6); tile < ntiles; tile += nwaves) {
+    int first, end, step;
+    {
+        const int b = blockIdx.x, g = gridDim.x, w = (int)(threadIdx.x >> 6);
+        if (g < kDies) {
+            first = b * kWaves + w;
+            end = ntiles;
+            step = g * kWaves;
+        } else {
+            const int d = b % kDies, j = b / kDies;
+            const int gd = (g - d + kDies - 1) / kDies;          // workgroups on die d
+            const int per = (ntiles + kDies - 1) / kDies;
+            first = d * per + j * kWaves + w;
+            end = min(ntiles, (d + 1) * per);
+            step = gd * kWaves;
+        }
+    }
+    for (int tile = first; tile < end; tile += step) {
         const int t = tile * kTetsPerWave + col;
         const bool tv = t < op.nt;
-        T wv[6], xv[NB];
+        const size_t tc = tv ? (size_t)t : 0;   // loads stay unconditional (clamped), so
+        T wv[6], xv[NB];                        // all of them are in flight together
+        int dv[NB];
 #pragma unroll
-        for (int k = 0; k < 6; k++) wv[k] = tv ? op.w[(size_t)t * 6 + k] : T(0);
+        for (int k = 0; k < 6; k++) wv[k] = op.w[tc * 6 + k];
 #pragma unroll
         for (int j = 0; j < NB; j++) {
             const int b = 4 * j + grp;
-            int d = -1;
-            if (tv && b < NLOC) d = op.emap[(size_t)t * NLOC + b];
-            xv[j] = d >= 0 ? X[d] : T(0);
+            dv[j] = op.emap[tc * NLOC + (b < NLOC ? b : 0)];
+            if (!tv || b >= NLOC) dv[j] = -1;
         }
+        // slots of this lane's results, loaded with the element map
+        int sv[MT][4];
+#pragma unroll
+        for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int a = 16 * mt + Acc<T>::row(grp, v);
+                sv[mt][v] = op.slot[tc * NLOC + (a < NLOC ? a : 0)];
+            }
+#pragma unroll
+        for (int j = 0; j < NB; j++) xv[j] = X[dv[j] >= 0 ? dv[j] : 0];
+        // keep the scheduler from interleaving the loads with their uses (it
+        // would otherwise reuse one address register and wait on each)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+                if (!tv || 16 * mt + Acc<T>::row(grp, v) >= NLOC) sv[mt][v] = -1;
+#pragma unroll
+        for (int j = 0; j < NB; j++)
+            if (dv[j] < 0) xv[j] = T(0);
+#pragma unroll
+        for (int k = 0; k < 6; k++)
+            if (!tv) wv[k] = T(0);
+
+        // B operand: lane (g, c) holds Z[(k, b)][c] = w_c,k x_c,b; formed for
+        // all steps before the contraction, so every gather is issued at once
+        T bv[KS];
+#pragma unroll
+        for (int s = 0; s < KS; s++) bv[s] = wv[s / NB] * xv[s % NB];
         typename Acc<T>::V acc[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; mt++) acc[mt] = typename Acc<T>::V{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < KS; s++) {
-            // B operand: lane (g, c) holds Z[(k, b)][c] = w_c,k x_c,b
-            const T bv = wv[s / NB] * xv[s % NB];
+        for (int s = 0; s < KS; s++)
 #pragma unroll
-            for (int mt = 0; mt < MT; mt++) acc[mt] = Acc<T>::mfma(areg[mt][s], bv, acc[mt]);
-        }
+            for (int mt = 0; mt < MT; mt++) acc[mt] = Acc<T>::mfma(areg[mt][s], bv[s], acc[mt]);
         // D: register v of this lane holds row Acc<T>::row(grp, v) of column c
-        if (tv) {
 #pragma unroll
-            for (int mt = 0; mt < MT; mt++)
+        for (int mt = 0; mt < MT; mt++)
 #pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    const int a = 16 * mt + Acc<T>::row(grp, v);
-                    if (a < NLOC) {
-                        const int p = op.slot[(size_t)t * NLOC + a];
-                        if (p >= 0) Yel[p] = acc[mt][v];
-                    }
-                }
-        }
+            for (int v = 0; v < 4; v++)
+                if (sv[mt][v] >= 0) Yel[sv[mt][v]] = acc[mt][v];
     }
 }
 
@@ -175,6 +218,8 @@ inline int cap_grid(long long need)
 template <typename T>
 void mf_apply(hipStream_t s, const MfView<T> &op, const T *x, T *Yel, const int *done)
 {
+    // (the element kernel's clamped loads read X[0]: nothing to do without unknowns)
+    if (op.n == 0 || op.nt == 0) return;
     // persistent waves: a few tiles each, so the operand tables are loaded once per wave
     const long long tiles = ((long long)op.nt + kTetsPerWave - 1) / kTetsPerWave;
     int g = (int)std::min<long long>((tiles + kWaves - 1) / kWaves, 1024);

@@ -735,6 +735,8 @@ struct aux_handle {
     }
 
     // one CG iteration: q = A p, alpha, x/r update, z = B r, beta, p update
+    // (forming p inside the product, from gathered z and p, measured twice as
+    // slow as the separate update pass)
     void cg_iteration(const CgState &st)
     {
         hipStream_t s = stream;
@@ -806,8 +808,12 @@ struct aux_handle {
         } else {
             work<double>();
         }
+        // two iterations per graph: half the gaps between graph launches
         const int key[4] = {opt.precision, opt.op, st.maxit, 1};
-        return captured(g_single, key, [&]() { cg_iteration(st); });
+        return captured(g_single, key, [&]() {
+            cg_iteration(st);
+            cg_iteration(st);
+        });
     }
 
     void drop_graph()
@@ -837,16 +843,25 @@ struct aux_handle {
         finish(s, partials, g, FIN_RZ, nullptr, st);
         cg_direction(s, n, z, p, st);
 
-        // one CG iteration as a HIP graph (its kernels have fixed arguments:
-        // the iteration index and the stopping state live in device memory);
-        // not used while kernel timing records events
+        // two CG iterations as a HIP graph (its kernels have fixed arguments:
+        // the iteration index and the stopping state live in device memory,
+        // and iterations past the stop return at once); not used while kernel
+        // timing records events
         hipGraphExec_t gexec = opt.graph && !prof_on ? iteration_graph(st) : nullptr;
         int issued = 0, iter = 0, done = 0, chunk = 2;
         while (true) {
-            for (int c = 0; c < chunk && issued < maxit; c++, issued++) {
-                prof_tag = issued + 1;
-                if (gexec) HIPCHECK(hipGraphLaunch(gexec, s));
-                else cg_iteration(st);
+            for (int c = 0; c < chunk && issued < maxit;) {
+                if (gexec) {
+                    prof_tag = issued + 1;
+                    HIPCHECK(hipGraphLaunch(gexec, s));
+                    issued += 2;
+                    c += 2;
+                } else {
+                    prof_tag = issued + 1;
+                    cg_iteration(st);
+                    issued++;
+                    c++;
+                }
             }
             HIPCHECK(hipMemcpyAsync(host_state, istate, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
