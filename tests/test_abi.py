@@ -43,7 +43,7 @@ def _mesh():
 
 
 @pytest.mark.parametrize("case", ["order", "kappa_zero", "kappa_nan", "xyz_nan", "vertex_range", "flat_tet",
-                                  "theta", "nu"])
+                                  "theta", "nu", "sell_window", "batch_tiles", "fuse_cycle", "no_interior"])
 def test_setup_rejects_bad_input(case):
     xyz, tets = _mesh()
     kappa = np.ones(len(tets))
@@ -68,6 +68,16 @@ def test_setup_rejects_bad_input(case):
         kw["theta"] = 1.5
     elif case == "nu":
         kw["nu"] = 0
+    elif case == "sell_window":
+        kw["sell_window"] = -5
+    elif case == "batch_tiles":
+        kw["batch_tiles"] = 3
+    elif case == "fuse_cycle":
+        kw["fuse_cycle"] = 2
+    elif case == "no_interior":                 # one tet: every node on the boundary
+        xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
+        tets = np.array([[0, 1, 2, 3]], dtype=np.int32)
+        kappa = None
     with pytest.raises(aux.AuxError) as e:
         aux.Solver(xyz, tets, order, kappa, **kw)
     assert e.value.code == -1
