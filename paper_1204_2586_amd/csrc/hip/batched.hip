@@ -58,7 +58,9 @@ __device__ void write_col_partials(double *partials, double v)
 constexpr int kChunk = 32;
 
 
-template <typename T, int NR, typename XL, typename BODY>
+// U: slots unrolled in the accumulation (more gathers in flight per lane;
+// worth it for A_h, not for the AMG level operators)
+template <typename T, int NR, int U, typename XL, typename BODY>
 __device__ __forceinline__ void bsell_slices(const DevSellView &A, XL xload, BODY body)
 {
     constexpr int RP = kBlock / NR, NP = kSlice / RP;
@@ -106,8 +108,9 @@ __device__ __forceinline__ void bsell_slices(const DevSellView &A, XL xload, BOD
                 }
             }
             __syncthreads();
-            // the NP rows of a lane are independent: their gathers are in
-            // flight together
+            // the NP rows of a lane are independent: their gathers (for U
+            // slots) are in flight together
+#pragma unroll U
             for (int jj = 0; jj < jn; jj++) {
                 T xv[NP], vv[NP];
 #pragma unroll
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void kb_sweep(DevSellView A, const T *__res
 {
     if (stop_all(all_done)) return;
     double acc = 0.0;
-    bsell_slices<T, NR>(A, [&](int j, int c) { return Zin[(size_t)j * NR + c]; }, [&](int row, int c, T s) {
+    bsell_slices<T, NR, 4>(A, [&](int j, int c) { return Zin[(size_t)j * NR + c]; }, [&](int row, int c, T s) {
         size_t o = (size_t)row * NR + c;
         T zi = Zin[o] + dinv[row] * ((T)RHS[o] - s);
         Zout[o] = (TZ)zi;
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void kb_resid(DevSellView A, const T *__res
                                                    T *__restrict__ Res, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    bsell_slices<T, NR>(A, [&](int j, int c) { return Z[(size_t)j * NR + c]; }, [&](int row, int c, T s) {
+    bsell_slices<T, NR, 4>(A, [&](int j, int c) { return Z[(size_t)j * NR + c]; }, [&](int row, int c, T s) {
         size_t o = (size_t)row * NR + c;
         Res[o] = RHS[o] - s;
     });
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void kb_spmv64(DevSellView A, const double 
 {
     if (stop_all(all_done)) return;
     double acc = 0.0;
-    bsell_slices<double, NR>(A, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int row, int c, double s) {
+    bsell_slices<double, NR, 4>(A, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int row, int c, double s) {
         size_t o = (size_t)row * NR + c;
         if (RESID) {
             Y[o] = F[o] - s;
@@ -309,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void kb_lmatvec(DevSellView M, const int *_
                                                      const T *__restrict__ X, T *__restrict__ Y, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    bsell_slices<T, NR>(M, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
+    bsell_slices<T, NR, 1>(M, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
         size_t o = (size_t)perm[r] * NR + c;
         if (MODE) Y[o] += s;
         else Y[o] = s;
@@ -323,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void kb_lmatvec2(DevSellView M, const int *
                                                       T *__restrict__ Y, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    bsell_slices<T, NR>(
+    bsell_slices<T, NR, 1>(
         M, [&](int j, int c) { return j < split ? X1[(size_t)j * NR + c] : X2[(size_t)(j - split) * NR + c]; },
         [&](int r, int c, T s) { Y[(size_t)perm[r] * NR + c] = s; });
 }
@@ -335,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void kb_lvpre(DevSellView A, const int *__r
                                                    T *__restrict__ X, T *__restrict__ R, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    bsell_slices<T, NR>(A, [&](int j, int c) { return dinv[j] * B[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
+    bsell_slices<T, NR, 1>(A, [&](int j, int c) { return dinv[j] * B[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
         const int i = perm[r];
         size_t o = (size_t)i * NR + c;
         T b = B[o];
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void kb_lsweep(DevSellView A, const int *__
                                                     const T *__restrict__ X, T *__restrict__ Y, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    bsell_slices<T, NR>(A, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
+    bsell_slices<T, NR, 1>(A, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
         const int i = perm[r];
         size_t o = (size_t)i * NR + c;
         Y[o] = X[o] + dinv[i] * (B[o] - s);
@@ -490,6 +493,38 @@ __global__ __launch_bounds__(kBlock) void kb_cg_update(int n, double *__restrict
             R[o] = ri;
         }
         acc += ri * ri;
+    }
+    write_col_partials<NR>(partials, acc);
+}
+
+// the update fused with the preconditioner's first sweep from zero (the
+// expressions of kb_jacobi0): Z0 = D^-1 R and RT = R in the type T
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void kb_cg_update_prep(int n, double *__restrict__ X, double *__restrict__ R,
+                                                            const double *__restrict__ P,
+                                                            const double *__restrict__ Q, BCgState st,
+                                                            double *partials, const T *__restrict__ dinv,
+                                                            T *__restrict__ Z0, T *__restrict__ RT)
+{
+    if (*st.all_done) return;
+    const int k = *st.k;
+    const int c = threadIdx.x % NR;
+    const bool active = st.done[c] == 0;
+    const double alpha = active ? st.rz[(size_t)k * NR + c] / st.pq[(size_t)k * NR + c] : 0.0;
+    double acc = 0.0;
+    FOR_BROWS(NR, n)
+    {
+        size_t o = (size_t)row * NR + c_;
+        double ri = R[o];
+        if (active) {
+            X[o] += alpha * P[o];
+            ri -= alpha * Q[o];
+            R[o] = ri;
+        }
+        acc += ri * ri;
+        T rt = (T)ri;
+        Z0[o] = dinv[row] * rt;
+        if (RT) RT[o] = rt;
     }
     write_col_partials<NR>(partials, acc);
 }
@@ -726,6 +761,20 @@ int bcg_update(hipStream_t s, int nr, int n, double *X, double *R, const double 
     NR_SWITCH(nr, hipLaunchKernelGGL((kb_cg_update<NR>), dim3(g), dim3(kBlock), 0, s, n, X, R, P, Q, st, partials));
     return g;
 }
+
+template <typename T>
+int bcg_update_prep(hipStream_t s, int nr, int n, double *X, double *R, const double *P, const double *Q,
+                    const BCgState &st, double *partials, const T *dinv, T *Z0, T *RT)
+{
+    int g = brows_grid(n, nr);
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_cg_update_prep<T, NR>), dim3(g), dim3(kBlock), 0, s, n, X, R, P, Q, st,
+                                     partials, dinv, Z0, RT));
+    return g;
+}
+template int bcg_update_prep<float>(hipStream_t, int, int, double *, double *, const double *, const double *,
+                                    const BCgState &, double *, const float *, float *, float *);
+template int bcg_update_prep<double>(hipStream_t, int, int, double *, double *, const double *, const double *,
+                                     const BCgState &, double *, const double *, double *, double *);
 
 void bcg_direction(hipStream_t s, int nr, int n, const double *Z, double *P, const BCgState &st)
 {

@@ -74,6 +74,11 @@ void bfinish(hipStream_t s, int nr, const double *partials, int nparts, FinishMo
 void bcg_init(hipStream_t s, int nr, const BCgState &st, double tol2, const double *ff, const double *rr0);
 int bcg_update(hipStream_t s, int nr, int n, double *X, double *R, const double *P, const double *Q,
                const BCgState &st, double *partials);
+// the same, also writing the preconditioner's first sweep from zero
+// (Z0 = D^-1 R) and, with RT non-null, R in the preconditioner's type
+template <typename T>
+int bcg_update_prep(hipStream_t s, int nr, int n, double *X, double *R, const double *P, const double *Q,
+                    const BCgState &st, double *partials, const T *dinv, T *Z0, T *RT);
 void bcg_direction(hipStream_t s, int nr, int n, const double *Z, double *P, const BCgState &st);
 void bgather(hipStream_t s, int nr, int n, int ld, const int *perm, const double *x, double *y);
 void bscatter(hipStream_t s, int nr, int n, int ld, const int *perm, const double *x, double *y);

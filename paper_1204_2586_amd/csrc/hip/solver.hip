@@ -1183,7 +1183,7 @@ struct aux_handle {
 
     // Zout = B Rin for the nr columns of a block (internal order)
     template <typename T>
-    int bapply_B(const double *Rin, double *Zout, double *rz_partials, const int *all_done)
+    int bapply_B(const double *Rin, double *Zout, double *rz_partials, const int *all_done, bool prepped = false)
     {
         Work<T> &w = bwork<T>();
         hipStream_t s = stream;
@@ -1195,9 +1195,12 @@ struct aux_handle {
         T *rTbuf = std::is_same<T, float>::value ? w.rT : nullptr;
         T *zc = w.za, *zn = w.zb;
         int pb = pbeg(AUX_PROF_APPLY);
-        int pk = pbeg(AUX_PROF_PK_FIRST);
-        bjacobi0<T>(s, nr, disc.ndof, d, Rin, zc, rTbuf, all_done);
-        pend(pk);
+        int pk = -1;
+        if (!prepped) {
+            pk = pbeg(AUX_PROF_PK_FIRST);
+            bjacobi0<T>(s, nr, disc.ndof, d, Rin, zc, rTbuf, all_done);
+            pend(pk);
+        }
         const T *rT = rTbuf ? (const T *)rTbuf : (const T *)(const void *)Rin;
         for (int k = 1; k < nu; k++) {
             pk = pbeg(AUX_PROF_PK_SWEEP);
@@ -1238,14 +1241,14 @@ struct aux_handle {
         return g;
     }
 
-    int bapply(const double *Rin, double *Zout, double *rz_partials, const int *all_done)
+    int bapply(const double *Rin, double *Zout, double *rz_partials, const int *all_done, bool prepped = false)
     {
         ensure_bops();
         if (opt.precision == AUX_MIXED) {
             ensure_fp32();
-            return bapply_B<float>(Rin, Zout, rz_partials, all_done);
+            return bapply_B<float>(Rin, Zout, rz_partials, all_done, prepped);
         }
-        return bapply_B<double>(Rin, Zout, rz_partials, all_done);
+        return bapply_B<double>(Rin, Zout, rz_partials, all_done, prepped);
     }
 
     // one lock-step iteration of every column: Q = A P, alpha, X/R update,
@@ -1261,9 +1264,17 @@ struct aux_handle {
                    : bsell_spmv64(s, nr, A64, bt.P, bt.Q, bt.partials, st.all_done);
         pend(pk);
         bfinish(s, nr, bt.partials, g, FIN_PQ, nullptr, st);
-        g = bcg_update(s, nr, n, bt.X, bt.R, bt.P, bt.Q, st, bt.partials);
+        // the update also starts the preconditioner: Z = D^-1 R
+        if (opt.precision == AUX_MIXED) {
+            ensure_fp32();
+            Work<float> &w = bwork<float>();
+            g = bcg_update_prep<float>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, st, bt.partials, dinv32, w.za, w.rT);
+        } else {
+            Work<double> &w = bwork<double>();
+            g = bcg_update_prep<double>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, st, bt.partials, dinv64, w.za, nullptr);
+        }
         bfinish(s, nr, bt.partials, g, FIN_RR, nullptr, st);
-        g = bapply(bt.R, bt.Z, bt.partials, st.all_done);
+        g = bapply(bt.R, bt.Z, bt.partials, st.all_done, true);
         bfinish(s, nr, bt.partials, g, FIN_RZ, nullptr, st);
         bcg_direction(s, nr, n, bt.Z, bt.P, st);
     }
