@@ -68,6 +68,9 @@ __device__ __forceinline__ void bsell_slices(const DevSellView &A, XL xload, BOD
     __shared__ int cs[kChunk * kSlice];
     const T *__restrict__ val = (const T *)A.val;
     const int c = threadIdx.x % NR, rl0 = threadIdx.x / NR;
+    // slices go round-robin over the workgroups (and so over the dies):
+    // giving each die a contiguous share of equal entries measured slower
+    // for every block kernel here (the sweeps by 9%, I_P by 38%)
     for (int sl = blockIdx.x; sl < A.nslices; sl += gridDim.x) {
         const int e0 = A.slice_off[sl], width = (A.slice_off[sl + 1] - e0) / kSlice;
         const int mode = A.mode[sl];
@@ -307,12 +310,12 @@ __global__ __launch_bounds__(kTileBlock) void kt_spmv64(DevTilesView A, const do
 // Row-permuted sliced ELL: internal row r of M is row perm[r] of the
 // operator; columns are not renumbered.
 
-template <typename T, int NR, int MODE>   // MODE 0: Y = M X, 1: Y += M X
+template <typename T, int NR, int MODE, int U>   // MODE 0: Y = M X, 1: Y += M X
 __global__ __launch_bounds__(kBlock) void kb_lmatvec(DevSellView M, const int *__restrict__ perm,
                                                      const T *__restrict__ X, T *__restrict__ Y, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    bsell_slices<T, NR, 1>(M, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
+    bsell_slices<T, NR, U>(M, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
         size_t o = (size_t)perm[r] * NR + c;
         if (MODE) Y[o] += s;
         else Y[o] = s;
@@ -320,25 +323,26 @@ __global__ __launch_bounds__(kBlock) void kb_lmatvec(DevSellView M, const int *_
 }
 
 // Y = M [X1; X2] (columns below split index X1, the others X2)
-template <typename T, int NR>
+template <typename T, int NR, int U>
 __global__ __launch_bounds__(kBlock) void kb_lmatvec2(DevSellView M, const int *__restrict__ perm,
                                                       const T *__restrict__ X1, const T *__restrict__ X2, int split,
                                                       T *__restrict__ Y, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    bsell_slices<T, NR, 1>(
+    bsell_slices<T, NR, U>(
         M, [&](int j, int c) { return j < split ? X1[(size_t)j * NR + c] : X2[(size_t)(j - split) * NR + c]; },
         [&](int r, int c, T s) { Y[(size_t)perm[r] * NR + c] = s; });
 }
 
-// X = D^-1 B, R = B - A X: the product gathers D^-1 B directly
-template <typename T, int NR>
-__global__ __launch_bounds__(kBlock) void kb_lvpre(DevSellView A, const int *__restrict__ perm,
+// X = D^-1 B, R = B - A X, with AD the values of A D^-1: the product
+// gathers B alone (one load per slot keeps the unrolled gathers in flight)
+template <typename T, int NR, int U>
+__global__ __launch_bounds__(kBlock) void kb_lvpre(DevSellView AD, const int *__restrict__ perm,
                                                    const T *__restrict__ dinv, const T *__restrict__ B,
                                                    T *__restrict__ X, T *__restrict__ R, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    bsell_slices<T, NR, 1>(A, [&](int j, int c) { return dinv[j] * B[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
+    bsell_slices<T, NR, U>(AD, [&](int j, int c) { return B[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
         const int i = perm[r];
         size_t o = (size_t)i * NR + c;
         T b = B[o];
@@ -348,13 +352,13 @@ __global__ __launch_bounds__(kBlock) void kb_lvpre(DevSellView A, const int *__r
 }
 
 // Y = X + D^-1 (B - A X)
-template <typename T, int NR>
+template <typename T, int NR, int U>
 __global__ __launch_bounds__(kBlock) void kb_lsweep(DevSellView A, const int *__restrict__ perm,
                                                     const T *__restrict__ dinv, const T *__restrict__ B,
                                                     const T *__restrict__ X, T *__restrict__ Y, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    bsell_slices<T, NR, 1>(A, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
+    bsell_slices<T, NR, U>(A, [&](int j, int c) { return X[(size_t)j * NR + c]; }, [&](int r, int c, T s) {
         const int i = perm[r];
         size_t o = (size_t)i * NR + c;
         Y[o] = X[o] + dinv[i] * (B[o] - s);
@@ -688,41 +692,60 @@ int bsell_residual64(hipStream_t s, int nr, const DevSellView &A, const double *
     return g;
 }
 
+// unroll: slots per lane whose gathers are in flight together (1 or 4).
+// Four pays off on operators with long rows (the level matrices, the
+// restrictions); on the short rows of the prolongations the extra registers
+// cost more occupancy than the overlap gains.
+#define U_SWITCH(unroll, CALL)             \
+    do {                                   \
+        if ((unroll) >= 4) {               \
+            constexpr int U = 4;           \
+            CALL;                          \
+        } else {                           \
+            constexpr int U = 1;           \
+            CALL;                          \
+        }                                  \
+    } while (0)
+
 template <typename T>
-void blevel_matvec(hipStream_t s, int nr, const DevSellView &M, const int *perm, const T *X, T *Y, bool add,
-                   const int *all_done)
+void blevel_matvec(hipStream_t s, int nr, const DevSellView &M, int unroll, const int *perm, const T *X, T *Y,
+                   bool add, const int *all_done)
 {
     int g = bsell_grid(M);
     if (add) {
-        NR_SWITCH(nr, hipLaunchKernelGGL((kb_lmatvec<T, NR, 1>), dim3(g), dim3(kBlock), 0, s, M, perm, X, Y, all_done));
+        U_SWITCH(unroll, NR_SWITCH(nr, hipLaunchKernelGGL((kb_lmatvec<T, NR, 1, U>), dim3(g), dim3(kBlock), 0, s, M, perm,
+                                                     X, Y, all_done)));
     } else {
-        NR_SWITCH(nr, hipLaunchKernelGGL((kb_lmatvec<T, NR, 0>), dim3(g), dim3(kBlock), 0, s, M, perm, X, Y, all_done));
+        U_SWITCH(unroll, NR_SWITCH(nr, hipLaunchKernelGGL((kb_lmatvec<T, NR, 0, U>), dim3(g), dim3(kBlock), 0, s, M, perm,
+                                                     X, Y, all_done)));
     }
 }
 
 template <typename T>
-void blevel_matvec2(hipStream_t s, int nr, const DevSellView &M, const int *perm, const T *X1, const T *X2, int split,
+void blevel_matvec2(hipStream_t s, int nr, const DevSellView &M, int unroll, const int *perm, const T *X1, const T *X2, int split,
                     T *Y, const int *all_done)
 {
     int g = bsell_grid(M);
-    NR_SWITCH(nr, hipLaunchKernelGGL((kb_lmatvec2<T, NR>), dim3(g), dim3(kBlock), 0, s, M, perm, X1, X2, split, Y,
-                                     all_done));
+    U_SWITCH(unroll, NR_SWITCH(nr, hipLaunchKernelGGL((kb_lmatvec2<T, NR, U>), dim3(g), dim3(kBlock), 0, s, M, perm, X1,
+                                                 X2, split, Y, all_done)));
 }
 
 template <typename T>
-void blevel_vpre(hipStream_t s, int nr, const DevSellView &A, const int *perm, const T *dinv, const T *B, T *X, T *R,
+void blevel_vpre(hipStream_t s, int nr, const DevSellView &AD, int unroll, const int *perm, const T *dinv, const T *B, T *X, T *R,
                  const int *all_done)
 {
-    int g = bsell_grid(A);
-    NR_SWITCH(nr, hipLaunchKernelGGL((kb_lvpre<T, NR>), dim3(g), dim3(kBlock), 0, s, A, perm, dinv, B, X, R, all_done));
+    int g = bsell_grid(AD);
+    U_SWITCH(unroll, NR_SWITCH(nr, hipLaunchKernelGGL((kb_lvpre<T, NR, U>), dim3(g), dim3(kBlock), 0, s, AD, perm, dinv,
+                                                 B, X, R, all_done)));
 }
 
 template <typename T>
-void blevel_sweep(hipStream_t s, int nr, const DevSellView &A, const int *perm, const T *dinv, const T *B, const T *X,
+void blevel_sweep(hipStream_t s, int nr, const DevSellView &A, int unroll, const int *perm, const T *dinv, const T *B, const T *X,
                   T *Y, const int *all_done)
 {
     int g = bsell_grid(A);
-    NR_SWITCH(nr, hipLaunchKernelGGL((kb_lsweep<T, NR>), dim3(g), dim3(kBlock), 0, s, A, perm, dinv, B, X, Y, all_done));
+    U_SWITCH(unroll, NR_SWITCH(nr, hipLaunchKernelGGL((kb_lsweep<T, NR, U>), dim3(g), dim3(kBlock), 0, s, A, perm, dinv,
+                                                 B, X, Y, all_done)));
 }
 
 
@@ -802,13 +825,13 @@ void bscatter(hipStream_t s, int nr, int n, int ld, const int *perm, const doubl
     template int bsell_sweep<T, T, T>(hipStream_t, int, const DevSellView &, const T *, const T *, const T *, T *, \
                                       const double *, double *, const int *);                                      \
     template int bsell_resid<T>(hipStream_t, int, const DevSellView &, const T *, const T *, T *, const int *);    \
-    template void blevel_matvec<T>(hipStream_t, int, const DevSellView &, const int *, const T *, T *, bool,      \
+    template void blevel_matvec<T>(hipStream_t, int, const DevSellView &, int, const int *, const T *, T *, bool,      \
                                    const int *);                                                                   \
-    template void blevel_matvec2<T>(hipStream_t, int, const DevSellView &, const int *, const T *, const T *, int, \
+    template void blevel_matvec2<T>(hipStream_t, int, const DevSellView &, int, const int *, const T *, const T *, int, \
                                     T *, const int *);                                                             \
-    template void blevel_vpre<T>(hipStream_t, int, const DevSellView &, const int *, const T *, const T *, T *,     \
+    template void blevel_vpre<T>(hipStream_t, int, const DevSellView &, int, const int *, const T *, const T *, T *,     \
                                  T *, const int *);                                                                \
-    template void blevel_sweep<T>(hipStream_t, int, const DevSellView &, const int *, const T *, const T *,         \
+    template void blevel_sweep<T>(hipStream_t, int, const DevSellView &, int, const int *, const T *, const T *,         \
                                   const T *, T *, const int *);                                                    \
     template void bdense<T>(hipStream_t, int, int, const T *, const T *, T *, const int *);
 

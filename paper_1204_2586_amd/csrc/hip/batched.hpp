@@ -51,19 +51,19 @@ int bsell_residual64(hipStream_t s, int nr, const DevSellView &A, const double *
 // AMG levels and transfers as row-permuted sliced ELL (row r of M is row
 // perm[r] of the operator, columns not renumbered)
 template <typename T>
-void blevel_matvec(hipStream_t s, int nr, const DevSellView &M, const int *perm, const T *X, T *Y, bool add,
+void blevel_matvec(hipStream_t s, int nr, const DevSellView &M, int unroll, const int *perm, const T *X, T *Y, bool add,
                    const int *all_done);
 // Y = M [X1; X2] (columns below split index X1, the others X2)
 template <typename T>
-void blevel_matvec2(hipStream_t s, int nr, const DevSellView &M, const int *perm, const T *X1, const T *X2, int split,
+void blevel_matvec2(hipStream_t s, int nr, const DevSellView &M, int unroll, const int *perm, const T *X1, const T *X2, int split,
                     T *Y, const int *all_done);
-// X = D^-1 B, R = B - A X
+// X = D^-1 B, R = B - (A D^-1) B; AD holds the values of A D^-1
 template <typename T>
-void blevel_vpre(hipStream_t s, int nr, const DevSellView &A, const int *perm, const T *dinv, const T *B, T *X, T *R,
+void blevel_vpre(hipStream_t s, int nr, const DevSellView &AD, int unroll, const int *perm, const T *dinv, const T *B, T *X, T *R,
                  const int *all_done);
 // Y = X + D^-1 (B - A X)
 template <typename T>
-void blevel_sweep(hipStream_t s, int nr, const DevSellView &A, const int *perm, const T *dinv, const T *B, const T *X,
+void blevel_sweep(hipStream_t s, int nr, const DevSellView &A, int unroll, const int *perm, const T *dinv, const T *B, const T *X,
                   T *Y, const int *all_done);
 template <typename T>
 void bdense(hipStream_t s, int nr, int n, const T *Ainv, const T *B, T *X, const int *all_done);

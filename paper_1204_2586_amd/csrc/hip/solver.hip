@@ -1077,8 +1077,21 @@ struct aux_handle {
     struct BOp {
         DevSell m;
         int *perm = nullptr;
+        // level matrices only: the values of A D^-1 (D = diag of the l1
+        // norms), formed in FP64 and rounded once, in the same layout, so
+        // the pre-smoothing residual b - A D^-1 b gathers b alone
+        double *s64 = nullptr;
+        float *s32 = nullptr;
+        int unroll = 1;          // slots in flight per lane in the block kernels
         template <typename T>
         DevSellView view() const { return m.view<T>(); }
+        template <typename T>
+        DevSellView scaled_view() const
+        {
+            DevSellView v = m.view<T>();
+            v.val = std::is_same<T, float>::value ? (const void *)s32 : (const void *)s64;
+            return v;
+        }
     };
     std::vector<BOp> bA, bP, bR;
     BOp bIP, bIR, bRF;
@@ -1124,6 +1137,8 @@ struct aux_handle {
         return &tiles[k];
     }
 
+    static constexpr double kLongRow = 8.0;   // mean entries per row
+    static constexpr int kFewSlices = 512;
     BOp upload_bop(const Csr &op)
     {
         Sell sl;
@@ -1132,6 +1147,12 @@ struct aux_handle {
         b.m = upload_sell(sl);
         b.m.v32 = upload(to_f32(sl.val));
         b.perm = upload(sl.perm);
+        // long rows (level matrices, restrictions) take the unrolled kernels,
+        // and so do small operators, whose few slices leave the chip idle and
+        // make every pass latency-bound; the short rows (a few entries) of
+        // the large prolongations do not
+        const bool long_rows = (double)op.col.size() >= kLongRow * op.n;
+        b.unroll = op.n > 0 && (long_rows || sl.nslices < kFewSlices) ? 4 : 1;
         return b;
     }
 
@@ -1150,6 +1171,12 @@ struct aux_handle {
             const AmgLevel &hl = hier.levels[l];
             if (l + 1 == L) continue;                 // coarsest: dense inverse
             bA[l] = upload_bop(hl.A);
+            Csr ad = hl.A;
+            for (size_t e = 0; e < ad.val.size(); e++) ad.val[e] /= hl.l1[ad.col[e]];
+            Sell sl;
+            build_sell(ad, kSlice, kSellWindow, false, sl, false);
+            bA[l].s64 = upload(sl.val);
+            bA[l].s32 = upload(to_f32(sl.val));
             bP[l] = upload_bop(hl.P);
             bR[l] = upload_bop(hl.R);
         }
@@ -1173,11 +1200,11 @@ struct aux_handle {
             return w.x[l];
         }
         const BOp &A_ = bA[l], &P_ = bP[l], &R_ = bR[l];
-        blevel_vpre<T>(s, nr, A_.view<T>(), A_.perm, ldinv<T>(l), w.b[l], w.x[l], w.r[l], all_done);
-        blevel_matvec<T>(s, nr, R_.view<T>(), R_.perm, w.r[l], w.b[l + 1], false, all_done);
+        blevel_vpre<T>(s, nr, A_.scaled_view<T>(), A_.unroll, A_.perm, ldinv<T>(l), w.b[l], w.x[l], w.r[l], all_done);
+        blevel_matvec<T>(s, nr, R_.view<T>(), R_.unroll, R_.perm, w.r[l], w.b[l + 1], false, all_done);
         const T *e = bvcycle<T>(l + 1, all_done);
-        blevel_matvec<T>(s, nr, P_.view<T>(), P_.perm, e, w.x[l], true, all_done);
-        blevel_sweep<T>(s, nr, A_.view<T>(), A_.perm, ldinv<T>(l), w.b[l], w.x[l], w.y[l], all_done);
+        blevel_matvec<T>(s, nr, P_.view<T>(), P_.unroll, P_.perm, e, w.x[l], true, all_done);
+        blevel_sweep<T>(s, nr, A_.view<T>(), A_.unroll, A_.perm, ldinv<T>(l), w.b[l], w.x[l], w.y[l], all_done);
         return w.y[l];
     }
 
@@ -1212,7 +1239,7 @@ struct aux_handle {
         if (!lev.empty()) {
             pk = pbeg(AUX_PROF_PK_RESID);
             if (opt.fuse_cycle) {
-                blevel_matvec2<T>(s, nr, bRF.view<T>(), bRF.perm, rT, zc, disc.ndof, w.b[0], all_done);
+                blevel_matvec2<T>(s, nr, bRF.view<T>(), bRF.unroll, bRF.perm, rT, zc, disc.ndof, w.b[0], all_done);
                 pend(pk);
                 pk = pbeg(AUX_PROF_COARSE);
             } else {
@@ -1220,10 +1247,10 @@ struct aux_handle {
                 else bsell_resid<T>(s, nr, Av, rT, zc, w.res, all_done);
                 pend(pk);
                 pk = pbeg(AUX_PROF_COARSE);
-                blevel_matvec<T>(s, nr, bIR.view<T>(), bIR.perm, w.res, w.b[0], false, all_done);
+                blevel_matvec<T>(s, nr, bIR.view<T>(), bIR.unroll, bIR.perm, w.res, w.b[0], false, all_done);
             }
             const T *e0 = bvcycle<T>(0, all_done);
-            blevel_matvec<T>(s, nr, bIP.view<T>(), bIP.perm, e0, zc, true, all_done);
+            blevel_matvec<T>(s, nr, bIP.view<T>(), bIP.unroll, bIP.perm, e0, zc, true, all_done);
             pend(pk);
         }
         for (int k = 1; k < nu; k++) {
