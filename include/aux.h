@@ -230,7 +230,11 @@ int pcg_solve(aux_handle *h, const double *f, double *u, double tol, int maxit, 
 /* nrhs independent CG solves in lock-step sharing every sparse-matrix pass.
  * F, U: device row-major [n_h][nrhs] (column j is right-hand side j).  Each
  * column follows exactly the single-right-hand-side algorithm and stops on
- * its own criterion.  infos: host [nrhs] or NULL.  Returns the worst status. */
+ * its own criterion.  infos: host [nrhs] or NULL.  Returns the worst status.
+ * The device blocks are n_h x w with w = nrhs rounded up to a power of two
+ * (at least 8); the block kernels address them with 32-bit byte offsets, so
+ * n_h * w * 8 bytes must not exceed 4 GiB (AUX_EINVAL otherwise: solve fewer
+ * right-hand sides per call). */
 int pcg_solve_batched(aux_handle *h, const double *F, double *U, int nrhs, double tol, int maxit,
                       aux_solve_info *infos);
 

@@ -1312,6 +1312,9 @@ struct aux_handle {
         if (maxit <= 0) maxit = opt.maxit;
         int nr = 8;
         while (nr < nrhs) nr *= 2;
+        if ((uint64_t)disc.ndof * nr * sizeof(double) > (uint64_t(1) << 32))
+            throw AuxError(AUX_EINVAL, "block of n_h x " + std::to_string(nr) +
+                                           " doubles exceeds 4 GiB; solve fewer right-hand sides per call");
         ensure_batch(nr, maxit);
         hipStream_t s = stream;
         const int n = disc.ndof;
