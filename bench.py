@@ -57,6 +57,17 @@ def measured_traffic(workload, operator, category, precision):
     return None
 
 
+def cycle_lanes(info):
+    """Storage the setup chose for the V-cycle's operators: "ell<L>" row-split
+    sliced ELL with L lanes per row, "csr<L>" CSR with L lanes per row."""
+    def name(v):
+        return f"ell{v}" if v > 0 else (f"csr{-v}" if v < 0 else "-")
+    levels = max(int(info.levels) - 1, 0)
+    return {"restrict": name(info.lanes_restrict), "prolong": name(info.lanes_prolong),
+            "down": [name(info.lanes_down[l]) for l in range(levels)],
+            "up": [name(info.lanes_up[l]) for l in range(levels)]}
+
+
 def index_bytes_per_entry(info):
     """Column-stream bytes per entry of the device A_h layout (16-bit offsets
     in some slices, 32-bit columns in the others), and the per-slice
@@ -225,6 +236,7 @@ def run(args):
                    "setup_s": round(setup_s, 2), "sell_window": int(s.info.sell_window),
                    "sell_16bit_slices": f"{int(s.info.sell_narrow_slices)}/{int(s.info.sell_slices)}",
                    "sell_tune_ms": [round(v, 4) for v in s.info.sell_tune_ms],
+                   "cycle_lanes": cycle_lanes(s.info),
                    "ms_per_step_profiled": round(mixed["ms_profiled"], 3)},
         "fp64": {"value": n / (fp64["ms"] * 1e-3), "ms_per_step": fp64["ms"],
                  "iterations": fp64["iterations"][-1], "true_rel_residual": fp64["true_rel_residual"],

@@ -106,6 +106,15 @@ typedef struct aux_options {
                                 precision (slices when sell_window > 0).  The products are
                                 identical; the inner products' partial sums are grouped
                                 differently (results agree to rounding) */
+    int cycle_lanes;         /* storage of the V-cycle's sparse operators (fused restriction,
+                                I_P, fused level operators) in the single-vector solve:
+                                0 (default) the fastest of CSR with 2-32 lanes per row and
+                                row-split sliced ELL with 1-32 lanes per row, timed per
+                                operator (for the level operators only on levels of at least
+                                8192 rows; CSR by a rule of the mean row length when
+                                sell_window > 0); L in {1,2,4,8,16,32}: row-split ELL with L
+                                lanes for all of them; -L: CSR with L lanes for all of them.
+                                Results agree to rounding (per-row summation order) */
 } aux_options;
 
 typedef struct aux_device {
@@ -144,6 +153,13 @@ typedef struct aux_info {
                                 candidate layouts: global sort with 16-bit offsets, global
                                 sort 32-bit, 4096-row windows 16-bit, windows 32-bit; 0 for a
                                 candidate not timed */
+    /* Storage of the V-cycle's sparse operators in the single-vector solve:
+     * L > 0 row-split sliced ELL with L lanes per row (64 / L rows per
+     * wavefront), -L CSR with L lanes per row. */
+    int32_t lanes_restrict;  /* fused restriction [I_R, -I_R A_h] (0 if not fused) */
+    int32_t lanes_prolong;   /* I_P */
+    int32_t lanes_down[32];  /* fused down operator of level l */
+    int32_t lanes_up[32];    /* fused up operator of level l */
 } aux_info;
 
 typedef struct aux_solve_info {

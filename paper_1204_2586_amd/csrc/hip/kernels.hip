@@ -225,6 +225,37 @@ __global__ __launch_bounds__(kBlock) void k_csr_matvec(int n, const int *__restr
     }
 }
 
+// Row-split sliced ELL product, one wavefront per slice of 64 / L rows.
+// MODE 0: y = M x1; 1: y += M x1; 2: y = M [x1; x2] (columns below split
+// index x1).  Every slot is one coalesced load of 64 values and 64 columns;
+// the slot count is uniform over the wavefront.
+template <typename T, int L, int MODE>
+__global__ __launch_bounds__(kBlock) void k_ell_matvec(int n, const int *__restrict__ off, const int *__restrict__ col,
+                                                       const T *__restrict__ val, const T *__restrict__ x1,
+                                                       const T *__restrict__ x2, int split, T *__restrict__ y,
+                                                       const int *done)
+{
+    if (stop(done)) return;
+    constexpr int C = 64 / L;
+    const int lane = threadIdx.x % 64;
+    const int nsl = (n + C - 1) / C;
+    for (int sl = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x / 64); sl < nsl; sl += gridDim.x * (kBlock / 64)) {
+        const int e1 = off[sl + 1];
+        T acc = T(0);
+#pragma unroll 8
+        for (int e = off[sl] + lane; e < e1; e += 64) {
+            const int j = col[e];
+            acc += val[e] * (MODE == 2 ? (j < split ? x1[j] : x2[j - split]) : x1[j]);
+        }
+        acc = group_sum<L>(acc);
+        const int row = sl * C + lane / L;
+        if (lane % L == 0 && row < n) {
+            if (MODE == 1) y[row] += acc;
+            else y[row] = acc;
+        }
+    }
+}
+
 // y = M [x1; x2]: columns below `split` index x1, the others x2
 template <typename T, int LPR>
 __global__ __launch_bounds__(kBlock) void k_csr_matvec2(int n, const int *__restrict__ ptr, const int *__restrict__ col,
@@ -518,9 +549,24 @@ int sell_residual64(hipStream_t s, const DevSellView &A, const double *f, const 
     return g;
 }
 
+static int ell_grid(int n, int lanes)
+{
+    const long long slices = ((long long)n * lanes + 63) / 64;
+    return grid_cap((slices + kBlock / 64 - 1) / (kBlock / 64));
+}
+
+template <typename T, int MODE>
+void ell_matvec(hipStream_t s, const DevCsrView &M, const T *x1, const T *x2, int split, T *y, const int *done)
+{
+    LPR_SWITCH(M.ell_lanes, hipLaunchKernelGGL((k_ell_matvec<T, L, MODE>), dim3(ell_grid(M.n, L)), dim3(kBlock), 0, s,
+                                               M.n, M.ell_off, M.ell_col, (const T *)M.ell_val, x1, x2, split, y,
+                                               done));
+}
+
 template <typename T>
 void csr_matvec(hipStream_t s, const DevCsrView &M, const T *x, T *y, const int *done)
 {
+    if (M.ell_lanes > 0) return ell_matvec<T, 0>(s, M, x, nullptr, 0, y, done);
     LPR_SWITCH(M.lpr, hipLaunchKernelGGL((k_csr_matvec<T, L, false>), dim3(rows_grid(M.n, L)), dim3(kBlock), 0, s,
                                          M.n, M.ptr, M.col, (const T *)M.val, x, y, done));
 }
@@ -528,6 +574,7 @@ void csr_matvec(hipStream_t s, const DevCsrView &M, const T *x, T *y, const int 
 template <typename T>
 void csr_matvec_add(hipStream_t s, const DevCsrView &M, const T *e, T *x, const int *done)
 {
+    if (M.ell_lanes > 0) return ell_matvec<T, 1>(s, M, e, nullptr, 0, x, done);
     LPR_SWITCH(M.lpr, hipLaunchKernelGGL((k_csr_matvec<T, L, true>), dim3(rows_grid(M.n, L)), dim3(kBlock), 0, s,
                                          M.n, M.ptr, M.col, (const T *)M.val, e, x, done));
 }
@@ -535,6 +582,7 @@ void csr_matvec_add(hipStream_t s, const DevCsrView &M, const T *e, T *x, const 
 template <typename T>
 void csr_matvec2(hipStream_t s, const DevCsrView &M, const T *x1, const T *x2, int split, T *y, const int *done)
 {
+    if (M.ell_lanes > 0) return ell_matvec<T, 2>(s, M, x1, x2, split, y, done);
     LPR_SWITCH(M.lpr, hipLaunchKernelGGL((k_csr_matvec2<T, L>), dim3(rows_grid(M.n, L)), dim3(kBlock), 0, s, M.n,
                                          M.ptr, M.col, (const T *)M.val, x1, x2, split, y, done));
 }

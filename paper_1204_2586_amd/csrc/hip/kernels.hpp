@@ -31,6 +31,15 @@ struct DevCsrView {
     const int *col;
     const void *val;     // double or float
     int lpr;
+    // Row-split sliced ELL copy of the same operator (ell_lanes > 0: the
+    // products use it): slices of 64 / ell_lanes rows, one wavefront each,
+    // entry k of the slice's row q in slot k / ell_lanes at lane
+    // q * ell_lanes + k % ell_lanes; ell_off[s] is the first entry of slice s
+    // (a multiple of 64), padding entries have column 0 and value 0.
+    int ell_lanes;
+    const int *ell_off;
+    const int *ell_col;
+    const void *ell_val;
 };
 
 struct DevSellView {

@@ -48,11 +48,21 @@ struct DevOp {   // CSR with values in both precisions
     double *v64 = nullptr;
     float *v32 = nullptr;
     int lpr = 1;
+    // row-split sliced ELL copy (ell_lanes > 0: the products use it)
+    int ell_lanes = 0;
+    int64_t ell_stored = 0;
+    int *ell_off = nullptr, *ell_col = nullptr;
+    double *ell_v64 = nullptr;
+    float *ell_v32 = nullptr;
     template <typename T>
     DevCsrView view() const
     {
-        return {n, ptr, col, std::is_same<T, float>::value ? (const void *)v32 : (const void *)v64, lpr};
+        const bool f = std::is_same<T, float>::value;
+        return {n, ptr, col, f ? (const void *)v32 : (const void *)v64, lpr,
+                ell_lanes, ell_off, ell_col, f ? (const void *)ell_v32 : (const void *)ell_v64};
     }
+    // lanes of the form in use: > 0 row-split ELL, < 0 CSR (minus its lanes per row)
+    int lanes_code() const { return ell_lanes > 0 ? ell_lanes : -lpr; }
 };
 
 struct DevSell {
@@ -314,22 +324,43 @@ struct aux_handle {
         for (size_t i = 0; i < v.size(); i++) o[i] = 1.0 / v[i];
         return o;
     }
-    // Lanes per row of a CSR operator: time one FP32 product (two-source
-    // form when split > 0) for each candidate and keep the fastest.  In the
-    // solve the operator's data has been evicted by the P^k passes, so each
-    // timed launch follows a write of `flush` bytes that clears the caches.
-    void tune_lpr(DevOp &op, int split, void *flush, size_t flush_bytes)
+    void drop_ell(DevOp &op)
+    {
+        for (void *b : {(void *)op.ell_off, (void *)op.ell_col, (void *)op.ell_v64, (void *)op.ell_v32}) dfree(b);
+        op.ell_off = op.ell_col = nullptr;
+        op.ell_v64 = nullptr;
+        op.ell_v32 = nullptr;
+        op.ell_lanes = 0;
+        op.ell_stored = 0;
+    }
+
+    void set_ell(DevOp &op, const Csr &c, int lanes)
+    {
+        drop_ell(op);
+        Ell e;
+        build_ell(c, lanes, e);
+        op.ell_off = upload(e.slice_off);
+        op.ell_col = upload(e.col);
+        op.ell_v64 = upload(e.val);
+        op.ell_v32 = upload(to_f32(e.val));
+        op.ell_stored = (int64_t)e.val.size();
+        op.ell_lanes = lanes;
+    }
+
+    // Storage and lanes of one V-cycle operator: time one FP32 product
+    // (two-source form when split > 0) for each candidate, CSR with 2-32
+    // lanes per row and row-split ELL with 1-32 lanes per row, and keep the
+    // fastest.  In the solve the operator's data has been evicted by the P^k
+    // passes, so each timed launch follows a write of `flush` bytes that
+    // clears the caches.
+    void tune_op(DevOp &op, const Csr &host, int split, void *flush, size_t flush_bytes)
     {
         if (!op.v32 || op.n == 0) return;
         float *x = dnew<float>(std::max(op.m, 1)), *y = dnew<float>(op.n);
         HIPCHECK(hipMemsetAsync(x, 0, (size_t)std::max(op.m, 1) * sizeof(float), stream));
         const double avg = (double)op.nnz / op.n;
-        double best = 1e300;
-        int pick = op.lpr;
         hipEvent_t a = take_event(), b = take_event();
-        for (int lpr : {2, 4, 8, 16, 32}) {
-            if (lpr > 4 * avg + 4) break;
-            op.lpr = lpr;
+        auto measure = [&]() {
             auto run = [&]() {
                 if (split > 0) csr_matvec2<float>(stream, op.view<float>(), x, x + split, split, y, nullptr);
                 else csr_matvec<float>(stream, op.view<float>(), x, y, nullptr);
@@ -346,13 +377,33 @@ struct aux_handle {
                 HIPCHECK(hipEventElapsedTime(&ms, a, b));
                 total += ms;
             }
-            if (total < best) {
-                best = total;
+            return total;
+        };
+        double best = 1e300;
+        int pick = op.lpr, pick_ell = 0;
+        drop_ell(op);
+        for (int lpr : {2, 4, 8, 16, 32}) {
+            if (lpr > 4 * avg + 4) break;
+            op.lpr = lpr;
+            const double t = measure();
+            if (t < best) {
+                best = t;
                 pick = lpr;
             }
         }
-        ev_used -= 2;
         op.lpr = pick;
+        for (int lanes : {1, 2, 4, 8, 16, 32}) {
+            if (lanes > 4 * avg + 4) break;
+            set_ell(op, host, lanes);
+            const double t = measure();
+            if (t < best) {
+                best = t;
+                pick_ell = lanes;
+            }
+        }
+        if (pick_ell > 0) set_ell(op, host, pick_ell);
+        else drop_ell(op);
+        ev_used -= 2;
         dfree(x);
         dfree(y);
     }
@@ -504,14 +555,30 @@ struct aux_handle {
             // (with a fixed layout window every choice is rule-based)
             // (I_P has one or two entries per row: its rule-based two lanes
             // per row measured best in the solve)
-            if (opt.sell_window <= 0) {
+            if (opt.cycle_lanes != 0) {                // one storage for all of them
+                auto force = [&](DevOp &op, const Csr &host) {
+                    if (opt.cycle_lanes > 0) {
+                        set_ell(op, host, opt.cycle_lanes);
+                    } else {
+                        drop_ell(op);
+                        op.lpr = -opt.cycle_lanes;
+                    }
+                };
+                force(RF, RF_host);
+                force(IP, IPi);
+                for (size_t l = 0; l + 1 < lev.size(); l++) {
+                    force(lev[l].down, fused_host[l].down);
+                    force(lev[l].up, fused_host[l].up);
+                }
+            } else if (opt.sell_window <= 0) {
                 const size_t fb = (size_t)512 << 20;    // twice the last-level cache
                 void *flush = dalloc(fb);
-                tune_lpr(RF, disc.ndof, flush, fb);
+                tune_op(RF, RF_host, disc.ndof, flush, fb);
+                tune_op(IP, IPi, 0, flush, fb);
                 for (size_t l = 0; l + 1 < lev.size(); l++) {
                     if (lev[l].A.n < 8192) break;
-                    tune_lpr(lev[l].down, 0, flush, fb);
-                    tune_lpr(lev[l].up, lev[l].A.n, flush, fb);
+                    tune_op(lev[l].down, fused_host[l].down, 0, flush, fb);
+                    tune_op(lev[l].up, fused_host[l].up, lev[l].A.n, flush, fb);
                 }
                 dfree(flush);
             }
@@ -1498,6 +1565,7 @@ void aux_default_options(aux_options *o)
     o->sell_index16 = 1;
     o->fuse_cycle = 1;
     o->batch_tiles = 1;
+    o->cycle_lanes = 0;
 }
 
 int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt, const aux_device *dev,
@@ -1520,6 +1588,11 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
         for (int flag : {o.graph, o.sell_index16, o.fuse_cycle, o.host_only})
             if (flag != 0 && flag != 1) throw AuxError(AUX_EINVAL, "a boolean option is not 0 or 1");
         if (o.batch_tiles < 0 || o.batch_tiles > 2) throw AuxError(AUX_EINVAL, "batch_tiles must be 0, 1 or 2");
+        {
+            const int a = o.cycle_lanes < 0 ? -o.cycle_lanes : o.cycle_lanes;
+            if (a != 0 && a != 1 && a != 2 && a != 4 && a != 8 && a != 16 && a != 32)
+                throw AuxError(AUX_EINVAL, "cycle_lanes must be 0 or +-1, 2, 4, 8, 16, 32");
+        }
         if (o.maxit < 1) o.maxit = 1000;
         auto *h = new aux_handle();
         try {
@@ -1640,6 +1713,12 @@ int aux_get_info(const aux_handle *h, aux_info *info)
         for (size_t l = 0; l < h->fused_host.size() && l < 32; l++) {
             info->level_nnz_down[l] = h->fused_host[l].down.nnz();
             info->level_nnz_up[l] = h->fused_host[l].up.nnz();
+        }
+        info->lanes_restrict = h->RF.n ? h->RF.lanes_code() : 0;
+        info->lanes_prolong = h->IP.lanes_code();
+        for (size_t l = 0; l + 1 < h->lev.size() && l < 32; l++) {
+            info->lanes_down[l] = h->lev[l].down.n ? h->lev[l].down.lanes_code() : 0;
+            info->lanes_up[l] = h->lev[l].up.n ? h->lev[l].up.lanes_code() : 0;
         }
         return AUX_OK;
     });

@@ -166,4 +166,34 @@ Csr permute_rows(const Csr &A, const std::vector<int> &perm)
     return B;
 }
 
+void build_ell(const Csr &A, int lanes, Ell &out)
+{
+    if (lanes < 1 || lanes > 64 || (64 % lanes) != 0) throw std::invalid_argument("build_ell: lanes must divide 64");
+    const int rows = 64 / lanes;
+    out = Ell();
+    out.n = A.n;
+    out.lanes = lanes;
+    out.nslices = (A.n + rows - 1) / rows;
+    out.slice_off.assign((size_t)out.nslices + 1, 0);
+    for (int s = 0; s < out.nslices; s++) {
+        int width = 0;
+        for (int q = 0; q < rows && s * rows + q < A.n; q++) {
+            const int i = s * rows + q;
+            width = std::max(width, (A.ptr[i + 1] - A.ptr[i] + lanes - 1) / lanes);
+        }
+        out.slice_off[s + 1] = out.slice_off[s] + 64 * width;
+    }
+    out.col.assign((size_t)out.slice_off[out.nslices], 0);
+    out.val.assign((size_t)out.slice_off[out.nslices], 0.0);
+    for (int s = 0; s < out.nslices; s++)
+        for (int q = 0; q < rows && s * rows + q < A.n; q++) {
+            const int i = s * rows + q;
+            for (int e = A.ptr[i], k = 0; e < A.ptr[i + 1]; e++, k++) {
+                const size_t at = (size_t)out.slice_off[s] + (size_t)(k / lanes) * 64 + q * lanes + k % lanes;
+                out.col[at] = A.col[e];
+                out.val[at] = A.val[e];
+            }
+        }
+}
+
 }  // namespace auxp

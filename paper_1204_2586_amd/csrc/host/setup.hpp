@@ -116,6 +116,20 @@ struct Sell {
     int max_width = 0;            // longest slice, in slots
 };
 
+// Row-split sliced ELL for the V-cycle's sparse operators: slices of
+// 64 / lanes consecutive rows, one wavefront each; entry k of the slice's
+// row q sits in slot k / lanes at lane q * lanes + k % lanes, so every slot
+// is 64 consecutive entries (coalesced loads) and a row's lanes add their
+// partial sums at the end.  Each slice is padded to its longest row with
+// column 0 and value 0.  Rows keep their order.
+struct Ell {
+    int n = 0, lanes = 1, nslices = 0;
+    std::vector<int> slice_off;   // [nslices+1], multiples of 64
+    std::vector<int> col;
+    std::vector<double> val;
+};
+void build_ell(const Csr &A, int lanes, Ell &out);
+
 // Row tiles for products with a block of vectors (batched solve).  Tile t
 // holds `tile` consecutive rows of A in the original order (neighbouring
 // dofs, which share most of their columns); ucols lists the distinct columns

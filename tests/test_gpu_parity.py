@@ -322,6 +322,30 @@ def test_fused_cycle_matches_stepwise(k, n, jit, kap):
             assert _rel(Uf[:, j].cpu().numpy(), Us[:, j].cpu().numpy()) <= 1e-8
 
 
+@pytest.mark.parametrize("k,n,lanes", [(2, 13, 1), (2, 13, 4), (2, 13, 32), (3, 9, 2), (3, 9, 8), (3, 9, 16),
+                                         (2, 13, -1), (3, 9, -8)])
+def test_cycle_operator_storage(k, n, lanes):
+    """Every storage of the V-cycle's operators (row-split sliced ELL with L
+    lanes per row, or CSR) gives the oracle's preconditioner to rounding;
+    the meshes leave ragged last slices at every level."""
+    print(f"[cycle storage k={k} n={n} lanes={lanes}]", flush=True)
+    xyz, tets, kappa = _case(k, n, jitter=0.2, kappa="rand")
+    lib = aux.Solver(xyz, tets, k, kappa, device=DEV, cycle_lanes=lanes)
+    i = lib.info
+    assert i.lanes_restrict == lanes and i.lanes_prolong == lanes
+    assert all(i.lanes_down[l] == lanes and i.lanes_up[l] == lanes for l in range(i.levels - 1))
+    orc = oracle.Problem(xyz, tets, k, kappa).setup_amg()
+    r = W.random_vector(lib.n, 5)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 2e-6)):
+        lib.set_precision(prec)
+        assert _rel(lib.apply(_t(r)).cpu().numpy(), orc.apply(r, fp32=(prec == "mixed"))) <= tol, prec
+    b = orc.load(W.manufactured_f)
+    lib.set_precision("fp64")
+    x, it, _, _ = orc.pcg(b, tol=1e-8)
+    u, info = lib.solve(_t(b), tol=0.0, maxit=it, check=False)
+    assert _rel(u.cpu().numpy(), x) <= 1e-10
+
+
 @pytest.mark.parametrize("nrhs", [5, 12, 32])
 def test_batched_tiles_equal_slices(nrhs):
     """Block products from LDS-staged row tiles and from 64-row slices sum each
