@@ -94,6 +94,24 @@ def algorithmic_bytes(cat, n, nnz, s, fmt):
     return None
 
 
+def matfree_bytes(cat, n, nt, nloc, s):
+    """Bytes of one matrix-free product pass: the element kernel reads the
+    element map and slot indices (4 B each per tet node), six weights per
+    tet, each gathered dof value once, and writes one result per tet node;
+    the per-dof gather-sum reads the incidence offsets and those results
+    back, plus the vectors of the fused update (as in algorithmic_bytes)."""
+    op = nt * nloc * (4 + 4 + 2 * s) + nt * 6 * s + n * s + 4 * (n + 1)
+    if cat == "pk_sweep":
+        return op + 3 * s * n
+    if cat == "pk_last":
+        return op + s * n + 16 * n
+    if cat == "pk_resid":
+        return op + 2 * s * n
+    if cat == "cg_spmv":       # FP64: p gathered (in op), q written
+        return matfree_bytes("pk_resid", n, nt, nloc, 8) - 8 * n
+    return None
+
+
 def restrict_bytes(info, s):
     """The fused restricted residual r_H = [I_R, -I_R A_h] [r; z]: CSR
     operator, both gathered vectors, the P^1 result."""
@@ -195,8 +213,12 @@ def run(args):
 
     # roofline of the dominant kernel of the timed (mixed) solve
     kernels = {}
+    nloc = (wl["k"] + 1) * (wl["k"] + 2) * (wl["k"] + 3) // 6
     for cat, (cnt, tot) in mixed["prof"].items():
-        ab = algorithmic_bytes(cat, n, nnz, 4, index_bytes_per_entry(s.info))
+        if args.operator == "matfree" and cat in ("pk_sweep", "pk_last", "cg_spmv"):
+            ab = matfree_bytes(cat, n, len(tets), nloc, 8 if cat == "cg_spmv" else 4)
+        else:
+            ab = algorithmic_bytes(cat, n, nnz, 4, index_bytes_per_entry(s.info))
         if cat == "pk_resid" and s.info.nnz_restrict > 0:
             ab = restrict_bytes(s.info, 4)
         if cnt and ab:

@@ -172,8 +172,9 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(MfView<T> op, const T *__
 }
 
 // gather-sum of the element results per dof, fused with the update:
-// MODE_RESID: out = rhs - Ax;  MODE_SWEEP: out = xin + dinv (rhs - Ax) (+ dot)
-enum { MF_RESID = 0, MF_SWEEP = 1 };
+// MF_RESID: out = rhs - Ax;  MF_SWEEP: out = xin + dinv (rhs - Ax);  MF_PRODUCT:
+// out = Ax (each + dot with rdot when DOT)
+enum { MF_RESID = 0, MF_SWEEP = 1, MF_PRODUCT = 2 };
 
 template <typename T, typename TR, typename TZ, int MODE, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_mf_gather(MfView<T> op, const T *__restrict__ Yel,
@@ -189,6 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_gather(MfView<T> op, const T *__r
         for (int p = op.inc_ptr[i]; p < op.inc_ptr[i + 1]; p++) s += Yel[p];
         T v;
         if (MODE == MF_RESID) v = (T)rhs[i] - s;
+        else if (MODE == MF_PRODUCT) v = s;
         else v = xin[i] + dinv[i] * ((T)rhs[i] - s);
         out[i] = (TZ)v;
         if (DOT) acc += rdot[i] * (double)(TZ)v;
@@ -252,9 +254,25 @@ int mf_sweep(hipStream_t s, const MfView<T> &op, const T *Yel, const T *xin, con
     return g;
 }
 
+template <typename T>
+int mf_product(hipStream_t s, const MfView<T> &op, const T *Yel, T *out, const double *rdot, double *partials,
+               const int *done)
+{
+    int g = cap_grid(((long long)op.n + kBlock - 1) / kBlock);
+    if (partials)
+        hipLaunchKernelGGL((k_mf_gather<T, T, T, MF_PRODUCT, true>), dim3(g), dim3(kBlock), 0, s, op, Yel,
+                           (const T *)nullptr, (const T *)nullptr, (const T *)nullptr, out, rdot, partials, done);
+    else
+        hipLaunchKernelGGL((k_mf_gather<T, T, T, MF_PRODUCT, false>), dim3(g), dim3(kBlock), 0, s, op, Yel,
+                           (const T *)nullptr, (const T *)nullptr, (const T *)nullptr, out, rdot, partials, done);
+    return g;
+}
+
 #define MFINST(T)                                                                                             \
     template void mf_apply<T>(hipStream_t, const MfView<T> &, const T *, T *, const int *);                   \
     template void mf_resid<T>(hipStream_t, const MfView<T> &, const T *, const T *, T *, const int *);        \
+    template int mf_product<T>(hipStream_t, const MfView<T> &, const T *, T *, const double *, double *,       \
+                               const int *);                                                                  \
     template int mf_sweep<T, T, T>(hipStream_t, const MfView<T> &, const T *, const T *, const T *, const T *, \
                                    T *, const double *, double *, const int *);
 

@@ -23,6 +23,11 @@ void mf_apply(hipStream_t s, const MfView<T> &op, const T *x, T *Yel, const int 
 // res = rhs - (sum of element results)
 template <typename T>
 void mf_resid(hipStream_t s, const MfView<T> &op, const T *Yel, const T *rhs, T *res, const int *done);
+// out = sum of element results (= A x for the x given to mf_apply); with
+// partials also sum rdot*out per block; returns the number of partials
+template <typename T>
+int mf_product(hipStream_t s, const MfView<T> &op, const T *Yel, T *out, const double *rdot, double *partials,
+               const int *done);
 // out = xin + dinv (rhs - sum of element results); with partials also sum rdot*out per block
 template <typename T, typename TR, typename TZ>
 int mf_sweep(hipStream_t s, const MfView<T> &op, const T *Yel, const T *xin, const T *dinv, const TR *rhs, TZ *out,

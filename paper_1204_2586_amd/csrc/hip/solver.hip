@@ -818,13 +818,21 @@ struct aux_handle {
     {
         hipStream_t s = stream;
         int n = disc.ndof;
-        DevSellView A64 = A.view<double>();
         int pk = pbeg(AUX_PROF_CG_SPMV);
-        int g = sell_spmv64(s, A64, p, q, partials, st.done);
+        int g;
+        if (use_mf()) {
+            // q = A_h p by the element operator in FP64 (half the bytes of
+            // the assembled product at P3), with the p . q partials
+            ensure_mf();
+            MfView<double> v = mf_view<double>();
+            mf_apply<double>(s, v, p, mf_Y64, st.done);
+            g = mf_product<double>(s, v, mf_Y64, q, p, partials, st.done);
+        } else {
+            g = sell_spmv64(s, A.view<double>(), p, q, partials, st.done);
+        }
         pend(pk);
         finish(s, partials, g, FIN_PQ, nullptr, st);
         // the update also starts the preconditioner: z = D^-1 r
-        if (use_mf()) ensure_mf();
         if (opt.precision == AUX_MIXED) {
             ensure_fp32();
             Work<float> &w = work<float>();
