@@ -78,15 +78,17 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(MfView<T> op, const T *__
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, grp = lane >> 4;
 
-    // A operand: lane (i = lane % 16, g) of step s holds S[16 mt + i][k nloc + b]
-    T areg[MT][KS];
-#pragma unroll
-    for (int mt = 0; mt < MT; mt++)
-#pragma unroll
-        for (int s = 0; s < KS; s++) {
-            const int row = 16 * mt + col, k = s / NB, b = 4 * (s % NB) + grp;
-            areg[mt][s] = (row < NLOC && b < NLOC) ? op.S[row * 6 * NLOC + k * NLOC + b] : T(0);
-        }
+    // A operand: lane (i = lane % 16, g) of step s holds S[16 mt + i][k nloc + b],
+    // staged in LDS in that lane order (one conflict-free read per step; in
+    // registers the tables would take 60 (FP32) or 120 (FP64) VGPRs and cap
+    // the waves per SIMD at 4 or 2)
+    __shared__ T sA[MT * KS * 64];
+    for (int i = threadIdx.x; i < MT * KS * 64; i += kBlock) {
+        const int l = i % 64, s = (i / 64) % KS, mt = i / (64 * KS);
+        const int row = 16 * mt + l % 16, k = s / NB, b = 4 * (s % NB) + l / 16;
+        sA[i] = (row < NLOC && b < NLOC) ? op.S[row * 6 * NLOC + k * NLOC + b] : T(0);
+    }
+    __syncthreads();
 
     // Each die (workgroups are dispatched round-robin over kDies dies, b to
     // b % kDies) takes a contiguous range of tiles, so the slots of a dof,
@@ -150,18 +152,17 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(MfView<T> op, const T *__
         for (int k = 0; k < 6; k++)
             if (!tv) wv[k] = T(0);
 
-        // B operand: lane (g, c) holds Z[(k, b)][c] = w_c,k x_c,b; formed for
-        // all steps before the contraction, so every gather is issued at once
-        T bv[KS];
-#pragma unroll
-        for (int s = 0; s < KS; s++) bv[s] = wv[s / NB] * xv[s % NB];
+        // B operand: lane (g, c) holds Z[(k, b)][c] = w_c,k x_c,b, formed step by
+        // step (the gathers above are all in flight before the first use)
         typename Acc<T>::V acc[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; mt++) acc[mt] = typename Acc<T>::V{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < KS; s++)
+        for (int s = 0; s < KS; s++) {
+            const T bv = wv[s / NB] * xv[s % NB];
 #pragma unroll
-            for (int mt = 0; mt < MT; mt++) acc[mt] = Acc<T>::mfma(areg[mt][s], bv[s], acc[mt]);
+            for (int mt = 0; mt < MT; mt++) acc[mt] = Acc<T>::mfma(sA[(mt * KS + s) * 64 + lane], bv, acc[mt]);
+        }
         // D: register v of this lane holds row Acc<T>::row(grp, v) of column c
 #pragma unroll
         for (int mt = 0; mt < MT; mt++)
@@ -222,9 +223,10 @@ void mf_apply(hipStream_t s, const MfView<T> &op, const T *x, T *Yel, const int 
 {
     // (the element kernel's clamped loads read X[0]: nothing to do without unknowns)
     if (op.n == 0 || op.nt == 0) return;
-    // persistent waves: a few tiles each, so the operand tables are loaded once per wave
+    // persistent waves, a few tiles each (the operand tables are staged once
+    // per workgroup); up to 8 workgroups per compute unit
     const long long tiles = ((long long)op.nt + kTetsPerWave - 1) / kTetsPerWave;
-    int g = (int)std::min<long long>((tiles + kWaves - 1) / kWaves, 1024);
+    int g = (int)std::min<long long>((tiles + kWaves - 1) / kWaves, 2048);
     if (g < 1) g = 1;
     if (op.nloc == 10)
         hipLaunchKernelGGL((k_mf_element<T, 10>), dim3(g), dim3(kBlock), 0, s, op, x, Yel, done);
