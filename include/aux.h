@@ -115,6 +115,13 @@ typedef struct aux_options {
                                 sell_window > 0); L in {1,2,4,8,16,32}: row-split ELL with L
                                 lanes for all of them; -L: CSR with L lanes for all of them.
                                 Results agree to rounding (per-row summation order) */
+    int dense_cycle_rows;    /* with fuse_cycle: the V-cycle from the first level of at most
+                                this many rows down to the coarsest (a fixed linear map, the
+                                cycle starting from zero) is formed at setup as one dense matrix
+                                T_l = N_l + Q_l T_{l+1} M_l (FP64, rounded once for FP32) and
+                                applied as one dense product, in the single-vector and the
+                                batched solve; 0 turns it off; at most 8192; default 2048.
+                                Results agree to rounding */
 } aux_options;
 
 typedef struct aux_device {
@@ -156,6 +163,7 @@ typedef struct aux_info {
     /* Storage of the V-cycle's sparse operators in the single-vector solve:
      * L > 0 row-split sliced ELL with L lanes per row (64 / L rows per
      * wavefront), -L CSR with L lanes per row. */
+    int32_t dense_cycle_level; /* first level evaluated by the dense cycle matrix, -1 if none */
     int32_t lanes_restrict;  /* fused restriction [I_R, -I_R A_h] (0 if not fused) */
     int32_t lanes_prolong;   /* I_P */
     int32_t lanes_down[32];  /* fused down operator of level l */

@@ -49,7 +49,7 @@ class _Options(ctypes.Structure):
                 ("maxit", ctypes.c_int), ("host_only", ctypes.c_int), ("op", ctypes.c_int),
                 ("sell_window", ctypes.c_int), ("graph", ctypes.c_int),
                 ("sell_index16", ctypes.c_int), ("fuse_cycle", ctypes.c_int),
-                ("batch_tiles", ctypes.c_int), ("cycle_lanes", ctypes.c_int)]
+                ("batch_tiles", ctypes.c_int), ("cycle_lanes", ctypes.c_int), ("dense_cycle_rows", ctypes.c_int)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -72,7 +72,8 @@ class _Info(ctypes.Structure):
                 ("sell_narrow_slices", ctypes.c_int64), ("sell_index_bytes", ctypes.c_int64),
                 ("nnz_restrict", ctypes.c_int64), ("level_nnz_down", ctypes.c_int64 * 32),
                 ("level_nnz_up", ctypes.c_int64 * 32), ("batch_tile_rows", ctypes.c_int32 * 2),
-                ("sell_tune_ms", ctypes.c_double * 4), ("lanes_restrict", ctypes.c_int32),
+                ("sell_tune_ms", ctypes.c_double * 4), ("dense_cycle_level", ctypes.c_int32),
+                ("lanes_restrict", ctypes.c_int32),
                 ("lanes_prolong", ctypes.c_int32), ("lanes_down", ctypes.c_int32 * 32),
                 ("lanes_up", ctypes.c_int32 * 32)]
 
@@ -165,7 +166,8 @@ class Solver:
                  coarse_max: int = 100, max_levels: int = 25, seed: int = 0, precision: str = "fp64",
                  maxit: int = 1000, host_only: bool = False, device=None, use_torch_allocator: bool = True,
                  operator: str = "assembled", sell_window: int = 0, graph: bool = True, sell_index16: bool = True,
-                 fuse_cycle: bool = True, batch_tiles: int = 1, cycle_lanes: int = 0):
+                 fuse_cycle: bool = True, batch_tiles: int = 1, cycle_lanes: int = 0,
+                 dense_cycle_rows: int = 2048):
         lib = load_library()
         self._h = ctypes.c_void_p()
         self.order = order
@@ -185,6 +187,7 @@ class Solver:
         opt.fuse_cycle = int(fuse_cycle)
         opt.batch_tiles = int(batch_tiles)
         opt.cycle_lanes = int(cycle_lanes)
+        opt.dense_cycle_rows = int(dense_cycle_rows)
         kap = None
         if kappa is not None:
             self._kappa = np.ascontiguousarray(kappa, dtype=np.float64)

@@ -138,6 +138,10 @@ struct aux_handle {
         float *dinv32 = nullptr;
     };
     DevOp RF;                        // composite restriction [I_R, -I_R A_h] (fuse_cycle)
+    // the cycle from level dense_first down, as one dense matrix (fuse_cycle)
+    size_t dense_first = SIZE_MAX;
+    double *dcyc64 = nullptr;
+    float *dcyc32 = nullptr;
     std::vector<FusedLevel> fused_host;
     Csr RF_host;
     std::vector<Lev> lev;
@@ -549,6 +553,19 @@ struct aux_handle {
                 lev[l].down = upload_op2(fused_host[l].down);
                 lev[l].up = upload_op2(fused_host[l].up);
             }
+            // the bottom of the cycle: each small level costs two launches
+            // of dependent-load latency (about 5 us each) for well under a
+            // microsecond of traffic; below the first level of at most
+            // dense_cycle_rows rows the cycle is one dense product instead
+            if (opt.dense_cycle_rows > 0)
+                for (size_t l = 0; l + 1 < lev.size(); l++)
+                    if (lev[l].A.n <= opt.dense_cycle_rows) {
+                        const std::vector<double> T = dense_cycle(fused_host, hier, l);
+                        dcyc64 = upload(T);
+                        dcyc32 = upload(to_f32(T));
+                        dense_first = l;
+                        break;
+                    }
             RF_host = fuse_restriction(IRi, permute_symmetric(disc.A, sell.perm, sell.iperm));
             RF = upload_op2(RF_host);
             // lanes per row of the large CSR passes, timed on the device
@@ -710,6 +727,13 @@ struct aux_handle {
     // ------------------------------------------------------------ preconditioner
     // one V(1,1) cycle from zero on level l; returns the device vector holding the result
     template <typename T>
+    const T *dcyc() const
+    {
+        if constexpr (std::is_same<T, float>::value) return dcyc32;
+        else return dcyc64;
+    }
+
+    template <typename T>
     const T *vcycle(size_t l, const int *done)
     {
         Work<T> &w = work<T>();
@@ -718,6 +742,10 @@ struct aux_handle {
         if (l + 1 == lev.size()) {
             dense_gemv<T>(s, L.A.n, cinv<T>(), w.b[l], w.x[l], done);
             return w.x[l];
+        }
+        if (opt.fuse_cycle && l == dense_first) {
+            dense_gemv<T>(s, L.A.n, dcyc<T>(), w.b[l], w.y[l], done);
+            return w.y[l];
         }
         if (opt.fuse_cycle) {
             // b' = P^T (I - A D^-1) b; recurse; y = (2 D^-1 - D^-1 A D^-1) b + (P - D^-1 A P) e
@@ -1274,6 +1302,10 @@ struct aux_handle {
             bdense<T>(s, nr, L.A.n, cinv<T>(), w.b[l], w.x[l], all_done);
             return w.x[l];
         }
+        if (l == dense_first) {
+            bdense<T>(s, nr, L.A.n, dcyc<T>(), w.b[l], w.y[l], all_done);
+            return w.y[l];
+        }
         const BOp &A_ = bA[l], &P_ = bP[l], &R_ = bR[l];
         blevel_vpre<T>(s, nr, A_.scaled_view<T>(), A_.unroll, A_.perm, ldinv<T>(l), w.b[l], w.x[l], w.r[l], all_done);
         blevel_matvec<T>(s, nr, R_.view<T>(), R_.unroll, R_.perm, w.r[l], w.b[l + 1], false, all_done);
@@ -1574,6 +1606,7 @@ void aux_default_options(aux_options *o)
     o->fuse_cycle = 1;
     o->batch_tiles = 1;
     o->cycle_lanes = 0;
+    o->dense_cycle_rows = 2048;
 }
 
 int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt, const aux_device *dev,
@@ -1596,6 +1629,8 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
         for (int flag : {o.graph, o.sell_index16, o.fuse_cycle, o.host_only})
             if (flag != 0 && flag != 1) throw AuxError(AUX_EINVAL, "a boolean option is not 0 or 1");
         if (o.batch_tiles < 0 || o.batch_tiles > 2) throw AuxError(AUX_EINVAL, "batch_tiles must be 0, 1 or 2");
+        if (o.dense_cycle_rows < 0 || o.dense_cycle_rows > 8192)
+            throw AuxError(AUX_EINVAL, "dense_cycle_rows must be in [0, 8192]");
         {
             const int a = o.cycle_lanes < 0 ? -o.cycle_lanes : o.cycle_lanes;
             if (a != 0 && a != 1 && a != 2 && a != 4 && a != 8 && a != 16 && a != 32)
@@ -1722,6 +1757,7 @@ int aux_get_info(const aux_handle *h, aux_info *info)
             info->level_nnz_down[l] = h->fused_host[l].down.nnz();
             info->level_nnz_up[l] = h->fused_host[l].up.nnz();
         }
+        info->dense_cycle_level = h->dense_first == SIZE_MAX ? -1 : (int32_t)h->dense_first;
         info->lanes_restrict = h->RF.n ? h->RF.lanes_code() : 0;
         info->lanes_prolong = h->IP.lanes_code();
         for (size_t l = 0; l + 1 < h->lev.size() && l < 32; l++) {

@@ -162,4 +162,40 @@ Csr fuse_restriction(const Csr &IR, const Csr &A)
     return side_by_side(IR, C);
 }
 
+std::vector<double> dense_cycle(const std::vector<FusedLevel> &fused, const Hierarchy &H, size_t l0)
+{
+    const size_t L = H.levels.size();
+    if (L == 0 || l0 >= L) throw std::invalid_argument("dense_cycle: level out of range");
+    std::vector<double> T = H.coarse_inv;        // nc x nc on the coarsest level
+    for (size_t l = L - 1; l-- > l0;) {
+        const int n = H.levels[l].A.n, nc = H.levels[l + 1].A.n;
+        const Csr &M = fused[l].down, &U = fused[l].up;
+        if (M.n != nc || M.m != n || U.n != n || U.m != n + nc)
+            throw std::invalid_argument("dense_cycle: operator shapes");
+        // Tn = N + (Q T) M, rows of U split at column n into N and Q
+        std::vector<double> Tn((size_t)n * n, 0.0), QT((size_t)nc);
+        for (int i = 0; i < n; i++) {
+            double *row = &Tn[(size_t)i * n];
+            std::fill(QT.begin(), QT.end(), 0.0);
+            for (int e = U.ptr[i]; e < U.ptr[i + 1]; e++) {
+                const int c = U.col[e];
+                if (c < n) {
+                    row[c] += U.val[e];
+                } else {
+                    const double q = U.val[e];
+                    const double *tr = &T[(size_t)(c - n) * nc];
+                    for (int k = 0; k < nc; k++) QT[k] += q * tr[k];
+                }
+            }
+            for (int k = 0; k < nc; k++) {
+                const double a = QT[k];
+                if (a == 0.0) continue;
+                for (int e = M.ptr[k]; e < M.ptr[k + 1]; e++) row[M.col[e]] += a * M.val[e];
+            }
+        }
+        T.swap(Tn);
+    }
+    return T;
+}
+
 }  // namespace auxp

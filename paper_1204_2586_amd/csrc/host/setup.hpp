@@ -91,6 +91,11 @@ struct FusedLevel {
 FusedLevel fuse_level(const AmgLevel &L);
 // [I_R, -I_R A] (n_H x 2 n_h): the restricted residual I_R (r - A z) of [r; z]
 Csr fuse_restriction(const Csr &IR, const Csr &A);
+// The cycle below and including level l0, from a zero guess, as one dense
+// matrix: y_l0 = T b_l0 with T = coarse_inv on the coarsest level and
+// T_l = N_l + Q_l T_{l+1} M_l above it (M_l = fused[l].down, [N_l Q_l] =
+// fused[l].up).  Row-major n_l0 x n_l0, formed in FP64.
+std::vector<double> dense_cycle(const std::vector<FusedLevel> &fused, const Hierarchy &H, size_t l0);
 
 }  // namespace auxp
 

@@ -337,7 +337,8 @@ def test_cycle_operator_storage(k, n, lanes):
     the meshes leave ragged last slices at every level."""
     print(f"[cycle storage k={k} n={n} lanes={lanes}]", flush=True)
     xyz, tets, kappa = _case(k, n, jitter=0.2, kappa="rand")
-    lib = aux.Solver(xyz, tets, k, kappa, device=DEV, cycle_lanes=lanes)
+    lib = aux.Solver(xyz, tets, k, kappa, device=DEV, cycle_lanes=lanes, dense_cycle_rows=0)
+    assert lib.info.dense_cycle_level == -1
     i = lib.info
     assert i.lanes_restrict == lanes and i.lanes_prolong == lanes
     assert all(i.lanes_down[l] == lanes and i.lanes_up[l] == lanes for l in range(i.levels - 1))
@@ -351,6 +352,39 @@ def test_cycle_operator_storage(k, n, lanes):
     x, it, _, _ = orc.pcg(b, tol=1e-8)
     u, info = lib.solve(_t(b), tol=0.0, maxit=it, check=False)
     assert _rel(u.cpu().numpy(), x) <= 1e-10
+
+
+@pytest.mark.parametrize("k,n,rows", [(2, 13, 0), (2, 13, 300), (2, 13, 1024), (2, 13, 8192), (3, 9, 1024),
+                                       (3, 9, 100)])
+def test_dense_cycle(k, n, rows):
+    """The cycle below the first level of at most `rows` rows, formed as one
+    dense matrix at setup, gives the oracle's preconditioner to rounding in
+    the single-vector and the batched solve (rows = 8192 takes the whole
+    cycle, 0 none)."""
+    print(f"[dense cycle k={k} n={n} rows={rows}]", flush=True)
+    xyz, tets, kappa = _case(k, n, jitter=0.2, kappa="rand")
+    lib = aux.Solver(xyz, tets, k, kappa, device=DEV, dense_cycle_rows=rows)
+    sizes = [r for r, _ in lib.levels]
+    first = next((l for l in range(len(sizes) - 1) if sizes[l] <= rows), -1) if rows else -1
+    assert lib.info.dense_cycle_level == first
+    orc = oracle.Problem(xyz, tets, k, kappa).setup_amg()
+    r = W.random_vector(lib.n, 9)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 2e-6)):
+        lib.set_precision(prec)
+        assert _rel(lib.apply(_t(r)).cpu().numpy(), orc.apply(r, fp32=(prec == "mixed"))) <= tol, prec
+    b = orc.load(W.manufactured_f)
+    lib.set_precision("fp64")
+    x, it, _, _ = orc.pcg(b, tol=1e-8)
+    u, info = lib.solve(_t(b), tol=0.0, maxit=it, check=False)
+    assert _rel(u.cpu().numpy(), x) <= 1e-10
+    F = np.stack([b, r], axis=1)
+    for prec in ("fp64", "mixed"):
+        lib.set_precision(prec)
+        U, infos = lib.solve_batched(_t(F), tol=1e-8)
+        for j in range(2):
+            xj, itj, _, _ = orc.pcg(F[:, j], tol=1e-8, fp32=(prec == "mixed"))
+            assert abs(infos[j].iterations - itj) <= 1
+            assert _rel(U[:, j].cpu().numpy(), orc.pcg(F[:, j], tol=1e-8)[0]) <= 1e-7
 
 
 @pytest.mark.parametrize("nrhs", [5, 12, 32])
