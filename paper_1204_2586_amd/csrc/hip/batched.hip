@@ -68,7 +68,8 @@ __device__ __forceinline__ T gather32(const T *__restrict__ base, unsigned idx)
 
 
 // U: slots unrolled in the accumulation (more gathers in flight per lane;
-// worth it for A_h, not for the AMG level operators)
+// 4 for A_h and for level operators with long rows or few slices, 1 for the
+// large prolongations)
 template <typename T, int NR, int U, typename XL, typename BODY>
 __device__ __forceinline__ void bsell_slices(const DevSellView &A, XL xload, BODY body)
 {
