@@ -27,6 +27,8 @@ WORKLOADS = {
     "p2_n48_jitter": dict(k=2, n=48, jitter=0.2, seed=0, kappa=None),
     "p2_n8": dict(k=2, n=8, jitter=0.0, seed=0, kappa=None),
     "p3_n32_grf": dict(k=3, n=32, jitter=0.0, seed=0, kappa=1),
+    # P4 (35 nodes per tet) at the same 857,375 unknowns, kappa = 1
+    "p4_n24": dict(k=4, n=24, jitter=0.0, seed=0, kappa=None),
     # 32 right-hand sides solved in lock-step (sources fourier_f(0..31))
     "p2_n64_32rhs": dict(k=2, n=64, jitter=0.0, seed=0, kappa=None, nrhs=32),
 }

@@ -375,18 +375,44 @@ __global__ __launch_bounds__(kBlock) void kb_lsweep(DevSellView A, const int *__
     });
 }
 
-// X = Ainv B for the dense coarsest inverse (rows spread over the grid)
+// X = M B for a dense row-major n x n matrix M (the coarsest inverse or the
+// dense sub-cycle).  A workgroup takes kDenseRows rows; its KG = kBlock / NR
+// lane groups split the inner index j (group g takes j = g, g + KG, ...), so
+// each lane keeps kDenseRows independent chains of n / KG terms, and the
+// groups' partial sums are added in LDS in a fixed order.
+constexpr int kDenseRows = 4;
+
 template <typename T, int NR>
-__global__ __launch_bounds__(kBlock) void kb_dense(int n, const T *__restrict__ Ainv, const T *__restrict__ B,
+__global__ __launch_bounds__(kBlock) void kb_dense(int n, const T *__restrict__ M, const T *__restrict__ B,
                                                    T *__restrict__ X, const int *all_done)
 {
     if (stop_all(all_done)) return;
-    FOR_BROWS(NR, n)
-    {
-        T s = T(0);
+    constexpr int KG = kBlock / NR;
+    __shared__ T red[KG][kDenseRows][NR];
+    const int c = threadIdx.x % NR, g = threadIdx.x / NR;
+    for (int r0 = blockIdx.x * kDenseRows; r0 < n; r0 += gridDim.x * kDenseRows) {
+        T acc[kDenseRows];
+#pragma unroll
+        for (int r = 0; r < kDenseRows; r++) acc[r] = T(0);
+        const T *m[kDenseRows];
+#pragma unroll
+        for (int r = 0; r < kDenseRows; r++) m[r] = M + (size_t)min(r0 + r, n - 1) * n;   // clamped rows unused
 #pragma unroll 4
-        for (int j = 0; j < n; j++) s += Ainv[(size_t)row * n + j] * B[(size_t)j * NR + c_];
-        X[(size_t)row * NR + c_] = s;
+        for (int j = g; j < n; j += KG) {
+            const T b = B[(size_t)j * NR + c];
+#pragma unroll
+            for (int r = 0; r < kDenseRows; r++) acc[r] += m[r][j] * b;
+        }
+#pragma unroll
+        for (int r = 0; r < kDenseRows; r++) red[g][r][c] = acc[r];
+        __syncthreads();
+        if (threadIdx.x < kDenseRows * NR) {
+            const int r = threadIdx.x / NR, cc = threadIdx.x % NR;
+            T s = T(0);
+            for (int k = 0; k < KG; k++) s += red[k][r][cc];
+            if (r0 + r < n) X[(size_t)(r0 + r) * NR + cc] = s;
+        }
+        __syncthreads();
     }
 }
 
@@ -764,7 +790,7 @@ void blevel_sweep(hipStream_t s, int nr, const DevSellView &A, int unroll, const
 template <typename T>
 void bdense(hipStream_t s, int nr, int n, const T *Ainv, const T *B, T *X, const int *all_done)
 {
-    int g = brows_grid(n, nr);
+    int g = grid_cap((n + kDenseRows - 1) / kDenseRows);
     NR_SWITCH(nr, hipLaunchKernelGGL((kb_dense<T, NR>), dim3(g), dim3(kBlock), 0, s, n, Ainv, B, X, all_done));
 }
 

@@ -65,6 +65,7 @@ void blevel_vpre(hipStream_t s, int nr, const DevSellView &AD, int unroll, const
 template <typename T>
 void blevel_sweep(hipStream_t s, int nr, const DevSellView &A, int unroll, const int *perm, const T *dinv, const T *B, const T *X,
                   T *Y, const int *all_done);
+// X = M B, M dense row-major n x n (coarsest inverse or dense sub-cycle)
 template <typename T>
 void bdense(hipStream_t s, int nr, int n, const T *Ainv, const T *B, T *X, const int *all_done);
 

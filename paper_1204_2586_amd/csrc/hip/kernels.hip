@@ -450,13 +450,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int n, const int *__restrict
 
 // ------------------------------------------------------------- adjoint
 
+constexpr int kMaxNloc = 35;   // P4
+
 __global__ __launch_bounds__(kBlock) void k_kappa_grad(int nt, int nloc, const int *__restrict__ tet_dof,
                                                        const double *__restrict__ G, const double *__restrict__ kappa,
                                                        const double *__restrict__ M, const double *__restrict__ u,
                                                        const double *__restrict__ lam, double *__restrict__ g)
 {
     for (int t = blockIdx.x * kBlock + threadIdx.x; t < nt; t += gridDim.x * kBlock) {
-        double ue[20], le[20];
+        double ue[kMaxNloc], le[kMaxNloc];
         for (int a = 0; a < nloc; a++) {
             int i = tet_dof[(size_t)t * nloc + a];
             ue[a] = i >= 0 ? u[i] : 0.0;

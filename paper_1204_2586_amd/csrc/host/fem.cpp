@@ -283,7 +283,7 @@ u128 pack_ids(const int *ids, int n)
 void build_discretization(Discretization &d, int nv, const double *xyz, int nt, const int32_t *tets, int k,
                           const double *kappa)
 {
-    if (k < 2 || k > 3) throw std::invalid_argument("order must be 2 or 3");
+    if (k < 2 || k > 4) throw std::invalid_argument("order must be 2, 3 or 4");
     check_mesh(nv, xyz, nt, tets, kappa);
     d.k = k;
     d.nv = nv;

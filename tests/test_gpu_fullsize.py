@@ -9,6 +9,7 @@ graph), against the CPU oracle solving the same systems.
   within 1e-7 of the oracle's FP64 solution.
 * P3, 32^3 cubes, kappa = exp(GRF) (857,375 unknowns): the same bars for the
   assembled and the matrix-free operator.
+* P4, 24^3 cubes, kappa = 1 (857,375 unknowns): the same bars.
 * 32 sources in lock-step on P2, 64^3 cubes (2,048,383 unknowns): the
   columns the oracle can afford (sources 0 and 31) are solved by the oracle
   and compared at the mixed bar; every column's true residual meets the
@@ -48,6 +49,7 @@ def _system(k, n, jitter, grf):
     ("p2_n48_jitter", 2, 48, 0.2, False, "assembled"),
     ("p3_n32_grf", 3, 32, 0.0, True, "assembled"),
     ("p3_n32_grf", 3, 32, 0.0, True, "matfree"),
+    ("p4_n24", 4, 24, 0.0, False, "assembled"),
 ])
 def test_full_size_solve_matches_oracle(name, k, n, jitter, grf, operator):
     print(f"[full size {name} {operator}]", flush=True)

@@ -38,6 +38,8 @@ CASES = {
     "p3_n6_grf": dict(k=3, n=6, kappa="grf"),
     "p3_n5_jitter": dict(k=3, n=5, jitter=0.15),
     "p2_n3_single_level": dict(k=2, n=3),                      # n_H = 8: coarse solve only
+    "p4_n4_jitter_rand": dict(k=4, n=4, jitter=0.2, kappa="rand"),
+    "p4_n7": dict(k=4, n=7),                                   # 19,683 P^4 unknowns
 }
 
 

@@ -16,7 +16,7 @@ def _rel(a, b):
     return abs(a - b).max() / max(abs(b).max(), 1e-300)
 
 
-CASES = [(2, 6, 0.2, None), (3, 5, 0.15, "grf"), (2, 10, 0.0, None), (2, 9, 0.2, "rand")]
+CASES = [(2, 6, 0.2, None), (3, 5, 0.15, "grf"), (2, 10, 0.0, None), (2, 9, 0.2, "rand"), (4, 4, 0.2, "rand")]
 
 
 @pytest.fixture(scope="module", params=CASES, ids=lambda c: f"P{c[0]}-n{c[1]}-j{c[2]}-{c[3]}")
@@ -57,7 +57,7 @@ def test_dof_xyz_reproduced_by_linear_transfer(pair):
     g = orc.xyz[interior] @ coef + 0.5
     IP = orc.csr("IP")
     full = np.isclose(np.asarray(IP.sum(axis=1)).ravel(), 1.0)
-    assert full.sum() > lib.n // 4
+    assert full.sum() > lib.n // 8          # enough rows away from the boundary to test
     assert np.max(np.abs((IP @ g)[full] - (X[full] @ coef + 0.5))) < 1e-12
     # nodes lie inside the cube, vertices of the key averaged
     assert np.all((X > 0) & (X < 1))

@@ -23,7 +23,7 @@ def _node_positions(P, xyz):
     return xyz[keys].mean(axis=1), keys
 
 
-@pytest.mark.parametrize("k,n", [(2, 3), (2, 5), (3, 3), (3, 4)])
+@pytest.mark.parametrize("k,n", [(2, 3), (2, 5), (3, 3), (3, 4), (4, 2), (4, 3)])
 def test_sizes(k, n):
     xyz, tets = W.kuhn_mesh(n)
     P = oracle.Problem(xyz, tets, k)
@@ -36,7 +36,7 @@ def test_sizes(k, n):
     assert all(tuple(keys[i]) < tuple(keys[i + 1]) for i in range(len(keys) - 1))
 
 
-@pytest.mark.parametrize("k,jit", [(2, 0.0), (2, 0.2), (3, 0.0), (3, 0.15)])
+@pytest.mark.parametrize("k,jit", [(2, 0.0), (2, 0.2), (3, 0.0), (3, 0.15), (4, 0.0), (4, 0.15)])
 def test_stiffness_consistency_with_load(k, jit):
     n = 6
     xyz, tets = W.kuhn_mesh(n, jitter=jit, seed=11)
@@ -78,7 +78,7 @@ def test_P1_matrix_is_scaled_7_point_laplacian(n):
     assert abs(AH - h * L7).max() < 1e-14
 
 
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [2, 3, 4])
 def test_galerkin_relation(k):
     xyz, tets = W.kuhn_mesh(5, jitter=0.2, seed=2)
     kappa = np.exp(2.0 * np.random.default_rng(9).normal(size=tets.shape[0]))
@@ -88,7 +88,7 @@ def test_galerkin_relation(k):
     assert np.max(np.abs(G - AH.toarray())) < 1e-13 * np.max(np.abs(AH.toarray()))
 
 
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [2, 3, 4])
 def test_transfer_of_linear_functions(k):
     xyz, tets = W.kuhn_mesh(4, jitter=0.2, seed=5)
     P = oracle.Problem(xyz, tets, k)

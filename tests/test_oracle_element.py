@@ -36,7 +36,7 @@ def test_basis_kronecker_and_unity(k):
         assert abs(s - 1.0) < 1e-13
 
 
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [2, 3, 4])
 def test_basis_reproduces_degree_k(k):
     al = oracle.multi_indices(k)
     rng = np.random.default_rng(5)
@@ -53,7 +53,7 @@ def test_basis_reproduces_degree_k(k):
         assert abs(v - p(lam)) < 1e-12
 
 
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [2, 3, 4])
 def test_basis_derivative_matches_difference_quotient(k):
     al = oracle.multi_indices(k)
     rng = np.random.default_rng(7)
@@ -150,7 +150,7 @@ def _exact_lagrange_stiffness(k):
     return np.array([[float(v) for v in row] for row in K])
 
 
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [2, 3, 4])
 def test_element_matrix_equals_exact_rational(k):
     xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
     # a mesh made of one tet is enough for an element matrix
@@ -160,7 +160,7 @@ def test_element_matrix_equals_exact_rational(k):
     assert np.max(np.abs(K - Kx)) < 1e-13 * np.max(np.abs(Kx))
 
 
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [2, 3, 4])
 def test_element_matrix_invariants(k):
     xyz, tets = W.kuhn_mesh(2, jitter=0.2, seed=4)
     kappa = np.exp(np.random.default_rng(1).normal(size=tets.shape[0]))
@@ -184,7 +184,7 @@ def test_element_matrix_invariants(k):
         assert abs(uq @ K @ uq - exact) < 1e-12 * exact
 
 
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [2, 3, 4])
 def test_six_term_edge_form_of_element_stiffness(k):
     """The form the matrix-free operator uses: since the barycentric gradients
     sum to zero, K_e = sum_{p<q} (-kappa G_pq) (M^pp + M^qq - M^pq - M^qp) with

@@ -26,7 +26,7 @@ def _problem(k, n, jitter=0.0, seed=0, kappa=None, **amg):
     return P
 
 
-@pytest.mark.parametrize("k,n", [(2, 2), (2, 3), (3, 2), (2, 5)])
+@pytest.mark.parametrize("k,n", [(2, 2), (2, 3), (3, 2), (2, 5), (4, 2)])
 def test_pcg_matches_dense_solve(k, n):
     P = _problem(k, n, jitter=0.1, seed=1)
     b = P.load(W.manufactured_f)
@@ -42,7 +42,7 @@ def _grad_u(p):
                              s[..., 0] * s[..., 1] * c[..., 2]], axis=-1)
 
 
-@pytest.mark.parametrize("k,ns", [(2, (4, 8, 16)), (3, (2, 4, 8))])
+@pytest.mark.parametrize("k,ns", [(2, (4, 8, 16)), (3, (2, 4, 8)), (4, (2, 4, 8))])
 def test_convergence_rates(k, ns):
     l2, h1 = [], []
     for n in ns:
@@ -57,7 +57,7 @@ def test_convergence_rates(k, ns):
     assert k - 0.2 < r1 < k + 0.5, (h1, r1)
 
 
-@pytest.mark.parametrize("k,n", [(2, 3), (2, 4), (3, 3)])
+@pytest.mark.parametrize("k,n", [(2, 3), (2, 4), (3, 3), (4, 2)])
 def test_preconditioner_spd(k, n):
     P = _problem(k, n, jitter=0.2, seed=3)
     E = np.eye(P.n)
@@ -100,7 +100,7 @@ def test_augmented_system_and_block_gauss_seidel():
     assert np.max(np.abs(IP @ v_next[:nH] + v_next[nH:] - u_next)) < 1e-12 * np.max(np.abs(u_next))
 
 
-@pytest.mark.parametrize("k,ns", [(2, (4, 8, 12)), (3, (4, 6, 8))])
+@pytest.mark.parametrize("k,ns", [(2, (4, 8, 12)), (3, (4, 6, 8)), (4, (6, 8, 10))])
 def test_two_level_iterations_flat_in_h(k, ns):
     its = []
     for n in ns:
