@@ -156,10 +156,16 @@ def _np_ptr(a):
 
 
 class Solver:
-    """One P^k problem: mesh + order + per-tet kappa, set up once.
+    """One P^k problem (order 2, 3 or 4): mesh + order + per-tet kappa, set up once.
 
-    ``host_only=True`` runs only the host setup (no GPU needed); the matrices
-    and AMG hierarchy can then be inspected with ``export_csr``/``export_cf``.
+    The keyword options map one to one onto ``aux_options`` in ``include/aux.h``
+    (smoothing sweeps ``nu``, strength threshold ``theta``, coarsest size,
+    precision, operator, layout window, graph replay, 16-bit columns, composite
+    cycle, batched layout, V-cycle operator storage ``cycle_lanes``, dense
+    sub-cycle threshold ``dense_cycle_rows``); the defaults are the timed
+    configuration.  ``host_only=True`` runs only the host setup (no GPU
+    needed); the matrices and AMG hierarchy can then be inspected with
+    ``export_csr``/``export_cf``.
     """
 
     def __init__(self, xyz, tets, order: int, kappa=None, *, nu: int = 2, theta: float = 0.8,
