@@ -260,7 +260,7 @@ def run(args):
                    "setup_s": round(setup_s, 2), "sell_window": int(s.info.sell_window),
                    "sell_16bit_slices": f"{int(s.info.sell_narrow_slices)}/{int(s.info.sell_slices)}",
                    "sell_tune_ms": [round(v, 4) for v in s.info.sell_tune_ms],
-                   "cycle_lanes": cycle_lanes(s.info),
+                   "cycle_lanes": cycle_lanes(s.info), "sell_split": int(s.info.sell_split),
                    "ms_per_step_profiled": round(mixed["ms_profiled"], 3)},
         "fp64": {"value": n / (fp64["ms"] * 1e-3), "ms_per_step": fp64["ms"],
                  "iterations": fp64["iterations"][-1], "true_rel_residual": fp64["true_rel_residual"],

@@ -164,6 +164,8 @@ typedef struct aux_info {
      * L > 0 row-split sliced ELL with L lanes per row (64 / L rows per
      * wavefront), -L CSR with L lanes per row. */
     int32_t dense_cycle_level; /* first level evaluated by the dense cycle matrix, -1 if none */
+    int32_t sell_split;      /* 1: the single-vector A_h passes give each slice two wavefronts
+                                (32-bit layout with slices of at least 56 slots on average) */
     int32_t lanes_restrict;  /* fused restriction [I_R, -I_R A_h] (0 if not fused) */
     int32_t lanes_prolong;   /* I_P */
     int32_t lanes_down[32];  /* fused down operator of level l */

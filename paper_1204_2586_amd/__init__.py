@@ -73,6 +73,7 @@ class _Info(ctypes.Structure):
                 ("nnz_restrict", ctypes.c_int64), ("level_nnz_down", ctypes.c_int64 * 32),
                 ("level_nnz_up", ctypes.c_int64 * 32), ("batch_tile_rows", ctypes.c_int32 * 2),
                 ("sell_tune_ms", ctypes.c_double * 4), ("dense_cycle_level", ctypes.c_int32),
+                ("sell_split", ctypes.c_int32),
                 ("lanes_restrict", ctypes.c_int32),
                 ("lanes_prolong", ctypes.c_int32), ("lanes_down", ctypes.c_int32 * 32),
                 ("lanes_up", ctypes.c_int32 * 32)]

@@ -55,15 +55,12 @@ inline int grid_cap(long long need)
 
 // ------------------------------------------------------------------ SELL
 
-// One wavefront per 64-row slice, one lane per row; consecutive slices go to
-// consecutive workgroups, which the dispatcher spreads round-robin over the
-// dies, so at any moment all dies gather from the same neighbourhood of the
-// vector and share it through the last-level cache (giving each die its own
-// contiguous range of slices measured twice as slow).
-#define FOR_SLICES(A)                                                                                      \
-    const int lane_ = threadIdx.x & 63;                                                                    \
-    for (int sl_ = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6); sl_ < (A).nslices;                \
-         sl_ += gridDim.x * (kBlock / 64))
+// One wavefront per 64-row slice (or two, see sell_rows), one lane per row;
+// consecutive slices go to consecutive workgroups, which the dispatcher
+// spreads round-robin over the dies, so at any moment all dies gather from
+// the same neighbourhood of the vector and share it through the last-level
+// cache (giving each die its own contiguous range of slices measured twice as
+// slow, and no faster when the ranges are balanced by entries).
 
 // MIXED = false: every slice has 32-bit columns, stored in entry order
 // (wide[e]); MIXED = true: a 16-bit or 32-bit choice per slice.
@@ -103,20 +100,83 @@ __device__ __forceinline__ T sell_row(const DevSellView &A, int slice, int lane,
     return s;
 }
 
-#define MIXED_SWITCH(A, CALL)        \
-    do {                             \
-        if ((A).mixed) {             \
-            constexpr bool M = true; \
-            CALL;                    \
-        } else {                     \
-            constexpr bool M = false; \
-            CALL;                    \
-        }                            \
+
+// Slots [half ? ceil(w/2) : 0, half ? w : ceil(w/2)) of a 32-bit slice of
+// width w (the split form)
+template <typename T, typename XF>
+__device__ __forceinline__ T sell_row_half(const DevSellView &A, int slice, int lane, int half, XF x)
+{
+    const T *__restrict__ val = (const T *)A.val;
+    const int *__restrict__ col = A.wide;
+    slice = __builtin_amdgcn_readfirstlane(slice);
+    const int e0 = A.slice_off[slice], e1 = A.slice_off[slice + 1];
+    const int wh = ((e1 - e0) / kSlice + 1) / 2;
+    const int b = half ? e0 + wh * kSlice : e0, end = half ? e1 : e0 + wh * kSlice;
+    T s = T(0);
+#pragma unroll 8
+    for (int e = b + lane; e < end; e += kSlice) s += val[e] * x(col[e]);
+    return s;
+}
+
+// Every row of A: s = (A x)_row, then epi(row, s).  F = 0: one wavefront per
+// 32-bit slice; F = 1: the same with per-slice 16/32-bit columns; F = 2 (wide
+// 32-bit slices): two wavefronts per slice, each summing half of its slots
+// (shorter dependent chains, twice the wavefronts in flight); the second
+// half's sums pass through LDS and are added to the first in a fixed order.
+// In the split form every thread of the block runs the same number of steps,
+// so the barriers are uniform.
+template <typename T, int F, typename XF, typename EPI>
+__device__ __forceinline__ void sell_rows(const DevSellView &A, XF x, EPI epi)
+{
+    const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
+    if constexpr (F != 2) {
+        for (int sl = blockIdx.x * (kBlock / 64) + w; sl < A.nslices; sl += gridDim.x * (kBlock / 64)) {
+            const T s = sell_row<T, F == 1>(A, sl, lane, x);
+            const int row = sl * kSlice + lane;
+            if (row < A.n) epi(row, s);
+        }
+    } else {
+        constexpr int kPairs = kBlock / 128;
+        __shared__ T part[kPairs][64];
+        const int q = w >> 1, h = w & 1;
+        const int per_step = kPairs * (int)gridDim.x;
+        const int steps = (A.nslices + per_step - 1) / per_step;
+        for (int it = 0; it < steps; it++) {
+            const int sl = (it * (int)gridDim.x + (int)blockIdx.x) * kPairs + q;
+            T s = T(0);
+            if (sl < A.nslices) s = sell_row_half<T>(A, sl, lane, h, x);
+            if (h == 1) part[q][lane] = s;
+            __syncthreads();
+            if (h == 0 && sl < A.nslices) {
+                s += part[q][lane];
+                const int row = sl * kSlice + lane;
+                if (row < A.n) epi(row, s);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+#define FORM_SWITCH(A, CALL)                                \
+    do {                                                    \
+        if ((A).mixed) {                                    \
+            constexpr int F = 1;                            \
+            CALL;                                           \
+        } else if ((A).split) {                             \
+            constexpr int F = 2;                            \
+            CALL;                                           \
+        } else {                                            \
+            constexpr int F = 0;                            \
+            CALL;                                           \
+        }                                                   \
     } while (0)
 
-inline int sell_grid(const DevSellView &A) { return grid_cap(((long long)A.nslices + 3) / 4); }
+inline int sell_grid(const DevSellView &A)
+{
+    return A.split && !A.mixed ? grid_cap(((long long)A.nslices + 1) / 2) : grid_cap(((long long)A.nslices + 3) / 4);
+}
 
-template <typename T, typename TR, typename TZ, bool DOT, bool MIXED>
+template <typename T, typename TR, typename TZ, bool DOT, int F>
 __global__ __launch_bounds__(kBlock) void k_sell_sweep(DevSellView A, const T *__restrict__ dinv,
                                                        const TR *__restrict__ rhs, const T *__restrict__ zin,
                                                        TZ *__restrict__ zout, const double *__restrict__ rdot,
@@ -124,60 +184,40 @@ __global__ __launch_bounds__(kBlock) void k_sell_sweep(DevSellView A, const T *_
 {
     if (stop(done)) return;
     double acc = 0.0;
-    FOR_SLICES(A)
-    {
-        const int row = sl_ * kSlice + lane_;
-        T s = sell_row<T, MIXED>(A, sl_, lane_, [&](int j) { return zin[j]; });
-        if (row < A.n) {
-            T zi = zin[row] + dinv[row] * ((T)rhs[row] - s);
-            zout[row] = (TZ)zi;
-            if (DOT) acc += rdot[row] * (double)(TZ)zi;
-        }
-    }
+    sell_rows<T, F>(A, [&](int j) { return zin[j]; }, [&](int row, T s) {
+        T zi = zin[row] + dinv[row] * ((T)rhs[row] - s);
+        zout[row] = (TZ)zi;
+        if (DOT) acc += rdot[row] * (double)(TZ)zi;
+    });
     if (DOT) write_partial(partials, acc);
 }
 
-template <typename T, bool MIXED>
+template <typename T, int F>
 __global__ __launch_bounds__(kBlock) void k_sell_resid(DevSellView A, const T *__restrict__ rhs,
                                                        const T *__restrict__ z, T *__restrict__ res, const int *done)
 {
     if (stop(done)) return;
-    FOR_SLICES(A)
-    {
-        const int row = sl_ * kSlice + lane_;
-        T s = sell_row<T, MIXED>(A, sl_, lane_, [&](int j) { return z[j]; });
-        if (row < A.n) res[row] = rhs[row] - s;
-    }
+    sell_rows<T, F>(A, [&](int j) { return z[j]; }, [&](int row, T s) { res[row] = rhs[row] - s; });
 }
 
-template <bool DOT, bool MIXED>
+template <bool DOT, int F>
 __global__ __launch_bounds__(kBlock) void k_sell_spmv64(DevSellView A, const double *__restrict__ x,
                                                         double *__restrict__ y, double *partials, const int *done)
 {
     if (stop(done)) return;
     double acc = 0.0;
-    FOR_SLICES(A)
-    {
-        const int row = sl_ * kSlice + lane_;
-        double s = sell_row<double, MIXED>(A, sl_, lane_, [&](int j) { return x[j]; });
-        if (row < A.n) {
-            y[row] = s;
-            if (DOT) acc += x[row] * s;
-        }
-    }
+    sell_rows<double, F>(A, [&](int j) { return x[j]; }, [&](int row, double s) {
+        y[row] = s;
+        if (DOT) acc += x[row] * s;
+    });
     if (DOT) write_partial(partials, acc);
 }
 
-template <bool MIXED>
+template <int F>
 __global__ __launch_bounds__(kBlock) void k_sell_residual64(DevSellView A, const double *__restrict__ f,
                                                             const double *__restrict__ u, double *__restrict__ r)
 {
-    FOR_SLICES(A)
-    {
-        const int row = sl_ * kSlice + lane_;
-        double s = sell_row<double, MIXED>(A, sl_, lane_, [&](int j) { return u[j]; });
-        if (row < A.n) r[row] = f[row] - s;
-    }
+    sell_rows<double, F>(A, [&](int j) { return u[j]; }, [&](int row, double s) { r[row] = f[row] - s; });
 }
 
 template <typename T>
@@ -517,9 +557,9 @@ int sell_sweep(hipStream_t s, const DevSellView &A, const T *dinv, const TR *rhs
                const double *rdot, double *partials, const int *done)
 {
     int g = sell_grid(A);
-    MIXED_SWITCH(A, if (partials) hipLaunchKernelGGL((k_sell_sweep<T, TR, TZ, true, M>), dim3(g), dim3(kBlock), 0, s, A,
+    FORM_SWITCH(A, if (partials) hipLaunchKernelGGL((k_sell_sweep<T, TR, TZ, true, F>), dim3(g), dim3(kBlock), 0, s, A,
                                                      dinv, rhs, zin, zout, rdot, partials, done);
-                 else hipLaunchKernelGGL((k_sell_sweep<T, TR, TZ, false, M>), dim3(g), dim3(kBlock), 0, s, A, dinv,
+                 else hipLaunchKernelGGL((k_sell_sweep<T, TR, TZ, false, F>), dim3(g), dim3(kBlock), 0, s, A, dinv,
                                          rhs, zin, zout, rdot, partials, done));
     return g;
 }
@@ -528,7 +568,7 @@ template <typename T>
 int sell_resid(hipStream_t s, const DevSellView &A, const T *rhs, const T *z, T *res, const int *done)
 {
     int g = sell_grid(A);
-    MIXED_SWITCH(A, hipLaunchKernelGGL((k_sell_resid<T, M>), dim3(g), dim3(kBlock), 0, s, A, rhs, z, res, done));
+    FORM_SWITCH(A, hipLaunchKernelGGL((k_sell_resid<T, F>), dim3(g), dim3(kBlock), 0, s, A, rhs, z, res, done));
     return g;
 }
 
@@ -536,10 +576,10 @@ int sell_spmv64(hipStream_t s, const DevSellView &A, const double *x, double *y,
 {
     int g = sell_grid(A);
     if (partials)
-        MIXED_SWITCH(A, hipLaunchKernelGGL((k_sell_spmv64<true, M>), dim3(g), dim3(kBlock), 0, s, A, x, y, partials,
+        FORM_SWITCH(A, hipLaunchKernelGGL((k_sell_spmv64<true, F>), dim3(g), dim3(kBlock), 0, s, A, x, y, partials,
                                            done));
     else
-        MIXED_SWITCH(A, hipLaunchKernelGGL((k_sell_spmv64<false, M>), dim3(g), dim3(kBlock), 0, s, A, x, y, partials,
+        FORM_SWITCH(A, hipLaunchKernelGGL((k_sell_spmv64<false, F>), dim3(g), dim3(kBlock), 0, s, A, x, y, partials,
                                            done));
     return g;
 }
@@ -547,7 +587,7 @@ int sell_spmv64(hipStream_t s, const DevSellView &A, const double *x, double *y,
 int sell_residual64(hipStream_t s, const DevSellView &A, const double *f, const double *u, double *r)
 {
     int g = sell_grid(A);
-    MIXED_SWITCH(A, hipLaunchKernelGGL((k_sell_residual64<M>), dim3(g), dim3(kBlock), 0, s, A, f, u, r));
+    FORM_SWITCH(A, hipLaunchKernelGGL((k_sell_residual64<F>), dim3(g), dim3(kBlock), 0, s, A, f, u, r));
     return g;
 }
 

@@ -55,6 +55,7 @@ struct DevSellView {
     const unsigned short *off;
     const int *wide;
     const void *val;     // double or float, padding entries are 0
+    int split;           // with mixed == 0: two wavefronts per slice (wide slices)
 };
 
 // State of a CG solve in device memory.

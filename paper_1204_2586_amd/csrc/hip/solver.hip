@@ -72,11 +72,16 @@ struct DevSell {
     unsigned short *off = nullptr;
     double *v64 = nullptr;
     float *v32 = nullptr;
+    // 32-bit layouts whose slices average at least this many slots give each
+    // slice two wavefronts in the single-vector kernels: P4 (72 slots) gains
+    // 10-14 %, P3 (47) loses up to 5 % in FP64, P2 (28) keeps one
+    static constexpr int kSplitSlots = 56;
+    bool split() const { return narrow_slices == 0 && nslices > 0 && stored >= (int64_t)kSplitSlots * 64 * nslices; }
     template <typename T>
     DevSellView view() const
     {
         return {n, nslices, max_width, narrow_slices > 0 ? 1 : 0, slice_off, mode, base, off, wide,
-                std::is_same<T, float>::value ? (const void *)v32 : (const void *)v64};
+                std::is_same<T, float>::value ? (const void *)v32 : (const void *)v64, split() ? 1 : 0};
     }
 };
 
@@ -1762,6 +1767,7 @@ int aux_get_info(const aux_handle *h, aux_info *info)
             info->level_nnz_up[l] = h->fused_host[l].up.nnz();
         }
         info->dense_cycle_level = h->dense_first == SIZE_MAX ? -1 : (int32_t)h->dense_first;
+        info->sell_split = h->A.split() ? 1 : 0;
         info->lanes_restrict = h->RF.n ? h->RF.lanes_code() : 0;
         info->lanes_prolong = h->IP.lanes_code();
         for (size_t l = 0; l + 1 < h->lev.size() && l < 32; l++) {

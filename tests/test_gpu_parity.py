@@ -389,6 +389,28 @@ def test_dense_cycle(k, n, rows):
             assert _rel(U[:, j].cpu().numpy(), orc.pcg(F[:, j], tol=1e-8)[0]) <= 1e-7
 
 
+@pytest.mark.parametrize("k,n,split", [(4, 7, 1), (2, 12, 0)])
+def test_split_slices(k, n, split):
+    """With 32-bit columns, wide slices (P4) are summed by two wavefronts each
+    and narrow ones (P2) by one; either gives the oracle's operator,
+    preconditioner and CG iterates to rounding."""
+    print(f"[split slices k={k} n={n}]", flush=True)
+    xyz, tets, kappa = _case(k, n, jitter=0.2, kappa="rand")
+    lib = aux.Solver(xyz, tets, k, kappa, device=DEV, sell_index16=False)
+    assert lib.info.sell_split == split and lib.info.sell_narrow_slices == 0
+    orc = oracle.Problem(xyz, tets, k, kappa).setup_amg()
+    r = W.random_vector(lib.n, 4)
+    assert _rel(lib.matvec(_t(r)).cpu().numpy(), orc.csr("A") @ r) <= 1e-13
+    for prec, tol in (("fp64", 1e-12), ("mixed", 2e-6)):
+        lib.set_precision(prec)
+        assert _rel(lib.apply(_t(r)).cpu().numpy(), orc.apply(r, fp32=(prec == "mixed"))) <= tol, prec
+    b = orc.load(W.manufactured_f)
+    lib.set_precision("fp64")
+    x, it, _, _ = orc.pcg(b, tol=1e-8)
+    u, info = lib.solve(_t(b), tol=0.0, maxit=it, check=False)
+    assert _rel(u.cpu().numpy(), x) <= 1e-10
+
+
 @pytest.mark.parametrize("nrhs", [5, 12, 32])
 def test_batched_tiles_equal_slices(nrhs):
     """Block products from LDS-staged row tiles and from 64-row slices sum each
