@@ -184,7 +184,7 @@ void aux_default_options(aux_options *opt);
 
 /* Build the discretisation, transfer and AMG hierarchy on the host and copy
  * the solve-phase data to the device.  mesh: host arrays as described; order
- * 2, 3 or 4 (the matrix-free operator: 2 or 3); kappa: host [n_tets]
+ * 2, 3 or 4; kappa: host [n_tets]
  * positive values, or NULL for kappa = 1; opt: NULL for defaults; dev: NULL
  * for hipMalloc on the current device and the default stream.  On success *out owns all buffers; release it with
  * aux_destroy.  Errors: AUX_EINVAL (order, empty or degenerate mesh, vertex id
@@ -206,7 +206,7 @@ int aux_set_precision(aux_handle *h, int precision);
 /* Choose how the preconditioner's P^k smoothing and residual products are
  * computed: AUX_OP_ASSEMBLED (sliced-ELL A_h) or AUX_OP_MATFREE (element
  * operator K_e = kappa_e sum_pq G^e_pq M^pq, Sec. 2 eq. (2.5), evaluated per
- * tet with MFMA and summed per dof; orders 2 and 3, AUX_EINVAL for 4).  With
+ * tet with MFMA and summed per dof).  With
  * the matrix-free operator the FP64 CG product uses it too.  The element data
  * are built on first use. */
 int aux_set_operator(aux_handle *h, int op);

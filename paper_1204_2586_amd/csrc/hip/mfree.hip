@@ -78,17 +78,18 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(MfView<T> op, const T *__
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, grp = lane >> 4;
 
+    // Output tiles of 16 rows handled per pass over the tets: all of them for
+    // P2/P3; one per pass for P4, whose 35-node tables (41.5 KB in FP32,
+    // 83 KB in FP64) would not leave room for enough workgroups per compute
+    // unit (the element map, weights and gathers are then read once per pass)
+    constexpr int MG = NLOC > 20 ? 1 : MT;
+    constexpr int NPASS = MT / MG;
+
     // A operand: lane (i = lane % 16, g) of step s holds S[16 mt + i][k nloc + b],
     // staged in LDS in that lane order (one conflict-free read per step; in
-    // registers the tables would take 60 (FP32) or 120 (FP64) VGPRs and cap
-    // the waves per SIMD at 4 or 2)
-    __shared__ T sA[MT * KS * 64];
-    for (int i = threadIdx.x; i < MT * KS * 64; i += kBlock) {
-        const int l = i % 64, s = (i / 64) % KS, mt = i / (64 * KS);
-        const int row = 16 * mt + l % 16, k = s / NB, b = 4 * (s % NB) + l / 16;
-        sA[i] = (row < NLOC && b < NLOC) ? op.S[row * 6 * NLOC + k * NLOC + b] : T(0);
-    }
-    __syncthreads();
+    // registers the tables would take 60 (FP32) or 120 (FP64) VGPRs at P3 and
+    // cap the waves per SIMD at 4 or 2)
+    __shared__ T sA[MG * KS * 64];
 
     // Each die (workgroups are dispatched round-robin over kDies dies, b to
     // b % kDies) takes a contiguous range of tiles, so the slots of a dof,
@@ -112,63 +113,72 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(MfView<T> op, const T *__
             step = gd * kWaves;
         }
     }
-    for (int tile = first; tile < end; tile += step) {
-        const int t = tile * kTetsPerWave + col;
-        const bool tv = t < op.nt;
-        const size_t tc = tv ? (size_t)t : 0;   // loads stay unconditional (clamped), so
-        T wv[6], xv[NB];                        // all of them are in flight together
-        int dv[NB];
-#pragma unroll
-        for (int k = 0; k < 6; k++) wv[k] = op.w[tc * 6 + k];
-#pragma unroll
-        for (int j = 0; j < NB; j++) {
-            const int b = 4 * j + grp;
-            dv[j] = op.emap[tc * NLOC + (b < NLOC ? b : 0)];
-            if (!tv || b >= NLOC) dv[j] = -1;
+    for (int pass = 0; pass < NPASS; pass++) {
+        if (pass > 0) __syncthreads();          // every wave is done with the previous tables
+        for (int i = threadIdx.x; i < MG * KS * 64; i += kBlock) {
+            const int l = i % 64, s = (i / 64) % KS, mt = pass * MG + i / (64 * KS);
+            const int row = 16 * mt + l % 16, k = s / NB, b = 4 * (s % NB) + l / 16;
+            sA[i] = (row < NLOC && b < NLOC) ? op.S[row * 6 * NLOC + k * NLOC + b] : T(0);
         }
-        // slots of this lane's results, loaded with the element map
-        int sv[MT][4];
+        __syncthreads();
+        for (int tile = first; tile < end; tile += step) {
+            const int t = tile * kTetsPerWave + col;
+            const bool tv = t < op.nt;
+            const size_t tc = tv ? (size_t)t : 0;   // loads stay unconditional (clamped), so
+            T wv[6], xv[NB];                        // all of them are in flight together
+            int dv[NB];
 #pragma unroll
-        for (int mt = 0; mt < MT; mt++)
+            for (int k = 0; k < 6; k++) wv[k] = op.w[tc * 6 + k];
 #pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int a = 16 * mt + Acc<T>::row(grp, v);
-                sv[mt][v] = op.slot[tc * NLOC + (a < NLOC ? a : 0)];
+            for (int j = 0; j < NB; j++) {
+                const int b = 4 * j + grp;
+                dv[j] = op.emap[tc * NLOC + (b < NLOC ? b : 0)];
+                if (!tv || b >= NLOC) dv[j] = -1;
             }
+            // slots of this lane's results, loaded with the element map
+            int sv[MG][4];
 #pragma unroll
-        for (int j = 0; j < NB; j++) xv[j] = X[dv[j] >= 0 ? dv[j] : 0];
-        // keep the scheduler from interleaving the loads with their uses (it
-        // would otherwise reuse one address register and wait on each)
-        __builtin_amdgcn_sched_barrier(0);
+            for (int m = 0; m < MG; m++)
 #pragma unroll
-        for (int mt = 0; mt < MT; mt++)
+                for (int v = 0; v < 4; v++) {
+                    const int a = 16 * (pass * MG + m) + Acc<T>::row(grp, v);
+                    sv[m][v] = op.slot[tc * NLOC + (a < NLOC ? a : 0)];
+                }
 #pragma unroll
-            for (int v = 0; v < 4; v++)
-                if (!tv || 16 * mt + Acc<T>::row(grp, v) >= NLOC) sv[mt][v] = -1;
+            for (int j = 0; j < NB; j++) xv[j] = X[dv[j] >= 0 ? dv[j] : 0];
+            // keep the scheduler from interleaving the loads with their uses (it
+            // would otherwise reuse one address register and wait on each)
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int j = 0; j < NB; j++)
-            if (dv[j] < 0) xv[j] = T(0);
+            for (int m = 0; m < MG; m++)
 #pragma unroll
-        for (int k = 0; k < 6; k++)
-            if (!tv) wv[k] = T(0);
+                for (int v = 0; v < 4; v++)
+                    if (!tv || 16 * (pass * MG + m) + Acc<T>::row(grp, v) >= NLOC) sv[m][v] = -1;
+#pragma unroll
+            for (int j = 0; j < NB; j++)
+                if (dv[j] < 0) xv[j] = T(0);
+#pragma unroll
+            for (int k = 0; k < 6; k++)
+                if (!tv) wv[k] = T(0);
 
-        // B operand: lane (g, c) holds Z[(k, b)][c] = w_c,k x_c,b, formed step by
-        // step (the gathers above are all in flight before the first use)
-        typename Acc<T>::V acc[MT];
+            // B operand: lane (g, c) holds Z[(k, b)][c] = w_c,k x_c,b, formed step
+            // by step (the gathers above are all in flight before the first use)
+            typename Acc<T>::V acc[MG];
 #pragma unroll
-        for (int mt = 0; mt < MT; mt++) acc[mt] = typename Acc<T>::V{0, 0, 0, 0};
+            for (int m = 0; m < MG; m++) acc[m] = typename Acc<T>::V{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < KS; s++) {
-            const T bv = wv[s / NB] * xv[s % NB];
+            for (int s = 0; s < KS; s++) {
+                const T bv = wv[s / NB] * xv[s % NB];
 #pragma unroll
-            for (int mt = 0; mt < MT; mt++) acc[mt] = Acc<T>::mfma(sA[(mt * KS + s) * 64 + lane], bv, acc[mt]);
+                for (int m = 0; m < MG; m++) acc[m] = Acc<T>::mfma(sA[(m * KS + s) * 64 + lane], bv, acc[m]);
+            }
+            // D: register v of this lane holds row Acc<T>::row(grp, v) of column c
+#pragma unroll
+            for (int m = 0; m < MG; m++)
+#pragma unroll
+                for (int v = 0; v < 4; v++)
+                    if (sv[m][v] >= 0) Yel[sv[m][v]] = acc[m][v];
         }
-        // D: register v of this lane holds row Acc<T>::row(grp, v) of column c
-#pragma unroll
-        for (int mt = 0; mt < MT; mt++)
-#pragma unroll
-            for (int v = 0; v < 4; v++)
-                if (sv[mt][v] >= 0) Yel[sv[mt][v]] = acc[mt][v];
     }
 }
 
@@ -230,8 +240,10 @@ void mf_apply(hipStream_t s, const MfView<T> &op, const T *x, T *Yel, const int 
     if (g < 1) g = 1;
     if (op.nloc == 10)
         hipLaunchKernelGGL((k_mf_element<T, 10>), dim3(g), dim3(kBlock), 0, s, op, x, Yel, done);
-    else
+    else if (op.nloc == 20)
         hipLaunchKernelGGL((k_mf_element<T, 20>), dim3(g), dim3(kBlock), 0, s, op, x, Yel, done);
+    else
+        hipLaunchKernelGGL((k_mf_element<T, 35>), dim3(g), dim3(kBlock), 0, s, op, x, Yel, done);
 }
 
 template <typename T>

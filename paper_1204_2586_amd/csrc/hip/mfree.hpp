@@ -9,7 +9,7 @@ template <typename T>
 struct MfView {
     int n;               // dofs (internal order)
     int nt;              // tets
-    int nloc;            // 10 (P2) or 20 (P3)
+    int nloc;            // 10 (P2), 20 (P3) or 35 (P4)
     const int *emap;     // [nt][nloc] internal dof of each local node, -1 on the boundary
     const T *w;          // [nt][6] edge weights -kappa_e G^e_pq, pairs (01,02,03,12,13,23)
     const T *S;          // [nloc][6 nloc] reference tables S[a][k nloc + b] = S^k_ab

@@ -1630,8 +1630,6 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
             throw AuxError(AUX_EINVAL, "bad coarse_max or max_levels");
         if (o.precision != AUX_FP64 && o.precision != AUX_MIXED) throw AuxError(AUX_EINVAL, "bad precision");
         if (o.op != AUX_OP_ASSEMBLED && o.op != AUX_OP_MATFREE) throw AuxError(AUX_EINVAL, "bad operator kind");
-        if (o.op == AUX_OP_MATFREE && order > 3)
-            throw AuxError(AUX_EINVAL, "the matrix-free operator supports orders 2 and 3");
         if (o.sell_window < 0) throw AuxError(AUX_EINVAL, "sell_window must be >= 0");
         for (int flag : {o.graph, o.sell_index16, o.fuse_cycle, o.host_only})
             if (flag != 0 && flag != 1) throw AuxError(AUX_EINVAL, "a boolean option is not 0 or 1");
@@ -1717,8 +1715,6 @@ int aux_set_operator(aux_handle *h, int op)
     return guarded([&]() {
         need_device(h);
         if (op != AUX_OP_ASSEMBLED && op != AUX_OP_MATFREE) throw AuxError(AUX_EINVAL, "bad operator kind");
-        if (op == AUX_OP_MATFREE && h->disc.k > 3)
-            throw AuxError(AUX_EINVAL, "the matrix-free operator supports orders 2 and 3");
         set_dev(h);
         h->opt.op = op;
         if (op == AUX_OP_MATFREE) h->ensure_mf();

@@ -44,7 +44,7 @@ def _mesh():
 
 @pytest.mark.parametrize("case", ["order", "kappa_zero", "kappa_nan", "xyz_nan", "vertex_range", "flat_tet",
                                   "theta", "nu", "sell_window", "batch_tiles", "fuse_cycle", "cycle_lanes",
-                                  "cycle_lanes_neg", "dense_cycle_rows", "matfree_p4", "no_interior"])
+                                  "cycle_lanes_neg", "dense_cycle_rows", "no_interior"])
 def test_setup_rejects_bad_input(case):
     xyz, tets = _mesh()
     kappa = np.ones(len(tets))
@@ -81,9 +81,6 @@ def test_setup_rejects_bad_input(case):
         kw["cycle_lanes"] = -64
     elif case == "dense_cycle_rows":
         kw["dense_cycle_rows"] = -1
-    elif case == "matfree_p4":
-        order = 4
-        kw["operator"] = "matfree"
     elif case == "no_interior":                 # one tet: every node on the boundary
         xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
         tets = np.array([[0, 1, 2, 3]], dtype=np.int32)

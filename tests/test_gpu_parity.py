@@ -188,7 +188,8 @@ def test_batched_fixed_iterations_fp64():
         assert _rel(U[:, j].cpu().numpy(), x) <= 1e-10
 
 
-@pytest.mark.parametrize("k,n,jit,kap", [(3, 6, 0.0, "grf"), (2, 7, 0.2, "rand"), (3, 5, 0.15, None)])
+@pytest.mark.parametrize("k,n,jit,kap", [(3, 6, 0.0, "grf"), (2, 7, 0.2, "rand"), (3, 5, 0.15, None),
+                                         (4, 4, 0.2, "rand"), (4, 3, 0.0, None)])
 def test_matfree_operator(k, n, jit, kap):
     """The matrix-free element operator (MFMA) inside the preconditioner equals
     the assembled one: FP64 to rounding, FP32 to single precision."""
