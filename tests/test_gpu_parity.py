@@ -157,11 +157,13 @@ def test_status_codes():
     assert info2.iterations == 0 and torch.equal(u, u2)
 
 
+@pytest.mark.parametrize("k,n", [(2, 8), (3, 5), (4, 4)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_batched_columns_match_single_solves(precision):
-    xyz, tets, kappa = _case(2, 8, jitter=0.2, kappa="rand")
-    lib = aux.Solver(xyz, tets, 2, kappa, device=DEV, precision=precision)
-    orc = oracle.Problem(xyz, tets, 2, kappa).setup_amg()
+def test_batched_columns_match_single_solves(precision, k, n):
+    print(f"[batched columns k={k} n={n} {precision}]", flush=True)
+    xyz, tets, kappa = _case(k, n, jitter=0.2, kappa="rand")
+    lib = aux.Solver(xyz, tets, k, kappa, device=DEV, precision=precision)
+    orc = oracle.Problem(xyz, tets, k, kappa).setup_amg()
     nrhs = 12                                   # padded to 16 lanes internally
     F = np.stack([orc.load(W.fourier_f(r)) for r in range(nrhs)], axis=1)
     U, infos = lib.solve_batched(_t(F), tol=1e-8)
