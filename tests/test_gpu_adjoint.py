@@ -7,7 +7,8 @@ Gradients with respect to the load vector f and to log kappa per tet come
 from one adjoint CG solve (A is symmetric, same preconditioner) and the
 element formula dL/dlog(kappa_t) = -lam_t^T K_t u_t; they are compared with
 central differences along 16 random unit directions (each perturbed kappa is
-set up from scratch), relative error <= 1e-5.
+set up from scratch), relative error <= 1e-5.  The same check runs at
+P3 and P4 on small meshes.
 """
 import numpy as np
 import pytest
@@ -25,14 +26,15 @@ def _loss(f, logk, ut, prob):
     return 0.5 * torch.sum((u - ut) ** 2)
 
 
-@pytest.mark.parametrize("n,ndir", [(8, 4), (40, 16)])
+@pytest.mark.parametrize("k,n,ndir", [(2, 8, 4), (2, 40, 16), (3, 5, 4), (4, 4, 4)])
 @pytest.mark.timeout(900)
-def test_adjoint_gradients_match_finite_differences(n, ndir):
+def test_adjoint_gradients_match_finite_differences(k, n, ndir):
+    print(f"[adjoint k={k} n={n}]", flush=True)
     xyz, tets = W.kuhn_mesh(n)
     logk = W.grf_log_kappa(xyz, tets, seed=1)
     logk_t = W.grf_log_kappa(xyz, tets, seed=2)
-    prob = aux.KappaSolve(xyz, tets, 2, tol=1e-12, device=DEV)
-    f = torch.tensor(aux.Solver(xyz, tets, 2, host_only=True).load(W.manufactured_f), device=DEV)
+    prob = aux.KappaSolve(xyz, tets, k, tol=1e-12, device=DEV)
+    f = torch.tensor(aux.Solver(xyz, tets, k, host_only=True).load(W.manufactured_f), device=DEV)
     with torch.no_grad():
         ut = aux.AuxSolveFn.apply(f, torch.tensor(logk_t, device=DEV), prob)
     fv = f.clone().requires_grad_(True)
