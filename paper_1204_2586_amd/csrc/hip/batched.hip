@@ -569,8 +569,8 @@ __global__ __launch_bounds__(kBlock) void kb_cg_update_prep(int n, double *__res
     write_col_partials<NR>(partials, acc);
 }
 
-template <int NR>
-__global__ __launch_bounds__(kBlock) void kb_cg_direction(int n, const double *__restrict__ Z, double *__restrict__ P,
+template <int NR, typename TZ>
+__global__ __launch_bounds__(kBlock) void kb_cg_direction(int n, const TZ *__restrict__ Z, double *__restrict__ P,
                                                           BCgState st)
 {
     if (*st.all_done) return;
@@ -581,7 +581,8 @@ __global__ __launch_bounds__(kBlock) void kb_cg_direction(int n, const double *_
     FOR_BROWS(NR, n)
     {
         size_t o = (size_t)row * NR + c_;
-        P[o] = k == 0 ? Z[o] : Z[o] + beta * P[o];
+        const double z = Z[o];
+        P[o] = k == 0 ? z : z + beta * P[o];
     }
 }
 
@@ -835,10 +836,11 @@ template int bcg_update_prep<float>(hipStream_t, int, int, double *, double *, c
 template int bcg_update_prep<double>(hipStream_t, int, int, double *, double *, const double *, const double *,
                                      const BCgState &, double *, const double *, double *, double *);
 
-void bcg_direction(hipStream_t s, int nr, int n, const double *Z, double *P, const BCgState &st)
+template <typename TZ>
+void bcg_direction(hipStream_t s, int nr, int n, const TZ *Z, double *P, const BCgState &st)
 {
     int g = brows_grid(n, nr);
-    NR_SWITCH(nr, hipLaunchKernelGGL((kb_cg_direction<NR>), dim3(g), dim3(kBlock), 0, s, n, Z, P, st));
+    NR_SWITCH(nr, hipLaunchKernelGGL((kb_cg_direction<NR, TZ>), dim3(g), dim3(kBlock), 0, s, n, Z, P, st));
 }
 
 void bgather(hipStream_t s, int nr, int n, int ld, const int *perm, const double *x, double *y)
@@ -873,9 +875,11 @@ void bscatter(hipStream_t s, int nr, int n, int ld, const int *perm, const doubl
 
 BINST(double)
 BINST(float)
-template int bsell_sweep<float, double, double>(hipStream_t, int, const DevSellView &, const float *, const double *,
-                                                const float *, double *, const double *, double *, const int *);
-template int btile_sweep<float, double, double>(hipStream_t, int, const DevTilesView &, const float *, const double *,
-                                                const float *, double *, const double *, double *, const int *);
+template void bcg_direction<double>(hipStream_t, int, int, const double *, double *, const BCgState &);
+template void bcg_direction<float>(hipStream_t, int, int, const float *, double *, const BCgState &);
+template int bsell_sweep<float, double, float>(hipStream_t, int, const DevSellView &, const float *, const double *,
+                                               const float *, float *, const double *, double *, const int *);
+template int btile_sweep<float, double, float>(hipStream_t, int, const DevTilesView &, const float *, const double *,
+                                               const float *, float *, const double *, double *, const int *);
 
 }  // namespace auxp

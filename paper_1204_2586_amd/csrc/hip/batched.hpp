@@ -80,7 +80,10 @@ int bcg_update(hipStream_t s, int nr, int n, double *X, double *R, const double 
 template <typename T>
 int bcg_update_prep(hipStream_t s, int nr, int n, double *X, double *R, const double *P, const double *Q,
                     const BCgState &st, double *partials, const T *dinv, T *Z0, T *RT);
-void bcg_direction(hipStream_t s, int nr, int n, const double *Z, double *P, const BCgState &st);
+// Z: the preconditioned block, FP64 or (mixed mode, whose last sweep rounds
+// it to FP32 anyway) FP32
+template <typename TZ>
+void bcg_direction(hipStream_t s, int nr, int n, const TZ *Z, double *P, const BCgState &st);
 void bgather(hipStream_t s, int nr, int n, int ld, const int *perm, const double *x, double *y);
 void bscatter(hipStream_t s, int nr, int n, int ld, const int *perm, const double *x, double *y);
 

@@ -1322,7 +1322,7 @@ struct aux_handle {
 
     // Zout = B Rin for the nr columns of a block (internal order)
     template <typename T>
-    int bapply_B(const double *Rin, double *Zout, double *rz_partials, const int *all_done, bool prepped = false)
+    int bapply_B(const double *Rin, T *Zout, double *rz_partials, const int *all_done, bool prepped = false)
     {
         Work<T> &w = bwork<T>();
         hipStream_t s = stream;
@@ -1373,21 +1373,30 @@ struct aux_handle {
             std::swap(zc, zn);
         }
         pk = pbeg(AUX_PROF_PK_LAST);
-        int g = tl ? btile_sweep<T, double, double>(s, nr, tl->view<T>(), d, Rin, zc, Zout, Rin, rz_partials, all_done)
-                   : bsell_sweep<T, double, double>(s, nr, Av, d, Rin, zc, Zout, Rin, rz_partials, all_done);
+        int g = tl ? btile_sweep<T, double, T>(s, nr, tl->view<T>(), d, Rin, zc, Zout, Rin, rz_partials, all_done)
+                   : bsell_sweep<T, double, T>(s, nr, Av, d, Rin, zc, Zout, Rin, rz_partials, all_done);
         pend(pk);
         pend(pb);
         return g;
     }
 
-    int bapply(const double *Rin, double *Zout, double *rz_partials, const int *all_done, bool prepped = false)
+    // Z = B R into the z block.  In mixed mode the last sweep's values are
+    // FP32 results, so the block is kept in FP32 (in the FP64 block's memory):
+    // the same values with half the bytes written and read back.
+    int bapply(const double *Rin, double *rz_partials, const int *all_done, bool prepped = false)
     {
         ensure_bops();
         if (opt.precision == AUX_MIXED) {
             ensure_fp32();
-            return bapply_B<float>(Rin, Zout, rz_partials, all_done, prepped);
+            return bapply_B<float>(Rin, (float *)bt.Z, rz_partials, all_done, prepped);
         }
-        return bapply_B<double>(Rin, Zout, rz_partials, all_done, prepped);
+        return bapply_B<double>(Rin, bt.Z, rz_partials, all_done, prepped);
+    }
+    // P = Z + beta P from the z block of the current precision
+    void bdirection(const BCgState &st)
+    {
+        if (opt.precision == AUX_MIXED) bcg_direction(stream, bt.nr, disc.ndof, (const float *)bt.Z, bt.P, st);
+        else bcg_direction(stream, bt.nr, disc.ndof, (const double *)bt.Z, bt.P, st);
     }
 
     // one lock-step iteration of every column: Q = A P, alpha, X/R update,
@@ -1413,9 +1422,9 @@ struct aux_handle {
             g = bcg_update_prep<double>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, st, bt.partials, dinv64, w.za, nullptr);
         }
         bfinish(s, nr, bt.partials, g, FIN_RR, nullptr, st);
-        g = bapply(bt.R, bt.Z, bt.partials, st.all_done, true);
+        g = bapply(bt.R, bt.partials, st.all_done, true);
         bfinish(s, nr, bt.partials, g, FIN_RZ, nullptr, st);
-        bcg_direction(s, nr, n, bt.Z, bt.P, st);
+        bdirection(st);
     }
 
     int pcg_batched(const double *Fext, double *Uext, int nrhs, double tol, int maxit, aux_solve_info *infos)
@@ -1443,9 +1452,9 @@ struct aux_handle {
         bfinish(s, nr, bt.partials, g, FIN_PLAIN, bt.rr0, st);
         bcg_init(s, nr, st, tol * tol, bt.ff, bt.rr0);
         prof_tag = 0;
-        g = bapply(bt.R, bt.Z, bt.partials, all_done);
+        g = bapply(bt.R, bt.partials, all_done);
         bfinish(s, nr, bt.partials, g, FIN_RZ, nullptr, st);
-        bcg_direction(s, nr, n, bt.Z, bt.P, st);
+        bdirection(st);
         // lock-step iterations, replayed as a HIP graph when not profiling
         hipGraphExec_t gexec = nullptr;
         if (opt.graph && !prof_on) {
