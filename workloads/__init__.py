@@ -31,7 +31,7 @@ __all__ = [
     "manufactured_f",
     "fourier_f",
     "random_vector",
-    "CONFIGS",
+    "WORKLOADS",
     "make_config",
 ]
 
@@ -186,7 +186,7 @@ def random_vector(n: int, seed: int, dtype=np.float64):
 
 
 # The five workloads: (name, k, n, jitter, kappa spec, rhs spec, extra)
-CONFIGS = {
+WORKLOADS = {
     "p2_n8": dict(k=2, n=8, jitter=0.0, kappa=None, rhs="manufactured"),
     "p2_n48_jitter": dict(k=2, n=48, jitter=0.2, jitter_seed=0, kappa=None, rhs="manufactured"),
     "p3_n32_grf": dict(k=3, n=32, jitter=0.0, kappa=("grf", 1), rhs="manufactured"),
@@ -201,7 +201,7 @@ def make_config(name: str, n: int | None = None):
 
     Returns dict(xyz, tets, kappa, k, n, rhs).
     """
-    c = dict(CONFIGS[name])
+    c = dict(WORKLOADS[name])
     if n is not None:
         c["n"] = n
     xyz, tets = kuhn_mesh(c["n"], c.get("jitter", 0.0), c.get("jitter_seed", 0))
