@@ -165,6 +165,7 @@ struct aux_handle {
     double *hist = nullptr;          // rz, pq, rr each [hist_cap]
     int hist_cap = 0;
     int *host_state = nullptr;       // pinned: iter, done
+    double *host_scal = nullptr;     // pinned: r.r window of the chunk prediction, target, final r.r and f.f
     std::vector<void *> host_bufs;   // other pinned buffers
 
     // adjoint data (external dof numbering)
@@ -616,6 +617,7 @@ struct aux_handle {
         scal = dnew<double>(8);
         istate = dnew<int>(4);
         HIPCHECK(hipHostMalloc((void **)&host_state, 4 * sizeof(int), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void **)&host_scal, 8 * sizeof(double), hipHostMallocDefault));
         ensure_hist(std::max(opt.maxit, 16));
     }
 
@@ -967,6 +969,7 @@ struct aux_handle {
         // timing records events
         hipGraphExec_t gexec = opt.graph && !prof_on ? iteration_graph(st) : nullptr;
         int issued = 0, iter = 0, done = 0, chunk = 2;
+        bool first_check = true;
         while (true) {
             for (int c = 0; c < chunk && issued < maxit;) {
                 if (gexec) {
@@ -981,17 +984,25 @@ struct aux_handle {
                     c++;
                 }
             }
+            // one round trip per check: the status, the r.r values of the last
+            // three issued iterations (unless the solve stopped, every issued
+            // iteration ran, so they are those of iterations iter-2..iter) and,
+            // on the first check, the stopping target, all into pinned memory
             HIPCHECK(hipMemcpyAsync(host_state, istate, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            const int win = std::min(issued, maxit);
+            if (win >= 2)
+                HIPCHECK(hipMemcpyAsync(host_scal, st.rr + win - 2, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+            if (first_check)
+                HIPCHECK(hipMemcpyAsync(host_scal + 3, st.scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
+            first_check = false;
             iter = host_state[0];
             done = host_state[1];
             if (done || issued >= maxit) break;
             // predict the remaining iterations from the observed contraction
             chunk = 2;
-            if (iter >= 2) {
-                double rr[3], target = 0.0;
-                HIPCHECK(hipMemcpy(rr, st.rr + iter - 2, 3 * sizeof(double), hipMemcpyDeviceToHost));
-                HIPCHECK(hipMemcpy(&target, st.scal + 2, sizeof(double), hipMemcpyDeviceToHost));
+            if (iter >= 2 && iter == win) {
+                const double *rr = host_scal, target = host_scal[3];
                 if (rr[2] > 0 && rr[0] > rr[2] && target > 0) {
                     double rate = std::sqrt(rr[2] / rr[0]);
                     double need = std::log(target / rr[2]) / std::log(rate);
@@ -1002,9 +1013,10 @@ struct aux_handle {
         vec_scatter(s, n, perm, xi, u);
         prof_tag = -1;
         prof_collect(iter);
-        double rrv = 0.0, ffv = 0.0;
-        HIPCHECK(hipMemcpy(&rrv, st.rr + iter, sizeof(double), hipMemcpyDeviceToHost));
-        HIPCHECK(hipMemcpy(&ffv, scal + 0, sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpyAsync(host_scal + 4, st.rr + iter, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipMemcpyAsync(host_scal + 5, scal + 0, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        const double rrv = host_scal[4], ffv = host_scal[5];
         int status = AUX_OK;
         if (done == 2 || (done == 0 && issued >= maxit)) status = AUX_ENOTCONV;
         else if (done == 3) status = AUX_EBREAKDOWN;
@@ -1562,6 +1574,8 @@ struct aux_handle {
         ev_pool.clear();
         if (host_state) hipHostFree(host_state);
         host_state = nullptr;
+        if (host_scal) hipHostFree(host_scal);
+        host_scal = nullptr;
         for (void *ptr : host_bufs) hipHostFree(ptr);
         host_bufs.clear();
     }
