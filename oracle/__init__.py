@@ -16,7 +16,8 @@ What it computes (Lee, Leng and Zhang, arXiv:1204.2586):
   extended+i interpolation (the BoomerAMG options named in Sec. 1 and 6.1);
 * the preconditioner of Algorithm 2.1 with presmoothing (Remark 2.1),
   l1-Jacobi smoothing, one V(1,1) AMG cycle for Step 1;
-* preconditioned CG, in FP64 or with the preconditioner in FP32.
+* preconditioned CG, in FP64 or with the preconditioner in FP32, and the
+  flexible GMRES(m) of the paper's experiments (Sec. 6.1).
 """
 from __future__ import annotations
 
@@ -68,6 +69,9 @@ def _load():
     lib.orc_pcg.restype = ctypes.c_int
     lib.orc_pcg.argtypes = [vp, ctypes.c_int, _f64p, _f64p, ctypes.c_double, ctypes.c_int,
                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+    lib.orc_fgmres.restype = ctypes.c_int
+    lib.orc_fgmres.argtypes = [vp, ctypes.c_int, _f64p, _f64p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                               vp, vp, _f64p]
     lib.orc_kappa_grad.argtypes = [vp, _f64p, _f64p, _f64p]
     lib.orc_gauss_jacobi.argtypes = [ctypes.c_int, ctypes.c_int, _f64p, _f64p]
     lib.orc_tet_rule.argtypes = [ctypes.c_int, _f64p, _f64p]
@@ -259,6 +263,21 @@ class Problem:
         st = _load().orc_pcg(self._h, int(fp32), np.ascontiguousarray(b, dtype=np.float64), x, tol,
                              maxit, ctypes.byref(it), ctypes.byref(rr))
         return x, it.value, rr.value, st
+
+    def fgmres(self, b, tol=1e-6, restart=30, maxit=1000, x0=None, prec: str = "fp64"):
+        """Flexible GMRES(restart), stopping at ||r|| <= tol ||r_0||.  prec is
+        'fp64', 'fp32' (B in single precision) or 'none' (B = I).  Returns
+        (x, iterations, true relative residual, status, history), history[0]
+        = ||r_0|| and history[j] the rotated residual norm after step j."""
+        assert prec == "none" or self._amg, "call setup_amg first"
+        mode = {"fp64": 0, "fp32": 1, "none": 2}[prec]
+        x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64)
+        it = ctypes.c_int(0)
+        rr = ctypes.c_double(0.0)
+        hist = np.zeros(maxit + 1)
+        st = _load().orc_fgmres(self._h, mode, np.ascontiguousarray(b, dtype=np.float64), x, tol, restart,
+                                maxit, ctypes.byref(it), ctypes.byref(rr), hist)
+        return x, it.value, rr.value, st, hist[: it.value + 1]
 
     def kappa_grad(self, u, lam) -> np.ndarray:
         g = np.zeros(self.tets.shape[0])

@@ -15,6 +15,8 @@ double orc_h1_error(const orc *o, int m, const double *gq, const double *u);
 int orc_apply_precond(const orc *o, int fp32, const double *r, double *z);
 int orc_pcg(const orc *o, int fp32, const double *b, double *x, double tol, int maxit,
             int *iters, double *relres);
+int orc_fgmres(const orc *o, int prec, const double *b, double *x, double tol, int m, int maxit,
+               int *iters, double *relres, double *hist);
 int orc_kappa_grad(const orc *o, const double *u, const double *lam, double *g);
 
 void orc_free(orc *o)

@@ -7,7 +7,8 @@
  * AMG V-cycle (Remark 2.1 allows "an AMG method or a few AMG cycles" for Step
  * 1), prolong with I_P (Step 2) and postsmooth (Step 3).  The smoother G_h,
  * which the paper leaves open, is l1-Jacobi: G_h = D_l1^{-1} with
- * D_l1 = diag(sum_j |a_ij|).  The outer iteration is preconditioned CG.
+ * D_l1 = diag(sum_j |a_ij|).  The outer iteration is preconditioned CG, or
+ * flexible GMRES(m), the method of the paper's experiments (Sec. 6.1).
  *
  * The "fp32" mode runs B in single precision: every stored operand of B is
  * rounded to float once, the input residual is rounded to float, and every
@@ -284,4 +285,103 @@ int orc_kappa_grad(const orc *o, const double *u, const double *lam, double *g)
     }
     free(K);
     return 0;
+}
+
+/* Flexible GMRES(m), the Krylov method of the paper's Sec. 6.1 (Saad's
+   flexible variant, right preconditioning): each Arnoldi step stores the
+   preconditioned vector z_j = B v_j, orthogonalises w = A z_j against
+   v_0..v_j by modified Gram-Schmidt, and the least-squares problem
+   min ||beta e_1 - Hbar y|| is kept triangular by Givens rotations; at the
+   end of a cycle x += Z y.  prec: 0 B in FP64, 1 B in FP32, 2 none (B = I).
+   Stops when the rotated residual norm |g_{j+1}| <= tol ||r_0||_2, r_0 the
+   residual of the initial x.  hist (optional, [maxit+1]) receives ||r_0||
+   and the rotated residual norm after every Arnoldi step.  Returns 0
+   converged, 1 not converged in maxit steps, 3 NaN; *relres is the true
+   ||b - A x|| / ||r_0|| at exit. */
+int orc_fgmres(const orc *o, int prec, const double *b, double *x, double tol, int m, int maxit,
+               int *iters, double *relres, double *hist)
+{
+    int n = o->ndof, status = 1, it = 0;
+    if (m < 1) return -1;
+    bops B;
+    bops_init(o, prec == 1, &B);
+    double *V = malloc((size_t)(m + 1) * n * sizeof(double));
+    double *Z = malloc((size_t)m * n * sizeof(double));
+    double *w = malloc((size_t)n * sizeof(double));
+    double *H = calloc((size_t)(m + 1) * m, sizeof(double));   /* H[i*m + j] */
+    double *cs = malloc((size_t)m * sizeof(double)), *sn = malloc((size_t)m * sizeof(double));
+    double *g = malloc((size_t)(m + 1) * sizeof(double)), *y = malloc((size_t)m * sizeof(double));
+
+    spmv(&o->A, x, w);
+    for (int i = 0; i < n; i++) w[i] = b[i] - w[i];
+    double beta = sqrt(dot(n, w, w)), r0 = beta;
+    if (hist) hist[0] = beta;
+    if (beta == 0.0) { status = 0; goto done; }
+    if (isnan(beta)) { status = 3; goto done; }
+    while (it < maxit) {
+        for (int i = 0; i < n; i++) V[i] = w[i] / beta;
+        memset(g, 0, (size_t)(m + 1) * sizeof(double));
+        g[0] = beta;
+        int jend = 0, stop = 0;
+        for (int j = 0; j < m && it < maxit; j++) {
+            double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
+            if (prec == 2) memcpy(zj, vj, (size_t)n * sizeof(double));
+            else apply_B(o, &B, vj, zj);
+            spmv(&o->A, zj, w);
+            for (int i = 0; i <= j; i++) {
+                const double *vi = V + (size_t)i * n;
+                double h = dot(n, w, vi);
+                H[(size_t)i * m + j] = h;
+                for (int k = 0; k < n; k++) w[k] -= h * vi[k];
+            }
+            double hn = sqrt(dot(n, w, w));
+            H[(size_t)(j + 1) * m + j] = hn;
+            if (hn > 0.0)
+                for (int k = 0; k < n; k++) V[(size_t)(j + 1) * n + k] = w[k] / hn;
+            /* earlier rotations on the new column, then the rotation that
+               zeroes its subdiagonal entry */
+            for (int i = 0; i < j; i++) {
+                double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+            double d = sqrt(a * a + c * c);
+            cs[j] = d > 0.0 ? a / d : 1.0;
+            sn[j] = d > 0.0 ? c / d : 0.0;
+            H[(size_t)j * m + j] = d;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            it++;
+            jend = j + 1;
+            double est = fabs(g[j + 1]);
+            if (hist) hist[it] = est;
+            if (isnan(est)) { status = 3; stop = 1; break; }
+            if (est <= tol * r0) { status = 0; stop = 1; break; }
+            if (hn == 0.0) break;   /* exact solution in this space */
+        }
+        if (status == 3) break;
+        /* back substitution R y = g, then x += Z y */
+        for (int i = jend - 1; i >= 0; i--) {
+            double s = g[i];
+            for (int k = i + 1; k < jend; k++) s -= H[(size_t)i * m + k] * y[k];
+            y[i] = s / H[(size_t)i * m + i];
+        }
+        for (int j = 0; j < jend; j++)
+            for (int k = 0; k < n; k++) x[k] += y[j] * Z[(size_t)j * n + k];
+        spmv(&o->A, x, w);
+        for (int i = 0; i < n; i++) w[i] = b[i] - w[i];
+        beta = sqrt(dot(n, w, w));
+        if (stop) break;
+        if (beta == 0.0) { status = 0; break; }
+    }
+done:
+    spmv(&o->A, x, w);
+    for (int i = 0; i < n; i++) w[i] = b[i] - w[i];
+    if (iters) *iters = it;
+    if (relres) *relres = r0 > 0.0 ? sqrt(dot(n, w, w)) / r0 : 0.0;
+    free(V); free(Z); free(w); free(H); free(cs); free(sn); free(g); free(y);
+    bops_free(&B);
+    return status;
 }
