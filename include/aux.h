@@ -265,6 +265,24 @@ int pcg_solve(aux_handle *h, const double *f, double *u, double tol, int maxit, 
 int pcg_solve_batched(aux_handle *h, const double *F, double *U, int nrhs, double tol, int maxit,
                       aux_solve_info *infos);
 
+/* Flexible GMRES(restart) on A_h x = b with the same preconditioner B, the
+ * Krylov method of the paper's experiments (Sec. 6.1; Saad's flexible
+ * variant, right preconditioning, so B in FP32 is allowed to vary).  b, x:
+ * device [n_h]; x is the initial guess in and the solution out.  Stops when
+ * the rotated residual norm of the least-squares problem is
+ * <= tol ||b - A_h x_0||_2 (with a zero right-hand side and a random initial
+ * guess, the paper's protocol, this is its relative residual), or after maxit
+ * Arnoldi steps (maxit <= 0 uses the handle's option).  restart in [1, 128];
+ * the basis takes (2 restart + 1) n_h doubles of device memory, kept until
+ * the handle is destroyed.  history (host, may be NULL) receives ||r_0||
+ * and then the rotated residual norm after every step (iterations + 1
+ * values, at most maxit + 1).  info->iterations counts Arnoldi steps and
+ * info->rel_residual is the true ||b - A_h x||_2 / ||r_0||_2 at exit.
+ * Synchronises the stream once per step.  Returns AUX_OK, AUX_ENOTCONV (x is
+ * the last iterate), AUX_ENAN or AUX_EINVAL. */
+int fgmres_solve(aux_handle *h, const double *b, double *x, double tol, int restart, int maxit, double *history,
+                 aux_solve_info *info);
+
 /* y = A_h x (device x, y [n_h]), FP64. */
 int aux_matvec(aux_handle *h, const double *x, double *y);
 

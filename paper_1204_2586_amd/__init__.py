@@ -26,6 +26,8 @@ __all__ = ["Solver", "SolveInfo", "AuxSolveFn", "KappaSolve", "library_path", "l
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libauxprec.so")
 FP64, MIXED = 0, 1
+# status codes of include/aux.h
+OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ENAN, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 _OPS = {"assembled": 0, "matfree": 1}
 
 _ERRORS = {-1: "AUX_EINVAL", -2: "AUX_ENOMEM", -3: "AUX_EHIP", -4: "AUX_ENOTCONV", -5: "AUX_EBREAKDOWN",
@@ -132,6 +134,7 @@ def load_library():
         "aux_apply": (ctypes.c_int, [vp, vp, vp]),
         "pcg_solve": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, P(_SolveInfo)]),
         "pcg_solve_batched": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, dbl, ctypes.c_int, P(_SolveInfo)]),
+        "fgmres_solve": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int, vp, P(_SolveInfo)]),
         "aux_matvec": (ctypes.c_int, [vp, vp, vp]),
         "aux_kappa_grad": (ctypes.c_int, [vp, vp, vp, vp]),
         "aux_profile": (ctypes.c_int, [vp, ctypes.c_int]),
@@ -186,6 +189,7 @@ class Solver:
         lib.aux_default_options(ctypes.byref(opt))
         opt.nu, opt.theta, opt.coarse_max, opt.max_levels = nu, theta, coarse_max, max_levels
         opt.pmis_seed, opt.maxit, opt.host_only = seed, maxit, int(host_only)
+        self._maxit = int(maxit)
         opt.precision = {"fp64": FP64, "mixed": MIXED}[precision]
         opt.op = _OPS[operator]
         opt.sell_window = sell_window
@@ -393,6 +397,30 @@ class Solver:
         elif rc not in (0, -4, -5, -6):
             _check(rc)
         return u, SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds)
+
+    def fgmres(self, b, tol: float = 1e-6, x0=None, restart: int = 30, maxit: int = 0, check: bool = True):
+        """Flexible GMRES(restart) on A_h x = b with the same preconditioner,
+        stopping at ||r|| <= tol ||r_0||.  Returns (x, SolveInfo, history),
+        history a numpy array of ||r_0|| and the residual norm after each
+        Arnoldi step."""
+        import numpy as np
+        b = self._vec(b, "b")
+        x = self._torch.zeros_like(b)
+        if x0 is not None:
+            x.copy_(self._vec(x0, "x0"))
+        cap = (int(maxit) if maxit > 0 else self._maxit) + 1
+        hist = np.zeros(cap)
+        info = _SolveInfo()
+        self._sync_stream()
+        rc = load_library().fgmres_solve(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), tol,
+                                         int(restart), int(maxit), hist.ctypes.data_as(ctypes.c_void_p),
+                                         ctypes.byref(info))
+        if check:
+            _check(rc)
+        elif rc not in (0, -4, -6):
+            _check(rc)
+        return x, SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds), \
+            hist[: info.iterations + 1]
 
     def solve_batched(self, F, tol: float = 1e-8, U0=None, maxit: int = 0, check: bool = True):
         """nrhs lock-step CG solves; F is a [n_h, nrhs] float64 device tensor."""

@@ -21,6 +21,7 @@
 #include "aux.h"
 #include "batched.hpp"
 #include "kernels.hpp"
+#include "krylov.hpp"
 #include "mfree.hpp"
 
 using namespace auxp;
@@ -1030,6 +1031,157 @@ struct aux_handle {
         return status;
     }
 
+    // ------------------------------------------------------------ FGMRES
+    // Flexible GMRES(m) (the Krylov method of the paper's Sec. 6.1; Saad's
+    // flexible variant): basis V (m+1 vectors) and preconditioned vectors Z
+    // (m) in HBM, the Hessenberg matrix and its Givens rotations on the host.
+    static constexpr int kHs = kMaxRestart + 1;   // stride of the coefficient slots
+    struct Fgm {
+        int m = 0;
+        double *V = nullptr, *Z = nullptr, *part = nullptr;
+        double *dh = nullptr;     // [0, kHs) first pass, [kHs, 2 kHs) second pass, [2 kHs] w.w, then y
+    } fg;
+    double *fg_host = nullptr;    // pinned mirror of fg.dh
+
+    void ensure_fgmres(int m)
+    {
+        const size_t n = disc.ndof;
+        if (fg.m < m) {
+            dfree(fg.V);
+            dfree(fg.Z);
+            fg.V = dnew<double>((size_t)(m + 1) * n);
+            fg.Z = dnew<double>((size_t)m * n);
+            fg.m = m;
+        }
+        if (!fg.part) {
+            fg.part = dnew<double>((size_t)kKrylovBlocks * kHs);
+            fg.dh = dnew<double>(4 * (size_t)kHs);
+            HIPCHECK(hipHostMalloc((void **)&fg_host, 4 * kHs * sizeof(double), hipHostMallocDefault));
+        }
+    }
+
+    // y = A_h x in FP64 by the operator of the solve
+    void op_product(const double *x, double *y)
+    {
+        if (use_mf()) {
+            ensure_mf();
+            MfView<double> v = mf_view<double>();
+            mf_apply<double>(stream, v, x, mf_Y64, nullptr);
+            mf_product<double>(stream, v, mf_Y64, y, nullptr, nullptr, nullptr);
+        } else {
+            sell_spmv64(stream, A.view<double>(), x, y, nullptr, nullptr);
+        }
+    }
+
+    int fgmres(const double *b, double *x, double tol, int m, int maxit, double *history, aux_solve_info *info)
+    {
+        auto t0 = std::chrono::steady_clock::now();
+        if (maxit <= 0) maxit = opt.maxit;
+        hipStream_t s = stream;
+        const int n = disc.ndof;
+        const long long ld = n;
+        ensure_fgmres(m);
+        if (use_mf()) ensure_mf();
+        double *V = fg.V, *Z = fg.Z, *hh = fg_host;
+        double *h1 = fg.dh, *h2 = fg.dh + kHs, *nrm = fg.dh + 2 * kHs, *yd = fg.dh + 2 * kHs + 1;
+        vec_gather(s, n, perm, b, fi);
+        vec_gather(s, n, perm, x, xi);
+        // v_0 <- r = b - A x (unnormalised) and ||r||, also the device copy of r.r
+        auto residual_norm = [&]() {
+            sell_residual64(s, A.view<double>(), fi, xi, V);
+            multi_dot(s, n, 1, V, ld, V, fg.part, nrm);
+            HIPCHECK(hipMemcpyAsync(hh + 2 * kHs, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipStreamSynchronize(s));
+            return std::sqrt(hh[2 * kHs]);
+        };
+        double beta = residual_norm();
+        const double r0 = beta;
+        if (history) history[0] = r0;
+        int it = 0, status = AUX_ENOTCONV;
+        std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+        auto Hc = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+        if (!std::isfinite(beta)) status = AUX_ENAN;
+        else if (beta == 0.0) status = AUX_OK;
+        while (status == AUX_ENOTCONV && it < maxit) {
+            scale_unit(s, n, V, nrm, V);
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            int jend = 0;
+            bool stop = false;
+            for (int j = 0; j < m && it < maxit; j++) {
+                double *vj = V + j * ld, *zj = Z + j * ld, *w = V + (j + 1) * ld;
+                apply(vj, zj, nullptr, nullptr);
+                op_product(zj, w);
+                // classical Gram-Schmidt, twice
+                multi_dot(s, n, j + 1, V, ld, w, fg.part, h1);
+                multi_axpy(s, n, j + 1, V, ld, h1, -1.0, w, nullptr, nullptr);
+                multi_dot(s, n, j + 1, V, ld, w, fg.part, h2);
+                multi_axpy(s, n, j + 1, V, ld, h2, -1.0, w, fg.part, nrm);
+                scale_unit(s, n, w, nrm, w);
+                HIPCHECK(hipMemcpyAsync(hh, h1, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHECK(hipMemcpyAsync(hh + kHs, h2, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHECK(hipMemcpyAsync(hh + 2 * kHs, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHECK(hipStreamSynchronize(s));
+                for (int i = 0; i <= j; i++) Hc(i, j) = hh[i] + hh[kHs + i];
+                const double hn = std::sqrt(hh[2 * kHs]);
+                Hc(j + 1, j) = hn;
+                // the rotations so far on the new column, then a new one that
+                // zeroes its subdiagonal entry; g stays Q^T beta e_1
+                for (int i = 0; i < j; i++) {
+                    const double u0 = Hc(i, j), u1 = Hc(i + 1, j);
+                    Hc(i, j) = cs[i] * u0 + sn[i] * u1;
+                    Hc(i + 1, j) = cs[i] * u1 - sn[i] * u0;
+                }
+                const double dj = Hc(j, j), ej = Hc(j + 1, j), rad = std::sqrt(dj * dj + ej * ej);
+                cs[j] = rad > 0.0 ? dj / rad : 1.0;
+                sn[j] = rad > 0.0 ? ej / rad : 0.0;
+                Hc(j, j) = rad;
+                Hc(j + 1, j) = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] *= cs[j];
+                it++;
+                jend = j + 1;
+                const double est = std::fabs(g[j + 1]);
+                if (history) history[it] = est;
+                if (!std::isfinite(est)) {
+                    status = AUX_ENAN;
+                    stop = true;
+                    break;
+                }
+                if (est <= tol * r0) {
+                    status = AUX_OK;
+                    stop = true;
+                    break;
+                }
+                if (hn == 0.0) break;   // the space holds the solution
+            }
+            if (status == AUX_ENAN) break;
+            // y = R^-1 g (upper triangular), x += Z y
+            for (int i = jend - 1; i >= 0; i--) {
+                double t = g[i];
+                for (int k = i + 1; k < jend; k++) t -= Hc(i, k) * y[k];
+                y[i] = t / Hc(i, i);
+            }
+            std::copy(y.begin(), y.begin() + jend, hh + 2 * kHs + 1);
+            HIPCHECK(hipMemcpyAsync(yd, hh + 2 * kHs + 1, (size_t)jend * sizeof(double), hipMemcpyHostToDevice, s));
+            multi_axpy(s, n, jend, Z, ld, yd, 1.0, xi, nullptr, nullptr);
+            beta = residual_norm();   // the true residual; also v_0 of the next cycle
+            if (stop) break;
+            if (!std::isfinite(beta)) status = AUX_ENAN;
+            else if (beta == 0.0) status = AUX_OK;
+        }
+        vec_scatter(s, n, perm, xi, x);
+        HIPCHECK(hipStreamSynchronize(s));
+        prof_collect(0);
+        if (info) {
+            info->iterations = it;
+            info->status = status;
+            info->rel_residual = r0 > 0.0 ? beta / r0 : 0.0;
+            info->seconds = seconds_since(t0);
+        }
+        return status;
+    }
+
     // ------------------------------------------------------------ batched CG
     struct Batch {
         int nr = 0, hist_cap = 0;
@@ -1576,6 +1728,8 @@ struct aux_handle {
         host_state = nullptr;
         if (host_scal) hipHostFree(host_scal);
         host_scal = nullptr;
+        if (fg_host) hipHostFree(fg_host);
+        fg_host = nullptr;
         for (void *ptr : host_bufs) hipHostFree(ptr);
         host_bufs.clear();
     }
@@ -1914,6 +2068,21 @@ int pcg_solve_batched(aux_handle *h, const double *F, double *U, int nrhs, doubl
         if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
         set_dev(h);
         int st = h->pcg_batched(F, U, nrhs, tol, maxit, infos);
+        HIPCHECK(hipGetLastError());
+        return st;
+    });
+}
+
+int fgmres_solve(aux_handle *h, const double *b, double *x, double tol, int restart, int maxit, double *history,
+                 aux_solve_info *info)
+{
+    return guarded([&]() {
+        need_device(h);
+        if (!b || !x) throw AuxError(AUX_EINVAL, "null vector");
+        if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
+        if (restart < 1 || restart > auxp::kMaxRestart) throw AuxError(AUX_EINVAL, "restart must be in [1, 128]");
+        set_dev(h);
+        int st = h->fgmres(b, x, tol, restart, maxit, history, info);
         HIPCHECK(hipGetLastError());
         return st;
     });

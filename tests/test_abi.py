@@ -96,3 +96,11 @@ def test_host_only_handle_refuses_device_calls():
     lib = aux.load_library()
     rc = lib.aux_apply(s._h, None, None)
     assert rc == -7 and b"host-only" in lib.aux_last_error()
+
+
+def test_fgmres_entry_checks_handle():
+    lib = aux.load_library()
+    assert lib.fgmres_solve(None, None, None, 1e-6, 30, 0, None, None) == -1
+    xyz, tets = _mesh()
+    s = aux.Solver(xyz, tets, 2, host_only=True)
+    assert lib.fgmres_solve(s._h, None, None, 1e-6, 30, 0, None, None) == -7
