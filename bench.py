@@ -158,6 +158,26 @@ def apply_bytes(info, s, nu, first=True):
     return total
 
 
+def kernel_table(prof, args, s, wl, nt):
+    """Per-category launches, average duration and algorithmic GB/s of a
+    profiled mixed-precision solve."""
+    n, nnz = s.n, int(s.info.nnz_A)
+    kernels = {}
+    nloc = (wl["k"] + 1) * (wl["k"] + 2) * (wl["k"] + 3) // 6
+    for cat, (cnt, tot) in prof.items():
+        if args.operator == "matfree" and cat in ("pk_sweep", "pk_last", "cg_spmv"):
+            ab = matfree_bytes(cat, n, nt, nloc, 8 if cat == "cg_spmv" else 4)
+        else:
+            ab = algorithmic_bytes(cat, n, nnz, 4, index_bytes_per_entry(s.info))
+        if cat == "pk_resid" and s.info.nnz_restrict > 0:
+            ab = restrict_bytes(s.info, 4)
+        if cnt and ab:
+            avg_ms = tot / cnt
+            kernels[cat] = dict(launches=cnt, total_ms=tot, avg_us=avg_ms * 1e3, bytes=ab,
+                                gbs=ab / (avg_ms * 1e-3) / 1e9)
+    return kernels
+
+
 def run(args):
     import numpy as np
     import torch
@@ -214,19 +234,7 @@ def run(args):
     diff = float(torch.linalg.norm(mixed["u"] - fp64["u"]) / torch.linalg.norm(fp64["u"]))
 
     # roofline of the dominant kernel of the timed (mixed) solve
-    kernels = {}
-    nloc = (wl["k"] + 1) * (wl["k"] + 2) * (wl["k"] + 3) // 6
-    for cat, (cnt, tot) in mixed["prof"].items():
-        if args.operator == "matfree" and cat in ("pk_sweep", "pk_last", "cg_spmv"):
-            ab = matfree_bytes(cat, n, len(tets), nloc, 8 if cat == "cg_spmv" else 4)
-        else:
-            ab = algorithmic_bytes(cat, n, nnz, 4, index_bytes_per_entry(s.info))
-        if cat == "pk_resid" and s.info.nnz_restrict > 0:
-            ab = restrict_bytes(s.info, 4)
-        if cnt and ab:
-            avg_ms = tot / cnt
-            kernels[cat] = dict(launches=cnt, total_ms=tot, avg_us=avg_ms * 1e3, bytes=ab,
-                                gbs=ab / (avg_ms * 1e-3) / 1e9)
+    kernels = kernel_table(mixed["prof"], args, s, wl, len(tets))
     dom = max(kernels, key=lambda c: kernels[c]["total_ms"])
     kd = kernels[dom]
     # whole preconditioner application: algorithmic bytes over its measured time
@@ -448,6 +456,96 @@ def cpu_baseline_single(xyz, tets, wl, args):
                       f"{it} iterations, {dt:.1f} s; the 32-source batch would take {32 * dt:.0f} s"}
 
 
+def run_fgmres(args):
+    """The paper's protocol (Sec. 6.1): flexible GMRES(restart) from a random
+    initial guess on a zero right-hand side, stopped at a 1e-6 relative
+    residual; one step is one solve."""
+    import numpy as np
+    import torch
+
+    import paper_1204_2586_amd as aux
+    import workloads as W
+
+    wl = WORKLOADS[args.workload]
+    xyz, tets = W.kuhn_mesh(wl["n"], jitter=wl["jitter"], seed=wl["seed"])
+    kappa = None
+    if wl["kappa"] is not None:
+        kappa = np.exp(W.grf_log_kappa(xyz, tets, seed=wl["kappa"]))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    s = aux.Solver(xyz, tets, wl["k"], kappa, precision="mixed", device=dev, operator=args.operator)
+    setup_s = time.time() - t0
+    n = s.n
+    x0 = torch.tensor(np.random.default_rng(7).uniform(-1.0, 1.0, n), dtype=torch.float64, device=dev)
+    zero = torch.zeros_like(x0)
+    r0 = float(torch.linalg.norm(s.matvec(x0)))
+
+    def timed(mode):
+        s.set_precision(mode)
+        for _ in range(args.warmup):
+            s.fgmres(zero, tol=args.tol, x0=x0, restart=args.restart)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            x, info, hist = s.fgmres(zero, tol=args.tol, x0=x0, restart=args.restart)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / args.steps
+        true_res = float(torch.linalg.norm(s.matvec(x))) / r0
+        s.profile(True)
+        for _ in range(args.steps):
+            s.fgmres(zero, tol=args.tol, x0=x0, restart=args.restart)
+        torch.cuda.synchronize()
+        prof = s.profile_read()
+        s.profile(False)
+        return dict(ms=ms, iterations=info.iterations, true_rel_residual=true_res, prof=prof)
+
+    mixed = timed("mixed")
+    fp64 = timed("fp64")
+    kernels = kernel_table(mixed["prof"], args, s, wl, len(tets))
+    dom = max(kernels, key=lambda c: kernels[c]["total_ms"])
+    kd = kernels[dom]
+    apply_us = mixed["prof"]["apply"][1] / max(mixed["prof"]["apply"][0], 1) * 1e3
+    out = {
+        "metric": "FGMRES solve throughput, paper protocol (zero right-hand side, random initial guess)",
+        "value": n / (mixed["ms"] * 1e-3),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 FGMRES / f32 preconditioner",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "krylov": f"fgmres({args.restart})", "operator": args.operator,
+                   "order": wl["k"], "cubes_per_side": wl["n"], "jitter": wl["jitter"], "n_h": n,
+                   "tol": args.tol, "iterations": mixed["iterations"],
+                   "true_rel_residual": mixed["true_rel_residual"], "setup_s": round(setup_s, 2),
+                   "apply_us_per_step": round(apply_us, 1),
+                   "us_per_arnoldi_step": round(mixed["ms"] * 1e3 / max(mixed["iterations"], 1), 1)},
+        "fp64": {"value": n / (fp64["ms"] * 1e-3), "ms_per_step": fp64["ms"], "iterations": fp64["iterations"],
+                 "true_rel_residual": fp64["true_rel_residual"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": kd["gbs"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, args.operator, dom, "mixed"),
+                     "bytes_per_launch": kd["bytes"], "avg_us": kd["avg_us"]},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        P = oracle.Problem(xyz, tets, wl["k"], kappa).setup_amg()
+        x0h = x0.cpu().numpy()
+        t0 = time.perf_counter()
+        _, it, rr, st, _ = P.fgmres(np.zeros(P.n), tol=args.tol, restart=args.restart, x0=x0h)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": P.n / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one FP64 FGMRES({args.restart}) solve of the full {args.workload} "
+                                         f"system (n_h={P.n}) by the paper's protocol to {args.tol:g}, {it} "
+                                         f"steps, {dt:.1f} s"}
+    return out
+
+
 def cpu_baseline(xyz, tets, wl, kappa, args):
     """The CPU oracle (single-threaded FP64 C) on the same system: one CG solve
     to the same tolerance from u = 0; its setup and its own load vector are
@@ -472,7 +570,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="p2_n48_jitter", choices=sorted(WORKLOADS))
-    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--tol", type=float, default=None,
+                    help="relative residual (default 1e-8 for CG, 1e-6 for FGMRES, the paper's)")
+    ap.add_argument("--krylov", default="cg", choices=["cg", "fgmres"],
+                    help="cg: time to 1e-8 from zero; fgmres: the paper's protocol (zero right-hand side, "
+                         "random initial guess)")
+    ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length")
     ap.add_argument("--operator", default="assembled", choices=["assembled", "matfree"],
                     help="P^k products inside the preconditioner: sliced-ELL A_h or the MFMA element operator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -487,7 +590,12 @@ def main():
     if args.calibrate_copy:
         print(json.dumps(calibrate_copy()), flush=True)
         return
-    fn = run_batched if "nrhs" in WORKLOADS[args.workload] else run
+    if args.tol is None:
+        args.tol = 1e-6 if args.krylov == "fgmres" else 1e-8
+    if args.krylov == "fgmres" and "nrhs" in WORKLOADS[args.workload]:
+        print(json.dumps({"error": "FGMRES is single right-hand side; pick a single-vector workload"}))
+        sys.exit(2)
+    fn = run_batched if "nrhs" in WORKLOADS[args.workload] else (run_fgmres if args.krylov == "fgmres" else run)
     print(json.dumps(fn(args)), flush=True)
 
 

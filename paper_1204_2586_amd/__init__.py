@@ -405,8 +405,10 @@ class Solver:
         Arnoldi step."""
         import numpy as np
         b = self._vec(b, "b")
-        x = self._torch.zeros_like(b)
-        if x0 is not None:
+        if x0 is None:
+            x = self._torch.zeros_like(b)
+        else:
+            x = self._torch.empty_like(b)
             x.copy_(self._vec(x0, "x0"))
         cap = (int(maxit) if maxit > 0 else self._maxit) + 1
         hist = np.zeros(cap)
