@@ -165,3 +165,21 @@ def test_full_size_paper_protocol():
     r0 = -lib.matvec(_t(x0))
     assert abs((torch.linalg.norm(r) / torch.linalg.norm(r0)).item() - info.rel_residual) <= 1e-9
     assert info.rel_residual <= 1.01e-6
+
+
+@pytest.mark.parametrize("theta", [0.2, 0.5, 0.8])
+@pytest.mark.parametrize("k,n", [(2, 10), (3, 6)])
+def test_paper_protocol_over_theta(k, n, theta):
+    """Sec. 6.2's strength-threshold sweep: the GPU's hierarchy for each theta
+    reproduces the oracle's steps and residual history."""
+    xyz, tets = W.kuhn_mesh(n, jitter=0.2, seed=0)
+    print(f"[fgmres theta={theta} k={k} n={n}]", flush=True)
+    lib = aux.Solver(xyz, tets, k, theta=theta, device=DEV)
+    orc = oracle.Problem(xyz, tets, k).setup_amg(theta=theta)
+    x0 = np.random.default_rng(7).uniform(-1.0, 1.0, lib.n)
+    zero = np.zeros(lib.n)
+    _, ito, _, sto, ho = orc.fgmres(zero, tol=1e-6, restart=30, maxit=200, x0=x0)
+    x, info, h = lib.fgmres(_t(zero), tol=1e-6, x0=_t(x0), restart=30, maxit=200)
+    assert sto == 0 and info.status == aux.OK and abs(info.iterations - ito) <= 1
+    m = min(len(h), len(ho))
+    np.testing.assert_allclose(h[:m], ho[:m], rtol=0, atol=1e-9 * ho[0])
