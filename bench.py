@@ -193,7 +193,7 @@ def run(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
-    s = aux.Solver(xyz, tets, wl["k"], kappa, precision="mixed", device=dev, operator=args.operator)
+    s = aux.Solver(xyz, tets, wl["k"], kappa, nu=args.nu, precision="mixed", device=dev, operator=args.operator)
     setup_s = time.time() - t0
     b = s.load(W.manufactured_f)
     f = torch.tensor(b, dtype=torch.float64, device=dev)
@@ -244,7 +244,7 @@ def run(args):
         us = tot / max(cnt, 1) * 1e3
         entry = {"us": us}
         if args.operator == "assembled":
-            ab = apply_bytes(s.info, sz, 2, first=res["prof"].get("pk_first", (0, 0))[0] > 0)
+            ab = apply_bytes(s.info, sz, args.nu, first=res["prof"].get("pk_first", (0, 0))[0] > 0)
             entry.update(bytes=ab, gbs=ab / (us * 1e-6) / 1e9, frac=ab / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
         precond[name] = entry
 
@@ -261,7 +261,8 @@ def run(args):
         "vs_baseline": None,
         "dtype": "f64 CG / f32 preconditioner",
         "data": "synthetic",
-        "config": {"workload": args.workload, "operator": args.operator, "order": wl["k"], "cubes_per_side": wl["n"],
+        "config": {"workload": args.workload, "operator": args.operator, "nu": args.nu, "order": wl["k"],
+                   "cubes_per_side": wl["n"],
                    "jitter": wl["jitter"], "n_h": n, "nnz_A": nnz, "tol": args.tol,
                    "iterations": mixed["iterations"][-1], "true_rel_residual": mixed["true_rel_residual"],
                    "amg_levels": int(s.info.levels), "op_complexity": round(float(s.info.op_complexity), 4),
@@ -320,7 +321,7 @@ def run_batched(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
-    s = aux.Solver(xyz, tets, wl["k"], None, precision="mixed", device=dev)
+    s = aux.Solver(xyz, tets, wl["k"], None, nu=args.nu, precision="mixed", device=dev)
     setup_s = time.time() - t0
     t0 = time.time()
     B = s.load_many(W.fourier_fields(range(nrhs)), nrhs, threads=args.threads)
@@ -438,7 +439,7 @@ def cpu_baseline_single(xyz, tets, wl, args):
 
     import oracle
     import workloads as W
-    P = oracle.Problem(xyz, tets, wl["k"], None).setup_amg()
+    P = oracle.Problem(xyz, tets, wl["k"], None).setup_amg(nu=args.nu)
     src = W.fourier_fields([0])
 
     def f(p):                                # evaluated in slices to bound memory
@@ -474,7 +475,7 @@ def run_fgmres(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
-    s = aux.Solver(xyz, tets, wl["k"], kappa, precision="mixed", device=dev, operator=args.operator)
+    s = aux.Solver(xyz, tets, wl["k"], kappa, nu=args.nu, precision="mixed", device=dev, operator=args.operator)
     setup_s = time.time() - t0
     n = s.n
     x0 = torch.tensor(np.random.default_rng(7).uniform(-1.0, 1.0, n), dtype=torch.float64, device=dev)
@@ -520,6 +521,7 @@ def run_fgmres(args):
         "dtype": "f64 FGMRES / f32 preconditioner",
         "data": "synthetic",
         "config": {"workload": args.workload, "krylov": f"fgmres({args.restart})", "operator": args.operator,
+                   "nu": args.nu,
                    "order": wl["k"], "cubes_per_side": wl["n"], "jitter": wl["jitter"], "n_h": n,
                    "tol": args.tol, "iterations": mixed["iterations"],
                    "true_rel_residual": mixed["true_rel_residual"], "setup_s": round(setup_s, 2),
@@ -534,7 +536,7 @@ def run_fgmres(args):
     }
     if not args.no_cpu_baseline:
         import oracle
-        P = oracle.Problem(xyz, tets, wl["k"], kappa).setup_amg()
+        P = oracle.Problem(xyz, tets, wl["k"], kappa).setup_amg(nu=args.nu)
         x0h = x0.cpu().numpy()
         t0 = time.perf_counter()
         _, it, rr, st, _ = P.fgmres(np.zeros(P.n), tol=args.tol, restart=args.restart, x0=x0h)
@@ -553,7 +555,7 @@ def cpu_baseline(xyz, tets, wl, kappa, args):
     import oracle
     import workloads as W
     t0 = time.time()
-    P = oracle.Problem(xyz, tets, wl["k"], kappa).setup_amg()
+    P = oracle.Problem(xyz, tets, wl["k"], kappa).setup_amg(nu=args.nu)
     setup = time.time() - t0
     b = P.load(W.manufactured_f)
     t0 = time.perf_counter()
@@ -576,6 +578,8 @@ def main():
                     help="cg: time to 1e-8 from zero; fgmres: the paper's protocol (zero right-hand side, "
                          "random initial guess)")
     ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length")
+    ap.add_argument("--nu", type=int, default=2,
+                    help="l1-Jacobi sweeps before and after the coarse correction (the workloads are defined with 2)")
     ap.add_argument("--operator", default="assembled", choices=["assembled", "matfree"],
                     help="P^k products inside the preconditioner: sliced-ELL A_h or the MFMA element operator")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -458,3 +458,31 @@ def test_degenerate_meshes(k, n):
     U, infos = lib.solve_batched(_t(np.stack([b, 2 * b, r], axis=1)), tol=1e-8)
     assert all(i.converged for i in infos)
     assert _rel(U[:, 1].cpu().numpy(), 2 * x) <= 1e-7
+
+
+@pytest.mark.parametrize("nu", [1, 3])
+@pytest.mark.parametrize("k,n", [(2, 8), (3, 5)])
+def test_smoothing_sweeps(k, n, nu):
+    """nu l1-Jacobi sweeps before and after the coarse correction (the paper
+    ran one of each, Remark 6.1) against the oracle with the same nu: the
+    application in FP64 and FP32, CG at the oracle's iteration count, and the
+    batched form."""
+    print(f"[smoothing sweeps nu={nu} k={k} n={n}]", flush=True)
+    xyz, tets, kappa = _case(k, n, jitter=0.2, kappa="rand")
+    orc = oracle.Problem(xyz, tets, k, kappa).setup_amg(nu=nu)
+    b = orc.load(W.manufactured_f)
+    lib = aux.Solver(xyz, tets, k, kappa, nu=nu, device=DEV)
+    r = W.random_vector(lib.n, 9)
+    assert _rel(lib.apply(_t(r)).cpu().numpy(), orc.apply(r)) <= 1e-12
+    x, it, rr, st = orc.pcg(b, tol=1e-8)
+    u, info = lib.solve(_t(b), tol=0.0, maxit=it, check=False)
+    assert st == 0 and info.iterations == it
+    assert _rel(u.cpu().numpy(), x) <= 1e-10
+    lib.set_precision("mixed")
+    assert _rel(lib.apply(_t(r)).cpu().numpy(), orc.apply(r, fp32=True)) <= 2e-6
+    F = np.stack([orc.load(W.fourier_f(c)) for c in range(6)], axis=1)
+    U, infos = lib.solve_batched(_t(F), tol=1e-8)
+    for j in range(6):
+        xj, itj, _, _ = orc.pcg(F[:, j], tol=1e-8, fp32=True)
+        assert infos[j].converged and abs(infos[j].iterations - itj) <= 1
+        assert _rel(U[:, j].cpu().numpy(), xj) <= 1e-7
