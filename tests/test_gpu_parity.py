@@ -486,3 +486,29 @@ def test_smoothing_sweeps(k, n, nu):
         xj, itj, _, _ = orc.pcg(F[:, j], tol=1e-8, fp32=True)
         assert infos[j].converged and abs(infos[j].iterations - itj) <= 1
         assert _rel(U[:, j].cpu().numpy(), xj) <= 1e-7
+
+
+@pytest.mark.parametrize("opts", [dict(theta=0.25), dict(coarse_max=500), dict(max_levels=2, theta=0.5),
+                                  dict(seed=7), dict(use_torch_allocator=False)],
+                         ids=["theta0.25", "coarse500", "levels2", "pmis_seed7", "hipmalloc"])
+def test_hierarchy_and_allocation_options(opts):
+    """Non-default AMG options (a coarsest level of a few hundred rows solved
+    densely, a level cap, another PMIS seed) against the oracle built with
+    the same options; device buffers from hipMalloc instead of the torch
+    allocator give the same bits."""
+    print(f"[options {opts}]", flush=True)
+    xyz, tets, kappa = _case(2, 10, jitter=0.2, kappa="rand")
+    amg = {k: v for k, v in opts.items() if k != "use_torch_allocator"}
+    orc = oracle.Problem(xyz, tets, 2, kappa).setup_amg(**amg)
+    lib = aux.Solver(xyz, tets, 2, kappa, device=DEV, **opts)
+    assert lib.info.levels == orc.nlev
+    b = orc.load(W.manufactured_f)
+    r = W.random_vector(lib.n, 10)
+    assert _rel(lib.apply(_t(r)).cpu().numpy(), orc.apply(r)) <= 1e-12
+    x, it, rr, st = orc.pcg(b, tol=1e-8)
+    u, info = lib.solve(_t(b), tol=0.0, maxit=it, check=False)
+    assert st == 0 and info.iterations == it and _rel(u.cpu().numpy(), x) <= 1e-10
+    if opts.get("use_torch_allocator") is False:
+        ref = aux.Solver(xyz, tets, 2, kappa, device=DEV)
+        u2, _ = ref.solve(_t(b), tol=0.0, maxit=it, check=False)
+        assert torch.equal(u, u2)

@@ -93,3 +93,21 @@ def test_operator_complexity_reported(pair):
     tot = sum(orc.csr("Alev", l).nnz for l in range(orc.nlev))
     assert abs(lib.info.amg_complexity - tot / orc.nnz_AH) < 1e-12
     assert abs(lib.info.op_complexity - (orc.nnz_A + tot) / orc.nnz_A) < 1e-12
+
+
+@pytest.mark.parametrize("theta,coarse_max,max_levels,seed", [(0.25, 100, 25, 0), (0.8, 20, 25, 7),
+                                                              (0.5, 100, 2, 0), (0.8, 500, 25, 123)])
+def test_hierarchy_options_identical(theta, coarse_max, max_levels, seed):
+    """The strength threshold, the coarsest size, the level cap and the PMIS
+    seed give the oracle's hierarchy level by level."""
+    xyz, tets = W.kuhn_mesh(10, jitter=0.2, seed=0)
+    lib = aux.Solver(xyz, tets, 2, host_only=True, theta=theta, coarse_max=coarse_max, max_levels=max_levels,
+                     seed=seed)
+    orc = oracle.Problem(xyz, tets, 2).setup_amg(theta=theta, coarse_max=coarse_max, max_levels=max_levels,
+                                                 seed=seed)
+    assert lib.info.levels == orc.nlev and lib.info.ncoarse == orc.ncoarse
+    assert orc.nlev <= max_levels and (orc.ncoarse <= coarse_max or orc.nlev == max_levels)
+    for l in range(orc.nlev - 1):
+        assert np.array_equal(lib.export_cf(l), orc.level_cf(l)), l
+        assert _rel(lib.export_csr("P", l), orc.csr("P", l)) < 1e-12
+        assert _rel(lib.export_csr("Alev", l + 1), orc.csr("Alev", l + 1)) < 1e-12
