@@ -490,27 +490,33 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int n, const int *__restrict
 
 // ------------------------------------------------------------- adjoint
 
-constexpr int kMaxNloc = 35;   // P4
-
-__global__ __launch_bounds__(kBlock) void k_kappa_grad(int nt, int nloc, const int *__restrict__ tet_dof,
+// One thread per tet; NLOC is a template argument so the element vectors
+// stay in registers (the node loops unroll) and the reference tables, read at
+// indices uniform over the wavefront, come through scalar loads.
+template <int NLOC>
+__global__ __launch_bounds__(kBlock) void k_kappa_grad(int nt, const int *__restrict__ tet_dof,
                                                        const double *__restrict__ G, const double *__restrict__ kappa,
                                                        const double *__restrict__ M, const double *__restrict__ u,
                                                        const double *__restrict__ lam, double *__restrict__ g)
 {
     for (int t = blockIdx.x * kBlock + threadIdx.x; t < nt; t += gridDim.x * kBlock) {
-        double ue[kMaxNloc], le[kMaxNloc];
-        for (int a = 0; a < nloc; a++) {
-            int i = tet_dof[(size_t)t * nloc + a];
+        double ue[NLOC], le[NLOC];
+#pragma unroll
+        for (int a = 0; a < NLOC; a++) {
+            const int i = tet_dof[(size_t)t * NLOC + a];
             ue[a] = i >= 0 ? u[i] : 0.0;
             le[a] = i >= 0 ? lam[i] : 0.0;
         }
         double s = 0.0;
+#pragma unroll 1
         for (int pq = 0; pq < 16; pq++) {
-            const double *Mpq = M + (size_t)pq * nloc * nloc;
+            const double *Mpq = M + (size_t)pq * NLOC * NLOC;
             double w = 0.0;
-            for (int a = 0; a < nloc; a++) {
+#pragma unroll
+            for (int a = 0; a < NLOC; a++) {
                 double ra = 0.0;
-                for (int b = 0; b < nloc; b++) ra += Mpq[a * nloc + b] * ue[b];
+#pragma unroll
+                for (int b = 0; b < NLOC; b++) ra += Mpq[a * NLOC + b] * ue[b];
                 w += le[a] * ra;
             }
             s += G[(size_t)t * 16 + pq] * w;
@@ -707,8 +713,19 @@ void vec_scatter(hipStream_t s, int n, const int *idx, const double *x, double *
 void kappa_grad(hipStream_t s, int nt, int nloc, const int *tet_dof, const double *G, const double *kappa,
                 const double *M, const double *u, const double *lam, double *g)
 {
-    hipLaunchKernelGGL(k_kappa_grad, dim3(vec_grid(nt)), dim3(kBlock), 0, s, nt, nloc, tet_dof, G, kappa, M, u, lam,
-                       g);
+    switch (nloc) {
+    case 10:
+        hipLaunchKernelGGL(k_kappa_grad<10>, dim3(vec_grid(nt)), dim3(kBlock), 0, s, nt, tet_dof, G, kappa, M, u, lam, g);
+        break;
+    case 20:
+        hipLaunchKernelGGL(k_kappa_grad<20>, dim3(vec_grid(nt)), dim3(kBlock), 0, s, nt, tet_dof, G, kappa, M, u, lam, g);
+        break;
+    case 35:
+        hipLaunchKernelGGL(k_kappa_grad<35>, dim3(vec_grid(nt)), dim3(kBlock), 0, s, nt, tet_dof, G, kappa, M, u, lam, g);
+        break;
+    default:
+        throw std::invalid_argument("kappa gradient: nodes per tet must be 10, 20 or 35");
+    }
 }
 
 #define INST(T)                                                                                              \
