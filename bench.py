@@ -9,6 +9,12 @@ on the unit cube cut into 48^3 cubes x 6 tets, interior vertices jittered by
 (857,375 unknowns).  The headline value is the FP32-preconditioner form
 (FP64 CG); the all-FP64 form is measured beside it at the same tolerance.
 
+Other modes: `--krylov fgmres` times the paper's own protocol (flexible
+GMRES(30) from a random initial guess on a zero right-hand side, to 1e-6);
+`--workload p2_n64_32rhs` the 32-source lock-step solve; `--workload
+p2_n40_adjoint` one forward and backward pass of a least-squares loss through
+the adjoint solve.
+
 Prints one JSON line.  Inputs are resident in HBM before the timed region.
 """
 import argparse
@@ -31,6 +37,10 @@ WORKLOADS = {
     "p4_n24": dict(k=4, n=24, jitter=0.0, seed=0, kappa=None),
     # 32 right-hand sides solved in lock-step (sources fourier_f(0..31))
     "p2_n64_32rhs": dict(k=2, n=64, jitter=0.0, seed=0, kappa=None, nrhs=32),
+    # gradient of L = |u - u_t|^2 / 2 with respect to f and log kappa: forward
+    # solve, adjoint solve and the per-tet gradient (kappa and the target
+    # coefficient from GRF seeds 1 and 2)
+    "p2_n40_adjoint": dict(k=2, n=40, jitter=0.0, seed=0, kappa=1, kappa_target=2, adjoint=True),
 }
 
 
@@ -548,6 +558,125 @@ def run_fgmres(args):
     return out
 
 
+def run_adjoint(args):
+    """One step = one forward and one backward pass of L = |u - u_t|^2 / 2
+    through the autograd function: the forward CG solve u = A(kappa)^-1 f,
+    the adjoint CG solve lam = A^-1 (u - u_t) and the per-tet gradient
+    dL/dlog kappa_t = -lam_t^T K_t u_t (dL/df = lam).  The coefficient does
+    not change between steps, so the host setup runs once, before timing."""
+    import numpy as np
+    import torch
+
+    import paper_1204_2586_amd as aux
+    import workloads as W
+
+    wl = WORKLOADS[args.workload]
+    xyz, tets = W.kuhn_mesh(wl["n"], jitter=wl["jitter"], seed=wl["seed"])
+    logk = W.grf_log_kappa(xyz, tets, seed=wl["kappa"])
+    logk_t = W.grf_log_kappa(xyz, tets, seed=wl["kappa_target"])
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    f = torch.tensor(aux.Solver(xyz, tets, wl["k"], host_only=True).load(W.manufactured_f), device=dev)
+    lk0 = torch.tensor(logk, device=dev)
+    res = {}
+    for prec in ("mixed", "fp64"):
+        prob = aux.KappaSolve(xyz, tets, wl["k"], tol=args.tol, device=dev, precision=prec, nu=args.nu)
+        with torch.no_grad():
+            ut = aux.AuxSolveFn.apply(f, torch.tensor(logk_t, device=dev), prob)
+
+        def step():
+            fv = f.clone().requires_grad_(True)
+            lk = lk0.clone().requires_grad_(True)
+            u = aux.AuxSolveFn.apply(fv, lk, prob)
+            loss = 0.5 * torch.sum((u - ut) ** 2)
+            loss.backward()
+            return u, lk.grad, fv.grad
+
+        t0 = time.time()
+        step()                                    # the host setup for this kappa
+        setup_s = time.time() - t0
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            u, gk, gf = step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / args.steps
+        s = prob._solver
+        _, fi = s.solve(f, tol=args.tol)
+        lam, ai = s.solve((u - ut).contiguous(), tol=args.tol)
+        # the gradient kernel alone, HIP events on the stream it runs on
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g = s.kappa_grad(u, lam)
+        ev0.record()
+        for _ in range(20):
+            s.kappa_grad(u, lam, out=g)
+        ev1.record()
+        torch.cuda.synchronize()
+        kg_us = ev0.elapsed_time(ev1) * 1e3 / 20
+        prof = None
+        if prec == "mixed":
+            s.profile(True)
+            for _ in range(args.steps):
+                s.solve(f, tol=args.tol)
+            torch.cuda.synchronize()
+            prof = s.profile_read()
+            s.profile(False)
+        res[prec] = dict(ms=ms, setup_s=setup_s, it_forward=fi.iterations, it_adjoint=ai.iterations, kg_us=kg_us,
+                         prof=prof, solver=s, gk=gk.clone())
+    s = res["mixed"]["solver"]
+    n, nt = s.n, len(tets)
+    nloc = (wl["k"] + 1) * (wl["k"] + 2) * (wl["k"] + 3) // 6
+    # per tet: nloc dof indices, the 4x4 metric, kappa and g; u and lam once
+    kg_bytes = nt * (4 * nloc + 16 * 8 + 8 + 8) + 2 * 8 * n
+    kernels = kernel_table(res["mixed"]["prof"], args, s, wl, nt)
+    dom = max(kernels, key=lambda c: kernels[c]["total_ms"])
+    kd = kernels[dom]
+    gdiff = float(torch.linalg.norm(res["mixed"]["gk"] - res["fp64"]["gk"]) / torch.linalg.norm(res["fp64"]["gk"]))
+    out = {
+        "metric": "adjoint gradient throughput: forward solve + adjoint solve + per-tet log-coefficient gradient",
+        "value": n / (res["mixed"]["ms"] * 1e-3),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["mixed"]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 CG / f32 preconditioner, f64 gradient",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "order": wl["k"], "cubes_per_side": wl["n"], "n_h": n, "n_tets": nt,
+                   "tol": args.tol, "nu": args.nu, "iterations_forward": res["mixed"]["it_forward"],
+                   "iterations_adjoint": res["mixed"]["it_adjoint"], "setup_s": round(res["mixed"]["setup_s"], 2),
+                   "kappa_grad_us": round(res["mixed"]["kg_us"], 2), "kappa_grad_bytes": kg_bytes,
+                   "kappa_grad_gbs": round(kg_bytes / (res["mixed"]["kg_us"] * 1e-6) / 1e9, 1),
+                   "grad_mixed_vs_fp64_rel_diff": gdiff},
+        "fp64": {"value": n / (res["fp64"]["ms"] * 1e-3), "ms_per_step": res["fp64"]["ms"],
+                 "iterations_forward": res["fp64"]["it_forward"], "iterations_adjoint": res["fp64"]["it_adjoint"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": kd["bytes"], "avg_us": kd["avg_us"]},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        P = oracle.Problem(xyz, tets, wl["k"], np.exp(logk)).setup_amg(nu=args.nu)
+        Pt = oracle.Problem(xyz, tets, wl["k"], np.exp(logk_t)).setup_amg(nu=args.nu)
+        b = f.cpu().numpy()
+        u_t, _, _, _ = Pt.pcg(b, tol=args.tol)
+        t0 = time.perf_counter()
+        uo, it1, _, _ = P.pcg(b, tol=args.tol)
+        lo, it2, _, _ = P.pcg(uo - u_t, tol=args.tol)
+        P.kappa_grad(uo, lo)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": P.n / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one FP64 forward solve ({it1} iterations), adjoint solve ({it2}) and "
+                                         f"per-tet gradient of the full {args.workload} system (n_h={P.n}), "
+                                         f"{dt:.1f} s"}
+    return out
+
+
 def cpu_baseline(xyz, tets, wl, kappa, args):
     """The CPU oracle (single-threaded FP64 C) on the same system: one CG solve
     to the same tolerance from u = 0; its setup and its own load vector are
@@ -596,10 +725,16 @@ def main():
         return
     if args.tol is None:
         args.tol = 1e-6 if args.krylov == "fgmres" else 1e-8
-    if args.krylov == "fgmres" and "nrhs" in WORKLOADS[args.workload]:
-        print(json.dumps({"error": "FGMRES is single right-hand side; pick a single-vector workload"}))
+    if args.krylov == "fgmres" and ("nrhs" in WORKLOADS[args.workload] or WORKLOADS[args.workload].get("adjoint")):
+        print(json.dumps({"error": "FGMRES runs the single-vector solve workloads only"}))
         sys.exit(2)
-    fn = run_batched if "nrhs" in WORKLOADS[args.workload] else (run_fgmres if args.krylov == "fgmres" else run)
+    wl = WORKLOADS[args.workload]
+    if "nrhs" in wl:
+        fn = run_batched
+    elif wl.get("adjoint"):
+        fn = run_adjoint
+    else:
+        fn = run_fgmres if args.krylov == "fgmres" else run
     print(json.dumps(fn(args)), flush=True)
 
 
