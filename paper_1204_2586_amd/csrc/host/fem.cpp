@@ -17,6 +17,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 
 #include "setup.hpp"
 
@@ -165,9 +166,11 @@ double tet_metric(const double *X0, const double *X1, const double *X2, const do
     return std::fabs(det);
 }
 
-void element_stiffness(const Discretization &d, int t, double *K)
+namespace {
+
+// K_t from the reference tables tb of the discretisation's order
+void element_stiffness_from(const Tables &tb, const Discretization &d, int t, double *K)
 {
-    const Tables &tb = tables(d.k);
     int n = tb.nloc;
     const int *v = &d.tets[4 * (size_t)t];
     double G[4][4];
@@ -182,6 +185,10 @@ void element_stiffness(const Discretization &d, int t, double *K)
             for (int i = 0; i < n * n; i++) K[i] += g * M[i];
         }
 }
+
+}  // namespace
+
+void element_stiffness(const Discretization &d, int t, double *K) { element_stiffness_from(tables(d.k), d, t, K); }
 
 // --------------------------------------------------------------- sparse
 
@@ -207,9 +214,51 @@ Csr transpose(const Csr &a)
 
 namespace {
 
+// Host threads for a setup pass over `work` items: up to 16, one per 64K
+// items.  Every parallel pass below produces exactly the result of the
+// sequential one (disjoint outputs, sums kept in their sequential order).
+int setup_threads(size_t work)
+{
+    const unsigned hw = std::thread::hardware_concurrency();
+    size_t n = std::min<size_t>(hw ? hw : 1, 16);
+    return (int)std::max<size_t>(1, std::min(n, work / 65536));
+}
+
+// f(task) for task in [0, ntask), one thread each
+template <typename F>
+void run_tasks(int ntask, F f)
+{
+    if (ntask == 1) {
+        f(0);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(ntask);
+    for (int i = 0; i < ntask; i++) th.emplace_back(f, i);
+    for (std::thread &t : th) t.join();
+}
+
+// std::sort's result, from chunks sorted in parallel and merged pairwise
+template <typename T>
+void parallel_sort(std::vector<T> &v)
+{
+    const int nch = setup_threads(v.size());
+    std::vector<size_t> b((size_t)nch + 1);
+    for (int i = 0; i <= nch; i++) b[i] = v.size() * (size_t)i / (size_t)nch;
+    run_tasks(nch, [&](int c) { std::sort(v.begin() + b[c], v.begin() + b[c + 1]); });
+    for (int w = 1; w < nch; w *= 2) {
+        std::vector<int> first;
+        for (int i = 0; i + w < nch; i += 2 * w) first.push_back(i);
+        run_tasks((int)first.size(), [&](int t) {
+            const int i = first[t], end = std::min(i + 2 * w, nch);
+            std::inplace_merge(v.begin() + b[i], v.begin() + b[i + w], v.begin() + b[end]);
+        });
+    }
+}
+
 // Sparsity pattern of the assembled operator whose element dof map is
 // emap [nt][nl] (-1 = eliminated): row i couples to every dof of every element
-// containing i.
+// containing i.  Rows are built in parallel ranges and concatenated in order.
 void build_pattern(int ndof, int nt, int nl, const int *emap, Csr &A)
 {
     // dof -> elements incidence
@@ -224,23 +273,31 @@ void build_pattern(int ndof, int nt, int nl, const int *emap, Csr &A)
     A.n = A.m = ndof;
     A.ptr.assign((size_t)ndof + 1, 0);
     A.col.clear();
-    std::vector<int> mark(ndof, -1), row;
-    for (int i = 0; i < ndof; i++) {
-        row.clear();
-        for (int e = cnt[i]; e < cnt[i + 1]; e++) {
-            const int *dm = emap + (size_t)inc[e] * nl;
-            for (int b = 0; b < nl; b++) {
-                int j = dm[b];
-                if (j >= 0 && mark[j] != i) {
-                    mark[j] = i;
-                    row.push_back(j);
+    const int nth = setup_threads((size_t)nt * nl * nl);
+    std::vector<std::vector<int>> cols(nth);
+    run_tasks(nth, [&](int w) {
+        const int r0 = (int)((long long)ndof * w / nth), r1 = (int)((long long)ndof * (w + 1) / nth);
+        std::vector<int> mark(ndof, -1), row;
+        for (int i = r0; i < r1; i++) {
+            row.clear();
+            for (int e = cnt[i]; e < cnt[i + 1]; e++) {
+                const int *dm = emap + (size_t)inc[e] * nl;
+                for (int b = 0; b < nl; b++) {
+                    int j = dm[b];
+                    if (j >= 0 && mark[j] != i) {
+                        mark[j] = i;
+                        row.push_back(j);
+                    }
                 }
             }
+            std::sort(row.begin(), row.end());
+            cols[w].insert(cols[w].end(), row.begin(), row.end());
+            A.ptr[i + 1] = (int)row.size();
         }
-        std::sort(row.begin(), row.end());
-        A.col.insert(A.col.end(), row.begin(), row.end());
-        A.ptr[i + 1] = (int)A.col.size();
-    }
+    });
+    for (int i = 0; i < ndof; i++) A.ptr[i + 1] += A.ptr[i];
+    A.col.reserve(A.ptr[ndof]);
+    for (const std::vector<int> &c : cols) A.col.insert(A.col.end(), c.begin(), c.end());
     A.val.assign(A.col.size(), 0.0);
 }
 
@@ -307,7 +364,7 @@ void build_discretization(Discretization &d, int nv, const double *xyz, int nt, 
             for (int i = 0; i < 4; i++) key = (key << 32) | (u128)(uint32_t)(i < k ? m[i] : 0);
             nk[(size_t)t * nl + a] = {key, (uint32_t)((size_t)t * nl + a)};
         }
-    std::sort(nk.begin(), nk.end());
+    parallel_sort(nk);
     std::vector<int> tet_node((size_t)nt * nl);
     std::vector<u128> node_key;
     for (const auto &x : nk) {
@@ -326,7 +383,7 @@ void build_discretization(Discretization &d, int nv, const double *xyz, int nt, 
             std::sort(v, v + 3);
             faces[(size_t)t * 4 + f] = pack_ids(v, 3);
         }
-    std::sort(faces.begin(), faces.end());
+    parallel_sort(faces);
     std::vector<u128> bsub;
     for (size_t s = 0; s < faces.size();) {
         size_t e = s;
@@ -377,14 +434,32 @@ void build_discretization(Discretization &d, int nv, const double *xyz, int nt, 
 
     // A_h
     build_pattern(d.ndof, nt, nl, d.tet_dof.data(), d.A);
-    std::vector<double> K((size_t)nl * nl);
-    for (int t = 0; t < nt; t++) {
-        element_stiffness(d, t, K.data());
-        const int *dm = &d.tet_dof[(size_t)t * nl];
-        for (int a = 0; a < nl; a++) {
-            if (dm[a] < 0) continue;
-            for (int b = 0; b < nl; b++)
-                if (dm[b] >= 0) d.A.val[find_col(d.A, dm[a], dm[b])] += K[(size_t)a * nl + b];
+    // blocks of tets: the element matrices in parallel, then the scatter in
+    // parallel row ranges, each walking the block's tets in order (so every
+    // entry is summed in tet order, as a sequential loop would)
+    {
+        const int nth = setup_threads((size_t)nt * nl * nl);
+        const int blk = std::max(256, (1 << 21) / (nl * nl));
+        const Tables &tb = tables(k);
+        std::vector<double> Kb((size_t)blk * nl * nl);
+        for (int t0 = 0; t0 < nt; t0 += blk) {
+            const int t1 = std::min(nt, t0 + blk), nb = t1 - t0;
+            run_tasks(nth, [&](int w) {
+                for (int t = t0 + (int)((long long)nb * w / nth); t < t0 + (int)((long long)nb * (w + 1) / nth); t++)
+                    element_stiffness_from(tb, d, t, &Kb[(size_t)(t - t0) * nl * nl]);
+            });
+            run_tasks(nth, [&](int w) {
+                const int r0 = (int)((long long)d.ndof * w / nth), r1 = (int)((long long)d.ndof * (w + 1) / nth);
+                for (int t = t0; t < t1; t++) {
+                    const int *dm = &d.tet_dof[(size_t)t * nl];
+                    const double *K = &Kb[(size_t)(t - t0) * nl * nl];
+                    for (int a = 0; a < nl; a++) {
+                        if (dm[a] < r0 || dm[a] >= r1) continue;
+                        for (int b = 0; b < nl; b++)
+                            if (dm[b] >= 0) d.A.val[find_col(d.A, dm[a], dm[b])] += K[(size_t)a * nl + b];
+                    }
+                }
+            });
         }
     }
     d.l1.assign(d.ndof, 0.0);
