@@ -354,16 +354,19 @@ void build_discretization(Discretization &d, int nv, const double *xyz, int nt, 
 
     // nodes: sorted vertex multisets, numbered in lexicographic order
     std::vector<std::pair<u128, uint32_t>> nk((size_t)nt * nl);
-    for (int t = 0; t < nt; t++)
-        for (int a = 0; a < nl; a++) {
-            int m[4], c = 0;
-            for (int p = 0; p < 4; p++)
-                for (int r = 0; r < al[4 * a + p]; r++) m[c++] = tets[4 * (size_t)t + p];
-            std::sort(m, m + k);
-            u128 key = 0;
-            for (int i = 0; i < 4; i++) key = (key << 32) | (u128)(uint32_t)(i < k ? m[i] : 0);
-            nk[(size_t)t * nl + a] = {key, (uint32_t)((size_t)t * nl + a)};
-        }
+    const int nkth = setup_threads((size_t)nt * nl);
+    run_tasks(nkth, [&](int w) {
+        for (int t = (int)((long long)nt * w / nkth); t < (int)((long long)nt * (w + 1) / nkth); t++)
+            for (int a = 0; a < nl; a++) {
+                int m[4], c = 0;
+                for (int p = 0; p < 4; p++)
+                    for (int r = 0; r < al[4 * a + p]; r++) m[c++] = tets[4 * (size_t)t + p];
+                std::sort(m, m + k);
+                u128 key = 0;
+                for (int i = 0; i < 4; i++) key = (key << 32) | (u128)(uint32_t)(i < k ? m[i] : 0);
+                nk[(size_t)t * nl + a] = {key, (uint32_t)((size_t)t * nl + a)};
+            }
+    });
     parallel_sort(nk);
     std::vector<int> tet_node((size_t)nt * nl);
     std::vector<u128> node_key;
@@ -463,8 +466,11 @@ void build_discretization(Discretization &d, int nv, const double *xyz, int nt, 
         }
     }
     d.l1.assign(d.ndof, 0.0);
-    for (int i = 0; i < d.ndof; i++)
-        for (int e = d.A.ptr[i]; e < d.A.ptr[i + 1]; e++) d.l1[i] += std::fabs(d.A.val[e]);
+    const int l1th = setup_threads(d.A.col.size());
+    run_tasks(l1th, [&](int w) {
+        for (int i = (int)((long long)d.ndof * w / l1th); i < (int)((long long)d.ndof * (w + 1) / l1th); i++)
+            for (int e = d.A.ptr[i]; e < d.A.ptr[i + 1]; e++) d.l1[i] += std::fabs(d.A.val[e]);
+    });
 
     // A_H: kappa |T| grad lam_p . grad lam_q over interior vertices
     std::vector<int> vmap((size_t)nt * 4);
