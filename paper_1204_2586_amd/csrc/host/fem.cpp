@@ -13,6 +13,7 @@
 //    times vertex j occurs in node i's multiset)/k, I_R = I_P^T (eq. "Prol").
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <stdexcept>
@@ -214,13 +215,18 @@ Csr transpose(const Csr &a)
 
 namespace {
 
-// Host threads for a setup pass over `work` items: up to 16, one per 64K
-// items.  Every parallel pass below produces exactly the result of the
-// sequential one (disjoint outputs, sums kept in their sequential order).
+// Host threads for a setup pass over `work` items: up to 16 (or the
+// AUXPREC_SETUP_THREADS environment variable, if set), one per 64K items.
+// Every parallel pass below produces exactly the result of the sequential
+// one (disjoint outputs, sums kept in their sequential order).
 int setup_threads(size_t work)
 {
     const unsigned hw = std::thread::hardware_concurrency();
     size_t n = std::min<size_t>(hw ? hw : 1, 16);
+    if (const char *env = std::getenv("AUXPREC_SETUP_THREADS")) {
+        const long v = std::strtol(env, nullptr, 10);
+        if (v >= 1) n = (size_t)std::min<long>(v, 64);
+    }
     return (int)std::max<size_t>(1, std::min(n, work / 65536));
 }
 
