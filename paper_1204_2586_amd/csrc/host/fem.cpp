@@ -459,13 +459,27 @@ void build_discretization(Discretization &d, int nv, const double *xyz, int nt, 
             });
             run_tasks(nth, [&](int w) {
                 const int r0 = (int)((long long)d.ndof * w / nth), r1 = (int)((long long)d.ndof * (w + 1) / nth);
+                std::vector<std::pair<int, int>> js(nl);   // (dof, local index), sorted by dof
                 for (int t = t0; t < t1; t++) {
                     const int *dm = &d.tet_dof[(size_t)t * nl];
                     const double *K = &Kb[(size_t)(t - t0) * nl * nl];
+                    int nj = -1;                           // sorted lazily, once per tet
                     for (int a = 0; a < nl; a++) {
-                        if (dm[a] < r0 || dm[a] >= r1) continue;
-                        for (int b = 0; b < nl; b++)
-                            if (dm[b] >= 0) d.A.val[find_col(d.A, dm[a], dm[b])] += K[(size_t)a * nl + b];
+                        const int i = dm[a];
+                        if (i < r0 || i >= r1) continue;
+                        if (nj < 0) {
+                            nj = 0;
+                            for (int b = 0; b < nl; b++)
+                                if (dm[b] >= 0) js[nj++] = {dm[b], b};
+                            std::sort(js.begin(), js.begin() + nj);
+                        }
+                        // one merge walk over row i's sorted columns
+                        const int *col = d.A.col.data();
+                        int e = d.A.ptr[i];
+                        for (int q = 0; q < nj; q++) {
+                            while (col[e] < js[q].first) e++;
+                            d.A.val[e] += K[(size_t)a * nl + js[q].second];
+                        }
                     }
                 }
             });
