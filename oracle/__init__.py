@@ -54,6 +54,11 @@ def _load():
     lib.orc_csr_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int, _i64p]
     lib.orc_csr_copy.argtypes = [vp, ctypes.c_int, ctypes.c_int, _i32p, _i32p, _f64p]
     lib.orc_level_cf.argtypes = [vp, ctypes.c_int, _i32p]
+    lib.orc_level_round.argtypes = [vp, ctypes.c_int, _i32p]
+    lib.orc_apply_vcycle.argtypes = [vp, ctypes.c_int, _f64p, _f64p]
+    lib.orc_interp_given.restype = ctypes.c_int
+    lib.orc_interp_given.argtypes = [ctypes.c_int, _i32p, _i32p, _f64p, ctypes.c_double, _i32p, ctypes.c_int,
+                                     _i32p, _i32p, _f64p]
     lib.orc_dof_keys.argtypes = [vp, _i32p]
     lib.orc_tet_dofs.argtypes = [vp, _i32p]
     lib.orc_l1.argtypes = [vp, _f64p]
@@ -133,6 +138,25 @@ def tet_rule(m: int):
     return lam.reshape(-1, 4), w
 
 
+def interp_given(A, cf, theta: float = 0.8):
+    """Extended+i interpolation of the square scipy CSR matrix A for the given
+    C/F splitting (cf[i] = +1 C, -1 F) with the strength sets of threshold
+    theta; returns P as a scipy CSR matrix (rows of A, columns = C points in
+    increasing index)."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    n = A.shape[0]
+    cf = np.ascontiguousarray(cf, dtype=np.int32)
+    cap = n * n + 1
+    ptr, col, val = np.zeros(n + 1, dtype=np.int32), np.zeros(cap, dtype=np.int32), np.zeros(cap)
+    nnz = _load().orc_interp_given(n, A.indptr.astype(np.int32), A.indices.astype(np.int32),
+                                   A.data.astype(np.float64), theta, cf, cap, ptr, col, val)
+    if nnz < 0:
+        raise RuntimeError("interpolation larger than expected")
+    return sp.csr_matrix((val[:nnz], col[:nnz], ptr), shape=(n, int((cf > 0).sum())))
+
+
 # ---------------------------------------------------------------- problem
 
 class Problem:
@@ -197,6 +221,15 @@ class Problem:
             raise IndexError("coarsest level has no splitting")
         return cf
 
+    def level_rounds(self, level: int) -> np.ndarray:
+        """PMIS round in which each point of the level was decided (0: points
+        influencing nobody, made F before the first round)."""
+        n = self.csr("Alev", level).shape[0]
+        rd = np.zeros(n, dtype=np.int32)
+        if _load().orc_level_round(self._h, level, rd):
+            raise IndexError("coarsest level has no splitting")
+        return rd
+
     def dof_keys(self) -> np.ndarray:
         keys = np.zeros(self.n * self.k, dtype=np.int32)
         _load().orc_dof_keys(self._h, keys)
@@ -253,6 +286,15 @@ class Problem:
         z = np.zeros(self.n)
         _load().orc_apply_precond(self._h, int(fp32), np.ascontiguousarray(r, dtype=np.float64), z)
         return z
+
+    def vcycle(self, b, fp32: bool = False) -> np.ndarray:
+        """One AMG V(1,1) cycle from zero on the P^1 system (Step 1 of
+        Algorithm 2.1 on its own): x = V b, b and x of length n_H."""
+        assert self._amg, "call setup_amg first"
+        x = np.zeros(self.nH)
+        if _load().orc_apply_vcycle(self._h, int(fp32), np.ascontiguousarray(b, dtype=np.float64), x):
+            raise ValueError("no P^1 unknowns")
+        return x
 
     def pcg(self, b, tol=1e-8, maxit=1000, x0=None, fp32: bool = False):
         """Returns (x, iterations, relative recursive residual, status)."""

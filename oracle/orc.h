@@ -25,6 +25,7 @@ typedef struct {
     ocsr A;        /* level operator */
     double *dl1;   /* l1 row norms sum_j |a_ij| */
     int *cf;       /* +1 coarse, -1 fine (not set on the coarsest level) */
+    int *round;    /* PMIS round in which each point was decided (0: before the first) */
     ocsr P;        /* interpolation n x nc (not set on the coarsest level) */
     ocsr R;        /* P transposed */
     int nc;

@@ -80,8 +80,10 @@ static int beats(const int *nst, const uint64_t *rho, int i, int j)
     return i < j;
 }
 
-/* PMIS coarse/fine splitting: cf[i] = +1 (C) or -1 (F) */
-static void pmis(const ocsr *S, const ocsr *ST, uint64_t seed, int level, int *cf)
+/* PMIS coarse/fine splitting: cf[i] = +1 (C) or -1 (F).  round[i] records
+   when i was decided: 0 for points that influence nobody (F before the
+   first round), r >= 1 for points that joined D or became F in round r. */
+static void pmis(const ocsr *S, const ocsr *ST, uint64_t seed, int level, int *cf, int *round)
 {
     int n = S->n;
     int *nst = malloc((size_t)(n > 0 ? n : 1) * sizeof(int));
@@ -91,8 +93,9 @@ static void pmis(const ocsr *S, const ocsr *ST, uint64_t seed, int level, int *c
         nst[i] = ST->ptr[i + 1] - ST->ptr[i];
         rho[i] = pmis_rho(seed, level, i);
         cf[i] = nst[i] == 0 ? -1 : 0;       /* influences nobody: F */
+        round[i] = 0;
     }
-    for (;;) {
+    for (int r = 1;; r++) {
         int left = 0;
         for (int i = 0; i < n; i++) left += cf[i] == 0;
         if (!left) break;
@@ -112,12 +115,12 @@ static void pmis(const ocsr *S, const ocsr *ST, uint64_t seed, int level, int *c
             inD[i] = (char)best;
         }
         for (int i = 0; i < n; i++)
-            if (inD[i]) cf[i] = 1;
+            if (inD[i]) { cf[i] = 1; round[i] = r; }
         /* undecided points that strongly depend on a new C point become F */
         for (int i = 0; i < n; i++) {
             if (cf[i] != 0) continue;
             for (int e = S->ptr[i]; e < S->ptr[i + 1]; e++)
-                if (inD[S->col[e]]) { cf[i] = -1; break; }
+                if (inD[S->col[e]]) { cf[i] = -1; round[i] = r; break; }
         }
     }
     free(nst); free(rho); free(inD);
@@ -292,14 +295,17 @@ int orc_amg_setup(orc *o)
         strength(&lv->A, o->theta, &S);
         pattern_transpose(&S, &ST);
         lv->cf = malloc((size_t)(n > 0 ? n : 1) * sizeof(int));
-        pmis(&S, &ST, o->seed, l, lv->cf);
+        lv->round = malloc((size_t)(n > 0 ? n : 1) * sizeof(int));
+        pmis(&S, &ST, o->seed, l, lv->cf, lv->round);
         int nc;
         ext_i_interp(&lv->A, &S, lv->cf, &lv->P, &nc);
         free(S.ptr); free(S.col); free(ST.ptr); free(ST.col); free(ST.val);
         if (nc == 0 || nc >= n) {                  /* no coarsening possible */
             ocsr_free(&lv->P);
             free(lv->cf);
+            free(lv->round);
             lv->cf = NULL;
+            lv->round = NULL;
             break;
         }
         lv->nc = nc;
@@ -320,3 +326,27 @@ int orc_amg_setup(orc *o)
 /* exported for the hash test vector */
 uint64_t orc_splitmix64(uint64_t z) { return splitmix64(z); }
 uint64_t orc_pmis_rho(uint64_t seed, int level, int i) { return pmis_rho(seed, level, i); }
+
+/* Extended+i interpolation of a caller-given matrix (CSR, sorted columns)
+   and C/F splitting (cf[i] = +1 C, -1 F), with the strength sets of the
+   Sec. 6.2 rule at threshold theta; for checking the interpolation step on
+   its own.  Writes at most cap entries of P (n rows, CSR) and returns its
+   number of entries, or -1 if cap is too small. */
+int orc_interp_given(int n, const int *ptr, const int *col, const double *val, double theta,
+                     const int *cf, int cap, int *pptr, int *pcol, double *pval)
+{
+    ocsr A = {n, n, (int *)ptr, (int *)col, (double *)val};
+    ocsr S, P;
+    int nc;
+    strength(&A, theta, &S);
+    ext_i_interp(&A, &S, cf, &P, &nc);
+    int nnz = P.ptr[n];
+    if (nnz <= cap) {
+        memcpy(pptr, P.ptr, ((size_t)n + 1) * sizeof(int));
+        memcpy(pcol, P.col, (size_t)nnz * sizeof(int));
+        memcpy(pval, P.val, (size_t)nnz * sizeof(double));
+    }
+    free(S.ptr); free(S.col);
+    ocsr_free(&P);
+    return nnz <= cap ? nnz : -1;
+}

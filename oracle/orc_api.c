@@ -26,7 +26,7 @@ void orc_free(orc *o)
     free(o->node_key); free(o->tet_node); free(o->node_dof); free(o->vert_dof);
     ocsr_free(&o->A); free(o->dl1); ocsr_free(&o->AH); ocsr_free(&o->IP); ocsr_free(&o->IR);
     for (int l = 0; l < o->nlev; l++) {
-        ocsr_free(&o->lev[l].A); free(o->lev[l].dl1); free(o->lev[l].cf);
+        ocsr_free(&o->lev[l].A); free(o->lev[l].dl1); free(o->lev[l].cf); free(o->lev[l].round);
         ocsr_free(&o->lev[l].P); ocsr_free(&o->lev[l].R);
     }
     free(o->chol);
@@ -105,6 +105,13 @@ int orc_level_cf(const orc *o, int level, int *cf)
 {
     if (level + 1 >= o->nlev) return -1;
     memcpy(cf, o->lev[level].cf, (size_t)o->lev[level].A.n * sizeof(int));
+    return 0;
+}
+
+int orc_level_round(const orc *o, int level, int *round)
+{
+    if (level + 1 >= o->nlev) return -1;
+    memcpy(round, o->lev[level].round, (size_t)o->lev[level].A.n * sizeof(int));
     return 0;
 }
 

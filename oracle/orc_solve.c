@@ -153,6 +153,20 @@ static void vcycle(const orc *o, const bops *B, int l, const double *b, double *
     free(r); free(t); free(bc); free(ec);
 }
 
+/* x = V b for the P^1 problem: the AMG V(1,1) cycle of Step 1 on its own */
+int orc_apply_vcycle(const orc *o, int fp32, const double *b, double *x)
+{
+    if (o->nlev < 1 || o->nH < 1) return -1;
+    bops B;
+    bops_init(o, fp32, &B);
+    double *bb = malloc((size_t)o->nH * sizeof(double));
+    for (int i = 0; i < o->nH; i++) bb[i] = B.R(b[i]);
+    vcycle(o, &B, 0, bb, x);
+    free(bb);
+    bops_free(&B);
+    return 0;
+}
+
 /* z = B r */
 static void apply_B(const orc *o, const bops *B, const double *rin, double *z)
 {

@@ -3,10 +3,13 @@
 // The P^k operator A_h is stored as sliced ELLPACK with 64-row slices
 // (one wavefront per slice, one lane per row, entries of a slice stored
 // column-major so every load of a wavefront is 64 consecutive words).  Its
-// rows are numbered in an internal order: within windows of consecutive dofs
-// the rows are sorted by length, which keeps the padding of each slice small
-// while the window keeps the gathered vector entries local.  The small AMG
-// operators and the transfers are CSR with LPR lanes per row.
+// rows are numbered in an internal order, sorted by length so the padding of
+// each slice stays small: either over the whole operator (a stable sort,
+// which on structured meshes groups nodes of one kind and keeps a slice's
+// gathers nearly contiguous) or within windows of consecutive dofs; the setup
+// times both on the device and keeps the faster (the global sort wins on the
+// benchmark meshes).  The AMG operators and the transfers are CSR with LPR
+// lanes per row or row-split sliced ELL, whichever the setup times faster.
 //
 // Dot products are reduced deterministically without atomics: every
 // workgroup writes one partial, and a one-workgroup "finish" kernel that

@@ -8,8 +8,10 @@
 // products of all six with the gathered element vectors form one dense
 // contraction Y[a][t] = sum_{(k,b)} S[a][(k,b)] Z[(k,b)][t] with
 // Z[(k,b)][t] = w_t,k x_t,b: an [nloc x 6 nloc] by [6 nloc x 16] product,
-// evaluated with v_mfma_*_16x16x4 (A operand = the reference tables, held in
-// registers for the whole kernel; B operand = Z built from LDS).
+// evaluated with v_mfma_*_16x16x4 (A operand = the reference tables, staged
+// once per workgroup in LDS in operand lane order and read back per step;
+// B operand = Z formed in registers from the lane's gathered values and its
+// tet's weights).
 //
 // Each element result (K_t x_t)_a is written to the slot of (t, a) in an
 // array ordered by dof, so the contributions to one dof are contiguous; a
@@ -65,8 +67,10 @@ constexpr int kWaves = kBlock / 64;
 // step s covering k = s / NB and b = 4 (s % NB) + g for the four lane groups
 // g = lane / 16 (NB = ceil(nloc / 4); b >= nloc is padding).  So lane (g, c)
 // of a wave needs only the six weights of its tet c and its NB gathered
-// values b = g, g+4, ..., held in registers -- no shared memory and no
-// barriers -- and every register index below is a compile-time constant.
+// values b = g, g+4, ..., held in registers, from which it forms its B
+// operand per step; the A operand (the reference tables) comes from LDS,
+// filled once per workgroup before a barrier.  Every register index below is
+// a compile-time constant.
 template <typename T, int NLOC>
 __global__ __launch_bounds__(kBlock) void k_mf_element(MfView<T> op, const T *__restrict__ X, T *__restrict__ Yel,
                                                        const int *done)

@@ -18,6 +18,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <exception>
 #include <thread>
 
 #include "setup.hpp"
@@ -230,7 +231,10 @@ int setup_threads(size_t work)
     return (int)std::max<size_t>(1, std::min(n, work / 65536));
 }
 
-// f(task) for task in [0, ntask), one thread each
+// f(task) for task in [0, ntask), one thread each.  An exception thrown by a
+// task (e.g. std::bad_alloc) is kept, every started thread is joined, and the
+// first task's exception in task order is rethrown on the calling thread; if a
+// thread cannot be started, the remaining tasks run on the calling thread.
 template <typename F>
 void run_tasks(int ntask, F f)
 {
@@ -238,10 +242,26 @@ void run_tasks(int ntask, F f)
         f(0);
         return;
     }
+    std::vector<std::exception_ptr> err((size_t)ntask);
+    auto body = [&](int i) {
+        try {
+            f(i);
+        } catch (...) {
+            err[i] = std::current_exception();
+        }
+    };
     std::vector<std::thread> th;
     th.reserve(ntask);
-    for (int i = 0; i < ntask; i++) th.emplace_back(f, i);
+    int started = 0;
+    try {
+        for (; started < ntask; started++) th.emplace_back(body, started);
+    } catch (...) {
+        // no further threads (std::system_error): run the rest here
+    }
+    for (int i = started; i < ntask; i++) body(i);
     for (std::thread &t : th) t.join();
+    for (const std::exception_ptr &e : err)
+        if (e) std::rethrow_exception(e);
 }
 
 // std::sort's result, from chunks sorted in parallel and merged pairwise

@@ -3,7 +3,8 @@
 graph), against the CPU oracle solving the same systems.
 
 * P2, 48^3 cubes x 6 tets, interior vertices jittered +-0.2h (857,375
-  unknowns), manufactured source: FP64 CG with the iteration count fixed to
+  unknowns), manufactured source: one preconditioner application in FP64
+  (1e-12) and FP32 (2e-6, and more than 1e-9 away from FP64); FP64 CG with the iteration count fixed to
   the oracle's agrees to 1e-10; free-running counts within +-1 (FP64 against
   the oracle's FP64, mixed against the oracle's FP32 mode); the mixed solution
   within 1e-7 of the oracle's FP64 solution; the same with the matrix-free
@@ -68,6 +69,17 @@ def test_full_size_solve_matches_oracle(name, k, n, jitter, grf, operator):
     lib = aux.Solver(xyz, tets, k, kappa, device=DEV, operator=operator)
     assert np.array_equal(lib.dof_keys(), orc.dof_keys())
     f = _t(b)
+    # one preconditioner application in both precisions against the oracle's;
+    # the FP32 form must visibly differ from the FP64 one (FP32 ran)
+    r = W.random_vector(lib.n, 7)
+    lib.set_precision("fp64")
+    z64 = lib.apply(_t(r)).cpu().numpy()
+    lib.set_precision("mixed")
+    z32 = lib.apply(_t(r)).cpu().numpy()
+    o64 = orc.apply(r)
+    assert _rel(z64, o64) <= 1e-12
+    assert _rel(z32, orc.apply(r, fp32=True)) <= 2e-6 and _rel(z32, o64) <= 2e-6
+    assert _rel(z32, o64) > 1e-9 and _rel(z32, z64) > 1e-9
     lib.set_precision("fp64")
     u, info = lib.solve(f, tol=1e-8)
     assert abs(info.iterations - it64) <= 1

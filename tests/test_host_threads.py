@@ -44,3 +44,41 @@ def _digest(k, n, threads):
 @pytest.mark.parametrize("k,n", [(2, 24), (3, 12), (4, 8)])
 def test_setup_independent_of_thread_count(k, n):
     assert _digest(k, n, 1) == _digest(k, n, 8)
+
+
+LIMIT_SCRIPT = r"""
+import resource, sys
+sys.path.insert(0, {root!r})
+import paper_1204_2586_amd as aux, workloads as W
+aux.load_library()
+xyz, tets = W.kuhn_mesh(24, jitter=0.2, seed=0)
+def vm():
+    for l in open('/proc/self/status'):
+        if l.startswith('VmSize'):
+            return int(l.split()[1]) * 1024
+lim = vm() + {mb} * 2 ** 20
+resource.setrlimit(resource.RLIMIT_AS, (lim, lim))
+try:
+    s = aux.Solver(xyz, tets, 2, host_only=True)
+    print("ok", s.info.levels)
+except aux.AuxError as e:
+    print("err", e.code)
+except MemoryError:
+    print("pyerr")       # the interpreter's own allocation hit the limit first
+"""
+
+
+def test_setup_out_of_memory_returns_status():
+    """Under an address-space limit the threaded host setup must fail with
+    AUX_ENOMEM (worker exceptions joined and rethrown, threads that cannot be
+    started replaced by the calling thread), never terminate the process."""
+    outcomes = []
+    for mb in (50, 100, 200, 300):
+        env = dict(os.environ, AUXPREC_SETUP_THREADS="8")
+        r = subprocess.run([sys.executable, "-c", LIMIT_SCRIPT.format(root=ROOT, mb=mb)], env=env,
+                           capture_output=True, text=True, timeout=600)
+        assert r.returncode == 0, (mb, r.returncode, r.stderr[-500:])
+        out = r.stdout.strip().splitlines()[-1].split()
+        assert out[0] in ("ok", "pyerr") or (out[0] == "err" and int(out[1]) == -2), (mb, out)
+        outcomes.append(out[0])
+    assert "err" in outcomes

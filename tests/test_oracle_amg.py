@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle_pins as pins
 import workloads as W
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -120,3 +121,25 @@ def test_unjittered_level0_stencil_all_axis_neighbours_strong():
         b, c = divmod(r, n1)
         axis_nb = sum(0 <= v + d < n1 for v in (a, b, c) for d in (-1, 1))
         assert len(S[i]) == axis_nb
+
+
+@pytest.mark.parametrize("theta,seed", [(0.8, 0), (0.25, 7)])
+def test_pmis_rounds(theta, seed):
+    """Each PMIS round: the new C points are exactly the undecided local
+    maxima of the measure over S u S^T (independent there), and exactly the
+    undecided points depending strongly on one of them become F."""
+    pins.check_pmis_rounds(theta=theta, seed=seed)
+
+
+def test_ext_i_harmonic_1d():
+    """Extended+i reproduces the harmonic extension -A_FF^{-1} A_FC on
+    tridiagonal M-matrices with F runs of length <= 2 (plain extended
+    interpolation does not)."""
+    pins.check_ext_i_harmonic_1d()
+
+
+def test_ext_i_exact_rationals():
+    """Extended+i weights on random small matrices (positive off-diagonals,
+    weak couplings, d_k = 0 cases, distance-two C points) equal the published
+    formula evaluated in exact rationals."""
+    pins.check_ext_i_rational()

@@ -16,6 +16,7 @@ import pytest
 import scipy.linalg as sla
 
 import oracle
+import oracle_pins as pins
 import workloads as W
 
 
@@ -72,6 +73,31 @@ def test_preconditioner_spd(k, n):
     assert lam[0] > 0 and lam[-1] <= 1 + 1e-10
     B32 = np.stack([P.apply(E[:, j], fp32=True) for j in range(P.n)], axis=1)
     assert np.max(np.abs(B32 - B)) < 1e-6 * np.max(np.abs(B))
+
+
+def test_vcycle_spd_multilevel():
+    """The AMG V(1,1) cycle alone on a 4-level hierarchy: symmetric, positive
+    definite, spectrum of V A_H in (0, 1]."""
+    pins.check_vcycle_spd(k=2, n=5, coarse_max=4, min_levels=4)
+    pins.check_vcycle_spd(k=3, n=4, coarse_max=4, min_levels=3)
+
+
+def test_vcycle_error_propagator():
+    """The cycle equals the textbook product form of its error propagator,
+    level by level, on a 5-level hierarchy (P2) and a 4-level one (P3)."""
+    pins.check_vcycle_error_propagator(k=2, n=6, coarse_max=4, min_levels=5)
+    pins.check_vcycle_error_propagator(k=3, n=5, coarse_max=6, min_levels=4)
+
+
+@pytest.mark.parametrize("k,n,cmax,minl", [(2, 4, 2, 4), (2, 5, 4, 4), (3, 4, 4, 3)])
+def test_preconditioner_spd_multilevel(k, n, cmax, minl):
+    """B with a 3-4 level V-cycle for Step 1: symmetric positive definite,
+    spectrum of B A_h in (0, 1]."""
+    pins.check_precond_spd_multilevel(k=k, n=n, coarse_max=cmax, min_levels=minl)
+
+
+def test_gamg_multilevel_flat_in_h():
+    pins.check_gamg_multilevel_flat_in_h()
 
 
 def test_augmented_system_and_block_gauss_seidel():
