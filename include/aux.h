@@ -254,6 +254,20 @@ int aux_apply(aux_handle *h, const double *r, double *z);
  * AUX_ENOTCONV, AUX_EBREAKDOWN or AUX_ENAN (u then holds the last iterate). */
 int pcg_solve(aux_handle *h, const double *f, double *u, double tol, int maxit, aux_solve_info *info);
 
+/* pcg_solve without any allocation, for callers that cannot allocate device
+ * memory (tight serving loops, code that forbids hipMalloc/hipFree or
+ * allocating library calls).  Same arguments, iterations, result and status
+ * as pcg_solve (the same kernels in the same order; every launch enqueued
+ * directly, no HIP graph).  The solve's scratch memory (reduction partials,
+ * CG state and per-iteration histories) is a fixed 128.1 KiB array in the
+ * library, one copy per GPU, held until the process ends; concurrent calls
+ * on one GPU (any handles) race on it and must be serialised by the caller.
+ * maxit (after the <= 0 default) must be at most 4094 (AUX_EINVAL).  The
+ * handle's data for the current precision and operator must exist: they are
+ * built by aux_setup, aux_set_precision and aux_set_operator (AUX_ESTATE
+ * otherwise).  Kernel timing (aux_profile) is not recorded by this call. */
+int pcg_solve_noalloc(aux_handle *h, const double *f, double *u, double tol, int maxit, aux_solve_info *info);
+
 /* nrhs independent CG solves in lock-step sharing every sparse-matrix pass.
  * F, U: device row-major [n_h][nrhs] (column j is right-hand side j).  Each
  * column follows exactly the single-right-hand-side algorithm and stops on

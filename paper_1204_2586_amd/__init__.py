@@ -133,6 +133,7 @@ def load_library():
         "aux_export_cf": (ctypes.c_int, [vp, ctypes.c_int, vp]),
         "aux_apply": (ctypes.c_int, [vp, vp, vp]),
         "pcg_solve": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, P(_SolveInfo)]),
+        "pcg_solve_noalloc": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, P(_SolveInfo)]),
         "pcg_solve_batched": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, dbl, ctypes.c_int, P(_SolveInfo)]),
         "fgmres_solve": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int, vp, P(_SolveInfo)]),
         "aux_matvec": (ctypes.c_int, [vp, vp, vp]),
@@ -397,6 +398,25 @@ class Solver:
         elif rc not in (0, -4, -5, -6):
             _check(rc)
         return u, SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds)
+
+    def solve_noalloc(self, f, u, tol: float = 1e-8, maxit: int = 0, check: bool = True):
+        """CG on A_h u = f through pcg_solve_noalloc (no allocation in the
+        library: its scratch memory is a fixed array per GPU).  u is the
+        caller's device vector, initial guess in and solution out; this
+        method allocates nothing either.  Returns SolveInfo."""
+        f = self._vec(f, "f")
+        if not (isinstance(u, self._torch.Tensor) and u.is_contiguous()):
+            raise ValueError("u must be a contiguous float64 device tensor (it receives the solution)")
+        u = self._vec(u, "u")
+        info = _SolveInfo()
+        self._sync_stream()
+        rc = load_library().pcg_solve_noalloc(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                              tol, int(maxit), ctypes.byref(info))
+        if check:
+            _check(rc)
+        elif rc not in (0, -4, -5, -6):
+            _check(rc)
+        return SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds)
 
     def fgmres(self, b, tol: float = 1e-6, x0=None, restart: int = 30, maxit: int = 0, check: bool = True):
         """Flexible GMRES(restart) on A_h x = b with the same preconditioner,

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <functional>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <stdexcept>
@@ -113,6 +114,44 @@ double seconds_since(std::chrono::steady_clock::time_point t0)
 }
 
 constexpr int kSellWindow = 4096;
+
+}  // namespace
+
+// Device memory of the allocation-free CG entry point (pcg_solve_noalloc):
+// the reduction partials, the CG state and the per-iteration r.z, p.Ap and
+// r.r histories of one solve.  Each GPU the library runs on holds its own
+// copy until the process ends; calls on one GPU share it (the last call's
+// contents stay), so such calls must not overlap on one device.  Host code
+// never uses the name of this array as an address: it takes each device's
+// address once with hipGetSymbolAddress (scratch_address below).
+constexpr int kNoAllocHist = 4096;                 // histories: maxit + 2 <= this
+constexpr size_t kScratchPartials = 0;
+constexpr size_t kScratchScal = kScratchPartials + kMaxBlocks;
+constexpr size_t kScratchState = kScratchScal + 8;  // 4 ints in 2 doubles
+constexpr size_t kScratchHist = kScratchState + 8;
+constexpr size_t kScratchDoubles = kScratchHist + 3 * (size_t)kNoAllocHist;   // 16,400 doubles, 128.1 KiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the scratch array on `device` (the current device), looked up
+// once per device.
+double *scratch_address(int device)
+{
+    if (device < 0 || device >= kMaxDevices) throw AuxError(AUX_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        HIPCHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw AuxError(AUX_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[device] = (double *)ptr;
+    }
+    return g_scratch_ptr[device];
+}
 
 }  // namespace
 
@@ -842,15 +881,26 @@ struct aux_handle {
     }
 
     // ------------------------------------------------------------ CG
-    CgState cg_state(int maxit)
+    // Device buffers one CG solve reduces into and keeps its state in: the
+    // handle's own (pcg_solve) or the file-scope scratch array (the
+    // allocation-free pcg_solve_noalloc).
+    struct CgBufs {
+        double *partials;    // [kMaxBlocks] per-workgroup partial sums
+        double *scal;        // [8] f.f, r0.r0, tol^2 f.f
+        int *istate;         // [4] iteration, stop flag
+        double *hist;        // rz, pq, rr, each [hist_cap]
+        int hist_cap;
+    };
+    CgBufs own_cg() const { return {partials, scal, istate, hist, hist_cap}; }
+    static CgState cg_state(const CgBufs &b, int maxit)
     {
-        return {istate, istate + 1, hist, hist + hist_cap, hist + 2 * hist_cap, scal, maxit};
+        return {b.istate, b.istate + 1, b.hist, b.hist + b.hist_cap, b.hist + 2 * b.hist_cap, b.scal, maxit};
     }
 
     // one CG iteration: q = A p, alpha, x/r update, z = B r, beta, p update
     // (forming p inside the product, from gathered z and p, measured twice as
     // slow as the separate update pass)
-    void cg_iteration(const CgState &st)
+    void cg_iteration(const CgState &st, double *part)
     {
         hipStream_t s = stream;
         int n = disc.ndof;
@@ -858,28 +908,28 @@ struct aux_handle {
         int g;
         if (use_mf()) {
             // q = A_h p by the element operator in FP64 (half the bytes of
-            // the assembled product at P3), with the p . q partials
+            // the assembled product at P3), with the p . q part
             ensure_mf();
             MfView<double> v = mf_view<double>();
             mf_apply<double>(s, v, p, mf_Y64, st.done);
-            g = mf_product<double>(s, v, mf_Y64, q, p, partials, st.done);
+            g = mf_product<double>(s, v, mf_Y64, q, p, part, st.done);
         } else {
-            g = sell_spmv64(s, A.view<double>(), p, q, partials, st.done);
+            g = sell_spmv64(s, A.view<double>(), p, q, part, st.done);
         }
         pend(pk);
-        finish(s, partials, g, FIN_PQ, nullptr, st);
+        finish(s, part, g, FIN_PQ, nullptr, st);
         // the update also starts the preconditioner: z = D^-1 r
         if (opt.precision == AUX_MIXED) {
             ensure_fp32();
             Work<float> &w = work<float>();
-            g = cg_update_prep<float>(s, n, xi, r, p, q, st, partials, dinv32, w.za, w.rT);
+            g = cg_update_prep<float>(s, n, xi, r, p, q, st, part, dinv32, w.za, w.rT);
         } else {
             Work<double> &w = work<double>();
-            g = cg_update_prep<double>(s, n, xi, r, p, q, st, partials, dinv64, w.za, nullptr);
+            g = cg_update_prep<double>(s, n, xi, r, p, q, st, part, dinv64, w.za, nullptr);
         }
-        finish(s, partials, g, FIN_RR, nullptr, st);
-        g = apply(r, z, partials, st.done, true);
-        finish(s, partials, g, FIN_RZ, nullptr, st);
+        finish(s, part, g, FIN_RR, nullptr, st);
+        g = apply(r, z, part, st.done, true);
+        finish(s, part, g, FIN_RZ, nullptr, st);
         cg_direction(s, n, z, p, st);
     }
 
@@ -932,8 +982,8 @@ struct aux_handle {
         // two iterations per graph: half the gaps between graph launches
         const int key[4] = {opt.precision, opt.op, st.maxit, 1};
         return captured(g_single, key, [&]() {
-            cg_iteration(st);
-            cg_iteration(st);
+            cg_iteration(st, partials);
+            cg_iteration(st, partials);
         });
     }
 
@@ -945,12 +995,24 @@ struct aux_handle {
 
     int pcg(const double *f, double *u, double tol, int maxit, aux_solve_info *info)
     {
-        auto t0 = std::chrono::steady_clock::now();
         if (maxit <= 0) maxit = opt.maxit;
         ensure_hist(maxit);
+        return pcg_run(own_cg(), f, u, tol, maxit, info, opt.graph && !prof_on);
+    }
+
+    // The CG solve on the given buffers.  use_graph: replay two iterations
+    // per captured graph (bound to the handle's own buffers); otherwise every
+    // launch is enqueued directly, and nothing is allocated on this path once
+    // the preconditioner's data for the current precision and operator exist.
+    int pcg_run(const CgBufs &cb, const double *f, double *u, double tol, int maxit, aux_solve_info *info,
+                bool use_graph)
+    {
+        auto t0 = std::chrono::steady_clock::now();
         hipStream_t s = stream;
         int n = disc.ndof;
-        CgState st = cg_state(maxit);
+        double *partials = cb.partials, *scal = cb.scal;
+        int *istate = cb.istate;
+        CgState st = cg_state(cb, maxit);
         vec_gather(s, n, perm, f, fi);
         vec_gather(s, n, perm, u, xi);
         sell_residual64(s, A.view<double>(), fi, xi, r);
@@ -968,7 +1030,7 @@ struct aux_handle {
         // the iteration index and the stopping state live in device memory,
         // and iterations past the stop return at once); not used while kernel
         // timing records events
-        hipGraphExec_t gexec = opt.graph && !prof_on ? iteration_graph(st) : nullptr;
+        hipGraphExec_t gexec = use_graph ? iteration_graph(st) : nullptr;
         int issued = 0, iter = 0, done = 0, chunk = 2;
         bool first_check = true;
         while (true) {
@@ -980,7 +1042,7 @@ struct aux_handle {
                     c += 2;
                 } else {
                     prof_tag = issued + 1;
-                    cg_iteration(st);
+                    cg_iteration(st, partials);
                     issued++;
                     c++;
                 }
@@ -1835,10 +1897,12 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
             if (h->disc.nH > 0) build_hierarchy(h->disc.AH, so, h->hier);
             if (!h->host_only) {
                 HIPCHECK(hipGetDevice(&h->device));
+                scratch_address(h->device);
                 h->upload_all();
                 if (o.precision == AUX_MIXED) h->ensure_fp32();
                 h->work<double>();
                 if (o.precision == AUX_MIXED) h->work<float>();
+                if (o.op == AUX_OP_MATFREE) h->ensure_mf();
                 HIPCHECK(hipDeviceSynchronize());
             }
             h->setup_seconds = seconds_since(t0);
@@ -2053,6 +2117,42 @@ int pcg_solve(aux_handle *h, const double *f, double *u, double tol, int maxit, 
         if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
         set_dev(h);
         int st = h->pcg(f, u, tol, maxit, info);
+        HIPCHECK(hipGetLastError());
+        return st;
+    });
+}
+
+int pcg_solve_noalloc(aux_handle *h, const double *f, double *u, double tol, int maxit, aux_solve_info *info)
+{
+    return guarded([&]() {
+        need_device(h);
+        if (!f || !u) throw AuxError(AUX_EINVAL, "null vector");
+        if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
+        if (maxit <= 0) maxit = h->opt.maxit;
+        if (maxit + 2 > kNoAllocHist)
+            throw AuxError(AUX_EINVAL, "maxit exceeds the limit of the allocation-free solve (" +
+                                           std::to_string(kNoAllocHist - 2) + ")");
+        set_dev(h);
+        // everything the solve reads must already exist (built by aux_setup,
+        // aux_set_precision and aux_set_operator): nothing is allocated here
+        const bool mixed = h->opt.precision == AUX_MIXED;
+        if ((mixed && (!h->fp32_ready || !h->w32.ready)) || (!mixed && !h->w64.ready) ||
+            (h->use_mf() && !h->mf_ready))
+            throw AuxError(AUX_ESTATE, "preconditioner data for the current precision or operator not built");
+        double *base = scratch_address(h->device);
+        aux_handle::CgBufs cb{base + kScratchPartials, base + kScratchScal, (int *)(base + kScratchState),
+                              base + kScratchHist, kNoAllocHist};
+        // kernel timing would create events: not recorded by this call
+        const bool prof = h->prof_on;
+        h->prof_on = false;
+        int st;
+        try {
+            st = h->pcg_run(cb, f, u, tol, maxit, info, false);
+        } catch (...) {
+            h->prof_on = prof;
+            throw;
+        }
+        h->prof_on = prof;
         HIPCHECK(hipGetLastError());
         return st;
     });
