@@ -78,6 +78,9 @@ def _load():
     lib.orc_fgmres.argtypes = [vp, ctypes.c_int, _f64p, _f64p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                vp, vp, _f64p]
     lib.orc_kappa_grad.argtypes = [vp, _f64p, _f64p, _f64p]
+    lib.orc_block_pcg.restype = ctypes.c_int
+    lib.orc_block_pcg.argtypes = [vp, ctypes.c_int, ctypes.c_int, _f64p, _f64p, ctypes.c_double, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_int), _f64p]
     lib.orc_gauss_jacobi.argtypes = [ctypes.c_int, ctypes.c_int, _f64p, _f64p]
     lib.orc_tet_rule.argtypes = [ctypes.c_int, _f64p, _f64p]
     lib.orc_local_multi_indices.argtypes = [ctypes.c_int, _i32p]
@@ -305,6 +308,20 @@ class Problem:
         st = _load().orc_pcg(self._h, int(fp32), np.ascontiguousarray(b, dtype=np.float64), x, tol,
                              maxit, ctypes.byref(it), ctypes.byref(rr))
         return x, it.value, rr.value, st
+
+    def block_pcg(self, F, tol=1e-8, maxit=1000, X0=None, fp32: bool = False):
+        """O'Leary's block preconditioned CG on A_h X = F (F [n, s]); stops
+        when every column meets ||r_j|| <= tol ||f_j||.  Returns (X,
+        iterations, per-column relative residuals, status: 0 converged,
+        1 maxit, 2 breakdown, 3 NaN)."""
+        assert self._amg, "call setup_amg first"
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        s = F.shape[1]
+        X = np.zeros_like(F) if X0 is None else np.array(X0, dtype=np.float64)
+        it = ctypes.c_int(0)
+        rel = np.zeros(s)
+        st = _load().orc_block_pcg(self._h, int(fp32), s, F, X, tol, maxit, ctypes.byref(it), rel)
+        return X, it.value, rel, st
 
     def fgmres(self, b, tol=1e-6, restart=30, maxit=1000, x0=None, prec: str = "fp64"):
         """Flexible GMRES(restart), stopping at ||r|| <= tol ||r_0||.  prec is

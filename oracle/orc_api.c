@@ -18,6 +18,8 @@ int orc_pcg(const orc *o, int fp32, const double *b, double *x, double tol, int 
 int orc_fgmres(const orc *o, int prec, const double *b, double *x, double tol, int m, int maxit,
                int *iters, double *relres, double *hist);
 int orc_kappa_grad(const orc *o, const double *u, const double *lam, double *g);
+int orc_block_pcg(const orc *o, int fp32, int s, const double *F, double *X, double tol, int maxit,
+                  int *iters, double *relres);
 
 void orc_free(orc *o)
 {

@@ -276,6 +276,169 @@ done:
     return status;
 }
 
+/* Cholesky factor of a small dense SPD matrix (s x s, row-major) in place
+   (lower triangle); returns 0, or -1 if a pivot is not positive. */
+static int small_cholesky(int s, double *M)
+{
+    for (int j = 0; j < s; j++) {
+        double d = M[j * s + j];
+        for (int p = 0; p < j; p++) d -= M[j * s + p] * M[j * s + p];
+        if (!(d > 0.0)) return -1;
+        d = sqrt(d);
+        M[j * s + j] = d;
+        for (int i = j + 1; i < s; i++) {
+            double t = M[i * s + j];
+            for (int p = 0; p < j; p++) t -= M[i * s + p] * M[j * s + p];
+            M[i * s + j] = t / d;
+        }
+    }
+    return 0;
+}
+
+/* Y = M^{-1} Y for the Cholesky factor L of M (L L^T Y = Y), Y s x s row-major */
+static void small_cholesky_solve(int s, const double *L, double *Y)
+{
+    for (int c = 0; c < s; c++) {
+        for (int i = 0; i < s; i++) {
+            double t = Y[i * s + c];
+            for (int p = 0; p < i; p++) t -= L[i * s + p] * Y[p * s + c];
+            Y[i * s + c] = t / L[i * s + i];
+        }
+        for (int i = s - 1; i >= 0; i--) {
+            double t = Y[i * s + c];
+            for (int p = i + 1; p < s; p++) t -= L[p * s + i] * Y[p * s + c];
+            Y[i * s + c] = t / L[i * s + i];
+        }
+    }
+}
+
+/* G = U^T V for blocks U, V of n rows and s columns (row-major [n][s]) */
+static void block_gram(int n, int s, const double *U, const double *V, double *G)
+{
+    for (int a = 0; a < s; a++)
+        for (int b = 0; b < s; b++) {
+            double t = 0.0;
+            for (int i = 0; i < n; i++) t += U[(size_t)i * s + a] * V[(size_t)i * s + b];
+            G[a * s + b] = t;
+        }
+}
+
+/* Per-column relative residuals ||r_j|| / ||f_j|| of a block R; returns 3 on
+   a NaN, 0 when every column with f_j != 0 meets tol, 1 otherwise. */
+static int block_status(int n, int s, const double *R, const double *fn, double tol, double *relres)
+{
+    int ok = 1, bad = 0;
+    for (int j = 0; j < s; j++) {
+        double r2 = 0.0;
+        for (int i = 0; i < n; i++) r2 += R[(size_t)i * s + j] * R[(size_t)i * s + j];
+        relres[j] = fn[j] > 0.0 ? sqrt(r2) / fn[j] : 0.0;
+        if (isnan(r2)) bad = 1;
+        if (fn[j] > 0.0 && !(sqrt(r2) <= tol * fn[j])) ok = 0;
+    }
+    return bad ? 3 : (ok ? 0 : 1);
+}
+
+/* Block preconditioned CG (O'Leary 1980) on A_h X = F with s right-hand
+   sides, blocks row-major [n][s], the preconditioner B applied column by
+   column.  With gamma = Z^T R and delta = P^T A P (s x s):
+       alpha = delta^{-1} gamma,  X += P alpha,  R -= A P alpha,
+       Z = B R,  beta = gamma^{-1} gamma_new,  P = Z + P beta.
+   Every column's iterate lies in the sum of the block Krylov spaces of all
+   columns.  Stops when every column has ||r_j|| <= tol ||f_j|| (columns with
+   f_j = 0 count as converged), after maxit iterations (status 1), on a
+   non-positive pivot of delta or gamma (status 2, breakdown) or a NaN (3).
+   relres[j] receives each column's final relative residual. */
+int orc_block_pcg(const orc *o, int fp32, int s, const double *F, double *X, double tol, int maxit,
+                  int *iters, double *relres)
+{
+    int n = o->ndof, status = 1, it = 0;
+    if (s < 1) return -1;
+    bops B;
+    bops_init(o, fp32, &B);
+    size_t ns = (size_t)n * s;
+    double *R = malloc(ns * sizeof(double)), *Z = malloc(ns * sizeof(double));
+    double *P = malloc(ns * sizeof(double)), *Q = malloc(ns * sizeof(double));
+    double *col = malloc((size_t)n * sizeof(double)), *out = malloc((size_t)n * sizeof(double));
+    double *gam = malloc((size_t)s * s * sizeof(double)), *gnew = malloc((size_t)s * s * sizeof(double));
+    double *del = malloc((size_t)s * s * sizeof(double)), *coef = malloc((size_t)s * s * sizeof(double));
+    double *fn = malloc((size_t)s * sizeof(double)), *Lg = malloc((size_t)s * s * sizeof(double));
+    double *tmp = malloc((size_t)s * sizeof(double));
+
+    /* R = F - A X, column by column */
+    for (int j = 0; j < s; j++) {
+        for (int i = 0; i < n; i++) col[i] = X[(size_t)i * s + j];
+        spmv(&o->A, col, out);
+        double f2 = 0.0;
+        for (int i = 0; i < n; i++) {
+            R[(size_t)i * s + j] = F[(size_t)i * s + j] - out[i];
+            f2 += F[(size_t)i * s + j] * F[(size_t)i * s + j];
+        }
+        fn[j] = sqrt(f2);
+    }
+    int c = block_status(n, s, R, fn, tol, relres);
+    if (c != 1) { status = c; goto done; }
+    /* Z = B R; gamma = Z^T R; P = Z */
+    for (int j = 0; j < s; j++) {
+        for (int i = 0; i < n; i++) col[i] = R[(size_t)i * s + j];
+        apply_B(o, &B, col, out);
+        for (int i = 0; i < n; i++) Z[(size_t)i * s + j] = out[i];
+    }
+    block_gram(n, s, Z, R, gam);
+    memcpy(P, Z, ns * sizeof(double));
+    while (it < maxit) {
+        /* Q = A P; delta = P^T Q; alpha = delta^{-1} gamma */
+        for (int j = 0; j < s; j++) {
+            for (int i = 0; i < n; i++) col[i] = P[(size_t)i * s + j];
+            spmv(&o->A, col, out);
+            for (int i = 0; i < n; i++) Q[(size_t)i * s + j] = out[i];
+        }
+        block_gram(n, s, P, Q, del);
+        if (small_cholesky(s, del)) { status = 2; break; }
+        memcpy(coef, gam, (size_t)s * s * sizeof(double));
+        small_cholesky_solve(s, del, coef);
+        /* X += P alpha; R -= Q alpha */
+        for (int i = 0; i < n; i++)
+            for (int b = 0; b < s; b++) {
+                double px = 0.0, qx = 0.0;
+                for (int a = 0; a < s; a++) {
+                    px += P[(size_t)i * s + a] * coef[a * s + b];
+                    qx += Q[(size_t)i * s + a] * coef[a * s + b];
+                }
+                X[(size_t)i * s + b] += px;
+                R[(size_t)i * s + b] -= qx;
+            }
+        it++;
+        c = block_status(n, s, R, fn, tol, relres);
+        if (c != 1) { status = c; break; }
+        /* Z = B R; beta = gamma^{-1} gamma_new; P = Z + P beta */
+        for (int j = 0; j < s; j++) {
+            for (int i = 0; i < n; i++) col[i] = R[(size_t)i * s + j];
+            apply_B(o, &B, col, out);
+            for (int i = 0; i < n; i++) Z[(size_t)i * s + j] = out[i];
+        }
+        block_gram(n, s, Z, R, gnew);
+        memcpy(Lg, gam, (size_t)s * s * sizeof(double));
+        if (small_cholesky(s, Lg)) { status = 2; break; }
+        memcpy(coef, gnew, (size_t)s * s * sizeof(double));
+        small_cholesky_solve(s, Lg, coef);
+        for (int i = 0; i < n; i++) {
+            for (int b = 0; b < s; b++) {
+                double t = 0.0;
+                for (int a = 0; a < s; a++) t += P[(size_t)i * s + a] * coef[a * s + b];
+                tmp[b] = t;
+            }
+            for (int b = 0; b < s; b++) P[(size_t)i * s + b] = Z[(size_t)i * s + b] + tmp[b];
+        }
+        memcpy(gam, gnew, (size_t)s * s * sizeof(double));
+    }
+done:
+    if (iters) *iters = it;
+    free(R); free(Z); free(P); free(Q); free(col); free(out); free(gam); free(gnew); free(del);
+    free(coef); free(fn); free(Lg); free(tmp);
+    bops_free(&B);
+    return status;
+}
+
 int orc_element_matrix(const orc *o, int t, double *K);
 
 /* dL/dlog(kappa_t) = -lam_t^T K_t u_t for L(u) with A u = f and

@@ -59,6 +59,18 @@ PLANTS = {
           "                if (cf[j] == 0 && !beats(nst, rho, i, j)) best = 0;\n"
           "            }\n", "")],
         ["test_oracle_amg.py::test_pmis_rounds"]),
+    # block CG: the s x s step alpha = delta^{-1} gamma applied transposed
+    "block_cg_alpha_transposed": (
+        [("orc_solve.c", "                    px += P[(size_t)i * s + a] * coef[a * s + b];\n"
+                         "                    qx += Q[(size_t)i * s + a] * coef[a * s + b];",
+          "                    px += P[(size_t)i * s + a] * coef[b * s + a];\n"
+          "                    qx += Q[(size_t)i * s + a] * coef[b * s + a];")],
+        ["test_oracle_block_cg.py::test_block_krylov_projection"]),
+    # block CG: beta = gamma_new instead of gamma^{-1} gamma_new
+    "block_cg_beta_without_gamma_inverse": (
+        [("orc_solve.c", "        small_cholesky_solve(s, Lg, coef);", "")],
+        ["test_oracle_block_cg.py::test_block_krylov_projection",
+         "test_oracle_block_cg.py::test_one_column_is_cg"]),
     # FGMRES: sign of the rotated right-hand side
     "fgmres_givens_rhs_sign": (
         [("orc_solve.c", "g[j + 1] = -sn[j] * g[j];", "g[j + 1] = sn[j] * g[j];")],
