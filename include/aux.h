@@ -279,6 +279,27 @@ int pcg_solve_noalloc(aux_handle *h, const double *f, double *u, double tol, int
 int pcg_solve_batched(aux_handle *h, const double *F, double *U, int nrhs, double tol, int maxit,
                       aux_solve_info *infos);
 
+/* Block preconditioned CG (O'Leary, "The block conjugate gradient algorithm
+ * and related methods", 1980) on A_h X = F for nrhs (1 to 64) right-hand
+ * sides with the preconditioner B of every column: every column's iterate
+ * lies in the sum of the block Krylov spaces of all columns, so the block
+ * converges in at most as many steps as its slowest column does alone.
+ * With gamma = Z^T R and delta = P^T A_h P (nrhs x nrhs):
+ *   alpha = delta^{-1} gamma, X += P alpha, R -= A_h P alpha, Z = B R,
+ *   beta = gamma^{-1} gamma_new, P = Z + P beta.
+ * F, U: device row-major [n_h][nrhs]; U is the initial guess in and the
+ * block out.  Stops when every column with f_j != 0 has ||r_j||_2 <= tol
+ * ||f_j||_2 (recursive residual), after maxit steps (AUX_ENOTCONV), on a
+ * non-positive pivot of delta or gamma (AUX_EBREAKDOWN: the columns of the
+ * residual block became linearly dependent, e.g. a zero or repeated
+ * right-hand side, or a tolerance near rounding) or a non-finite value
+ * (AUX_ENAN).  infos (host [nrhs] or NULL): the common step count and each
+ * column's relative residual.  Synchronises the stream a few times per step
+ * (the nrhs x nrhs solves run on the host).  The 4 GiB block limit of
+ * pcg_solve_batched applies. */
+int pcg_solve_block(aux_handle *h, const double *F, double *U, int nrhs, double tol, int maxit,
+                    aux_solve_info *infos);
+
 /* Flexible GMRES(restart) on A_h x = b with the same preconditioner B, the
  * Krylov method of the paper's experiments (Sec. 6.1; Saad's flexible
  * variant, right preconditioning, so B in FP32 is allowed to vary).  b, x:

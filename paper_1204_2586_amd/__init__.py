@@ -134,6 +134,7 @@ def load_library():
         "aux_apply": (ctypes.c_int, [vp, vp, vp]),
         "pcg_solve": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, P(_SolveInfo)]),
         "pcg_solve_noalloc": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, P(_SolveInfo)]),
+        "pcg_solve_block": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, dbl, ctypes.c_int, P(_SolveInfo)]),
         "pcg_solve_batched": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, dbl, ctypes.c_int, P(_SolveInfo)]),
         "fgmres_solve": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int, vp, P(_SolveInfo)]),
         "aux_matvec": (ctypes.c_int, [vp, vp, vp]),
@@ -458,6 +459,26 @@ class Solver:
                                               nrhs, tol, int(maxit), infos)
         self.info = self._info()                  # the layout chosen for this block width
         if check:
+            _check(rc)
+        return U, [SolveInfo(i.iterations, i.status, i.rel_residual, i.seconds) for i in infos]
+
+    def solve_block(self, F, tol: float = 1e-8, U0=None, maxit: int = 0, check: bool = True):
+        """O'Leary's block preconditioned CG on the nrhs columns of F
+        ([n_h, nrhs] float64 device tensor, nrhs <= 64).  Returns (U, [SolveInfo])."""
+        t = self._torch
+        if F.dim() != 2:
+            raise ValueError("F must be [n_h, nrhs]")
+        nrhs = F.shape[1]
+        F = self._vec(F, "F", ncols=nrhs)
+        U = t.zeros_like(F) if U0 is None else self._vec(U0, "U0", ncols=nrhs).clone()
+        infos = (_SolveInfo * nrhs)()
+        self._sync_stream()
+        rc = load_library().pcg_solve_block(self._h, ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(U.data_ptr()),
+                                            nrhs, tol, int(maxit), infos)
+        self.info = self._info()
+        if check:
+            _check(rc)
+        elif rc not in (0, -4, -5, -6):
             _check(rc)
         return U, [SolveInfo(i.iterations, i.status, i.rel_residual, i.seconds) for i in infos]
 

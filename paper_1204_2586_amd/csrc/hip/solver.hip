@@ -21,6 +21,7 @@
 #include "../host/setup.hpp"
 #include "aux.h"
 #include "batched.hpp"
+#include "blockcg.hpp"
 #include "kernels.hpp"
 #include "krylov.hpp"
 #include "mfree.hpp"
@@ -1735,6 +1736,208 @@ struct aux_handle {
         return worst;
     }
 
+    // ------------------------------------------------------------ block CG
+    // O'Leary's block preconditioned CG on the batched block buffers: with
+    // gamma = Z^T R and delta = P^T A P, alpha = delta^{-1} gamma,
+    // X += P alpha, R -= A P alpha, Z = B R, beta = gamma^{-1} gamma_new,
+    // P = Z + P beta.  The nrhs x nrhs Cholesky solves run on the host from
+    // one pinned copy of each Gram matrix per step; the padded columns of the
+    // block (zero right-hand sides) get zero rows and columns in alpha and
+    // beta, so they stay zero.
+    struct BlockCg {
+        double *gram_part = nullptr, *G = nullptr, *coef = nullptr, *colsum = nullptr;
+        double *host = nullptr;        // pinned: gram [nr*nr], coef [nr*nr], colsum [nr]
+        int nr = 0;
+    } bk;
+
+    void ensure_block(int nr)
+    {
+        if (bk.nr == nr) return;
+        dfree(bk.gram_part);
+        dfree(bk.G);
+        dfree(bk.coef);
+        dfree(bk.colsum);
+        bk.gram_part = dnew<double>((size_t)kBlockGramParts * nr * nr);
+        bk.G = dnew<double>((size_t)nr * nr);
+        bk.coef = dnew<double>((size_t)nr * nr);
+        bk.colsum = dnew<double>((size_t)nr);
+        if (!bk.host) {
+            HIPCHECK(hipHostMalloc((void **)&bk.host, (2 * 64 * 64 + 64) * sizeof(double), hipHostMallocDefault));
+            host_bufs.push_back(bk.host);
+        }
+        bk.nr = nr;
+    }
+
+    // Cholesky of the leading s x s block of M (row-major, stride nr) in place
+    static bool host_cholesky(int s, int nr, double *M)
+    {
+        for (int j = 0; j < s; j++) {
+            double d = M[j * nr + j];
+            for (int p = 0; p < j; p++) d -= M[j * nr + p] * M[j * nr + p];
+            if (!(d > 0.0) || !std::isfinite(d)) return false;
+            d = std::sqrt(d);
+            M[j * nr + j] = d;
+            for (int i = j + 1; i < s; i++) {
+                double t = M[i * nr + j];
+                for (int p = 0; p < j; p++) t -= M[i * nr + p] * M[j * nr + p];
+                M[i * nr + j] = t / d;
+            }
+        }
+        return true;
+    }
+    // C = M^{-1} Y on the leading s x s blocks (L the Cholesky factor of M),
+    // every other entry of C zero
+    static void host_cholesky_solve(int s, int nr, const double *L, const double *Y, double *C)
+    {
+        std::fill(C, C + (size_t)nr * nr, 0.0);
+        for (int c = 0; c < s; c++) {
+            for (int i = 0; i < s; i++) {
+                double t = Y[i * nr + c];
+                for (int p = 0; p < i; p++) t -= L[i * nr + p] * C[p * nr + c];
+                C[i * nr + c] = t / L[i * nr + i];
+            }
+            for (int i = s - 1; i >= 0; i--) {
+                double t = C[i * nr + c];
+                for (int p = i + 1; p < s; p++) t -= L[p * nr + i] * C[p * nr + c];
+                C[i * nr + c] = t / L[i * nr + i];
+            }
+        }
+    }
+
+    // Gram matrix U^T V of the block (U the z block in its precision or an
+    // FP64 block) into host memory
+    void block_gram_host(const void *U, bool u_f32, const double *V, double *host_out)
+    {
+        const int nr = bt.nr, n = disc.ndof;
+        if (u_f32) block_gram<float>(stream, nr, n, (const float *)U, V, bk.gram_part, bk.G);
+        else block_gram<double>(stream, nr, n, (const double *)U, V, bk.gram_part, bk.G);
+        HIPCHECK(hipMemcpyAsync(host_out, bk.G, (size_t)nr * nr * sizeof(double), hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+    }
+
+    // per-column squared norms of an FP64 block into host memory
+    void block_colnorms_host(const double *Y, double *host_out)
+    {
+        const int nr = bt.nr, n = disc.ndof;
+        BCgState st = bstate(1);
+        int g = bvec_dot(stream, nr, n, Y, Y, bt.partials);
+        bfinish(stream, nr, bt.partials, g, FIN_PLAIN, bk.colsum, st);
+        HIPCHECK(hipMemcpyAsync(host_out, bk.colsum, nr * sizeof(double), hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+    }
+
+    int block_pcg(const double *Fext, double *Uext, int nrhs, double tol, int maxit, aux_solve_info *infos)
+    {
+        auto t0 = std::chrono::steady_clock::now();
+        if (maxit <= 0) maxit = opt.maxit;
+        int nr = 8;
+        while (nr < nrhs) nr *= 2;
+        if (nr > 64) throw AuxError(AUX_EINVAL, "block CG takes at most 64 right-hand sides");
+        if ((uint64_t)disc.ndof * nr * sizeof(double) > (uint64_t(1) << 32))
+            throw AuxError(AUX_EINVAL, "block of n_h x " + std::to_string(nr) +
+                                           " doubles exceeds 4 GiB; solve fewer right-hand sides per call");
+        ensure_batch(nr, 1);
+        ensure_block(nr);
+        ensure_bops();
+        const bool mixed = opt.precision == AUX_MIXED;
+        if (mixed) ensure_fp32();
+        hipStream_t s = stream;
+        const int n = disc.ndof;
+        DevSellView A64 = A.view<double>();
+        const DevTiles *tl = tiles_for<double>(nr);
+        bgather(s, nr, n, nrhs, perm, Fext, bt.F);
+        bgather(s, nr, n, nrhs, perm, Uext, bt.X);
+        if (tl) btile_residual64(s, nr, tl->view<double>(), bt.F, bt.X, bt.R);
+        else bsell_residual64(s, nr, A64, bt.F, bt.X, bt.R);
+        double *gam = bk.host, *tmp = bk.host + 64 * 64, *cols = bk.host + 2 * 64 * 64;
+        std::vector<double> ff(nr), rr(nr), gcur((size_t)nr * nr), coef((size_t)nr * nr);
+        block_colnorms_host(bt.F, cols);
+        std::copy(cols, cols + nr, ff.begin());
+        block_colnorms_host(bt.R, cols);
+        std::copy(cols, cols + nr, rr.begin());
+        auto status_of = [&]() {
+            bool ok = true;
+            for (int c = 0; c < nrhs; c++) {
+                if (!std::isfinite(rr[c])) return 3;
+                if (ff[c] > 0.0 && !(rr[c] <= tol * tol * ff[c])) ok = false;
+            }
+            return ok ? 0 : 1;
+        };
+        int it = 0, status = status_of();
+        prof_tag = 0;
+        if (status == 1) {
+            // Z = B R, gamma = Z^T R, P = Z
+            bapply(bt.R, nullptr, nullptr);
+            block_gram_host(bt.Z, mixed, bt.R, gam);
+            std::copy(gam, gam + (size_t)nr * nr, gcur.begin());
+            if (mixed) block_direction<float>(s, nr, n, (const float *)bt.Z, bt.P, nullptr, true);
+            else block_direction<double>(s, nr, n, bt.Z, bt.P, nullptr, true);
+            while (it < maxit) {
+                prof_tag = it + 1;
+                // Q = A P; delta = P^T Q; alpha = delta^{-1} gamma
+                int pk = pbeg(AUX_PROF_CG_SPMV);
+                if (tl) btile_spmv64(s, nr, tl->view<double>(), bt.P, bt.Q, nullptr, nullptr);
+                else bsell_spmv64(s, nr, A64, bt.P, bt.Q, nullptr, nullptr);
+                pend(pk);
+                block_gram_host(bt.P, false, bt.Q, tmp);
+                if (!host_cholesky(nrhs, nr, tmp)) {
+                    status = 2;
+                    break;
+                }
+                host_cholesky_solve(nrhs, nr, tmp, gcur.data(), coef.data());
+                std::copy(coef.begin(), coef.end(), tmp);
+                HIPCHECK(hipMemcpyAsync(bk.coef, tmp, (size_t)nr * nr * sizeof(double), hipMemcpyHostToDevice, s));
+                // X += P alpha, R -= Q alpha, r.r per column, Z0 = D^-1 R
+                int g;
+                if (mixed) {
+                    Work<float> &w = bwork<float>();
+                    g = block_update<float>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, bk.coef, bt.partials, dinv32, w.za, w.rT);
+                } else {
+                    Work<double> &w = bwork<double>();
+                    g = block_update<double>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, bk.coef, bt.partials, dinv64, w.za,
+                                             nullptr);
+                }
+                BCgState st = bstate(1);
+                bfinish(s, nr, bt.partials, g, FIN_PLAIN, bk.colsum, st);
+                HIPCHECK(hipMemcpyAsync(cols, bk.colsum, nr * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHECK(hipStreamSynchronize(s));
+                std::copy(cols, cols + nr, rr.begin());
+                it++;
+                status = status_of();
+                if (status != 1) break;
+                // Z = B R (its first sweep came with the update); beta =
+                // gamma^{-1} gamma_new; P = Z + P beta
+                bapply(bt.R, nullptr, nullptr, true);
+                block_gram_host(bt.Z, mixed, bt.R, gam);
+                std::copy(gcur.begin(), gcur.end(), tmp);
+                if (!host_cholesky(nrhs, nr, tmp)) {
+                    status = 2;
+                    break;
+                }
+                host_cholesky_solve(nrhs, nr, tmp, gam, coef.data());
+                std::copy(gam, gam + (size_t)nr * nr, gcur.begin());
+                std::copy(coef.begin(), coef.end(), tmp);
+                HIPCHECK(hipMemcpyAsync(bk.coef, tmp, (size_t)nr * nr * sizeof(double), hipMemcpyHostToDevice, s));
+                if (mixed) block_direction<float>(s, nr, n, (const float *)bt.Z, bt.P, bk.coef, false);
+                else block_direction<double>(s, nr, n, bt.Z, bt.P, bk.coef, false);
+            }
+        }
+        bscatter(s, nr, n, nrhs, perm, bt.X, Uext);
+        prof_tag = -1;
+        prof_collect(it + 1);
+        HIPCHECK(hipStreamSynchronize(s));
+        const int code = status == 0 ? AUX_OK : status == 2 ? AUX_EBREAKDOWN : status == 3 ? AUX_ENAN : AUX_ENOTCONV;
+        const double secs = seconds_since(t0);
+        if (infos)
+            for (int c = 0; c < nrhs; c++) {
+                infos[c].iterations = it;
+                infos[c].status = code;
+                infos[c].rel_residual = ff[c] > 0 ? std::sqrt(rr[c] / ff[c]) : 0.0;
+                infos[c].seconds = secs;
+            }
+        return code;
+    }
+
     void apply_external(const double *rext, double *zext)
     {
         int n = disc.ndof;
@@ -2153,6 +2356,21 @@ int pcg_solve_noalloc(aux_handle *h, const double *f, double *u, double tol, int
             throw;
         }
         h->prof_on = prof;
+        HIPCHECK(hipGetLastError());
+        return st;
+    });
+}
+
+int pcg_solve_block(aux_handle *h, const double *F, double *U, int nrhs, double tol, int maxit,
+                    aux_solve_info *infos)
+{
+    return guarded([&]() {
+        need_device(h);
+        if (!F || !U) throw AuxError(AUX_EINVAL, "null block");
+        if (nrhs < 1 || nrhs > 64) throw AuxError(AUX_EINVAL, "nrhs must be in [1, 64]");
+        if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
+        set_dev(h);
+        int st = h->block_pcg(F, U, nrhs, tol, maxit, infos);
         HIPCHECK(hipGetLastError());
         return st;
     });
