@@ -188,6 +188,182 @@ def kernel_table(prof, args, s, wl, nt):
     return kernels
 
 
+def host_cpu():
+    """Model name of the host CPU and the number of logical CPUs this process
+    may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def timed_solves(s, f, u, args, mode):
+    """K unprofiled solves (each CG iteration replayed as a HIP graph; the
+    throughput figures come from these), then the same K solves with HIP
+    events around every launch for the per-kernel durations."""
+    import torch
+    s.set_precision(mode)
+    for _ in range(args.warmup):
+        s.solve(f, tol=args.tol, out=u)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    its = []
+    for _ in range(args.steps):
+        _, info = s.solve(f, tol=args.tol, out=u)
+        its.append(info.iterations)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    sol = u.clone()
+    true_res = float(torch.linalg.norm(f - s.matvec(sol)) / torch.linalg.norm(f))
+    s.profile(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        s.solve(f, tol=args.tol, out=u)
+    torch.cuda.synchronize()
+    ms_prof = (time.perf_counter() - t) * 1e3 / args.steps
+    prof = s.profile_read()
+    s.profile(False)
+    return dict(ms=ms, ms_profiled=ms_prof, iterations=its, true_rel_residual=true_res, prof=prof, u=sol)
+
+
+def measure_single(s, f, args, wl, nt, operator):
+    """Mixed and FP64 timed solves of one system with one operator, the
+    dominant kernel's roofline and the whole preconditioner's bandwidth."""
+    import torch
+    s.set_operator(operator)
+    u = torch.zeros_like(f)
+    mixed = timed_solves(s, f, u, args, "mixed")
+    fp64 = timed_solves(s, f, u, args, "fp64")
+    ka = argparse.Namespace(operator=operator)
+    kernels = kernel_table(mixed["prof"], ka, s, wl, nt)
+    dom = max(kernels, key=lambda c: kernels[c]["total_ms"])
+    kd = kernels[dom]
+    precond = {}
+    for name, res, sz in (("mixed", mixed, 4), ("fp64", fp64, 8)):
+        cnt, tot = res["prof"]["apply"]
+        us = tot / max(cnt, 1) * 1e3
+        entry = {"us": us}
+        if operator == "assembled":
+            ab = apply_bytes(s.info, sz, args.nu, first=res["prof"].get("pk_first", (0, 0))[0] > 0)
+            entry.update(bytes=ab, gbs=ab / (us * 1e-6) / 1e9, frac=ab / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+        precond[name] = entry
+    return dict(mixed=mixed, fp64=fp64, kernels=kernels, dom=dom, kd=kd, precond=precond)
+
+
+def roofline_entry(workload, operator, m):
+    kd = m["kd"]
+    return {"bound": "hbm", "kernel": m["dom"], "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(workload, operator, m["dom"], "mixed"),
+            "bytes_per_launch": kd["bytes"], "avg_us": kd["avg_us"]}
+
+
+def rel_err(u_gpu, x_ref):
+    import numpy as np
+    x = np.asarray(x_ref)
+    return float(np.linalg.norm(u_gpu.cpu().numpy() - x) / np.linalg.norm(x))
+
+
+def oracle_reference(xyz, tets, wl, kappa, args, reps):
+    """The CPU oracle (single-threaded FP64 C) on the same system, with its
+    own load vector of the manufactured source: `reps` timed CG solves to the
+    benchmark's tolerance from u = 0 on one core (median reported; its setup
+    is not timed), and one untimed solve to 1e-13, the discrete solution
+    within rounding.  Returns the timing entry and both oracle solutions."""
+    import statistics
+
+    import oracle
+    import workloads as W
+    t0 = time.time()
+    P = oracle.Problem(xyz, tets, wl["k"], kappa).setup_amg(nu=args.nu)
+    b = P.load(W.manufactured_f)
+    setup = time.time() - t0
+    model, ncpu = host_cpu()
+    keep = os.sched_getaffinity(0)
+    one = {min(keep)}
+    times = []
+    os.sched_setaffinity(0, one)             # the oracle is single-threaded: one core
+    try:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            x, it, rr, st = P.pcg(b, tol=args.tol)
+            times.append(time.perf_counter() - t0)
+        x_tight, it_tight, _, _ = P.pcg(b, tol=1e-13)
+    finally:
+        os.sched_setaffinity(0, keep)
+    dt = statistics.median(times)
+    entry = {"value": P.n / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+             "cpu_model": model, "host_cpus": ncpu, "repeats": reps,
+             "seconds": [round(v, 2) for v in times], "iterations": it,
+             "sample": f"median of {reps} FP64 CG solves of the full {args.workload_name} system (n_h={P.n}) "
+                       f"to {args.tol:g}, {it} iterations, {dt:.1f} s each, pinned to one core; oracle setup "
+                       f"{setup:.1f} s and a 1e-13 reference solve ({it_tight} iterations) not timed"}
+    return entry, x, x_tight
+
+
+def oracle_errors(res, x, x_tight):
+    """Each GPU result against the FP64 oracle: its solution at the same
+    tolerance and its 1e-13 solution (the discrete solution)."""
+    return {"mixed_vs_oracle_rel_err": rel_err(res["mixed"]["u"], x),
+            "fp64_vs_oracle_rel_err": rel_err(res["fp64"]["u"], x),
+            "mixed_vs_discrete_solution_rel_err": rel_err(res["mixed"]["u"], x_tight),
+            "fp64_vs_discrete_solution_rel_err": rel_err(res["fp64"]["u"], x_tight)}
+
+
+def single_summary(name, operator, n, m, errs=None):
+    mixed, fp64 = m["mixed"], m["fp64"]
+    d = {"operator": operator, "n_h": n,
+         "mixed": {"ms": round(mixed["ms"], 3), "dof_per_s": n / (mixed["ms"] * 1e-3),
+                   "iterations": mixed["iterations"][-1], "true_rel_residual": mixed["true_rel_residual"]},
+         "fp64": {"ms": round(fp64["ms"], 3), "dof_per_s": n / (fp64["ms"] * 1e-3),
+                  "iterations": fp64["iterations"][-1], "true_rel_residual": fp64["true_rel_residual"]},
+         "roofline": roofline_entry(name, operator, m),
+         "precond_apply": m["precond"],
+         "kernels_mixed": {c: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in dd.items()}
+                           for c, dd in m["kernels"].items()}}
+    if errs:
+        d.update(errs)
+    return d
+
+
+def run_extra_p3(args):
+    """P3 on 32^3 cubes with kappa = exp(GRF seed 1): assembled and
+    matrix-free, each mixed and FP64, against one oracle solve."""
+    import numpy as np
+    import torch
+
+    import paper_1204_2586_amd as aux
+    import workloads as W
+    name = "p3_n32_grf"
+    wl = WORKLOADS[name]
+    xyz, tets = W.kuhn_mesh(wl["n"], jitter=wl["jitter"], seed=wl["seed"])
+    kappa = np.exp(W.grf_log_kappa(xyz, tets, seed=wl["kappa"]))
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    s = aux.Solver(xyz, tets, wl["k"], kappa, nu=args.nu, precision="mixed", device=dev)
+    setup_s = time.time() - t0
+    b = s.load(W.manufactured_f)
+    f = torch.tensor(b, dtype=torch.float64, device=dev)
+    out = {"order": wl["k"], "cubes_per_side": wl["n"], "kappa": "exp(GRF seed 1)", "n_h": s.n,
+           "nnz_A": int(s.info.nnz_A), "setup_s": round(setup_s, 2)}
+    ms = {op: measure_single(s, f, args, wl, len(tets), op) for op in ("assembled", "matfree")}
+    s.set_operator("assembled")
+    ref = None
+    if not args.no_cpu_baseline:
+        a = argparse.Namespace(**vars(args))
+        a.workload_name = name
+        ref = oracle_reference(xyz, tets, wl, kappa, a, reps=1)
+        out["cpu_baseline"] = ref[0]
+    for op, m in ms.items():
+        out[op] = single_summary(name, op, s.n, m, oracle_errors(m, ref[1], ref[2]) if ref else None)
+    return out
+
+
 def run(args):
     import numpy as np
     import torch
@@ -207,56 +383,11 @@ def run(args):
     setup_s = time.time() - t0
     b = s.load(W.manufactured_f)
     f = torch.tensor(b, dtype=torch.float64, device=dev)
-    u = torch.zeros_like(f)
     n, nnz = s.n, int(s.info.nnz_A)
 
-    def timed(mode):
-        """K unprofiled solves (each CG iteration replayed as a HIP graph):
-        the throughput figures come from these."""
-        s.set_precision(mode)
-        for _ in range(args.warmup):
-            s.solve(f, tol=args.tol, out=u)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        its = []
-        for _ in range(args.steps):
-            _, info = s.solve(f, tol=args.tol, out=u)
-            its.append(info.iterations)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t) * 1e3 / args.steps
-        sol = u.clone()
-        true_res = float(torch.linalg.norm(f - s.matvec(sol)) / torch.linalg.norm(f))
-        # the same K solves again with HIP events around every launch (eager
-        # launches): per-kernel durations for the roofline
-        s.profile(True)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(args.steps):
-            s.solve(f, tol=args.tol, out=u)
-        torch.cuda.synchronize()
-        ms_prof = (time.perf_counter() - t) * 1e3 / args.steps
-        prof = s.profile_read()
-        s.profile(False)
-        return dict(ms=ms, ms_profiled=ms_prof, iterations=its, true_rel_residual=true_res, prof=prof, u=sol)
-
-    mixed = timed("mixed")
-    fp64 = timed("fp64")
+    m = measure_single(s, f, args, wl, len(tets), args.operator)
+    mixed, fp64, kd = m["mixed"], m["fp64"], m["kd"]
     diff = float(torch.linalg.norm(mixed["u"] - fp64["u"]) / torch.linalg.norm(fp64["u"]))
-
-    # roofline of the dominant kernel of the timed (mixed) solve
-    kernels = kernel_table(mixed["prof"], args, s, wl, len(tets))
-    dom = max(kernels, key=lambda c: kernels[c]["total_ms"])
-    kd = kernels[dom]
-    # whole preconditioner application: algorithmic bytes over its measured time
-    precond = {}
-    for name, res, sz in (("mixed", mixed, 4), ("fp64", fp64, 8)):
-        cnt, tot = res["prof"]["apply"]
-        us = tot / max(cnt, 1) * 1e3
-        entry = {"us": us}
-        if args.operator == "assembled":
-            ab = apply_bytes(s.info, sz, args.nu, first=res["prof"].get("pk_first", (0, 0))[0] > 0)
-            entry.update(bytes=ab, gbs=ab / (us * 1e-6) / 1e9, frac=ab / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
-        precond[name] = entry
 
     out = {
         "metric": METRIC,
@@ -285,19 +416,37 @@ def run(args):
                  "iterations": fp64["iterations"][-1], "true_rel_residual": fp64["true_rel_residual"],
                  "mixed_vs_fp64_rel_diff": diff,
                  "speedup_mixed_over_fp64": fp64["ms"] / mixed["ms"]},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": kd["gbs"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, args.operator, dom, "mixed"),
-                     "bytes_per_launch": kd["bytes"], "avg_us": kd["avg_us"]},
+        "roofline": roofline_entry(args.workload, args.operator, m),
         "kernels_mixed": {c: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
-                          for c, d in kernels.items()},
-        "precond_apply": precond,
+                          for c, d in m["kernels"].items()},
+        "precond_apply": m["precond"],
     }
     # achievable HBM bandwidth on this device: plain 1 GiB device copies
     out["hbm_copy_gbs"] = round(calibrate_copy(reps=5)["copy_gbs"], 1)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(xyz, tets, wl, kappa, args)
+        a = argparse.Namespace(**vars(args))
+        a.workload_name = args.workload
+        entry, x, x_tight = oracle_reference(xyz, tets, wl, kappa, a, reps=3)
+        out["cpu_baseline"] = entry
+        out["oracle_error"] = oracle_errors(m, x, x_tight)
+    if args.extras:
+        # the metric's P3 case and the lock-step batch (the clean HBM case),
+        # each with its own roofline and oracle comparison
+        del s, m, mixed, fp64
+        torch.cuda.empty_cache()
+        out["workloads"] = {"p3_n32_grf": run_extra_p3(args)}
+        torch.cuda.empty_cache()
+        a = argparse.Namespace(**vars(args))
+        a.workload = "p2_n64_32rhs"
+        out["workloads"]["p2_n64_32rhs"] = summarize_batched(run_batched(a))
     return out
+
+
+def summarize_batched(r):
+    """The batched record as an entry of the default line."""
+    keys = ("value", "ms_per_step", "config", "fp64", "single_rhs_sequential", "roofline", "kernels_mixed",
+            "precond_apply_us", "cpu_baseline", "oracle_error")
+    return {k: r[k] for k in keys if k in r}
 
 
 def batched_bytes(cat, n, nnz, s, nr, fmt):
@@ -421,7 +570,10 @@ def run_batched(args):
         "precond_apply_us": {"mixed": tot / max(cnt, 1) * 1e3},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_single(xyz, tets, wl, args)
+        entry, x = cpu_baseline_single(xyz, tets, wl, args)
+        out["cpu_baseline"] = entry
+        out["oracle_error"] = {"column": 0, "mixed_vs_oracle_rel_err": rel_err(mixed["U"][:, 0], x),
+                               "fp64_vs_oracle_rel_err": rel_err(fp64["U"][:, 0], x)}
     return out
 
 
@@ -444,7 +596,8 @@ def calibrate_copy(nbytes=1 << 30, reps=3):
 
 def cpu_baseline_single(xyz, tets, wl, args):
     """The CPU oracle on one of the batched sources (column 0): one FP64 CG
-    solve at full size; the oracle's own setup and load vector are not timed."""
+    solve at full size on one core; the oracle's own setup and load vector
+    are not timed.  Returns the timing entry and the oracle's solution."""
     import numpy as np
 
     import oracle
@@ -459,12 +612,20 @@ def cpu_baseline_single(xyz, tets, wl, args):
         return out
 
     b = P.load(f)
-    t0 = time.perf_counter()
-    x, it, rr, st = P.pcg(b, tol=args.tol)
-    dt = time.perf_counter() - t0
-    return {"value": P.n / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"one FP64 CG solve of source 0 of {args.workload} (n_h={P.n}) to {args.tol:g}, "
-                      f"{it} iterations, {dt:.1f} s; the 32-source batch would take {32 * dt:.0f} s"}
+    model, ncpu = host_cpu()
+    keep = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {min(keep)})
+    try:
+        t0 = time.perf_counter()
+        x, it, rr, st = P.pcg(b, tol=args.tol)
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, keep)
+    entry = {"value": P.n / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle", "cpu_model": model,
+             "host_cpus": ncpu, "repeats": 1, "seconds": [round(dt, 2)], "iterations": it,
+             "sample": f"one FP64 CG solve of source 0 of {args.workload} (n_h={P.n}) to {args.tol:g} on one "
+                       f"core, {it} iterations, {dt:.1f} s; the 32-source batch would take {32 * dt:.0f} s"}
+    return entry, x
 
 
 def run_fgmres(args):
@@ -677,24 +838,6 @@ def run_adjoint(args):
     return out
 
 
-def cpu_baseline(xyz, tets, wl, kappa, args):
-    """The CPU oracle (single-threaded FP64 C) on the same system: one CG solve
-    to the same tolerance from u = 0; its setup and its own load vector are
-    not timed."""
-    import oracle
-    import workloads as W
-    t0 = time.time()
-    P = oracle.Problem(xyz, tets, wl["k"], kappa).setup_amg(nu=args.nu)
-    setup = time.time() - t0
-    b = P.load(W.manufactured_f)
-    t0 = time.perf_counter()
-    x, it, rr, st = P.pcg(b, tol=args.tol)
-    dt = time.perf_counter() - t0
-    return {"value": P.n / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"one FP64 CG solve of the full {args.workload} system (n_h={P.n}) to {args.tol:g}, "
-                      f"{it} iterations, {dt:.1f} s; oracle setup {setup:.1f} s not timed"}
-
-
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -712,6 +855,8 @@ def main():
     ap.add_argument("--operator", default="assembled", choices=["assembled", "matfree"],
                     help="P^k products inside the preconditioner: sliced-ELL A_h or the MFMA element operator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="with the default workload, skip the P3 32^3 and 32-source P2 64^3 entries of the line")
     ap.add_argument("--threads", type=int, default=16, help="host threads for the load vectors of the batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 1 GiB device-to-device copies (reference for HBM byte counters)")
@@ -725,6 +870,8 @@ def main():
         return
     if args.tol is None:
         args.tol = 1e-6 if args.krylov == "fgmres" else 1e-8
+    args.extras = (not args.no_extras and args.workload == "p2_n48_jitter" and args.krylov == "cg"
+                   and args.operator == "assembled")
     if args.krylov == "fgmres" and ("nrhs" in WORKLOADS[args.workload] or WORKLOADS[args.workload].get("adjoint")):
         print(json.dumps({"error": "FGMRES runs the single-vector solve workloads only"}))
         sys.exit(2)
