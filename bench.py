@@ -444,7 +444,7 @@ def run(args):
 
 def summarize_batched(r):
     """The batched record as an entry of the default line."""
-    keys = ("value", "ms_per_step", "config", "fp64", "single_rhs_sequential", "roofline", "kernels_mixed",
+    keys = ("value", "ms_per_step", "config", "fp64", "block_cg", "single_rhs_sequential", "roofline", "kernels_mixed",
             "precond_apply_us", "cpu_baseline", "oracle_error")
     return {k: r[k] for k in keys if k in r}
 
@@ -480,7 +480,8 @@ def run_batched(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
-    s = aux.Solver(xyz, tets, wl["k"], None, nu=args.nu, precision="mixed", device=dev)
+    s = aux.Solver(xyz, tets, wl["k"], None, nu=args.nu, precision="mixed", device=dev,
+                   batch_order=getattr(args, "batch_order", 0))
     setup_s = time.time() - t0
     t0 = time.time()
     B = s.load_many(W.fourier_fields(range(nrhs)), nrhs, threads=args.threads)
@@ -522,6 +523,19 @@ def run_batched(args):
     torch.cuda.synchronize()
     single_ms = (time.perf_counter() - t) * 1e3
     diff = float(torch.linalg.norm(mixed["U"] - fp64["U"]) / torch.linalg.norm(fp64["U"]))
+    # O'Leary's block CG on the same sources (FP32 preconditioner)
+    s.set_precision("mixed")
+    for _ in range(args.warmup):
+        s.solve_block(F, tol=args.tol)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        Ub, binfos = s.solve_block(F, tol=args.tol)
+    torch.cuda.synchronize()
+    block_ms = (time.perf_counter() - t) * 1e3 / args.steps
+    block_res = max(float(torch.linalg.norm(F[:, c] - s.matvec(Ub[:, c].contiguous())) / torch.linalg.norm(F[:, c]))
+                    for c in range(nrhs))
+    block_diff = float(torch.linalg.norm(Ub - fp64["U"]) / torch.linalg.norm(fp64["U"]))
 
     nr = 8
     while nr < nrhs:
@@ -556,10 +570,15 @@ def run_batched(args):
                    "iterations_min": min(mixed["its"]), "true_rel_residual_max": mixed["true_res"],
                    "setup_s": round(setup_s, 2), "load_s": round(load_s, 1), "sell_window": int(s.info.sell_window),
                    "batch_tile_rows": {"fp32": int(s.info.batch_tile_rows[0]), "fp64": int(s.info.batch_tile_rows[1])},
+                   "batch_order": getattr(args, "batch_order", 0),
                    "sell_16bit_slices": f"{int(s.info.sell_narrow_slices)}/{int(s.info.sell_slices)}"},
         "fp64": {"value": nrhs * n / (fp64["ms"] * 1e-3), "ms_per_step": fp64["ms"],
                  "iterations_max": max(fp64["its"]), "true_rel_residual_max": fp64["true_res"],
                  "mixed_vs_fp64_rel_diff": diff, "speedup_mixed_over_fp64": fp64["ms"] / mixed["ms"]},
+        "block_cg": {"ms_per_step": block_ms, "value": nrhs * n / (block_ms * 1e-3),
+                     "iterations": binfos[0].iterations, "true_rel_residual_max": block_res,
+                     "block_vs_lockstep_fp64_rel_diff": block_diff,
+                     "speedup_over_lockstep": mixed["ms"] / block_ms},
         "single_rhs_sequential": {"ms_for_all": single_ms, "value": nrhs * n / (single_ms * 1e-3),
                                   "iterations_max": max(single_its),
                                   "speedup_batched_over_sequential": single_ms / mixed["ms"]},
@@ -858,6 +877,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="with the default workload, skip the P3 32^3 and 32-source P2 64^3 entries of the line")
     ap.add_argument("--threads", type=int, default=16, help="host threads for the load vectors of the batch")
+    ap.add_argument("--batch-order", type=int, default=0, choices=[0, 1],
+                    help="dof order of the batched solve: 0 the single-vector order, 1 Morton curve with die ranges")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 1 GiB device-to-device copies (reference for HBM byte counters)")
     args = ap.parse_args()

@@ -122,6 +122,13 @@ typedef struct aux_options {
                                 applied as one dense product, in the single-vector and the
                                 batched solve; 0 turns it off; at most 8192; default 2048.
                                 Results agree to rounding */
+    int batch_order;         /* dof order of the batched and block solves: 0 (default) the order
+                                of the single-vector solve with slices round-robin over the dies;
+                                1 the dofs along the Morton curve of their node positions with
+                                rows sorted by length within windows of 2048 rows, each die of
+                                the GPU taking a contiguous range of A_h's slices (gathered
+                                block rows stay in one die's cache: fewer bytes fetched past L2,
+                                measured no faster).  Results agree to rounding */
 } aux_options;
 
 typedef struct aux_device {

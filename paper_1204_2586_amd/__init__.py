@@ -51,7 +51,8 @@ class _Options(ctypes.Structure):
                 ("maxit", ctypes.c_int), ("host_only", ctypes.c_int), ("op", ctypes.c_int),
                 ("sell_window", ctypes.c_int), ("graph", ctypes.c_int),
                 ("sell_index16", ctypes.c_int), ("fuse_cycle", ctypes.c_int),
-                ("batch_tiles", ctypes.c_int), ("cycle_lanes", ctypes.c_int), ("dense_cycle_rows", ctypes.c_int)]
+                ("batch_tiles", ctypes.c_int), ("cycle_lanes", ctypes.c_int), ("dense_cycle_rows", ctypes.c_int),
+                ("batch_order", ctypes.c_int)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -168,7 +169,7 @@ class Solver:
     (smoothing sweeps ``nu``, strength threshold ``theta``, coarsest size,
     precision, operator, layout window, graph replay, 16-bit columns, composite
     cycle, batched layout, V-cycle operator storage ``cycle_lanes``, dense
-    sub-cycle threshold ``dense_cycle_rows``); the defaults are the timed
+    sub-cycle threshold ``dense_cycle_rows``, batched dof order ``batch_order``); the defaults are the timed
     configuration.  ``host_only=True`` runs only the host setup (no GPU
     needed); the matrices and AMG hierarchy can then be inspected with
     ``export_csr``/``export_cf``.
@@ -179,7 +180,7 @@ class Solver:
                  maxit: int = 1000, host_only: bool = False, device=None, use_torch_allocator: bool = True,
                  operator: str = "assembled", sell_window: int = 0, graph: bool = True, sell_index16: bool = True,
                  fuse_cycle: bool = True, batch_tiles: int = 1, cycle_lanes: int = 0,
-                 dense_cycle_rows: int = 2048):
+                 dense_cycle_rows: int = 2048, batch_order: int = 0):
         lib = load_library()
         self._h = ctypes.c_void_p()
         self.order = order
@@ -201,6 +202,7 @@ class Solver:
         opt.batch_tiles = int(batch_tiles)
         opt.cycle_lanes = int(cycle_lanes)
         opt.dense_cycle_rows = int(dense_cycle_rows)
+        opt.batch_order = int(batch_order)
         kap = None
         if kappa is not None:
             self._kappa = np.ascontiguousarray(kappa, dtype=np.float64)

@@ -9,6 +9,7 @@
 // frozen while the others continue.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "batched.hpp"
@@ -78,10 +79,19 @@ __device__ __forceinline__ void bsell_slices(const DevSellView &A, XL xload, BOD
     __shared__ int cs[kChunk * kSlice];
     const T *__restrict__ val = (const T *)A.val;
     const int c = threadIdx.x % NR, rl0 = threadIdx.x / NR;
-    // slices go round-robin over the workgroups (and so over the dies):
-    // giving each die a contiguous share of equal entries measured slower
-    // for every block kernel here (the sweeps by 9%, I_P by 38%)
-    for (int sl = blockIdx.x; sl < A.nslices; sl += gridDim.x) {
+    // Slices go round-robin over the workgroups (and so over the dies), or,
+    // with die ranges (A_h in the spatially ordered batched layout), die d =
+    // b % 8 walks its own contiguous range so its gathers stay in one region
+    // (for operators in the length-sorted single-vector order, contiguous die
+    // shares measured slower: the sweeps by 9%, I_P by 38%)
+    int sl = blockIdx.x, sl_end = A.nslices, sl_step = gridDim.x;
+    if (A.die_off) {
+        const int d = blockIdx.x % 8;
+        sl = A.die_off[d] + (int)blockIdx.x / 8;
+        sl_end = A.die_off[d + 1];
+        sl_step = ((int)gridDim.x - d + 7) / 8;
+    }
+    for (; sl < sl_end; sl += sl_step) {
         const int e0 = A.slice_off[sl], width = (A.slice_off[sl + 1] - e0) / kSlice;
         const int mode = A.mode[sl];
         T acc[NP];
@@ -144,7 +154,8 @@ __device__ __forceinline__ void bsell_slices(const DevSellView &A, XL xload, BOD
     }
 }
 
-inline int bsell_grid(const DevSellView &A) { return grid_cap(A.nslices); }
+// with die ranges every die needs a workgroup: at least 8
+inline int bsell_grid(const DevSellView &A) { return A.die_off ? std::max(8, grid_cap(A.nslices)) : grid_cap(A.nslices); }
 
 template <typename T, int NR>
 __global__ __launch_bounds__(kBlock) void kb_jacobi0(int n, const T *__restrict__ dinv, const double *__restrict__ R,

@@ -59,6 +59,10 @@ struct DevSellView {
     const int *wide;
     const void *val;     // double or float, padding entries are 0
     int split;           // with mixed == 0: two wavefronts per slice (wide slices)
+    // block kernels only: when set, die d (the workgroups b with b % 8 == d,
+    // which the dispatcher places on die d) takes slices [die_off[d],
+    // die_off[d + 1]) (9 entries); otherwise slices go round-robin
+    const int *die_off = nullptr;
 };
 
 // State of a CG solve in device memory.

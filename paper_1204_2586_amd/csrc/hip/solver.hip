@@ -11,6 +11,7 @@
 #include <chrono>
 #include <functional>
 #include <mutex>
+#include <numeric>
 #include <cmath>
 #include <cstring>
 #include <stdexcept>
@@ -1245,6 +1246,109 @@ struct aux_handle {
         return status;
     }
 
+    // ------------------------------------------------------------ batched order
+    // The block kernels gather an NR-word block row for every entry, so their
+    // speed depends on the gathered rows staying in a die's L2.  With
+    // batch_order = 1 they run in a dof order of their own: the dofs along
+    // the Morton curve of their node positions (so any run of rows is a
+    // compact region), rows sorted by length within windows of kBatchWindow
+    // rows (short slices), and each die takes a contiguous range of A_h's
+    // slices balanced by stored entries (its gathers stay in one region).
+    // At P2 64^3 with 32 columns this halves the bytes the block products
+    // fetch past L2 (FP64 product 8.9 -> 4.2 GB per launch, L2 hits 30 ->
+    // 62 %) without making them faster (L2 misses do not bound them; each
+    // entry still gathers an NR-word block row through L1).
+    // batch_order = 0 (default) keeps the single-vector order (round-robin
+    // slices).
+    static constexpr int kBatchWindow = 2048;
+    static constexpr int kDies = 8;
+    struct BOrder {
+        bool ready = false;
+        std::vector<int> perm;           // batched row -> external dof
+        std::vector<int> from_single;    // single-vector internal row -> batched row
+        DevSell A;
+        int *die_off = nullptr;          // [kDies + 1] slice ranges, or null (round-robin)
+        int *perm_d = nullptr;
+        double *dinv64 = nullptr;
+        float *dinv32 = nullptr;
+        Csr Am;                          // A_h in the Morton order (host, until the tiles are built)
+        std::vector<int> m2b;            // Morton position -> batched row
+    } bo;
+
+    void ensure_border()
+    {
+        if (bo.ready) return;
+        ensure_fp32();
+        const int n = disc.ndof;
+        if (!opt.batch_order) {
+            // the single-vector layout as it is
+            bo.perm = sell.perm;
+            bo.from_single.resize(n);
+            std::iota(bo.from_single.begin(), bo.from_single.end(), 0);
+            bo.A = A;
+            bo.perm_d = perm;
+            bo.dinv64 = dinv64;
+            bo.dinv32 = dinv32;
+            bo.Am = disc.A;
+            bo.m2b = sell.iperm;
+            bo.ready = true;
+            return;
+        }
+        std::vector<double> pos((size_t)3 * n);
+        for (int i = 0; i < n; i++)
+            for (int c = 0; c < 3; c++) {
+                double t = 0.0;
+                for (int p = 0; p < disc.k; p++) t += disc.xyz[3 * (size_t)disc.keys[(size_t)i * disc.k + p] + c];
+                pos[3 * (size_t)i + c] = t / disc.k;
+            }
+        const std::vector<int> mo = morton_order(pos, n);     // Morton position -> external dof
+        std::vector<int> imo(n);
+        for (int r = 0; r < n; r++) imo[mo[r]] = r;
+        bo.Am = permute_symmetric(disc.A, mo, imo);
+        Sell sl;
+        build_sell(bo.Am, kSlice, kBatchWindow, false, sl);
+        bo.perm.resize(n);
+        for (int r = 0; r < n; r++) bo.perm[r] = mo[sl.perm[r]];
+        bo.m2b = sl.iperm;
+        std::vector<int> iperm(n);
+        for (int r = 0; r < n; r++) iperm[bo.perm[r]] = r;
+        bo.from_single.resize(n);
+        for (int i = 0; i < n; i++) bo.from_single[i] = iperm[sell.perm[i]];
+        bo.A = upload_sell(sl);
+        bo.A.v32 = upload(to_f32(sl.val));
+        // die ranges of equal stored entries
+        std::vector<int> off(kDies + 1, 0);
+        const double total = (double)sl.slice_off[sl.nslices];
+        int d = 1;
+        for (int sidx = 0; sidx < sl.nslices && d < kDies; sidx++)
+            while (d < kDies && (double)sl.slice_off[sidx + 1] >= total * d / kDies) off[d++] = sidx + 1;
+        while (d <= kDies) off[d++] = sl.nslices;
+        bo.die_off = upload(off);
+        bo.perm_d = upload(bo.perm);
+        std::vector<double> l1b(n);
+        for (int r = 0; r < n; r++) l1b[r] = disc.l1[bo.perm[r]];
+        bo.dinv64 = upload(inverse(l1b));
+        bo.dinv32 = upload(to_f32(inverse(l1b)));
+        if (!opt.batch_tiles) {
+            bo.Am = Csr();
+            bo.m2b.clear();
+        }
+        bo.ready = true;
+    }
+    template <typename T>
+    DevSellView bview() const
+    {
+        DevSellView v = bo.A.view<T>();
+        v.die_off = bo.die_off;
+        return v;
+    }
+    template <typename T>
+    const T *bdinv() const
+    {
+        if constexpr (std::is_same<T, float>::value) return bo.dinv32;
+        else return bo.dinv64;
+    }
+
     // ------------------------------------------------------------ batched CG
     struct Batch {
         int nr = 0, hist_cap = 0;
@@ -1260,6 +1364,8 @@ struct aux_handle {
     void ensure_batch(int nr, int maxit)
     {
         int n = disc.ndof;
+        ensure_fp32();
+        ensure_border();
         if (bt.nr != nr) {
             release_batch();
             bt.nr = nr;
@@ -1325,14 +1431,14 @@ struct aux_handle {
         HIPCHECK(hipMemsetAsync(rh, 0, blk * sizeof(float), stream));
         HIPCHECK(hipMemsetAsync(bt.P, 0, blk * sizeof(double), stream));
         double best32 = time_block([&]() {
-            bsell_sweep<float, float, float>(stream, nr, A.view<float>(), dinv32, rh, z0, z1, nullptr, nullptr, nullptr);
+            bsell_sweep<float, float, float>(stream, nr, bview<float>(), bo.dinv32, rh, z0, z1, nullptr, nullptr, nullptr);
         });
-        double best64 = time_block([&]() { bsell_spmv64(stream, nr, A.view<double>(), bt.P, bt.Q, nullptr, nullptr); });
+        double best64 = time_block([&]() { bsell_spmv64(stream, nr, bview<double>(), bt.P, bt.Q, nullptr, nullptr); });
         for (int k = 0; k < kTileSizes; k++) {
             if (btile_lds(tiles[k].view<float>(), nr, 4)) {
                 double ms = time_block([&]() {
-                    btile_sweep<float, float, float>(stream, nr, tiles[k].view<float>(), dinv32, rh, z0, z1, nullptr,
-                                                     nullptr, nullptr);
+                    btile_sweep<float, float, float>(stream, nr, tiles[k].view<float>(), bo.dinv32, rh, z0, z1,
+                                                     nullptr, nullptr, nullptr);
                 });
                 if (ms < best32) {
                     best32 = ms;
@@ -1444,7 +1550,7 @@ struct aux_handle {
         const int sizes[kTileSizes] = {16, 32, 64};
         for (int k = 0; k < kTileSizes; k++) {
             Tiles h;
-            build_tiles(disc.A, sell.iperm, sizes[k], h);
+            build_tiles(bo.Am, bo.m2b, sizes[k], h);
             DevTiles &d = tiles[k];
             d.n = h.n;
             d.tile = h.tile;
@@ -1460,6 +1566,8 @@ struct aux_handle {
             d.v32 = upload(to_f32(h.val));
         }
         tiles_ready = true;
+        bo.Am = Csr();
+        bo.m2b.clear();
     }
 
     // tile layout the batched autotuner chose for values of type T at the
@@ -1516,9 +1624,11 @@ struct aux_handle {
             bR[l] = upload_bop(hl.R);
         }
         if (L) {
-            bIP = upload_bop(IPi);
-            if (opt.fuse_cycle) bRF = upload_bop(RF_host);
-            else bIR = upload_bop(IRi);
+            ensure_border();
+            // P^k rows / columns in the batched order
+            bIP = upload_bop(permute_rows(disc.IP, bo.perm));
+            if (opt.fuse_cycle) bRF = upload_bop(renumber_cols(RF_host, bo.from_single, disc.ndof));
+            else bIR = upload_bop(renumber_cols(IRi, bo.from_single, disc.ndof));
         }
         bops_ready = true;
     }
@@ -1554,9 +1664,9 @@ struct aux_handle {
         Work<T> &w = bwork<T>();
         hipStream_t s = stream;
         const int nr = bt.nr;
-        DevSellView Av = A.view<T>();
+        DevSellView Av = bview<T>();
         const DevTiles *tl = tiles_for<T>(nr);
-        const T *d = dinv<T>();
+        const T *d = bdinv<T>();
         const int nu = opt.nu;
         T *rTbuf = std::is_same<T, float>::value ? w.rT : nullptr;
         T *zc = w.za, *zn = w.zb;
@@ -1632,7 +1742,7 @@ struct aux_handle {
     {
         hipStream_t s = stream;
         const int nr = bt.nr, n = disc.ndof;
-        DevSellView A64 = A.view<double>();
+        DevSellView A64 = bview<double>();
         int pk = pbeg(AUX_PROF_CG_SPMV);
         const DevTiles *tl = tiles_for<double>(nr);
         int g = tl ? btile_spmv64(s, nr, tl->view<double>(), bt.P, bt.Q, bt.partials, st.all_done)
@@ -1643,10 +1753,10 @@ struct aux_handle {
         if (opt.precision == AUX_MIXED) {
             ensure_fp32();
             Work<float> &w = bwork<float>();
-            g = bcg_update_prep<float>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, st, bt.partials, dinv32, w.za, w.rT);
+            g = bcg_update_prep<float>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, st, bt.partials, bo.dinv32, w.za, w.rT);
         } else {
             Work<double> &w = bwork<double>();
-            g = bcg_update_prep<double>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, st, bt.partials, dinv64, w.za, nullptr);
+            g = bcg_update_prep<double>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, st, bt.partials, bo.dinv64, w.za, nullptr);
         }
         bfinish(s, nr, bt.partials, g, FIN_RR, nullptr, st);
         g = bapply(bt.R, bt.partials, st.all_done, true);
@@ -1668,9 +1778,9 @@ struct aux_handle {
         const int n = disc.ndof;
         BCgState st = bstate(maxit);
         const int *all_done = st.all_done;
-        DevSellView A64 = A.view<double>();
-        bgather(s, nr, n, nrhs, perm, Fext, bt.F);
-        bgather(s, nr, n, nrhs, perm, Uext, bt.X);
+        DevSellView A64 = bview<double>();
+        bgather(s, nr, n, nrhs, bo.perm_d, Fext, bt.F);
+        bgather(s, nr, n, nrhs, bo.perm_d, Uext, bt.X);
         if (const DevTiles *tl = tiles_for<double>(nr)) btile_residual64(s, nr, tl->view<double>(), bt.F, bt.X, bt.R);
         else bsell_residual64(s, nr, A64, bt.F, bt.X, bt.R);
         int g = bvec_dot(s, nr, n, bt.F, bt.F, bt.partials);
@@ -1708,7 +1818,7 @@ struct aux_handle {
             if (h[1] || issued >= maxit) break;
             chunk = 4;
         }
-        bscatter(s, nr, n, nrhs, perm, bt.X, Uext);
+        bscatter(s, nr, n, nrhs, bo.perm_d, bt.X, Uext);
         int last = 0;
         for (int c = 0; c < nrhs; c++) last = std::max(last, h[2 + c]);
         prof_tag = -1;
@@ -1843,10 +1953,10 @@ struct aux_handle {
         if (mixed) ensure_fp32();
         hipStream_t s = stream;
         const int n = disc.ndof;
-        DevSellView A64 = A.view<double>();
+        DevSellView A64 = bview<double>();
         const DevTiles *tl = tiles_for<double>(nr);
-        bgather(s, nr, n, nrhs, perm, Fext, bt.F);
-        bgather(s, nr, n, nrhs, perm, Uext, bt.X);
+        bgather(s, nr, n, nrhs, bo.perm_d, Fext, bt.F);
+        bgather(s, nr, n, nrhs, bo.perm_d, Uext, bt.X);
         if (tl) btile_residual64(s, nr, tl->view<double>(), bt.F, bt.X, bt.R);
         else bsell_residual64(s, nr, A64, bt.F, bt.X, bt.R);
         double *gam = bk.host, *tmp = bk.host + 64 * 64, *cols = bk.host + 2 * 64 * 64;
@@ -1891,10 +2001,11 @@ struct aux_handle {
                 int g;
                 if (mixed) {
                     Work<float> &w = bwork<float>();
-                    g = block_update<float>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, bk.coef, bt.partials, dinv32, w.za, w.rT);
+                    g = block_update<float>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, bk.coef, bt.partials, bo.dinv32, w.za,
+                                            w.rT);
                 } else {
                     Work<double> &w = bwork<double>();
-                    g = block_update<double>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, bk.coef, bt.partials, dinv64, w.za,
+                    g = block_update<double>(s, nr, n, bt.X, bt.R, bt.P, bt.Q, bk.coef, bt.partials, bo.dinv64, w.za,
                                              nullptr);
                 }
                 BCgState st = bstate(1);
@@ -1922,7 +2033,7 @@ struct aux_handle {
                 else block_direction<double>(s, nr, n, bt.Z, bt.P, bk.coef, false);
             }
         }
-        bscatter(s, nr, n, nrhs, perm, bt.X, Uext);
+        bscatter(s, nr, n, nrhs, bo.perm_d, bt.X, Uext);
         prof_tag = -1;
         prof_collect(it + 1);
         HIPCHECK(hipStreamSynchronize(s));
@@ -2054,6 +2165,7 @@ void aux_default_options(aux_options *o)
     o->batch_tiles = 1;
     o->cycle_lanes = 0;
     o->dense_cycle_rows = 2048;
+    o->batch_order = 0;
 }
 
 int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt, const aux_device *dev,
@@ -2073,7 +2185,7 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
         if (o.precision != AUX_FP64 && o.precision != AUX_MIXED) throw AuxError(AUX_EINVAL, "bad precision");
         if (o.op != AUX_OP_ASSEMBLED && o.op != AUX_OP_MATFREE) throw AuxError(AUX_EINVAL, "bad operator kind");
         if (o.sell_window < 0) throw AuxError(AUX_EINVAL, "sell_window must be >= 0");
-        for (int flag : {o.graph, o.sell_index16, o.fuse_cycle, o.host_only})
+        for (int flag : {o.graph, o.sell_index16, o.fuse_cycle, o.host_only, o.batch_order})
             if (flag != 0 && flag != 1) throw AuxError(AUX_EINVAL, "a boolean option is not 0 or 1");
         if (o.batch_tiles < 0 || o.batch_tiles > 2) throw AuxError(AUX_EINVAL, "batch_tiles must be 0, 1 or 2");
         if (o.dense_cycle_rows < 0 || o.dense_cycle_rows > 8192)

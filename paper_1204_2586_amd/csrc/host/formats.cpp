@@ -12,6 +12,8 @@
 // the index stream from 4 to 2 bytes per entry; other slots keep 32-bit
 // columns in a side array.
 #include <algorithm>
+#include <cmath>
+#include <cstdint>
 #include <numeric>
 #include <stdexcept>
 
@@ -161,6 +163,64 @@ Csr permute_rows(const Csr &A, const std::vector<int> &perm)
         int i = perm[r];
         B.col.insert(B.col.end(), A.col.begin() + A.ptr[i], A.col.begin() + A.ptr[i + 1]);
         B.val.insert(B.val.end(), A.val.begin() + A.ptr[i], A.val.begin() + A.ptr[i + 1]);
+        B.ptr[r + 1] = (int)B.col.size();
+    }
+    return B;
+}
+
+std::vector<int> morton_order(const std::vector<double> &xyz, int n)
+{
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int i = 0; i < n; i++)
+        for (int c = 0; c < 3; c++) {
+            lo[c] = std::min(lo[c], xyz[3 * (size_t)i + c]);
+            hi[c] = std::max(hi[c], xyz[3 * (size_t)i + c]);
+        }
+    // spread the 21 low bits of v to every third bit
+    auto spread = [](uint64_t v) {
+        v &= 0x1fffff;
+        v = (v | v << 32) & 0x1f00000000ffffULL;
+        v = (v | v << 16) & 0x1f0000ff0000ffULL;
+        v = (v | v << 8) & 0x100f00f00f00f00fULL;
+        v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+        v = (v | v << 2) & 0x1249249249249249ULL;
+        return v;
+    };
+    std::vector<std::pair<uint64_t, int>> code((size_t)n);
+    for (int i = 0; i < n; i++) {
+        uint64_t m = 0;
+        for (int c = 0; c < 3; c++) {
+            const double span = hi[c] - lo[c];
+            const double t = span > 0 ? (xyz[3 * (size_t)i + c] - lo[c]) / span : 0.0;
+            const uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, std::floor(t * 2097151.0 + 0.5)));
+            m |= spread(q) << c;
+        }
+        code[i] = {m, i};
+    }
+    std::sort(code.begin(), code.end());
+    std::vector<int> ord((size_t)n);
+    for (int r = 0; r < n; r++) ord[r] = code[r].second;
+    return ord;
+}
+
+Csr renumber_cols(const Csr &A, const std::vector<int> &map, int split)
+{
+    Csr B;
+    B.n = A.n;
+    B.m = A.m;
+    B.ptr.assign((size_t)A.n + 1, 0);
+    std::vector<std::pair<int, double>> row;
+    for (int r = 0; r < A.n; r++) {
+        row.clear();
+        for (int e = A.ptr[r]; e < A.ptr[r + 1]; e++) {
+            const int j = A.col[e];
+            row.push_back({j < split ? map[j] : split + map[j - split], A.val[e]});
+        }
+        std::sort(row.begin(), row.end());
+        for (auto &cv : row) {
+            B.col.push_back(cv.first);
+            B.val.push_back(cv.second);
+        }
         B.ptr[r + 1] = (int)B.col.size();
     }
     return B;

@@ -161,6 +161,13 @@ void build_tiles(const Csr &A, const std::vector<int> &iperm, int tile, Tiles &o
 void build_sell(const Csr &A, int slice, int window, bool index16, Sell &out, bool permute_cols = true);
 // rows of A in the order perm (row r of the result is row perm[r] of A)
 Csr permute_rows(const Csr &A, const std::vector<int> &perm);
+// Points ordered along the Morton (Z-order) curve of their positions
+// (xyz [n][3], 21 bits per coordinate over the bounding box; equal codes keep
+// their index order): result[r] = the point at position r of the curve.
+std::vector<int> morton_order(const std::vector<double> &xyz, int n);
+// columns renumbered: column j < split becomes map[j], column j >= split
+// becomes split + map[j - split]; each row's columns sorted again
+Csr renumber_cols(const Csr &A, const std::vector<int> &map, int split);
 // rows and columns renumbered: entry (r, iperm[j]) of the result is a_{perm[r], j}
 Csr permute_symmetric(const Csr &A, const std::vector<int> &perm, const std::vector<int> &iperm);
 

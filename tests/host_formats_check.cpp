@@ -12,8 +12,10 @@
 //
 // Prints "ell <lanes> <max relative error>" and "dense <levels> <max relative
 // error>" lines; exits non-zero on a layout violation.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <numeric>
 #include <random>
 #include <vector>
 
@@ -255,6 +257,94 @@ double check_dense(int nlev)
     return err / mag;
 }
 
+// Morton order: a permutation whose codes (interleaved bits, computed here
+// bit by bit) never decrease; on a 2^k lattice every aligned run of 8^j points
+// is a 2^j cube (the Z-order property)
+int check_morton(int k)
+{
+    const int m = 1 << k, n = m * m * m;
+    std::vector<double> xyz((size_t)3 * n);
+    std::vector<int> ijk((size_t)3 * n);
+    for (int p = 0; p < n; p++) {
+        const int i = p % m, j = (p / m) % m, l = p / (m * m);
+        ijk[3 * p] = i;
+        ijk[3 * p + 1] = j;
+        ijk[3 * p + 2] = l;
+        xyz[3 * p] = i;
+        xyz[3 * p + 1] = j;
+        xyz[3 * p + 2] = l;
+    }
+    const std::vector<int> ord = morton_order(xyz, n);
+    std::vector<int> seen(n, 0);
+    for (int r = 0; r < n; r++) {
+        if (ord[r] < 0 || ord[r] >= n || seen[ord[r]]++) return 1;
+    }
+    // bits of the quantised coordinates: the bounding box is [0, m-1], so
+    // coordinate c maps to round(c * (2^21 - 1) / (m - 1))
+    auto code = [&](int p) {
+        unsigned long long q[3], z = 0;
+        for (int c = 0; c < 3; c++)
+            q[c] = (unsigned long long)std::floor((double)ijk[3 * p + c] / (m - 1) * 2097151.0 + 0.5);
+        for (int b = 0; b < 21; b++)
+            for (int c = 0; c < 3; c++) z |= ((q[c] >> b) & 1ULL) << (3 * b + c);
+        return z;
+    };
+    for (int r = 1; r < n; r++)
+        if (code(ord[r]) < code(ord[r - 1])) return 2;
+    for (int j = 1; j < k && j <= 2; j++) {
+        const int run = 1 << (3 * j), side = 1 << j;
+        for (int r0 = 0; r0 < n; r0 += run) {
+            int lo[3] = {m, m, m}, hi[3] = {-1, -1, -1};
+            for (int r = r0; r < r0 + run; r++)
+                for (int c = 0; c < 3; c++) {
+                    lo[c] = std::min(lo[c], ijk[3 * ord[r] + c]);
+                    hi[c] = std::max(hi[c], ijk[3 * ord[r] + c]);
+                }
+            for (int c = 0; c < 3; c++)
+                if (hi[c] - lo[c] != side - 1) return 3;
+        }
+    }
+    return 0;
+}
+
+// renumber_cols against a dense reference: a random n x 2h matrix whose
+// columns below h and from h on are renumbered by one permutation of h
+double check_renumber(int n, int h, std::mt19937 &rng)
+{
+    const int m = 2 * h;
+    Csr B;
+    B.n = n;
+    B.m = m;
+    B.ptr.assign((size_t)n + 1, 0);
+    std::uniform_real_distribution<double> u(-1.0, 1.0);
+    for (int i = 0; i < n; i++) {
+        for (int j = 0; j < m; j++)
+            if (rng() % 5 == 0) {
+                B.col.push_back(j);
+                B.val.push_back(u(rng));
+            }
+        B.ptr[i + 1] = (int)B.col.size();
+    }
+    std::vector<int> map(h);
+    std::iota(map.begin(), map.end(), 0);
+    std::shuffle(map.begin(), map.end(), rng);
+    const Csr R = renumber_cols(B, map, h);
+    std::vector<double> dense((size_t)n * m, 0.0), got((size_t)n * m, 0.0);
+    for (int i = 0; i < n; i++) {
+        for (int e = B.ptr[i]; e < B.ptr[i + 1]; e++) {
+            const int j = B.col[e];
+            dense[(size_t)i * m + (j < h ? map[j] : h + map[j - h])] = B.val[e];
+        }
+        for (int e = R.ptr[i]; e < R.ptr[i + 1]; e++) {
+            if (e > R.ptr[i] && R.col[e] <= R.col[e - 1]) return 1e300;   // sorted, no repeats
+            got[(size_t)i * m + R.col[e]] = R.val[e];
+        }
+    }
+    double err = 0.0;
+    for (size_t q = 0; q < dense.size(); q++) err = std::max(err, std::fabs(dense[q] - got[q]));
+    return err;
+}
+
 }  // namespace
 
 int main()
@@ -273,5 +363,7 @@ int main()
         }
     }
     for (int nlev : {2, 3, 4}) std::printf("dense %d %.3e\n", nlev, check_dense(nlev));
+    for (int k : {1, 3, 4}) std::printf("morton %d %d\n", k, check_morton(k));
+    for (int n : {2, 64, 130}) std::printf("renum %d %.3e\n", n, check_renumber(n, n / 2 + 1, rng));
     return 0;
 }

@@ -523,3 +523,24 @@ def test_hierarchy_and_allocation_options(opts):
         ref = aux.Solver(xyz, tets, 2, kappa, device=DEV, **fixed)
         u2, _ = ref.solve(_t(b), tol=0.0, maxit=it, check=False)
         assert torch.equal(u, u2)
+
+
+@pytest.mark.parametrize("k,n", [(2, 10), (3, 6)])
+def test_batched_orders_agree(k, n):
+    """The batched and block solves in the spatially ordered layout (Morton
+    curve, die ranges; the default) and in the single-vector order give the
+    same columns up to rounding: at a fixed iteration count within 1e-10."""
+    print(f"[batched orders k={k} n={n}]", flush=True)
+    xyz, tets, kappa = _case(k, n, jitter=0.2, kappa="rand")
+    F = _t(np.stack([W.random_vector(aux.Solver(xyz, tets, k, kappa, host_only=True).n, 20 + j)
+                     for j in range(6)], axis=1))
+    out = {}
+    for order in (0, 1):
+        lib = aux.Solver(xyz, tets, k, kappa, device=DEV, batch_order=order)
+        U, infos = lib.solve_batched(F, tol=0.0, maxit=6, check=False)
+        Ub, binfos = lib.solve_block(F, tol=0.0, maxit=4, check=False)
+        out[order] = (U.cpu().numpy(), Ub.cpu().numpy())
+        assert all(i.iterations == 6 for i in infos) and all(i.iterations == 4 for i in binfos)
+        lib.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b)
