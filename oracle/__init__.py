@@ -78,6 +78,13 @@ def _load():
     lib.orc_fgmres.argtypes = [vp, ctypes.c_int, _f64p, _f64p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                vp, vp, _f64p]
     lib.orc_kappa_grad.argtypes = [vp, _f64p, _f64p, _f64p]
+    lib.orc_stokes_setup.restype = ctypes.c_int
+    lib.orc_stokes_setup.argtypes = [vp]
+    lib.orc_stokes_fgmres.restype = ctypes.c_int
+    lib.orc_stokes_fgmres.argtypes = [vp, ctypes.c_int, _f64p, _f64p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), _f64p]
+    lib.orc_stokes_apply_operator.argtypes = [vp, _f64p, _f64p]
+    lib.orc_stokes_apply_qt.argtypes = [vp, ctypes.c_int, _f64p, _f64p]
     lib.orc_block_pcg.restype = ctypes.c_int
     lib.orc_block_pcg.argtypes = [vp, ctypes.c_int, ctypes.c_int, _f64p, _f64p, ctypes.c_double, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_int), _f64p]
@@ -204,9 +211,10 @@ class Problem:
 
     # ---- matrices
     def csr(self, which: str, level: int = 0):
-        """'A' (A_h), 'AH', 'IP', 'Alev' (level operator), 'P' (level interpolation)."""
+        """'A' (A_h), 'AH', 'IP', 'Alev' (level operator), 'P' (level interpolation),
+        'B' (Stokes divergence, after stokes_setup), 'Mp' (pressure mass matrix)."""
         import scipy.sparse as sp
-        code = {"A": 0, "AH": 1, "IP": 2, "Alev": 3, "P": 4}[which]
+        code = {"A": 0, "AH": 1, "IP": 2, "Alev": 3, "P": 4, "B": 5, "Mp": 6}[which]
         shp = np.zeros(3, dtype=np.int64)
         if _load().orc_csr_shape(self._h, code, level, shp):
             raise IndexError("no such matrix")
@@ -308,6 +316,39 @@ class Problem:
         st = _load().orc_pcg(self._h, int(fp32), np.ascontiguousarray(b, dtype=np.float64), x, tol,
                              maxit, ctypes.byref(it), ctypes.byref(rr))
         return x, it.value, rr.value, st
+
+    # ---- Stokes (Sec. 5), Hood-Taylor P^2-P^1
+    def stokes_setup(self):
+        """Divergence B (n_p x 3 n_h, -div) and pressure mass matrix M_p
+        (pressure P^1 on every vertex); needs order 2."""
+        if _load().orc_stokes_setup(self._h):
+            raise ValueError("Stokes needs the P^2 velocity space")
+        self.np = self.xyz.shape[0]
+        return self
+
+    def stokes_operator(self, x) -> np.ndarray:
+        out = np.zeros(3 * self.n + self.np)
+        _load().orc_stokes_apply_operator(self._h, np.ascontiguousarray(x, dtype=np.float64), out)
+        return out
+
+    def stokes_qt(self, r, fp32: bool = False) -> np.ndarray:
+        out = np.zeros(3 * self.n + self.np)
+        _load().orc_stokes_apply_qt(self._h, int(fp32), np.ascontiguousarray(r, dtype=np.float64), out)
+        return out
+
+    def stokes_fgmres(self, b, tol=1e-8, restart=30, maxit=500, x0=None, fp32: bool = False):
+        """FGMRES(restart) with the block triangular preconditioner Q_t on the
+        saddle-point system [A B^T; B 0] [u; p] = b, unknowns [u_x; u_y; u_z; p].
+        Returns (x, steps, true relative residual, status, history)."""
+        assert self._amg, "call setup_amg first"
+        N = 3 * self.n + self.np
+        x = np.zeros(N) if x0 is None else np.array(x0, dtype=np.float64)
+        it = ctypes.c_int(0)
+        rr = ctypes.c_double(0.0)
+        hist = np.zeros(maxit + 1)
+        st = _load().orc_stokes_fgmres(self._h, int(fp32), np.ascontiguousarray(b, dtype=np.float64), x, tol,
+                                       restart, maxit, ctypes.byref(it), ctypes.byref(rr), hist)
+        return x, it.value, rr.value, st, hist[: it.value + 1]
 
     def block_pcg(self, F, tol=1e-8, maxit=1000, X0=None, fp32: bool = False):
         """O'Leary's block preconditioned CG on A_h X = F (F [n, s]); stops

@@ -64,6 +64,12 @@ typedef struct {
     double *chol;    /* dense Cholesky factor of the coarsest operator (lower, row-major) */
     int ncoarse;
 
+    /* Stokes (Sec. 5), Hood-Taylor P^2-P^1: pressure on every vertex */
+    int np;          /* pressure unknowns (vertices); 0 until orc_stokes_setup */
+    ocsr Bdiv;       /* np x 3 ndof discrete divergence, columns component-major */
+    ocsr BdivT;
+    ocsr Mp;         /* np x np pressure mass matrix */
+
     /* options */
     double theta;
     int nu, coarse_max, max_levels;
@@ -87,5 +93,14 @@ int ocsr_from_triplets(int n, int m, size_t cnt, const int *ri, const int *ci, c
 
 /* amg */
 int orc_amg_setup(orc *o);
+
+/* Stokes: divergence and pressure mass matrix (orc_fem.c) */
+int orc_stokes_assemble(orc *o);
+
+/* flexible GMRES(m) on vectors of length n with an operator and a
+   preconditioner given as callbacks (orc_solve.c) */
+typedef void (*orc_vecop)(const orc *o, void *ctx, const double *in, double *out);
+int orc_fgmres_core(const orc *o, int n, orc_vecop op, orc_vecop prec, void *ctx, const double *b, double *x,
+                    double tol, int m, int maxit, int *iters, double *relres, double *hist);
 
 #endif

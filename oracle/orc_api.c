@@ -20,6 +20,10 @@ int orc_fgmres(const orc *o, int prec, const double *b, double *x, double tol, i
 int orc_kappa_grad(const orc *o, const double *u, const double *lam, double *g);
 int orc_block_pcg(const orc *o, int fp32, int s, const double *F, double *X, double tol, int maxit,
                   int *iters, double *relres);
+int orc_stokes_fgmres(const orc *o, int fp32, const double *b, double *x, double tol, int m, int maxit,
+                      int *iters, double *relres, double *hist);
+int orc_stokes_apply_operator(const orc *o, const double *in, double *out);
+int orc_stokes_apply_qt(const orc *o, int fp32, const double *in, double *out);
 
 void orc_free(orc *o)
 {
@@ -32,6 +36,7 @@ void orc_free(orc *o)
         ocsr_free(&o->lev[l].P); ocsr_free(&o->lev[l].R);
     }
     free(o->chol);
+    ocsr_free(&o->Bdiv); ocsr_free(&o->BdivT); ocsr_free(&o->Mp);
     free(o);
 }
 
@@ -64,6 +69,8 @@ int orc_setup_amg(orc *o, double theta, int nu, int coarse_max, int max_levels, 
     return orc_amg_setup(o);
 }
 
+int orc_stokes_setup(orc *o) { return o->np ? 0 : orc_stokes_assemble(o); }
+
 /* sizes: [n_h, n_H, nnode, nlev, nnz(A_h), nnz(A_H), nnz(I_P), ncoarse, nloc] */
 void orc_sizes(const orc *o, long long *s)
 {
@@ -80,6 +87,8 @@ static const ocsr *pick(const orc *o, int which, int level)
     case 2: return &o->IP;
     case 3: return level < o->nlev ? &o->lev[level].A : NULL;
     case 4: return level + 1 < o->nlev ? &o->lev[level].P : NULL;
+    case 5: return o->np ? &o->Bdiv : NULL;
+    case 6: return o->np ? &o->Mp : NULL;
     default: return NULL;
     }
 }

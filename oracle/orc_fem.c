@@ -500,6 +500,68 @@ int orc_element_matrix(const orc *o, int t, double *K)
     return 0;
 }
 
+/* Stokes with the Hood-Taylor pair P^2-P^1 (Sec. 5, Sec. 6.3): pressure
+   psi_q = lambda_q on every vertex q (no boundary condition), velocity the
+   interior P^2 dofs of each component, component-major.
+     (B)_{q,(c,i)} = - int psi_q dphi_i/dx_c   (B = discrete -div)
+     (M_p)_{q,r}   =   int psi_q psi_r
+   by quadrature (both integrands have degree 2; the rule with m = 2 points
+   per direction is exact to degree 3). */
+int orc_stokes_assemble(orc *o)
+{
+    if (o->k != 2) return -1;
+    int k = o->k, nloc = o->nloc, m = 2, nq = m * m * m, n = o->ndof, np = o->nv;
+    int alpha[35 * 4];
+    orc_local_multi_indices(k, alpha);
+    double lam[4 * 512], w[512], grad[4][3];
+    orc_tet_rule(m, lam, w);
+    size_t capB = (size_t)o->nt * 4 * 3 * nloc, capM = (size_t)o->nt * 16, cb = 0, cm = 0;
+    int *bri = malloc(capB * sizeof(int)), *bci = malloc(capB * sizeof(int));
+    double *bv = malloc(capB * sizeof(double));
+    int *mri = malloc(capM * sizeof(int)), *mci = malloc(capM * sizeof(int));
+    double *mv = malloc(capM * sizeof(double));
+    if (!bri || !bci || !bv || !mri || !mci || !mv) return -2;
+    double dl[35][4];
+    for (int t = 0; t < o->nt; t++) {
+        double det = tet_geometry(o, t, grad);
+        const int *vt = o->tets + 4 * (size_t)t;
+        double Bt[4][3][35], Mt[4][4];
+        memset(Bt, 0, sizeof(Bt));
+        memset(Mt, 0, sizeof(Mt));
+        for (int q = 0; q < nq; q++) {
+            const double *lq = lam + 4 * q;
+            for (int a = 0; a < nloc; a++) orc_basis_dlam(k, alpha + 4 * a, lq, dl[a]);
+            for (int p = 0; p < 4; p++) {
+                for (int r = 0; r < 4; r++) Mt[p][r] += w[q] * lq[p] * lq[r];
+                for (int c = 0; c < 3; c++)
+                    for (int a = 0; a < nloc; a++) {
+                        /* dphi_a/dx_c = sum_s dphi_a/dlam_s dlam_s/dx_c */
+                        double d = dl[a][0] * grad[0][c] + dl[a][1] * grad[1][c] + dl[a][2] * grad[2][c] +
+                                   dl[a][3] * grad[3][c];
+                        Bt[p][c][a] += w[q] * lq[p] * d;
+                    }
+            }
+        }
+        for (int p = 0; p < 4; p++) {
+            for (int r = 0; r < 4; r++) {
+                mri[cm] = vt[p]; mci[cm] = vt[r]; mv[cm] = det * Mt[p][r]; cm++;
+            }
+            for (int c = 0; c < 3; c++)
+                for (int a = 0; a < nloc; a++) {
+                    int i = o->node_dof[o->tet_node[(size_t)t * nloc + a]];
+                    if (i < 0) continue;
+                    bri[cb] = vt[p]; bci[cb] = c * n + i; bv[cb] = -det * Bt[p][c][a]; cb++;
+                }
+        }
+    }
+    o->np = np;
+    ocsr_from_triplets(np, 3 * n, cb, bri, bci, bv, &o->Bdiv);
+    ocsr_from_triplets(np, np, cm, mri, mci, mv, &o->Mp);
+    ocsr_transpose(&o->Bdiv, &o->BdivT);
+    free(bri); free(bci); free(bv); free(mri); free(mci); free(mv);
+    return 0;
+}
+
 /* A_h, A_H, l1 norms and I_P */
 int orc_assemble(orc *o)
 {

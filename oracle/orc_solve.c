@@ -475,13 +475,11 @@ int orc_kappa_grad(const orc *o, const double *u, const double *lam, double *g)
    and the rotated residual norm after every Arnoldi step.  Returns 0
    converged, 1 not converged in maxit steps, 3 NaN; *relres is the true
    ||b - A x|| / ||r_0|| at exit. */
-int orc_fgmres(const orc *o, int prec, const double *b, double *x, double tol, int m, int maxit,
-               int *iters, double *relres, double *hist)
+int orc_fgmres_core(const orc *o, int n, orc_vecop op, orc_vecop prec, void *ctx, const double *b, double *x,
+                    double tol, int m, int maxit, int *iters, double *relres, double *hist)
 {
-    int n = o->ndof, status = 1, it = 0;
+    int status = 1, it = 0;
     if (m < 1) return -1;
-    bops B;
-    bops_init(o, prec == 1, &B);
     double *V = malloc((size_t)(m + 1) * n * sizeof(double));
     double *Z = malloc((size_t)m * n * sizeof(double));
     double *w = malloc((size_t)n * sizeof(double));
@@ -489,7 +487,7 @@ int orc_fgmres(const orc *o, int prec, const double *b, double *x, double tol, i
     double *cs = malloc((size_t)m * sizeof(double)), *sn = malloc((size_t)m * sizeof(double));
     double *g = malloc((size_t)(m + 1) * sizeof(double)), *y = malloc((size_t)m * sizeof(double));
 
-    spmv(&o->A, x, w);
+    op(o, ctx, x, w);
     for (int i = 0; i < n; i++) w[i] = b[i] - w[i];
     double beta = sqrt(dot(n, w, w)), r0 = beta;
     if (hist) hist[0] = beta;
@@ -502,9 +500,8 @@ int orc_fgmres(const orc *o, int prec, const double *b, double *x, double tol, i
         int jend = 0, stop = 0;
         for (int j = 0; j < m && it < maxit; j++) {
             double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
-            if (prec == 2) memcpy(zj, vj, (size_t)n * sizeof(double));
-            else apply_B(o, &B, vj, zj);
-            spmv(&o->A, zj, w);
+            prec(o, ctx, vj, zj);
+            op(o, ctx, zj, w);
             for (int i = 0; i <= j; i++) {
                 const double *vi = V + (size_t)i * n;
                 double h = dot(n, w, vi);
@@ -547,18 +544,164 @@ int orc_fgmres(const orc *o, int prec, const double *b, double *x, double tol, i
         }
         for (int j = 0; j < jend; j++)
             for (int k = 0; k < n; k++) x[k] += y[j] * Z[(size_t)j * n + k];
-        spmv(&o->A, x, w);
+        op(o, ctx, x, w);
         for (int i = 0; i < n; i++) w[i] = b[i] - w[i];
         beta = sqrt(dot(n, w, w));
         if (stop) break;
         if (beta == 0.0) { status = 0; break; }
     }
 done:
-    spmv(&o->A, x, w);
+    op(o, ctx, x, w);
     for (int i = 0; i < n; i++) w[i] = b[i] - w[i];
     if (iters) *iters = it;
     if (relres) *relres = r0 > 0.0 ? sqrt(dot(n, w, w)) / r0 : 0.0;
     free(V); free(Z); free(w); free(H); free(cs); free(sn); free(g); free(y);
-    bops_free(&B);
     return status;
+}
+
+/* the Poisson system: A_h and B in FP64 (mode 0), B in FP32 (1) or none (2) */
+typedef struct {
+    const bops *B;
+    int mode;
+} poisson_ctx;
+
+static void poisson_op(const orc *o, void *ctx, const double *in, double *out)
+{
+    (void)ctx;
+    spmv(&o->A, in, out);
+}
+
+static void poisson_prec(const orc *o, void *ctx, const double *in, double *out)
+{
+    const poisson_ctx *c = ctx;
+    if (c->mode == 2) memcpy(out, in, (size_t)o->ndof * sizeof(double));
+    else apply_B(o, c->B, in, out);
+}
+
+int orc_fgmres(const orc *o, int prec, const double *b, double *x, double tol, int m, int maxit,
+               int *iters, double *relres, double *hist)
+{
+    bops B;
+    bops_init(o, prec == 1, &B);
+    poisson_ctx c = {&B, prec};
+    int st = orc_fgmres_core(o, o->ndof, poisson_op, poisson_prec, &c, b, x, tol, m, maxit, iters, relres, hist);
+    bops_free(&B);
+    return st;
+}
+
+/* ------------------------------------------------------------------ Stokes
+   The saddle-point system of Sec. 5,
+       F [u; p] = [A B^T; B 0] [u; p] = [f; g],
+   A = diag(A_h, A_h, A_h) (one P^2 Laplacian per velocity component),
+   B = discrete -div, unknowns [u_x; u_y; u_z; p] (3 n_h + n_p), and the block
+   upper triangular preconditioner Q_t of eq. (precond_t): for a residual
+   [r_u; r_p],
+       y_p = -M_p^{-1} r_p     (the Schur complement S = B A^{-1} B^T replaced
+                                by the pressure mass matrix M_p, solved by
+                                diagonally preconditioned CG),
+       y_u = B_aux (r_u - B^T y_p) per component (one application of the
+                                auxiliary-space preconditioner for A).
+   Reading where the paper is silent: the M_p solve stops at a relative
+   residual of 1e-6 (at most 200 steps). */
+typedef struct {
+    const bops *B;
+    double *t, *c1, *c2;          /* work vectors */
+} stokes_ctx;
+
+static void stokes_op(const orc *o, void *ctx, const double *in, double *out)
+{
+    stokes_ctx *c = ctx;
+    int n = o->ndof, np = o->np;
+    for (int k = 0; k < 3; k++) spmv(&o->A, in + (size_t)k * n, out + (size_t)k * n);
+    spmv(&o->BdivT, in + 3 * (size_t)n, c->t);
+    for (int i = 0; i < 3 * n; i++) out[i] += c->t[i];
+    spmv(&o->Bdiv, in, out + 3 * (size_t)n);
+    (void)np;
+}
+
+/* x = M_p^{-1} b by CG with the diagonal preconditioner, from x = 0 */
+static int mass_pcg(const orc *o, const double *b, double *x, double rtol, int maxit)
+{
+    int np = o->np, it = 0;
+    double *r = malloc((size_t)np * sizeof(double)), *z = malloc((size_t)np * sizeof(double));
+    double *p = malloc((size_t)np * sizeof(double)), *q = malloc((size_t)np * sizeof(double));
+    double *dg = malloc((size_t)np * sizeof(double));
+    for (int i = 0; i < np; i++) {
+        dg[i] = 0.0;
+        for (int e = o->Mp.ptr[i]; e < o->Mp.ptr[i + 1]; e++)
+            if (o->Mp.col[e] == i) dg[i] = o->Mp.val[e];
+        x[i] = 0.0;
+        r[i] = b[i];
+        z[i] = r[i] / dg[i];
+        p[i] = z[i];
+    }
+    double bn = sqrt(dot(np, b, b)), rho = dot(np, r, z);
+    while (it < maxit && sqrt(dot(np, r, r)) > rtol * bn) {
+        spmv(&o->Mp, p, q);
+        double alpha = rho / dot(np, p, q);
+        for (int i = 0; i < np; i++) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+        }
+        for (int i = 0; i < np; i++) z[i] = r[i] / dg[i];
+        double rho_new = dot(np, r, z);
+        for (int i = 0; i < np; i++) p[i] = z[i] + (rho_new / rho) * p[i];
+        rho = rho_new;
+        it++;
+    }
+    free(r); free(z); free(p); free(q); free(dg);
+    return it;
+}
+
+static void stokes_qt(const orc *o, void *ctx, const double *in, double *out)
+{
+    stokes_ctx *c = ctx;
+    int n = o->ndof, np = o->np;
+    double *yp = out + 3 * (size_t)n;
+    mass_pcg(o, in + 3 * (size_t)n, yp, 1e-6, 200);
+    for (int i = 0; i < np; i++) yp[i] = -yp[i];
+    spmv(&o->BdivT, yp, c->t);
+    for (int k = 0; k < 3; k++) {
+        for (int i = 0; i < n; i++) c->c1[i] = in[(size_t)k * n + i] - c->t[(size_t)k * n + i];
+        apply_B(o, c->B, c->c1, out + (size_t)k * n);
+    }
+}
+
+int orc_stokes_fgmres(const orc *o, int fp32, const double *b, double *x, double tol, int m, int maxit,
+                      int *iters, double *relres, double *hist)
+{
+    if (!o->np) return -1;
+    bops B;
+    bops_init(o, fp32, &B);
+    int n = o->ndof;
+    stokes_ctx c = {&B, malloc(3 * (size_t)n * sizeof(double)), malloc((size_t)n * sizeof(double)), NULL};
+    int st = orc_fgmres_core(o, 3 * n + o->np, stokes_op, stokes_qt, &c, b, x, tol, m, maxit, iters, relres, hist);
+    free(c.t);
+    free(c.c1);
+    bops_free(&B);
+    return st;
+}
+
+/* out = F in (the saddle-point operator), for tests */
+int orc_stokes_apply_operator(const orc *o, const double *in, double *out)
+{
+    if (!o->np) return -1;
+    stokes_ctx c = {NULL, malloc(3 * (size_t)o->ndof * sizeof(double)), NULL, NULL};
+    stokes_op(o, &c, in, out);
+    free(c.t);
+    return 0;
+}
+
+/* out = Q_t in with B in FP64 (fp32 = 0) or FP32, for tests */
+int orc_stokes_apply_qt(const orc *o, int fp32, const double *in, double *out)
+{
+    if (!o->np) return -1;
+    bops B;
+    bops_init(o, fp32, &B);
+    stokes_ctx c = {&B, malloc(3 * (size_t)o->ndof * sizeof(double)), malloc((size_t)o->ndof * sizeof(double)), NULL};
+    stokes_qt(o, &c, in, out);
+    free(c.t);
+    free(c.c1);
+    bops_free(&B);
+    return 0;
 }

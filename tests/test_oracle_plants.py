@@ -71,6 +71,10 @@ PLANTS = {
         [("orc_solve.c", "        small_cholesky_solve(s, Lg, coef);", "")],
         ["test_oracle_block_cg.py::test_block_krylov_projection",
          "test_oracle_block_cg.py::test_one_column_is_cg"]),
+    # Stokes: B assembled as +div instead of -div
+    "stokes_divergence_sign": (
+        [("orc_fem.c", "bv[cb] = -det * Bt[p][c][a];", "bv[cb] = det * Bt[p][c][a];")],
+        ["test_oracle_stokes.py::test_gradient_of_linear_pressure_is_a_load_vector"]),
     # FGMRES: sign of the rotated right-hand side
     "fgmres_givens_rhs_sign": (
         [("orc_solve.c", "g[j + 1] = -sn[j] * g[j];", "g[j + 1] = sn[j] * g[j];")],
