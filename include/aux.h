@@ -200,6 +200,21 @@ void aux_default_options(aux_options *opt);
 int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt,
               const aux_device *dev, aux_handle **out);
 
+/* A new per-tet coefficient on the same mesh (Sec. 2, eq. (2.5) with kappa
+ * one positive value per tet): kappa host [n_tets].  The device assembles
+ * A_h into its existing sliced-ELL slots (FP64 and FP32), its l1 norms, the
+ * P^1 stiffness A_H and the matrix-free weights, repeating the host
+ * assembly's arithmetic in its order (the operators equal those of a new
+ * aux_setup bit for bit); the host builds the AMG hierarchy of the new A_H
+ * (strength, PMIS, extended+i, Galerkin products) and the coefficient-
+ * dependent device data are rebuilt.  The dof numbering, patterns, layouts,
+ * I_P and tet metrics are kept.  The first call also builds the mesh-only
+ * assembly maps (each entry's list of element-matrix contributions, about
+ * nnz(A_h) * 3 int32 of device memory).  aux_info.setup_seconds then reports
+ * this call's time.  Synchronises the stream.  Errors: AUX_EINVAL (kappa <= 0
+ * or not finite), AUX_ENOMEM, AUX_EHIP. */
+int aux_set_kappa(aux_handle *h, const double *kappa);
+
 /* Release everything the handle owns (waits for its stream).  NULL is a no-op. */
 int aux_destroy(aux_handle *h);
 

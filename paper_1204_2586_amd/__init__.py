@@ -135,6 +135,7 @@ def load_library():
         "aux_apply": (ctypes.c_int, [vp, vp, vp]),
         "pcg_solve": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, P(_SolveInfo)]),
         "pcg_solve_noalloc": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, P(_SolveInfo)]),
+        "aux_set_kappa": (ctypes.c_int, [vp, vp]),
         "pcg_solve_block": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, dbl, ctypes.c_int, P(_SolveInfo)]),
         "pcg_solve_batched": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, dbl, ctypes.c_int, P(_SolveInfo)]),
         "fgmres_solve": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int, vp, P(_SolveInfo)]),
@@ -260,6 +261,17 @@ class Solver:
     def _sync_stream(self):
         s = self._torch.cuda.current_stream(self.device).cuda_stream
         _check(load_library().aux_set_stream(self._h, ctypes.c_void_p(s)))
+
+    def set_kappa(self, kappa):
+        """A new per-tet coefficient on the same mesh: the device re-assembles
+        A_h, A_H and the l1 norms (bitwise as a new setup would), the host
+        rebuilds the AMG hierarchy."""
+        kap = np.ascontiguousarray(kappa, dtype=np.float64)
+        if kap.shape != (self.n_tets,):
+            raise ValueError(f"kappa must have shape ({self.n_tets},)")
+        self._kappa = kap
+        _check(load_library().aux_set_kappa(self._h, _np_ptr(kap)))
+        self.info = self._info()
 
     def set_precision(self, precision: str):
         _check(load_library().aux_set_precision(self._h, {"fp64": FP64, "mixed": MIXED}[precision]))
@@ -514,8 +526,10 @@ class Solver:
 class KappaSolve:
     """Mesh, order and options for the differentiable solve u = A(kappa)^{-1} f.
 
-    The AMG hierarchy depends on kappa, so a new kappa triggers a new host
-    setup; the last solver is cached by the kappa values.
+    One solver per mesh: the first kappa runs the full setup, a new kappa
+    re-assembles on the device and rebuilds the AMG hierarchy
+    (Solver.set_kappa).  The solver's current kappa is tracked so a backward
+    pass whose forward used another kappa re-assembles that one first.
     """
 
     def __init__(self, xyz, tets, order: int, tol: float = 1e-12, **options):
@@ -523,12 +537,17 @@ class KappaSolve:
         self._key = None
         self._solver = None
 
+    @staticmethod
+    def key_of(kappa: np.ndarray):
+        return hash(kappa.tobytes())
+
     def solver_for(self, kappa: np.ndarray) -> Solver:
-        key = hash(kappa.tobytes())
-        if self._key != key:
-            # the previous solver stays alive while an autograd graph refers to it
+        key = self.key_of(kappa)
+        if self._solver is None:
             self._solver = Solver(self.xyz, self.tets, self.order, kappa, **self.options)
-            self._key = key
+        elif self._key != key:
+            self._solver.set_kappa(kappa)
+        self._key = key
         return self._solver
 
 
@@ -549,7 +568,7 @@ def _make_autograd():
             kappa = torch.exp(log_kappa.detach().double()).cpu().numpy()
             s = problem.solver_for(kappa)
             u, info = s.solve(f.detach().double().contiguous(), tol=problem.tol)
-            ctx.solver, ctx.tol = s, problem.tol
+            ctx.solver, ctx.tol, ctx.problem, ctx.kappa = s, problem.tol, problem, kappa
             ctx.kdtype, ctx.kdevice = log_kappa.dtype, log_kappa.device
             ctx.save_for_backward(u)
             return u
@@ -557,7 +576,8 @@ def _make_autograd():
         @staticmethod
         def backward(ctx, grad_u):
             (u,) = ctx.saved_tensors
-            s = ctx.solver
+            # the operator of this forward pass (another may have run since)
+            s = ctx.problem.solver_for(ctx.kappa)
             lam, _ = s.solve(grad_u.double().contiguous(), tol=ctx.tol)
             g = s.kappa_grad(u, lam)
             return lam, g.to(dtype=ctx.kdtype, device=ctx.kdevice), None

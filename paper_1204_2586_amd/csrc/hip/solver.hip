@@ -21,6 +21,7 @@
 
 #include "../host/setup.hpp"
 #include "aux.h"
+#include "assemble.hpp"
 #include "batched.hpp"
 #include "blockcg.hpp"
 #include "kernels.hpp"
@@ -576,13 +577,36 @@ struct aux_handle {
             }
         }
         perm = upload(sell.perm);
-        l1i.resize(disc.ndof);
-        for (int i = 0; i < disc.ndof; i++) l1i[i] = disc.l1[sell.perm[i]];
-        dinv64 = upload(inverse(l1i));
         IPi = permute_rows(disc.IP, sell.perm);
         IRi = transpose(IPi);
         IP = upload_op2(IPi);
         IR = upload_op(IRi);
+        upload_coefficient_part(true);
+        int n = disc.ndof;
+        r = dnew<double>(n);
+        z = dnew<double>(n);
+        p = dnew<double>(n);
+        q = dnew<double>(n);
+        xi = dnew<double>(n);
+        fi = dnew<double>(n);
+        partials = dnew<double>(kMaxBlocks);
+        scal = dnew<double>(8);
+        istate = dnew<int>(4);
+        HIPCHECK(hipHostMalloc((void **)&host_state, 4 * sizeof(int), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void **)&host_scal, 8 * sizeof(double), hipHostMallocDefault));
+        ensure_hist(std::max(opt.maxit, 16));
+    }
+
+    // Everything on the device that depends on the coefficient beyond A_h's
+    // values, built from the host discretisation and hierarchy: the l1
+    // diagonal, the AMG levels and coarse inverse, the composite cycle
+    // operators, the dense sub-cycle and the fused restriction, with the
+    // storage of the cycle's operators chosen again (first: I_P's as well).
+    void upload_coefficient_part(bool first)
+    {
+        l1i.resize(disc.ndof);
+        for (int i = 0; i < disc.ndof; i++) l1i[i] = disc.l1[sell.perm[i]];
+        dinv64 = upload(inverse(l1i));
         lev.resize(hier.levels.size());
         for (size_t l = 0; l < hier.levels.size(); l++) {
             const AmgLevel &hl = hier.levels[l];
@@ -630,7 +654,7 @@ struct aux_handle {
                     }
                 };
                 force(RF, RF_host);
-                force(IP, IPi);
+                if (first) force(IP, IPi);
                 for (size_t l = 0; l + 1 < lev.size(); l++) {
                     force(lev[l].down, fused_host[l].down);
                     force(lev[l].up, fused_host[l].up);
@@ -639,7 +663,7 @@ struct aux_handle {
                 const size_t fb = (size_t)512 << 20;    // twice the last-level cache
                 void *flush = dalloc(fb);
                 tune_op(RF, RF_host, disc.ndof, flush, fb);
-                tune_op(IP, IPi, 0, flush, fb);
+                if (first) tune_op(IP, IPi, 0, flush, fb);
                 for (size_t l = 0; l + 1 < lev.size(); l++) {
                     if (lev[l].A.n < 8192) break;
                     tune_op(lev[l].down, fused_host[l].down, 0, flush, fb);
@@ -648,19 +672,6 @@ struct aux_handle {
                 dfree(flush);
             }
         }
-        int n = disc.ndof;
-        r = dnew<double>(n);
-        z = dnew<double>(n);
-        p = dnew<double>(n);
-        q = dnew<double>(n);
-        xi = dnew<double>(n);
-        fi = dnew<double>(n);
-        partials = dnew<double>(kMaxBlocks);
-        scal = dnew<double>(8);
-        istate = dnew<int>(4);
-        HIPCHECK(hipHostMalloc((void **)&host_state, 4 * sizeof(int), hipHostMallocDefault));
-        HIPCHECK(hipHostMalloc((void **)&host_scal, 8 * sizeof(double), hipHostMallocDefault));
-        ensure_hist(std::max(opt.maxit, 16));
     }
 
     void ensure_hist(int maxit)
@@ -674,9 +685,15 @@ struct aux_handle {
     {
         if (fp32_ready) return;
         A.v32 = upload(to_f32(sell.val));
-        dinv32 = upload(to_f32(inverse(l1i)));
         if (!IP.v32) IP.v32 = upload(to_f32(IPi.val));
         IR.v32 = upload(to_f32(IRi.val));
+        fp32_coefficient_part();
+        fp32_ready = true;
+    }
+    // FP32 copies of the coefficient-dependent operators
+    void fp32_coefficient_part()
+    {
+        dinv32 = upload(to_f32(inverse(l1i)));
         for (size_t l = 0; l < hier.levels.size(); l++) {
             const AmgLevel &hl = hier.levels[l];
             lev[l].A.v32 = upload(to_f32(hl.A.val));
@@ -687,7 +704,6 @@ struct aux_handle {
             }
         }
         cinv32 = upload(to_f32(hier.coarse_inv));
-        fp32_ready = true;
     }
 
     template <typename T>
@@ -2049,6 +2065,145 @@ struct aux_handle {
         return code;
     }
 
+    // ------------------------------------------------------------ new coefficient
+    // A new per-tet kappa on the same mesh (aux_set_kappa).  The device
+    // assembles A_h into its sliced-ELL slots (FP64 and FP32), its l1 norms,
+    // A_H and the matrix-free weights, repeating the host assembly's
+    // arithmetic in its order (bitwise equal); the host keeps copies of the
+    // values for its own use and builds the AMG hierarchy of the new A_H,
+    // then the coefficient-dependent device data are rebuilt.  What depends
+    // on the mesh alone (dof numbering, patterns, layouts, I_P, the tet
+    // metrics and each entry's list of element-matrix contributions) is kept.
+    struct AsmMaps {
+        bool ready = false;
+        int *a_ptr = nullptr, *a_idx = nullptr, *a_pos = nullptr, *a_rowptr = nullptr;
+        int *h_ptr = nullptr, *h_idx = nullptr;
+    } asmd;
+
+    void ensure_assembly_maps()
+    {
+        if (asmd.ready) return;
+        ensure_adjoint();                          // tet metrics, kappa, reference tables on the device
+        const int n = disc.ndof, nt = disc.nt;
+        std::vector<int> ptr, idx;
+        assembly_map(disc.A, nt, disc.nloc, disc.tet_dof.data(), ptr, idx);
+        asmd.a_ptr = upload(ptr);
+        asmd.a_idx = upload(idx);
+        std::vector<int> pos(disc.A.col.size());
+        for (int r = 0; r < n; r++) {
+            const int sl = r / kSlice, lane = r % kSlice, i = sell.perm[r];
+            for (int e = disc.A.ptr[i], j = 0; e < disc.A.ptr[i + 1]; e++, j++)
+                pos[e] = sell.slice_off[sl] + j * kSlice + lane;
+        }
+        asmd.a_pos = upload(pos);
+        asmd.a_rowptr = upload(disc.A.ptr);
+        std::vector<int> vmap((size_t)nt * 4);
+        for (size_t q = 0; q < vmap.size(); q++) vmap[q] = disc.vert_dof[disc.tets[q]];
+        assembly_map(disc.AH, nt, 4, vmap.data(), ptr, idx);
+        asmd.h_ptr = upload(ptr);
+        asmd.h_idx = upload(idx);
+        asmd.ready = true;
+    }
+
+    void free_op(DevOp &op)
+    {
+        drop_ell(op);
+        for (void *b : {(void *)op.ptr, (void *)op.col, (void *)op.v64, (void *)op.v32}) dfree(b);
+        op = DevOp();
+    }
+
+    // every device buffer built from the coefficient-dependent operators
+    void release_coefficient_part()
+    {
+        drop_graph();
+        dfree(dinv64);
+        dfree(dinv32);
+        dinv64 = nullptr;
+        dinv32 = nullptr;
+        for (Lev &L : lev) {
+            for (DevOp *op : {&L.A, &L.P, &L.R, &L.down, &L.up}) free_op(*op);
+            dfree(L.dinv64);
+            dfree(L.dinv32);
+        }
+        lev.clear();
+        for (void *b : {(void *)cinv64, (void *)cinv32, (void *)dcyc64, (void *)dcyc32}) dfree(b);
+        cinv64 = dcyc64 = nullptr;
+        cinv32 = dcyc32 = nullptr;
+        dense_first = SIZE_MAX;
+        free_op(RF);
+        RF_host = Csr();
+        fused_host.clear();
+        release_work(w64);
+        release_work(w32);
+        // batched forms: rebuilt on their next use
+        release_batch();
+        auto free_bop = [&](BOp &b) {
+            free_sell(b.m);
+            for (void *q : {(void *)b.perm, (void *)b.s64, (void *)b.s32}) dfree(q);
+            b = BOp();
+        };
+        for (std::vector<BOp> *v : {&bA, &bP, &bR})
+            for (BOp &b : *v) free_bop(b);
+        bA.clear();
+        bP.clear();
+        bR.clear();
+        for (BOp *b : {&bIP, &bIR, &bRF}) free_bop(*b);
+        bops_ready = false;
+        for (DevTiles &d : tiles) {
+            for (void *q : {(void *)d.rows, (void *)d.row_ptr, (void *)d.col_off, (void *)d.ucols, (void *)d.lidx,
+                            (void *)d.v64, (void *)d.v32})
+                dfree(q);
+            d = DevTiles();
+        }
+        tiles_ready = false;
+        if (opt.batch_order && bo.ready) {
+            free_sell(bo.A);
+            for (void *q : {(void *)bo.die_off, (void *)bo.perm_d, (void *)bo.dinv64, (void *)bo.dinv32}) dfree(q);
+        }
+        bo = BOrder();
+    }
+
+    void set_kappa(const double *kap)
+    {
+        const int nt = disc.nt, nl = disc.nloc, n = disc.ndof;
+        for (int t = 0; t < nt; t++)
+            if (!(kap[t] > 0.0) || !std::isfinite(kap[t])) throw AuxError(AUX_EINVAL, "kappa must be positive and finite");
+        ensure_fp32();                             // A_h's FP32 slots are refreshed with the FP64 ones
+        ensure_assembly_maps();
+        hipStream_t s = stream;
+        HIPCHECK(hipMemcpyAsync(kappa_d, kap, (size_t)nt * sizeof(double), hipMemcpyHostToDevice, s));
+        const size_t nnzA = disc.A.col.size(), nnzH = disc.AH.col.size();
+        double *Ke = dnew<double>((size_t)nt * nl * nl);
+        double *aval = dnew<double>(nnzA), *l1e = dnew<double>(n), *hval = dnew<double>(std::max<size_t>(nnzH, 1));
+        element_matrices(s, nt, nl, G, kappa_d, Mtab, Ke);
+        gather_entries(s, (long long)nnzA, asmd.a_ptr, asmd.a_idx, Ke, nullptr, aval, asmd.a_pos, A.v64, A.v32);
+        row_l1(s, n, asmd.a_rowptr, aval, l1e);
+        if (nnzH) gather_entries(s, (long long)nnzH, asmd.h_ptr, asmd.h_idx, G, kappa_d, hval, nullptr, nullptr, nullptr);
+        if (mf_ready) mf_weights(s, nt, G, kappa_d, mf_w64, mf_w32);
+        // host copies of the new values
+        HIPCHECK(hipMemcpyAsync(disc.A.val.data(), aval, nnzA * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipMemcpyAsync(sell.val.data(), A.v64, sell.val.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipMemcpyAsync(disc.l1.data(), l1e, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (nnzH) HIPCHECK(hipMemcpyAsync(disc.AH.val.data(), hval, nnzH * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        for (void *b : {(void *)Ke, (void *)aval, (void *)l1e, (void *)hval}) dfree(b);
+        disc.kappa.assign(kap, kap + nt);
+        // the hierarchy of the new A_H and everything built from it
+        release_coefficient_part();
+        hier = Hierarchy();
+        SetupOptions so;
+        so.theta = opt.theta;
+        so.coarse_max = opt.coarse_max;
+        so.max_levels = opt.max_levels;
+        so.seed = opt.pmis_seed;
+        if (disc.nH > 0) build_hierarchy(disc.AH, so, hier);
+        upload_coefficient_part(false);
+        if (fp32_ready) fp32_coefficient_part();
+        work<double>();
+        if (opt.precision == AUX_MIXED) work<float>();
+        HIPCHECK(hipStreamSynchronize(s));
+    }
+
     void apply_external(const double *rext, double *zext)
     {
         int n = disc.ndof;
@@ -2408,6 +2563,20 @@ int aux_export_cf(const aux_handle *h, int level, int32_t *cf)
             throw AuxError(AUX_EINVAL, "no splitting on this level");
         const auto &v = h->hier.levels[level].cf;
         std::memcpy(cf, v.data(), v.size() * sizeof(int32_t));
+        return AUX_OK;
+    });
+}
+
+int aux_set_kappa(aux_handle *h, const double *kappa)
+{
+    return guarded([&]() {
+        need_device(h);
+        if (!kappa) throw AuxError(AUX_EINVAL, "null kappa");
+        set_dev(h);
+        auto t0 = std::chrono::steady_clock::now();
+        h->set_kappa(kappa);
+        HIPCHECK(hipGetLastError());
+        h->setup_seconds = seconds_since(t0);
         return AUX_OK;
     });
 }

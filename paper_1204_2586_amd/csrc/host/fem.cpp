@@ -552,6 +552,36 @@ void build_discretization(Discretization &d, int nv, const double *xyz, int nt, 
     d.IR = transpose(d.IP);
 }
 
+// ------------------------------------------------------------ assembly maps
+
+void assembly_map(const Csr &A, int nt, int nl, const int *emap, std::vector<int> &ptr, std::vector<int> &idx)
+{
+    if ((int64_t)nt * nl * nl > 0x7fffffff) throw std::invalid_argument("assembly map: too many element entries");
+    const size_t nnz = A.col.size();
+    ptr.assign(nnz + 1, 0);
+    // entry of row i, column j (columns of a row are sorted)
+    auto entry = [&](int i, int j) { return find_col(A, i, j); };
+    for (int t = 0; t < nt; t++) {
+        const int *dm = emap + (size_t)t * nl;
+        for (int a = 0; a < nl; a++) {
+            if (dm[a] < 0) continue;
+            for (int b = 0; b < nl; b++)
+                if (dm[b] >= 0) ptr[entry(dm[a], dm[b]) + 1]++;
+        }
+    }
+    for (size_t e = 0; e < nnz; e++) ptr[e + 1] += ptr[e];
+    idx.assign((size_t)ptr[nnz], 0);
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (int t = 0; t < nt; t++) {             // increasing t: the host assembly's order
+        const int *dm = emap + (size_t)t * nl;
+        for (int a = 0; a < nl; a++) {
+            if (dm[a] < 0) continue;
+            for (int b = 0; b < nl; b++)
+                if (dm[b] >= 0) idx[fill[entry(dm[a], dm[b])]++] = (t * nl + a) * nl + b;
+        }
+    }
+}
+
 // ------------------------------------------------------------ load vector
 
 namespace {

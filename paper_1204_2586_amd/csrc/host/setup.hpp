@@ -61,6 +61,12 @@ struct Hierarchy {
 // local multi-indices of the P^k tet (|alpha| = k), lexicographic
 std::vector<int> multi_indices(int k);
 
+// For each entry e of the operator A assembled from the element map emap
+// [nt][nl] (-1 = eliminated): the element-matrix entries (t * nl + a) * nl + b
+// that sum into it, in increasing t, the order of the host assembly
+// (entry e takes idx[ptr[e] .. ptr[e+1])).  Depends on the mesh only.
+void assembly_map(const Csr &A, int nt, int nl, const int *emap, std::vector<int> &ptr, std::vector<int> &idx);
+
 // Throws std::invalid_argument on bad input.
 void build_discretization(Discretization &d, int nv, const double *xyz, int nt, const int32_t *tets,
                           int k, const double *kappa);
