@@ -364,6 +364,83 @@ def run_extra_p3(args):
     return out
 
 
+def run_stokes(args):
+    """Stokes, Hood-Taylor P2-P1 (Sec. 5) on the jittered P2 48^3 mesh:
+    FGMRES(30) with the block triangular preconditioner Q_t to 1e-8 from
+    zero, body force of a smooth manufactured solution; one step is one
+    solve.  The oracle solves the 16^3 system of the same family (the CPU
+    sample, and the GPU's error against it at that size)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1204_2586_amd as aux
+    import workloads as W
+    dev = torch.device("cuda:0")
+
+    def system(n):
+        xyz, tets = W.kuhn_mesh(n, jitter=0.2, seed=0)
+        t0 = time.time()
+        s = aux.Solver(xyz, tets, 2, nu=args.nu, precision="mixed", device=dev)
+        npr = s.stokes_setup()
+        setup_s = time.time() - t0
+        b = np.concatenate([s.load(W.stokes_f(c)) for c in range(3)] + [np.zeros(npr)])
+        return xyz, tets, s, b, setup_s
+
+    xyz, tets, s, b, setup_s = system(48)
+    bt = torch.tensor(b, dtype=torch.float64, device=dev)
+    N = 3 * s.n + s.n_p
+    reps = max(1, min(args.steps, 5))
+    res = {}
+    for mode in ("mixed", "fp64"):
+        s.set_precision(mode)
+        s.stokes_fgmres(bt, tol=1e-8, restart=30)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            x, info, _ = s.stokes_fgmres(bt, tol=1e-8, restart=30)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / reps
+        true_res = float(torch.linalg.norm(bt - s.stokes_operator(x)) / torch.linalg.norm(bt))
+        res[mode] = dict(ms=ms, iterations=info.iterations, true_rel_residual=true_res)
+    r = torch.zeros(N, dtype=torch.float64, device=dev)
+    r[3 * s.n:] = torch.tensor(np.random.default_rng(3).standard_normal(s.n_p), dtype=torch.float64, device=dev)
+    _, mass_steps = s.stokes_qt(r)
+    out = {"metric": "Stokes FGMRES(30) + Q_t solve throughput to 1e-8", "unit": "unknowns/s",
+           "value": N / (res["mixed"]["ms"] * 1e-3), "ms_per_solve": round(res["mixed"]["ms"], 3),
+           "dtype": "f64 FGMRES / f32 velocity preconditioner / f64 pressure mass CG",
+           "config": {"workload": "stokes_p2p1_n48_jitter", "cubes_per_side": 48, "jitter": 0.2,
+                      "n_velocity": 3 * s.n, "n_pressure": s.n_p, "unknowns": N,
+                      "iterations": res["mixed"]["iterations"],
+                      "true_rel_residual": res["mixed"]["true_rel_residual"],
+                      "us_per_fgmres_step": round(res["mixed"]["ms"] * 1e3 / max(res["mixed"]["iterations"], 1), 1),
+                      "mass_cg_steps_per_qt": mass_steps, "setup_s": round(setup_s, 2)},
+           "fp64": {"value": N / (res["fp64"]["ms"] * 1e-3), "ms_per_solve": round(res["fp64"]["ms"], 3),
+                    "iterations": res["fp64"]["iterations"], "true_rel_residual": res["fp64"]["true_rel_residual"]}}
+    del s, bt
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        xyz, tets, s, b, _ = system(16)
+        x, info, _ = s.stokes_fgmres(torch.tensor(b, dtype=torch.float64, device=dev), tol=1e-8, restart=30)
+        x = x.cpu().numpy()
+        P = oracle.Problem(xyz, tets, 2).setup_amg(nu=args.nu).stokes_setup()
+        t0 = time.perf_counter()
+        xo, it, rr, st, _ = P.stokes_fgmres(b, tol=1e-8, restart=30, fp32=True)
+        dt = time.perf_counter() - t0
+        m = s.n
+        pm = lambda v: v[3 * m:] - v[3 * m:].mean()
+        out["cpu_baseline"] = {"value": len(b) / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one FGMRES(30) + Q_t solve (FP32 velocity preconditioner) of the "
+                                         f"jittered P2-P1 16^3 system ({len(b)} unknowns) to 1e-8, {it} steps, "
+                                         f"{dt:.1f} s"}
+        out["oracle_error_16"] = {"gpu_steps": info.iterations, "oracle_steps": it,
+                                  "velocity_rel_diff": float(np.linalg.norm(x[:3 * m] - xo[:3 * m])
+                                                             / np.linalg.norm(xo[:3 * m])),
+                                  "pressure_rel_diff_mod_const": float(np.linalg.norm(pm(x) - pm(xo))
+                                                                       / np.linalg.norm(pm(xo)))}
+    return out
+
+
 def run(args):
     import numpy as np
     import torch
@@ -439,6 +516,8 @@ def run(args):
         a = argparse.Namespace(**vars(args))
         a.workload = "p2_n64_32rhs"
         out["workloads"]["p2_n64_32rhs"] = summarize_batched(run_batched(a))
+        torch.cuda.empty_cache()
+        out["workloads"]["stokes_p2p1_n48_jitter"] = run_stokes(args)
     return out
 
 
@@ -865,9 +944,9 @@ def main():
     ap.add_argument("--workload", default="p2_n48_jitter", choices=sorted(WORKLOADS))
     ap.add_argument("--tol", type=float, default=None,
                     help="relative residual (default 1e-8 for CG, 1e-6 for FGMRES, the paper's)")
-    ap.add_argument("--krylov", default="cg", choices=["cg", "fgmres"],
+    ap.add_argument("--krylov", default="cg", choices=["cg", "fgmres", "stokes"],
                     help="cg: time to 1e-8 from zero; fgmres: the paper's protocol (zero right-hand side, "
-                         "random initial guess)")
+                         "random initial guess); stokes: the P2-P1 Stokes solve with Q_t on the 48^3 mesh")
     ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length")
     ap.add_argument("--nu", type=int, default=2,
                     help="l1-Jacobi sweeps before and after the coarse correction (the workloads are defined with 2)")
@@ -897,7 +976,9 @@ def main():
         print(json.dumps({"error": "FGMRES runs the single-vector solve workloads only"}))
         sys.exit(2)
     wl = WORKLOADS[args.workload]
-    if "nrhs" in wl:
+    if args.krylov == "stokes":
+        fn = run_stokes
+    elif "nrhs" in wl:
         fn = run_batched
     elif wl.get("adjoint"):
         fn = run_adjoint

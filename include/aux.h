@@ -256,7 +256,8 @@ int aux_qpoints(const aux_handle *h, int32_t t0, int32_t t1, double *xyzq);
 int aux_load_accumulate(const aux_handle *h, int32_t t0, int32_t t1, const double *fq, double *b);
 
 /* Export a host copy of a matrix for inspection.  which: 0 = A_h, 1 = A_H,
- * 2 = I_P, 3 = AMG level operator A_level, 4 = AMG interpolation P_level.
+ * 2 = I_P, 3 = AMG level operator A_level, 4 = AMG interpolation P_level,
+ * 5 = Stokes B, 6 = pressure mass matrix M_p (after aux_stokes_setup).
  * With ptr == NULL only shape[3] = {rows, cols, nnz} is written; otherwise
  * ptr host int32 [rows+1], col int32 [nnz], val double [nnz] receive the CSR. */
 int aux_export_csr(const aux_handle *h, int which, int level, int64_t *shape, int32_t *ptr,
@@ -339,6 +340,46 @@ int pcg_solve_block(aux_handle *h, const double *F, double *U, int nrhs, double 
  * the last iterate), AUX_ENAN or AUX_EINVAL. */
 int fgmres_solve(aux_handle *h, const double *b, double *x, double tol, int restart, int maxit, double *history,
                  aux_solve_info *info);
+
+/* Stokes system of the Hood-Taylor P^2-P^1 pair (Sec. 5, the paper's second
+ * test problem) on the handle's mesh, order-2 handles only:
+ *     [A  B^T] [u]   [f]
+ *     [B   0 ] [p] = [g],   A = diag(A_h, A_h, A_h),
+ * velocity u = (u_0, u_1, u_2) on the handle's dofs (zero on the boundary;
+ * A_h with the handle's kappa as viscosity), pressure p in P^1 on every mesh
+ * vertex (no boundary condition; constants are the null space of B^T),
+ * B_{q,(c,i)} = -int lam_q dphi_i/dx_c (the discrete -div) and M_p the P^1
+ * pressure mass matrix (int lam_q lam_r), both integrated exactly.  A Stokes
+ * vector is a device double array [3 n_h + n_v]: u_0, u_1, u_2 in the dof
+ * order of aux_dof_keys, then p in vertex order.
+ *
+ * aux_stokes_setup builds B and M_p (host assembly, then a device copy of B,
+ * B^T and M_p, about 24 nnz(A_h) bytes) and writes n_v to *n_p (may be NULL);
+ * on a host-only handle it builds the host matrices only (aux_export_csr
+ * which = 5 is B, 6 is M_p afterwards).  The other calls run it on first
+ * use.  Errors: AUX_EINVAL (order other than 2), AUX_ENOMEM, AUX_EHIP. */
+int aux_stokes_setup(aux_handle *h, int32_t *n_p);
+/* y = [A B^T; B 0] x in FP64 (device x, y [3 n_h + n_v]; the handle's
+ * operator form for A_h). */
+int stokes_apply_operator(aux_handle *h, const double *x, double *y);
+/* z = Q_t r, the block triangular preconditioner of Sec. 5 with the Schur
+ * complement replaced by M_p and A^{-1} by the auxiliary-space preconditioner
+ * B (one application per velocity component, the handle's precision):
+ *     z_p = -M_p^{-1} r_p,   z_c = B (r_c - (B^T z_p)_c),
+ * with M_p^{-1} r_p computed by diagonally preconditioned CG from zero until
+ * ||r_p - M_p x|| <= 1e-6 ||r_p|| (at most 200 steps).  Device r, z
+ * [3 n_h + n_v], not aliased.  mass_steps (host, may be NULL) receives the CG
+ * step count.  Synchronises the stream (the mass CG's stop test). */
+int stokes_apply_qt(aux_handle *h, const double *r, double *z, int32_t *mass_steps);
+/* Flexible GMRES(restart) on the Stokes system with Q_t as the right
+ * preconditioner (the paper's Stokes solver: FGMRES with Q_t).  Arguments,
+ * stopping rule, history and statuses as fgmres_solve, on vectors
+ * [3 n_h + n_v]; the basis takes (2 restart + 1) (3 n_h + n_v) doubles of
+ * device memory, kept until the handle is destroyed.  A right-hand side
+ * with a pressure part orthogonal to the constants and a compatible
+ * velocity part has solutions unique up to a constant pressure. */
+int stokes_fgmres_solve(aux_handle *h, const double *b, double *x, double tol, int restart, int maxit,
+                        double *history, aux_solve_info *info);
 
 /* y = A_h x (device x, y [n_h]), FP64. */
 int aux_matvec(aux_handle *h, const double *x, double *y);

@@ -84,6 +84,7 @@ def _load():
     lib.orc_stokes_fgmres.argtypes = [vp, ctypes.c_int, _f64p, _f64p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), _f64p]
     lib.orc_stokes_apply_operator.argtypes = [vp, _f64p, _f64p]
+    lib.orc_stokes_apply_qt.restype = ctypes.c_int
     lib.orc_stokes_apply_qt.argtypes = [vp, ctypes.c_int, _f64p, _f64p]
     lib.orc_block_pcg.restype = ctypes.c_int
     lib.orc_block_pcg.argtypes = [vp, ctypes.c_int, ctypes.c_int, _f64p, _f64p, ctypes.c_double, ctypes.c_int,
@@ -331,10 +332,11 @@ class Problem:
         _load().orc_stokes_apply_operator(self._h, np.ascontiguousarray(x, dtype=np.float64), out)
         return out
 
-    def stokes_qt(self, r, fp32: bool = False) -> np.ndarray:
+    def stokes_qt(self, r, fp32: bool = False, steps: bool = False):
+        """Q_t r; with steps=True also the pressure mass solve's CG step count."""
         out = np.zeros(3 * self.n + self.np)
-        _load().orc_stokes_apply_qt(self._h, int(fp32), np.ascontiguousarray(r, dtype=np.float64), out)
-        return out
+        k = _load().orc_stokes_apply_qt(self._h, int(fp32), np.ascontiguousarray(r, dtype=np.float64), out)
+        return (out, k) if steps else out
 
     def stokes_fgmres(self, b, tol=1e-8, restart=30, maxit=500, x0=None, fp32: bool = False):
         """FGMRES(restart) with the block triangular preconditioner Q_t on the

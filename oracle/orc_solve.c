@@ -606,6 +606,7 @@ int orc_fgmres(const orc *o, int prec, const double *b, double *x, double tol, i
 typedef struct {
     const bops *B;
     double *t, *c1, *c2;          /* work vectors */
+    int mass_steps;               /* CG steps of the last pressure mass solve */
 } stokes_ctx;
 
 static void stokes_op(const orc *o, void *ctx, const double *in, double *out)
@@ -658,7 +659,7 @@ static void stokes_qt(const orc *o, void *ctx, const double *in, double *out)
     stokes_ctx *c = ctx;
     int n = o->ndof, np = o->np;
     double *yp = out + 3 * (size_t)n;
-    mass_pcg(o, in + 3 * (size_t)n, yp, 1e-6, 200);
+    c->mass_steps = mass_pcg(o, in + 3 * (size_t)n, yp, 1e-6, 200);
     for (int i = 0; i < np; i++) yp[i] = -yp[i];
     spmv(&o->BdivT, yp, c->t);
     for (int k = 0; k < 3; k++) {
@@ -692,16 +693,17 @@ int orc_stokes_apply_operator(const orc *o, const double *in, double *out)
     return 0;
 }
 
-/* out = Q_t in with B in FP64 (fp32 = 0) or FP32, for tests */
+/* out = Q_t in with B in FP64 (fp32 = 0) or FP32, for tests; returns the
+   pressure mass solve's CG step count (-1 before orc_stokes_setup) */
 int orc_stokes_apply_qt(const orc *o, int fp32, const double *in, double *out)
 {
     if (!o->np) return -1;
     bops B;
     bops_init(o, fp32, &B);
-    stokes_ctx c = {&B, malloc(3 * (size_t)o->ndof * sizeof(double)), malloc((size_t)o->ndof * sizeof(double)), NULL};
+    stokes_ctx c = {&B, malloc(3 * (size_t)o->ndof * sizeof(double)), malloc((size_t)o->ndof * sizeof(double)), NULL, 0};
     stokes_qt(o, &c, in, out);
     free(c.t);
     free(c.c1);
     bops_free(&B);
-    return 0;
+    return c.mass_steps;
 }

@@ -139,6 +139,10 @@ def load_library():
         "pcg_solve_block": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, dbl, ctypes.c_int, P(_SolveInfo)]),
         "pcg_solve_batched": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, dbl, ctypes.c_int, P(_SolveInfo)]),
         "fgmres_solve": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int, vp, P(_SolveInfo)]),
+        "aux_stokes_setup": (ctypes.c_int, [vp, P(i32)]),
+        "stokes_apply_operator": (ctypes.c_int, [vp, vp, vp]),
+        "stokes_apply_qt": (ctypes.c_int, [vp, vp, vp, P(i32)]),
+        "stokes_fgmres_solve": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int, vp, P(_SolveInfo)]),
         "aux_matvec": (ctypes.c_int, [vp, vp, vp]),
         "aux_kappa_grad": (ctypes.c_int, [vp, vp, vp, vp]),
         "aux_profile": (ctypes.c_int, [vp, ctypes.c_int]),
@@ -238,6 +242,7 @@ class Solver:
         self.n = int(self.info.n_h)
         self.nH = int(self.info.n_H)
         self.n_tets = int(self.info.n_tets)
+        self.n_p = None      # pressure count, set by stokes_setup
 
     # ------------------------------------------------------------ lifecycle
     def close(self):
@@ -347,7 +352,7 @@ class Solver:
 
     def export_csr(self, which: str, level: int = 0):
         import scipy.sparse as sp
-        code = {"A": 0, "AH": 1, "IP": 2, "Alev": 3, "P": 4}[which]
+        code = {"A": 0, "AH": 1, "IP": 2, "Alev": 3, "P": 4, "B": 5, "Mp": 6}[which]
         shape = (ctypes.c_int64 * 3)()
         lib = load_library()
         _check(lib.aux_export_csr(self._h, code, level, shape, None, None, None))
@@ -452,6 +457,68 @@ class Solver:
         rc = load_library().fgmres_solve(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), tol,
                                          int(restart), int(maxit), hist.ctypes.data_as(ctypes.c_void_p),
                                          ctypes.byref(info))
+        if check:
+            _check(rc)
+        elif rc not in (0, -4, -6):
+            _check(rc)
+        return x, SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds), \
+            hist[: info.iterations + 1]
+
+    # ------------------------------------------------------------ Stokes
+    def stokes_setup(self) -> int:
+        """Build the Hood-Taylor P2-P1 Stokes blocks B and M_p (order 2);
+        returns the pressure count n_p (the vertex count).  Stokes vectors have
+        3 n_h + n_p entries: u_0, u_1, u_2 in dof order, then p per vertex."""
+        n_p = ctypes.c_int32(0)
+        _check(load_library().aux_stokes_setup(self._h, ctypes.byref(n_p)))
+        self.n_p = int(n_p.value)
+        return self.n_p
+
+    def _stokes_len(self):
+        if self.n_p is None:
+            self.stokes_setup()
+        return 3 * self.n + self.n_p
+
+    def stokes_operator(self, x, out=None):
+        """y = [A B^T; B 0] x."""
+        m = self._stokes_len()
+        x = self._vec(x, "x", n=m)
+        y = self._torch.empty_like(x) if out is None else self._vec(out, "out", n=m)
+        self._sync_stream()
+        _check(load_library().stokes_apply_operator(self._h, ctypes.c_void_p(x.data_ptr()),
+                                                    ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def stokes_qt(self, r, out=None):
+        """z = Q_t r (block triangular preconditioner).  Returns (z, the
+        pressure mass-matrix CG step count)."""
+        m = self._stokes_len()
+        r = self._vec(r, "r", n=m)
+        z = self._torch.empty_like(r) if out is None else self._vec(out, "out", n=m)
+        steps = ctypes.c_int32(0)
+        self._sync_stream()
+        _check(load_library().stokes_apply_qt(self._h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                              ctypes.byref(steps)))
+        return z, int(steps.value)
+
+    def stokes_fgmres(self, b, tol: float = 1e-8, x0=None, restart: int = 30, maxit: int = 0, check: bool = True):
+        """FGMRES(restart) with Q_t on the Stokes system.  Returns (x,
+        SolveInfo, history) as fgmres."""
+        import numpy as np
+        m = self._stokes_len()
+        b = self._vec(b, "b", n=m)
+        if x0 is None:
+            x = self._torch.zeros_like(b)
+        else:
+            x = self._torch.empty_like(b)
+            x.copy_(self._vec(x0, "x0", n=m))
+        cap = (int(maxit) if maxit > 0 else self._maxit) + 1
+        hist = np.zeros(cap)
+        info = _SolveInfo()
+        self._sync_stream()
+        rc = load_library().stokes_fgmres_solve(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                                tol, int(restart), int(maxit), hist.ctypes.data_as(ctypes.c_void_p),
+                                                ctypes.byref(info))
         if check:
             _check(rc)
         elif rc not in (0, -4, -6):

@@ -115,6 +115,11 @@ __global__ __launch_bounds__(kBlock) void k_scale_unit(int n, const double *w, c
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) out[i] = w[i] * inv;
 }
 
+__global__ __launch_bounds__(kBlock) void k_sub_from(int n, const double *__restrict__ a, double *__restrict__ y)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) y[i] = a[i] - y[i];
+}
+
 int krylov_grid(int n)
 {
     long long g = ((long long)n + kBlock - 1) / kBlock;
@@ -147,6 +152,11 @@ void multi_axpy(hipStream_t s, int n, int nv, const double *V, long long ld, con
 void scale_unit(hipStream_t s, int n, const double *w, const double *nrm2, double *out)
 {
     hipLaunchKernelGGL(k_scale_unit, dim3(krylov_grid(n)), dim3(kBlock), 0, s, n, w, nrm2, out);
+}
+
+void sub_from(hipStream_t s, int n, const double *a, double *y)
+{
+    hipLaunchKernelGGL(k_sub_from, dim3(krylov_grid(n)), dim3(kBlock), 0, s, n, a, y);
 }
 
 }  // namespace auxp

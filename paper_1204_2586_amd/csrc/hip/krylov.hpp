@@ -18,5 +18,7 @@ void multi_axpy(hipStream_t s, int n, int nv, const double *V, long long ld, con
                 double *partials, double *nrm2);
 // out = w / sqrt(nrm2[0]) (out = 0 when nrm2[0] is 0); out may equal w
 void scale_unit(hipStream_t s, int n, const double *w, const double *nrm2, double *out);
+// y = a - y (a residual from a product written into y)
+void sub_from(hipStream_t s, int n, const double *a, double *y);
 
 }  // namespace auxp

@@ -27,6 +27,7 @@
 #include "kernels.hpp"
 #include "krylov.hpp"
 #include "mfree.hpp"
+#include "stokes.hpp"
 
 using namespace auxp;
 
@@ -1118,20 +1119,21 @@ struct aux_handle {
     static constexpr int kHs = kMaxRestart + 1;   // stride of the coefficient slots
     struct Fgm {
         int m = 0;
+        size_t len = 0;           // vector length the basis holds
         double *V = nullptr, *Z = nullptr, *part = nullptr;
         double *dh = nullptr;     // [0, kHs) first pass, [kHs, 2 kHs) second pass, [2 kHs] w.w, then y
     } fg;
     double *fg_host = nullptr;    // pinned mirror of fg.dh
 
-    void ensure_fgmres(int m)
+    void ensure_fgmres(int m, size_t len)
     {
-        const size_t n = disc.ndof;
-        if (fg.m < m) {
+        if (fg.m < m || fg.len < len) {
             dfree(fg.V);
             dfree(fg.Z);
-            fg.V = dnew<double>((size_t)(m + 1) * n);
-            fg.Z = dnew<double>((size_t)m * n);
-            fg.m = m;
+            fg.m = std::max(fg.m, m);
+            fg.len = std::max(fg.len, len);
+            fg.V = dnew<double>((size_t)(fg.m + 1) * fg.len);
+            fg.Z = dnew<double>((size_t)fg.m * fg.len);
         }
         if (!fg.part) {
             fg.part = dnew<double>((size_t)kKrylovBlocks * kHs);
@@ -1153,22 +1155,51 @@ struct aux_handle {
         }
     }
 
+    // A system for the flexible GMRES core, on device vectors of length len
+    // in the handle's internal layout.
+    struct KrylovSystem {
+        size_t len;
+        std::function<void(const double *, double *)> prec;                        // z = M v
+        std::function<void(const double *, double *)> op;                          // w = F z
+        std::function<void(const double *, const double *, double *)> residual;    // r = b - F x
+    };
+
     int fgmres(const double *b, double *x, double tol, int m, int maxit, double *history, aux_solve_info *info)
     {
         auto t0 = std::chrono::steady_clock::now();
+        const int n = disc.ndof;
+        if (use_mf()) ensure_mf();
+        vec_gather(stream, n, perm, b, fi);
+        vec_gather(stream, n, perm, x, xi);
+        KrylovSystem K{(size_t)n, [&](const double *v, double *z) { apply(v, z, nullptr, nullptr); },
+                       [&](const double *z, double *w) { op_product(z, w); },
+                       [&](const double *bb, const double *xx, double *r) {
+                           sell_residual64(stream, A.view<double>(), bb, xx, r);
+                       }};
+        const int status = fgmres_core(K, fi, xi, tol, m, maxit, history, info);
+        vec_scatter(stream, n, perm, xi, x);
+        HIPCHECK(hipStreamSynchronize(stream));
+        prof_collect(0);
+        if (info) info->seconds = seconds_since(t0);
+        return status;
+    }
+
+    // Flexible GMRES(m) on F x = b (internal layout, x updated in place):
+    // returns the status and fills info except its time.
+    int fgmres_core(const KrylovSystem &K, const double *b, double *x, double tol, int m, int maxit, double *history,
+                    aux_solve_info *info)
+    {
         if (maxit <= 0) maxit = opt.maxit;
         hipStream_t s = stream;
-        const int n = disc.ndof;
-        const long long ld = n;
-        ensure_fgmres(m);
-        if (use_mf()) ensure_mf();
+        const size_t len = K.len;
+        const int n = (int)len;
+        const long long ld = (long long)len;
+        ensure_fgmres(m, len);
         double *V = fg.V, *Z = fg.Z, *hh = fg_host;
         double *h1 = fg.dh, *h2 = fg.dh + kHs, *nrm = fg.dh + 2 * kHs, *yd = fg.dh + 2 * kHs + 1;
-        vec_gather(s, n, perm, b, fi);
-        vec_gather(s, n, perm, x, xi);
-        // v_0 <- r = b - A x (unnormalised) and ||r||, also the device copy of r.r
+        // v_0 <- r = b - F x (unnormalised) and ||r||
         auto residual_norm = [&]() {
-            sell_residual64(s, A.view<double>(), fi, xi, V);
+            K.residual(b, x, V);
             multi_dot(s, n, 1, V, ld, V, fg.part, nrm);
             HIPCHECK(hipMemcpyAsync(hh + 2 * kHs, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
@@ -1190,8 +1221,8 @@ struct aux_handle {
             bool stop = false;
             for (int j = 0; j < m && it < maxit; j++) {
                 double *vj = V + j * ld, *zj = Z + j * ld, *w = V + (j + 1) * ld;
-                apply(vj, zj, nullptr, nullptr);
-                op_product(zj, w);
+                K.prec(vj, zj);
+                K.op(zj, w);
                 // classical Gram-Schmidt, twice
                 multi_dot(s, n, j + 1, V, ld, w, fg.part, h1);
                 multi_axpy(s, n, j + 1, V, ld, h1, -1.0, w, nullptr, nullptr);
@@ -1244,21 +1275,208 @@ struct aux_handle {
             }
             std::copy(y.begin(), y.begin() + jend, hh + 2 * kHs + 1);
             HIPCHECK(hipMemcpyAsync(yd, hh + 2 * kHs + 1, (size_t)jend * sizeof(double), hipMemcpyHostToDevice, s));
-            multi_axpy(s, n, jend, Z, ld, yd, 1.0, xi, nullptr, nullptr);
+            multi_axpy(s, n, jend, Z, ld, yd, 1.0, x, nullptr, nullptr);
             beta = residual_norm();   // the true residual; also v_0 of the next cycle
             if (stop) break;
             if (!std::isfinite(beta)) status = AUX_ENAN;
             else if (beta == 0.0) status = AUX_OK;
         }
-        vec_scatter(s, n, perm, xi, x);
-        HIPCHECK(hipStreamSynchronize(s));
-        prof_collect(0);
         if (info) {
             info->iterations = it;
             info->status = status;
             info->rel_residual = r0 > 0.0 ? beta / r0 : 0.0;
-            info->seconds = seconds_since(t0);
         }
+        return status;
+    }
+
+    // ------------------------------------------------------------ Stokes
+    // Hood-Taylor P^2-P^1 Stokes system (Sec. 5) on the handle's mesh,
+    //   F = [A  B^T; B  0],  A = diag(A_h, A_h, A_h),
+    // with the block triangular preconditioner (Sec. 5, Q_t)
+    //   Q_t = [A  B^T; 0  -S]^{-1},  S replaced by the pressure mass matrix
+    // M_p and A^{-1} by the auxiliary-space preconditioner B per component:
+    //   y_p = -M_p^{-1} r_p  (diagonal PCG from zero to a relative 1e-6, at
+    //   most 200 steps),  y_c = B (r_c - (B^T y_p)_c).
+    // Internal layout of a Stokes vector: the three velocity components, each
+    // in the internal dof order, then the pressure in vertex order.
+    static constexpr double kMassTol = 1e-6;
+    static constexpr int kMassMaxit = 200;
+    struct StokesData {
+        bool host_ready = false, ready = false;
+        int np = 0;
+        Csr B, Mp;                   // host, external numbering
+        DevOp Bi, BTi, M;            // FP64 device operators, internal velocity order
+        double *mdinv = nullptr;     // 1 / diag(M_p)
+        double *mx = nullptr, *mr = nullptr, *mz = nullptr, *mp = nullptr, *mq = nullptr;
+        double *t3 = nullptr;        // velocity scratch [3 n_h]
+        double *bi = nullptr, *xi = nullptr;   // internal right-hand side and iterate
+        double *part = nullptr, *scal = nullptr, *hist = nullptr;
+        int *istate = nullptr;
+        int *host_state = nullptr;   // pinned: iterations, stop flag
+        int mass_chunk = 8;          // mass-CG steps enqueued before the first check
+        int64_t mass_solves = 0, mass_steps = 0;
+    } sk;
+
+    void stokes_host()
+    {
+        if (sk.host_ready) return;
+        try {
+            build_stokes(disc, sk.B, sk.Mp);
+        } catch (const std::invalid_argument &e) {
+            throw AuxError(AUX_EINVAL, e.what());
+        }
+        sk.np = disc.nv;
+        sk.host_ready = true;
+    }
+
+    void stokes_setup()
+    {
+        stokes_host();
+        if (sk.ready || host_only) return;
+        const int n = disc.ndof, np = sk.np;
+        std::vector<int> map3((size_t)3 * n);
+        for (int c = 0; c < 3; c++)
+            for (int i = 0; i < n; i++) map3[(size_t)c * n + i] = c * n + sell.iperm[i];
+        Csr Bi = renumber_cols(sk.B, map3, 3 * n);
+        sk.Bi = upload_op(Bi);
+        sk.BTi = upload_op(transpose(Bi));
+        sk.M = upload_op(sk.Mp);
+        std::vector<double> dinv(np, 0.0);
+        for (int i = 0; i < np; i++)
+            for (int e = sk.Mp.ptr[i]; e < sk.Mp.ptr[i + 1]; e++)
+                if (sk.Mp.col[e] == i) dinv[i] = 1.0 / sk.Mp.val[e];
+        sk.mdinv = upload(dinv);
+        for (double **v : {&sk.mx, &sk.mr, &sk.mz, &sk.mp, &sk.mq}) *v = dnew<double>(np);
+        sk.t3 = dnew<double>((size_t)3 * n);
+        sk.bi = dnew<double>((size_t)3 * n + np);
+        sk.xi = dnew<double>((size_t)3 * n + np);
+        sk.part = dnew<double>(2 * (size_t)kMaxBlocks);
+        sk.scal = dnew<double>(8);
+        sk.hist = dnew<double>(3 * (size_t)(kMassMaxit + 2));
+        sk.istate = (int *)dnew<double>(2);
+        HIPCHECK(hipHostMalloc((void **)&sk.host_state, 2 * sizeof(int), hipHostMallocDefault));
+        host_bufs.push_back(sk.host_state);
+        sk.ready = true;
+    }
+
+    size_t stokes_len() const { return (size_t)3 * disc.ndof + sk.np; }
+
+    // sk.mx = M_p^{-1} b (device b [n_p]) by diagonal PCG from zero, stopped
+    // at ||r|| <= 1e-6 ||b|| or 200 steps.  The steps run with their state in
+    // device memory; the host enqueues as many as the last solve took (plus
+    // one) and then two at a time until the stop flag is set.  Returns the
+    // step count.
+    int mass_solve(const double *b)
+    {
+        hipStream_t s = stream;
+        const int np = sk.np;
+        CgState st = cg_state(CgBufs{sk.part, sk.scal, sk.istate, sk.hist, kMassMaxit + 2}, kMassMaxit);
+        double *part_rz = sk.part + kMaxBlocks;
+        int g = mass_start(s, np, b, sk.mdinv, sk.mx, sk.mr, sk.mz, sk.part);
+        finish(s, sk.part, g, FIN_PLAIN, sk.scal + 0, st);
+        finish(s, sk.part, g, FIN_PLAIN, sk.scal + 1, st);
+        cg_init(s, st, kMassTol * kMassTol);
+        finish(s, part_rz, g, FIN_RZ, nullptr, st);
+        cg_direction(s, np, sk.mz, sk.mp, st);
+        const DevCsrView Mv = sk.M.view<double>();
+        int issued = 0, chunk = sk.mass_chunk;
+        while (true) {
+            for (int c = 0; c < chunk && issued < kMassMaxit; c++, issued++) {
+                g = mass_product(s, Mv, sk.mp, sk.mq, sk.part, st);
+                finish(s, sk.part, g, FIN_PQ, nullptr, st);
+                g = mass_update(s, np, sk.mx, sk.mr, sk.mp, sk.mq, sk.mdinv, sk.mz, sk.part, st);
+                finish(s, sk.part, g, FIN_RR, nullptr, st);
+                finish(s, part_rz, g, FIN_RZ, nullptr, st);
+                cg_direction(s, np, sk.mz, sk.mp, st);
+            }
+            HIPCHECK(hipMemcpyAsync(sk.host_state, sk.istate, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipStreamSynchronize(s));
+            if (sk.host_state[1] || issued >= kMassMaxit) break;
+            chunk = 2;
+        }
+        const int steps = sk.host_state[0];
+        sk.mass_chunk = std::max(2, steps + 1);
+        sk.mass_solves++;
+        sk.mass_steps += steps;
+        return steps;
+    }
+
+    // y = F x (internal layout)
+    void stokes_product(const double *x, double *y)
+    {
+        const size_t n = disc.ndof;
+        for (int c = 0; c < 3; c++) op_product(x + c * n, y + c * n);
+        csr_matvec_add<double>(stream, sk.BTi.view<double>(), x + 3 * n, y, nullptr);   // y_u += B^T x_p
+        csr_matvec<double>(stream, sk.Bi.view<double>(), x, y + 3 * n, nullptr);        // y_p = B x_u
+    }
+
+    // y = Q_t r (internal layout)
+    void stokes_qt(const double *r, double *y)
+    {
+        const size_t n = disc.ndof, nu = 3 * n;
+        mass_solve(r + nu);                                   // mx = M_p^{-1} r_p
+        vec_negate(stream, sk.np, sk.mx, y + nu);             // y_p = -M_p^{-1} r_p
+        HIPCHECK(hipMemcpyAsync(sk.t3, r, nu * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        csr_matvec_add<double>(stream, sk.BTi.view<double>(), sk.mx, sk.t3, nullptr);   // r_u - B^T y_p
+        for (int c = 0; c < 3; c++) apply(sk.t3 + c * n, y + c * n, nullptr, nullptr);
+    }
+
+    // external <-> internal Stokes vectors
+    void stokes_in(const double *ext, double *in)
+    {
+        const size_t n = disc.ndof;
+        for (int c = 0; c < 3; c++) vec_gather(stream, (int)n, perm, ext + c * n, in + c * n);
+        HIPCHECK(hipMemcpyAsync(in + 3 * n, ext + 3 * n, (size_t)sk.np * sizeof(double), hipMemcpyDeviceToDevice,
+                                stream));
+    }
+    void stokes_out(const double *in, double *ext)
+    {
+        const size_t n = disc.ndof;
+        for (int c = 0; c < 3; c++) vec_scatter(stream, (int)n, perm, in + c * n, ext + c * n);
+        HIPCHECK(hipMemcpyAsync(ext + 3 * n, in + 3 * n, (size_t)sk.np * sizeof(double), hipMemcpyDeviceToDevice,
+                                stream));
+    }
+
+    void stokes_prepare()
+    {
+        stokes_setup();
+        if (use_mf()) ensure_mf();
+        if (opt.precision == AUX_MIXED) ensure_fp32();
+    }
+
+    void stokes_operator_external(const double *x, double *y)
+    {
+        stokes_prepare();
+        stokes_in(x, sk.bi);
+        stokes_product(sk.bi, sk.xi);
+        stokes_out(sk.xi, y);
+    }
+
+    void stokes_qt_external(const double *r, double *y)
+    {
+        stokes_prepare();
+        stokes_in(r, sk.bi);
+        stokes_qt(sk.bi, sk.xi);
+        stokes_out(sk.xi, y);
+    }
+
+    int stokes_fgmres(const double *b, double *x, double tol, int m, int maxit, double *history, aux_solve_info *info)
+    {
+        auto t0 = std::chrono::steady_clock::now();
+        stokes_prepare();
+        stokes_in(b, sk.bi);
+        stokes_in(x, sk.xi);
+        const size_t len = stokes_len();
+        KrylovSystem K{len, [&](const double *v, double *z) { stokes_qt(v, z); },
+                       [&](const double *z, double *w) { stokes_product(z, w); },
+                       [&](const double *bb, const double *xx, double *r) {
+                           stokes_product(xx, r);
+                           sub_from(stream, (int)len, bb, r);
+                       }};
+        const int status = fgmres_core(K, sk.bi, sk.xi, tol, m, maxit, history, info);
+        stokes_out(sk.xi, x);
+        HIPCHECK(hipStreamSynchronize(stream));
+        if (info) info->seconds = seconds_since(t0);
         return status;
     }
 
@@ -2541,6 +2759,8 @@ int aux_export_csr(const aux_handle *h, int which, int level, int64_t *shape, in
         case 2: c = &h->disc.IP; break;
         case 3: if (level >= 0 && level < nl) c = &h->hier.levels[level].A; break;
         case 4: if (level >= 0 && level + 1 < nl) c = &h->hier.levels[level].P; break;
+        case 5: if (h->sk.host_ready) c = &h->sk.B; break;
+        case 6: if (h->sk.host_ready) c = &h->sk.Mp; break;
         default: break;
         }
         if (!c) throw AuxError(AUX_EINVAL, "no such matrix");
@@ -2682,6 +2902,59 @@ int fgmres_solve(aux_handle *h, const double *b, double *x, double tol, int rest
         if (restart < 1 || restart > auxp::kMaxRestart) throw AuxError(AUX_EINVAL, "restart must be in [1, 128]");
         set_dev(h);
         int st = h->fgmres(b, x, tol, restart, maxit, history, info);
+        HIPCHECK(hipGetLastError());
+        return st;
+    });
+}
+
+int aux_stokes_setup(aux_handle *h, int32_t *n_p)
+{
+    return guarded([&]() {
+        if (!h) throw AuxError(AUX_EINVAL, "null handle");
+        if (!h->host_only) set_dev(h);
+        h->stokes_setup();
+        if (!h->host_only) HIPCHECK(hipGetLastError());
+        if (n_p) *n_p = h->sk.np;
+        return AUX_OK;
+    });
+}
+
+int stokes_apply_operator(aux_handle *h, const double *x, double *y)
+{
+    return guarded([&]() {
+        need_device(h);
+        if (!x || !y) throw AuxError(AUX_EINVAL, "null vector");
+        set_dev(h);
+        h->stokes_operator_external(x, y);
+        HIPCHECK(hipGetLastError());
+        return AUX_OK;
+    });
+}
+
+int stokes_apply_qt(aux_handle *h, const double *r, double *z, int32_t *mass_steps)
+{
+    return guarded([&]() {
+        need_device(h);
+        if (!r || !z) throw AuxError(AUX_EINVAL, "null vector");
+        set_dev(h);
+        const int64_t before = h->sk.mass_steps;
+        h->stokes_qt_external(r, z);
+        HIPCHECK(hipGetLastError());
+        if (mass_steps) *mass_steps = (int32_t)(h->sk.mass_steps - before);
+        return AUX_OK;
+    });
+}
+
+int stokes_fgmres_solve(aux_handle *h, const double *b, double *x, double tol, int restart, int maxit,
+                        double *history, aux_solve_info *info)
+{
+    return guarded([&]() {
+        need_device(h);
+        if (!b || !x) throw AuxError(AUX_EINVAL, "null vector");
+        if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
+        if (restart < 1 || restart > auxp::kMaxRestart) throw AuxError(AUX_EINVAL, "restart must be in [1, 128]");
+        set_dev(h);
+        int st = h->stokes_fgmres(b, x, tol, restart, maxit, history, info);
         HIPCHECK(hipGetLastError());
         return st;
     });

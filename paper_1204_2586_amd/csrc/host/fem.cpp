@@ -143,7 +143,28 @@ const Tables &tables(int k)
 
 const std::vector<double> &stiffness_tables(int k) { return tables(k).M; }
 
-double tet_metric(const double *X0, const double *X1, const double *X2, const double *X3, double G[4][4])
+std::vector<double> coupling_tables(int k)
+{
+    std::vector<int> al = multi_indices(k);
+    const int n = (int)al.size() / 4;
+    std::vector<double> C((size_t)4 * n * 4, 0.0);
+    for (int q = 0; q < 4; q++)
+        for (int a = 0; a < n; a++) {
+            const std::vector<Term> d = dphi(k, &al[4 * a], q);
+            for (int p = 0; p < 4; p++) {
+                double s = 0.0;
+                for (const Term &x : d) {
+                    int e[4] = {x.e[0], x.e[1], x.e[2], x.e[3]};
+                    e[p]++;
+                    s += x.c * simplex_moment(e);
+                }
+                C[((size_t)q * n + a) * 4 + p] = s;
+            }
+        }
+    return C;
+}
+
+double tet_gradients(const double *X0, const double *X1, const double *X2, const double *X3, double g[4][3])
 {
     double e1[3], e2[3], e3[3];
     for (int d = 0; d < 3; d++) {
@@ -155,13 +176,19 @@ double tet_metric(const double *X0, const double *X1, const double *X2, const do
     double n2[3] = {e3[1] * e1[2] - e3[2] * e1[1], e3[2] * e1[0] - e3[0] * e1[2], e3[0] * e1[1] - e3[1] * e1[0]};
     double n3[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
     double det = e1[0] * n1[0] + e1[1] * n1[1] + e1[2] * n1[2];
-    double g[4][3];
     for (int d = 0; d < 3; d++) {
         g[1][d] = n1[d] / det;
         g[2][d] = n2[d] / det;
         g[3][d] = n3[d] / det;
         g[0][d] = -g[1][d] - g[2][d] - g[3][d];
     }
+    return det;
+}
+
+double tet_metric(const double *X0, const double *X1, const double *X2, const double *X3, double G[4][4])
+{
+    double g[4][3];
+    const double det = tet_gradients(X0, X1, X2, X3, g);
     double vol = std::fabs(det) / 6.0;
     for (int p = 0; p < 4; p++)
         for (int q = 0; q < 4; q++) G[p][q] = vol * (g[p][0] * g[q][0] + g[p][1] * g[q][1] + g[p][2] * g[q][2]);

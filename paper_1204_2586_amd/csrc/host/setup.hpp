@@ -79,6 +79,19 @@ void element_stiffness(const Discretization &d, int t, double *K);
 // gradient inner products |T| grad(lam_p).grad(lam_q) (4x4) of tet t, returns |det J|
 double tet_metric(const double *X0, const double *X1, const double *X2, const double *X3,
                   double G[4][4]);
+// barycentric gradients g[p] = grad lam_p of a tet, returns the signed det J
+double tet_gradients(const double *X0, const double *X1, const double *X2, const double *X3, double g[4][3]);
+// C[q][a][p] = (1/|T|) int_T lam_p dphi_a/dlam_q for the P^k basis
+// ([4][nloc][4], exact integration of barycentric monomials)
+std::vector<double> coupling_tables(int k);
+
+// Hood-Taylor P^2-P^1 Stokes blocks (stokes.cpp), pressure on every mesh
+// vertex (vertex id order), velocity on the interior P^2 dofs, component
+// blocks c = 0, 1, 2 of n_h columns each:
+//   B   (n_v x 3 n_h):  B_{p, c n_h + i} = -int lam_p dphi_i/dx_c  (-div)
+//   M_p (n_v x n_v):    (M_p)_pq = int lam_p lam_q
+// Entries are summed in tet order.  Throws std::invalid_argument unless k = 2.
+void build_stokes(const Discretization &d, Csr &B, Csr &Mp);
 
 // load vector by the conical-product rule with k+2 points per direction
 int load_rule_points(int k);                               // points per tet

@@ -18,9 +18,6 @@ import pytest
 import oracle
 import workloads as W
 
-PI = np.pi
-
-
 def _stokes(n, jitter=0.2, seed=0):
     xyz, tets = W.kuhn_mesh(n, jitter=jitter, seed=seed)
     return oracle.Problem(xyz, tets, 2).setup_amg().stokes_setup()
@@ -76,56 +73,6 @@ def test_fgmres_qt_matches_dense_solve(n):
     assert np.max(np.abs(F @ x - b)) <= 1e-10 * np.max(np.abs(b))
 
 
-# manufactured solution: u = curl(0, 0, psi), psi = sin^2(pi x) sin^2(pi y)
-# sin^2(pi z) (u and grad psi vanish on the boundary, div u = 0), p = cos(pi x)
-# cos(pi y) cos(pi z) (zero mean); f = -Lap u + grad p
-def _s2(t):
-    return np.sin(PI * t) ** 2
-
-
-def _d1(t):       # d/dt sin^2(pi t)
-    return PI * np.sin(2 * PI * t)
-
-
-def _d2(t):
-    return 2 * PI ** 2 * np.cos(2 * PI * t)
-
-
-def _d3(t):
-    return -4 * PI ** 3 * np.sin(2 * PI * t)
-
-
-def u_exact(c):
-    def f(q):
-        x, y, z = q[:, 0], q[:, 1], q[:, 2]
-        if c == 0:
-            return _s2(x) * _d1(y) * _s2(z)
-        if c == 1:
-            return -_d1(x) * _s2(y) * _s2(z)
-        return np.zeros(q.shape[0])
-    return f
-
-
-def f_field(c):
-    def f(q):
-        x, y, z = q[:, 0], q[:, 1], q[:, 2]
-        if c == 0:
-            lap = _d2(x) * _d1(y) * _s2(z) + _s2(x) * _d3(y) * _s2(z) + _s2(x) * _d1(y) * _d2(z)
-            gp = -PI * np.sin(PI * x) * np.cos(PI * y) * np.cos(PI * z)
-        elif c == 1:
-            lap = -(_d3(x) * _s2(y) * _s2(z) + _d1(x) * _d2(y) * _s2(z) + _d1(x) * _s2(y) * _d2(z))
-            gp = -PI * np.cos(PI * x) * np.sin(PI * y) * np.cos(PI * z)
-        else:
-            lap = 0.0
-            gp = -PI * np.cos(PI * x) * np.cos(PI * y) * np.sin(PI * z)
-        return -lap + gp
-    return f
-
-
-def p_exact(q):
-    return np.cos(PI * q[:, 0]) * np.cos(PI * q[:, 1]) * np.cos(PI * q[:, 2])
-
-
 def _pressure_l2(P, ph, m=5):
     lam, w = oracle.tet_rule(m)
     X = P.xyz[P.tets]                                   # [nt, 4, 3]
@@ -133,7 +80,7 @@ def _pressure_l2(P, ph, m=5):
     det = np.abs(np.linalg.det(J))
     pts = np.einsum("qp,tpd->tqd", lam, X)              # [nt, nq, 3]
     vals = np.einsum("qp,tp->tq", lam, ph[P.tets])
-    ex = p_exact(pts.reshape(-1, 3)).reshape(vals.shape)
+    ex = W.stokes_p(pts.reshape(-1, 3)).reshape(vals.shape)
     return np.sqrt(np.sum(det[:, None] * w[None, :] * (vals - ex) ** 2))
 
 
@@ -146,11 +93,11 @@ def test_hood_taylor_convergence_rates_and_flat_steps():
     for n in ns:
         P = _stokes(n, jitter=0.2)
         m = P.n
-        b = np.concatenate([P.load(f_field(c)) for c in range(3)] + [np.zeros(P.np)])
+        b = np.concatenate([P.load(W.stokes_f(c)) for c in range(3)] + [np.zeros(P.np)])
         x, it, rr, st, hist = P.stokes_fgmres(b, tol=1e-12, maxit=3000)
         assert st == 0
         steps.append(P.stokes_fgmres(b, tol=1e-8, maxit=3000)[1])
-        eu.append(np.sqrt(sum(P.l2_error(u_exact(c), x[c * m:(c + 1) * m]) ** 2 for c in range(3))))
+        eu.append(np.sqrt(sum(P.l2_error(W.stokes_u(c), x[c * m:(c + 1) * m]) ** 2 for c in range(3))))
         ph = x[3 * m:]
         M = P.csr("Mp")
         one = np.ones(P.np)

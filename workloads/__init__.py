@@ -16,6 +16,9 @@ cube with u = 0 on the boundary, Sec. 2, eq. (2.1); the paper uses kappa = 1):
 * ``manufactured_f`` / ``manufactured_u`` -- u = sin(pi x) sin(pi y) sin(pi z),
   f = 3 pi^2 u.
 * ``fourier_f(r)`` -- a smooth random source made of 16 sine modes.
+* ``stokes_u`` / ``stokes_p`` / ``stokes_f`` -- a smooth divergence-free
+  velocity with zero boundary values, a zero-mean pressure and the body force
+  of the Stokes system (Sec. 5) they solve.
 """
 from __future__ import annotations
 
@@ -122,6 +125,64 @@ def manufactured_u(p):
 def manufactured_f(p):
     """f = -Laplace(u) for u = sin(pi x) sin(pi y) sin(pi z)."""
     return 3.0 * np.pi ** 2 * manufactured_u(p)
+
+
+# Stokes manufactured solution (velocity u = curl(0, 0, psi) with
+# psi = sin^2(pi x) sin^2(pi y) sin^2(pi z): divergence free, u and grad psi
+# vanish on the boundary; pressure p = cos(pi x) cos(pi y) cos(pi z), zero
+# mean), body force f = -Laplace(u) + grad(p).
+def _s2(t):
+    return np.sin(np.pi * t) ** 2
+
+
+def _d1(t):       # d/dt sin^2(pi t)
+    return np.pi * np.sin(2 * np.pi * t)
+
+
+def _d2(t):
+    return 2 * np.pi ** 2 * np.cos(2 * np.pi * t)
+
+
+def _d3(t):
+    return -4 * np.pi ** 3 * np.sin(2 * np.pi * t)
+
+
+def stokes_u(c: int):
+    """Component c of the manufactured Stokes velocity."""
+    def f(q):
+        q = np.asarray(q, dtype=np.float64)
+        x, y, z = q[..., 0], q[..., 1], q[..., 2]
+        if c == 0:
+            return _s2(x) * _d1(y) * _s2(z)
+        if c == 1:
+            return -_d1(x) * _s2(y) * _s2(z)
+        return np.zeros(q.shape[:-1])
+    return f
+
+
+def stokes_p(q):
+    q = np.asarray(q, dtype=np.float64)
+    return np.cos(np.pi * q[..., 0]) * np.cos(np.pi * q[..., 1]) * np.cos(np.pi * q[..., 2])
+
+
+def stokes_f(c: int):
+    """Component c of the body force -Laplace(u) + grad(p) of the manufactured solution."""
+    pi = np.pi
+
+    def f(q):
+        q = np.asarray(q, dtype=np.float64)
+        x, y, z = q[..., 0], q[..., 1], q[..., 2]
+        if c == 0:
+            lap = _d2(x) * _d1(y) * _s2(z) + _s2(x) * _d3(y) * _s2(z) + _s2(x) * _d1(y) * _d2(z)
+            gp = -pi * np.sin(pi * x) * np.cos(pi * y) * np.cos(pi * z)
+        elif c == 1:
+            lap = -(_d3(x) * _s2(y) * _s2(z) + _d1(x) * _d2(y) * _s2(z) + _d1(x) * _s2(y) * _d2(z))
+            gp = -pi * np.cos(pi * x) * np.sin(pi * y) * np.cos(pi * z)
+        else:
+            lap = 0.0
+            gp = -pi * np.cos(pi * x) * np.cos(pi * y) * np.sin(pi * z)
+        return -lap + gp
+    return f
 
 
 def fourier_f(r: int, n_modes: int = 16, kmax: int = 4):
