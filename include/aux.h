@@ -401,8 +401,10 @@ int aux_kappa_grad(aux_handle *h, const double *u, const double *lam, double *g)
 #define AUX_PROF_NCAT 7
 /* With enable = 1, later preconditioner and CG calls record a HIP event pair
  * on the handle's stream around each launch of the categories above (launches
- * enqueued after convergence that returned at once are not counted).
- * Resets the sums.  enable = 0 stops recording. */
+ * enqueued after convergence that returned at once are not counted).  With
+ * enable = 2 only whole applications (AUX_PROF_APPLY) are recorded, so their
+ * times carry no event records between the application's own launches.
+ * Resets the sums.  enable = 0 stops recording (AUX_EINVAL for other values). */
 int aux_profile(aux_handle *h, int enable);
 /* Launch count and summed elapsed milliseconds of a category since the last
  * aux_profile call (synchronises the stream). */

@@ -565,9 +565,12 @@ class Solver:
 
     PROF = {"pk_first": 0, "pk_sweep": 1, "pk_last": 2, "pk_resid": 3, "coarse": 4, "cg_spmv": 5, "apply": 6}
 
-    def profile(self, enable: bool = True):
-        """Start (and reset) or stop HIP-event timing of the solve-phase kernels."""
-        _check(load_library().aux_profile(self._h, int(enable)))
+    def profile(self, enable=True):
+        """Start (and reset) or stop HIP-event timing of the solve-phase kernels
+        (enable=True: every launch; "apply": whole preconditioner applications
+        only; False: stop)."""
+        mode = 2 if enable == "apply" else int(bool(enable))
+        _check(load_library().aux_profile(self._h, mode))
 
     def profile_read(self):
         """{category: (launches, total ms)} since the last profile() call."""

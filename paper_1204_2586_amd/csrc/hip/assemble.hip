@@ -101,6 +101,56 @@ __global__ __launch_bounds__(kAsmBlock) void k_mf_weights(int nt, const double *
     }
 }
 
+// Values of the block -I_R A_h of the composite restriction
+// RF = [I_R, -I_R A_h] (internal numbering, n columns per block) on its fixed
+// pattern: the entry of row I, column n + j, is -sum_k IR[I][k] A[k][j] over
+// row I of I_R in storage order, the order of the host's row-by-row product
+// (so the values equal the host's bit for bit).  A_h in external CSR
+// numbering (columns sorted), perm: internal -> external dof.  One wavefront
+// per row, a lane per entry; with ell_lanes > 0 the values also go to the
+// row-split ELL copy (entry k of row I at slot k / L of lane (I % (64/L)) L +
+// k % L of its slice).
+__global__ __launch_bounds__(kAsmBlock) void k_restrict_values(
+    int nrows, int n, const int *__restrict__ rf_ptr, const int *__restrict__ rf_col, const int *__restrict__ ir_ptr,
+    const int *__restrict__ ir_col, const double *__restrict__ ir_val, const int *__restrict__ a_ptr,
+    const int *__restrict__ a_col, const double *__restrict__ a_val, const int *__restrict__ perm,
+    double *__restrict__ v64, float *__restrict__ v32, int ell_lanes, const int *__restrict__ ell_off,
+    double *__restrict__ e64, float *__restrict__ e32)
+{
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x % 64;
+    for (int I = blockIdx.x * (kAsmBlock / 64) + (int)(threadIdx.x / 64); I < nrows;
+         I += gridDim.x * (kAsmBlock / 64)) {
+        const int r0 = rf_ptr[I], r1 = rf_ptr[I + 1], c0 = ir_ptr[I], c1 = ir_ptr[I + 1];
+        for (int e = r0 + lane; e < r1; e += 64) {
+            const int col = rf_col[e];
+            if (col < n) continue;                          // the I_R block does not change
+            const int j = perm[col - n];
+            double s = 0.0;
+            for (int c = c0; c < c1; c++) {
+                const int k = perm[ir_col[c]], end = a_ptr[k + 1];
+                int lo = a_ptr[k], hi = end;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (a_col[mid] < j) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo < end && a_col[lo] == j) s += ir_val[c] * a_val[lo];
+            }
+            const double v = -s;
+            v64[e] = v;
+            v32[e] = (float)v;
+            if (ell_lanes > 0) {
+                const int rows = 64 / ell_lanes, q = e - r0;
+                const long long at = (long long)ell_off[I / rows] + (long long)(q / ell_lanes) * 64 +
+                                     (I % rows) * ell_lanes + q % ell_lanes;
+                e64[at] = v;
+                e32[at] = (float)v;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 void element_matrices(hipStream_t s, int nt, int nl, const double *G, const double *kappa, const double *M, double *Ke)
@@ -124,6 +174,16 @@ void row_l1(hipStream_t s, int n, const int *ptr, const double *val, double *l1)
 void mf_weights(hipStream_t s, int nt, const double *G, const double *kappa, double *w64, float *w32)
 {
     hipLaunchKernelGGL(k_mf_weights, dim3(asm_grid(6LL * nt)), dim3(kAsmBlock), 0, s, nt, G, kappa, w64, w32);
+}
+
+void restrict_values(hipStream_t s, int nrows, int n, const int *rf_ptr, const int *rf_col, const int *ir_ptr,
+                     const int *ir_col, const double *ir_val, const int *a_ptr, const int *a_col, const double *a_val,
+                     const int *perm, double *v64, float *v32, int ell_lanes, const int *ell_off, double *e64,
+                     float *e32)
+{
+    hipLaunchKernelGGL(k_restrict_values, dim3(asm_grid(((long long)nrows + 3) / 4 * kAsmBlock)), dim3(kAsmBlock), 0, s,
+                       nrows, n, rf_ptr, rf_col, ir_ptr, ir_col, ir_val, a_ptr, a_col, a_val, perm, v64, v32,
+                       ell_lanes, ell_off, e64, e32);
 }
 
 }  // namespace auxp

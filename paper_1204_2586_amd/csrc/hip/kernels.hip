@@ -355,9 +355,19 @@ __global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const T *__restric
     if (stop(done)) return;
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     for (int i = blockIdx.x * (kBlock / 64) + w; i < n; i += gridDim.x * (kBlock / 64)) {
-        T s = T(0);
-        for (int j = l; j < n; j += 64) s += Ainv[(size_t)i * n + j] * b[j];
-        s = group_sum<64>(s);
+        // four accumulators, loads unrolled: a lane's loads of the row in flight together
+        const T *__restrict__ row = Ainv + (size_t)i * n;
+        T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+        int j = l;
+#pragma unroll 4
+        for (; j + 192 < n; j += 256) {
+            s0 += row[j] * b[j];
+            s1 += row[j + 64] * b[j + 64];
+            s2 += row[j + 128] * b[j + 128];
+            s3 += row[j + 192] * b[j + 192];
+        }
+        for (; j < n; j += 64) s0 += row[j] * b[j];
+        T s = group_sum<64>((s0 + s1) + (s2 + s3));
         if (l == 0) x[i] = s;
     }
 }

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <functional>
 #include <mutex>
@@ -317,6 +318,7 @@ struct aux_handle {
         int cat, tag;
     };
     bool prof_on = false;
+    bool prof_apply_only = false;    // record whole preconditioner applications only
     int prof_tag = -1;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -484,6 +486,7 @@ struct aux_handle {
     }
 
     Csr IPi, IRi;                    // internal-order transfers (host, for the FP32 copies)
+    std::vector<std::array<int, 2>> tuned_lanes;   // storage chosen at setup per level (down, up)
     std::vector<double> l1i;         // l1 norms in internal order
 
     DevSell upload_sell(const Sell &sl)
@@ -639,12 +642,18 @@ struct aux_handle {
                         dense_first = l;
                         break;
                     }
-            RF_host = fuse_restriction(IRi, permute_symmetric(disc.A, sell.perm, sell.iperm));
-            RF = upload_op2(RF_host);
+            // the composite restriction depends on A_h's values through
+            // I_R A_h on a pattern fixed by the mesh: built here once; a new
+            // coefficient refreshes its values on the device (set_kappa)
+            if (first) {
+                RF_host = fuse_restriction(IRi, permute_symmetric(disc.A, sell.perm, sell.iperm));
+                RF = upload_op2(RF_host);
+            }
             // lanes per row of the large CSR passes, timed on the device
             // (with a fixed layout window every choice is rule-based)
             // (I_P has one or two entries per row: its rule-based two lanes
-            // per row measured best in the solve)
+            // per row measured best in the solve).  A new coefficient keeps
+            // the storage chosen at setup for each level index.
             if (opt.cycle_lanes != 0) {                // one storage for all of them
                 auto force = [&](DevOp &op, const Csr &host) {
                     if (opt.cycle_lanes > 0) {
@@ -654,23 +663,37 @@ struct aux_handle {
                         op.lpr = -opt.cycle_lanes;
                     }
                 };
-                force(RF, RF_host);
-                if (first) force(IP, IPi);
+                if (first) {
+                    force(RF, RF_host);
+                    force(IP, IPi);
+                }
                 for (size_t l = 0; l + 1 < lev.size(); l++) {
                     force(lev[l].down, fused_host[l].down);
                     force(lev[l].up, fused_host[l].up);
                 }
-            } else if (opt.sell_window <= 0) {
+            } else if (opt.sell_window <= 0 && first) {
                 const size_t fb = (size_t)512 << 20;    // twice the last-level cache
                 void *flush = dalloc(fb);
                 tune_op(RF, RF_host, disc.ndof, flush, fb);
-                if (first) tune_op(IP, IPi, 0, flush, fb);
+                tune_op(IP, IPi, 0, flush, fb);
+                tuned_lanes.clear();
                 for (size_t l = 0; l + 1 < lev.size(); l++) {
                     if (lev[l].A.n < 8192) break;
                     tune_op(lev[l].down, fused_host[l].down, 0, flush, fb);
                     tune_op(lev[l].up, fused_host[l].up, lev[l].A.n, flush, fb);
+                    tuned_lanes.push_back({lev[l].down.lanes_code(), lev[l].up.lanes_code()});
                 }
                 dfree(flush);
+            } else if (opt.sell_window <= 0) {
+                auto restore = [&](DevOp &op, const Csr &host, int code) {
+                    if (code > 0) set_ell(op, host, code);
+                    else op.lpr = -code;
+                };
+                for (size_t l = 0; l + 1 < lev.size() && l < tuned_lanes.size(); l++) {
+                    if (lev[l].A.n < 8192) break;
+                    restore(lev[l].down, fused_host[l].down, tuned_lanes[l][0]);
+                    restore(lev[l].up, fused_host[l].up, tuned_lanes[l][1]);
+                }
             }
         }
     }
@@ -761,7 +784,7 @@ struct aux_handle {
     }
     int pbeg(int cat)
     {
-        if (!prof_on) return -1;
+        if (!prof_on || (prof_apply_only && cat != AUX_PROF_APPLY)) return -1;
         ProfRec rec{take_event(), take_event(), cat, prof_tag};
         HIPCHECK(hipEventRecord(rec.a, stream));
         prof.push_back(rec);
@@ -2294,7 +2317,7 @@ struct aux_handle {
     // metrics and each entry's list of element-matrix contributions) is kept.
     struct AsmMaps {
         bool ready = false;
-        int *a_ptr = nullptr, *a_idx = nullptr, *a_pos = nullptr, *a_rowptr = nullptr;
+        int *a_ptr = nullptr, *a_idx = nullptr, *a_pos = nullptr, *a_rowptr = nullptr, *a_col = nullptr;
         int *h_ptr = nullptr, *h_idx = nullptr;
     } asmd;
 
@@ -2315,6 +2338,7 @@ struct aux_handle {
         }
         asmd.a_pos = upload(pos);
         asmd.a_rowptr = upload(disc.A.ptr);
+        asmd.a_col = upload(disc.A.col);
         std::vector<int> vmap((size_t)nt * 4);
         for (size_t q = 0; q < vmap.size(); q++) vmap[q] = disc.vert_dof[disc.tets[q]];
         assembly_map(disc.AH, nt, 4, vmap.data(), ptr, idx);
@@ -2348,8 +2372,6 @@ struct aux_handle {
         cinv64 = dcyc64 = nullptr;
         cinv32 = dcyc32 = nullptr;
         dense_first = SIZE_MAX;
-        free_op(RF);
-        RF_host = Csr();
         fused_host.clear();
         release_work(w64);
         release_work(w32);
@@ -2398,11 +2420,18 @@ struct aux_handle {
         row_l1(s, n, asmd.a_rowptr, aval, l1e);
         if (nnzH) gather_entries(s, (long long)nnzH, asmd.h_ptr, asmd.h_idx, G, kappa_d, hval, nullptr, nullptr, nullptr);
         if (mf_ready) mf_weights(s, nt, G, kappa_d, mf_w64, mf_w32);
+        // the composite restriction's block -I_R A_h, in place (same pattern)
+        if (RF.ptr)
+            restrict_values(s, RF.n, n, RF.ptr, RF.col, IR.ptr, IR.col, IR.v64, asmd.a_rowptr, asmd.a_col, aval, perm,
+                            RF.v64, RF.v32, RF.ell_lanes, RF.ell_off, RF.ell_v64, RF.ell_v32);
         // host copies of the new values
         HIPCHECK(hipMemcpyAsync(disc.A.val.data(), aval, nnzA * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipMemcpyAsync(sell.val.data(), A.v64, sell.val.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipMemcpyAsync(disc.l1.data(), l1e, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
         if (nnzH) HIPCHECK(hipMemcpyAsync(disc.AH.val.data(), hval, nnzH * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (RF.ptr)
+            HIPCHECK(hipMemcpyAsync(RF_host.val.data(), RF.v64, RF_host.val.size() * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         for (void *b : {(void *)Ke, (void *)aval, (void *)l1e, (void *)hval}) dfree(b);
         disc.kappa.assign(kap, kap + nt);
@@ -2990,8 +3019,10 @@ int aux_profile(aux_handle *h, int enable)
     return guarded([&]() {
         need_device(h);
         set_dev(h);
+        if (enable < 0 || enable > 2) throw AuxError(AUX_EINVAL, "enable must be 0, 1 or 2");
         h->prof_collect(1 << 30);
         h->prof_on = enable != 0;
+        h->prof_apply_only = enable == 2;
         for (int c = 0; c < AUX_PROF_NCAT; c++) {
             h->prof_ms[c] = 0.0;
             h->prof_n[c] = 0;

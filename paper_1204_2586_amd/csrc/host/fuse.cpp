@@ -16,15 +16,19 @@
 // [r; z]).  Products are formed exactly in FP64 (the FP32 copies round the
 // composite entries once); only the summation order of the cycle changes.
 #include <algorithm>
+#include <cstdint>
 #include <stdexcept>
 
+#include "parallel.hpp"
 #include "setup.hpp"
 
 namespace auxp {
 
 namespace {
 
-// C = A B (Gustavson, dense accumulator per row, columns sorted)
+// C = A B (Gustavson, dense accumulator per row, columns sorted).  Rows are
+// independent: contiguous row ranges go to worker threads, each summing its
+// rows in the sequential order, and the ranges are concatenated.
 Csr multiply(const Csr &A, const Csr &B)
 {
     if (A.m != B.n) throw std::invalid_argument("multiply: shape mismatch");
@@ -32,29 +36,47 @@ Csr multiply(const Csr &A, const Csr &B)
     C.n = A.n;
     C.m = B.m;
     C.ptr.assign((size_t)A.n + 1, 0);
-    std::vector<double> acc((size_t)B.m, 0.0);
-    std::vector<int> mark((size_t)B.m, -1), cols;
-    for (int i = 0; i < A.n; i++) {
-        cols.clear();
-        for (int e = A.ptr[i]; e < A.ptr[i + 1]; e++) {
-            const int k = A.col[e];
-            const double a = A.val[e];
-            for (int f = B.ptr[k]; f < B.ptr[k + 1]; f++) {
-                const int j = B.col[f];
-                if (mark[j] != i) {
-                    mark[j] = i;
-                    acc[j] = 0.0;
-                    cols.push_back(j);
+    int64_t work = 0;
+    for (int i = 0; i < A.n; i++)
+        for (int e = A.ptr[i]; e < A.ptr[i + 1]; e++) work += B.ptr[A.col[e] + 1] - B.ptr[A.col[e]];
+    const int nth = setup_threads((size_t)work);
+    std::vector<std::vector<int>> cols_t(nth);
+    std::vector<std::vector<double>> vals_t(nth);
+    run_tasks(nth, [&](int w) {
+        const int r0 = (int)((long long)A.n * w / nth), r1 = (int)((long long)A.n * (w + 1) / nth);
+        std::vector<double> acc((size_t)B.m, 0.0);
+        std::vector<int> mark((size_t)B.m, -1), cols;
+        std::vector<int> &oc = cols_t[w];
+        std::vector<double> &ov = vals_t[w];
+        for (int i = r0; i < r1; i++) {
+            cols.clear();
+            for (int e = A.ptr[i]; e < A.ptr[i + 1]; e++) {
+                const int k = A.col[e];
+                const double a = A.val[e];
+                for (int f = B.ptr[k]; f < B.ptr[k + 1]; f++) {
+                    const int j = B.col[f];
+                    if (mark[j] != i) {
+                        mark[j] = i;
+                        acc[j] = 0.0;
+                        cols.push_back(j);
+                    }
+                    acc[j] += a * B.val[f];
                 }
-                acc[j] += a * B.val[f];
             }
+            std::sort(cols.begin(), cols.end());
+            for (int j : cols) {
+                oc.push_back(j);
+                ov.push_back(acc[j]);
+            }
+            C.ptr[i + 1] = (int)cols.size();
         }
-        std::sort(cols.begin(), cols.end());
-        for (int j : cols) {
-            C.col.push_back(j);
-            C.val.push_back(acc[j]);
-        }
-        C.ptr[i + 1] = (int)C.col.size();
+    });
+    for (int i = 0; i < A.n; i++) C.ptr[i + 1] += C.ptr[i];
+    C.col.reserve(C.ptr[A.n]);
+    C.val.reserve(C.ptr[A.n]);
+    for (int w = 0; w < nth; w++) {
+        C.col.insert(C.col.end(), cols_t[w].begin(), cols_t[w].end());
+        C.val.insert(C.val.end(), vals_t[w].begin(), vals_t[w].end());
     }
     return C;
 }
