@@ -84,6 +84,12 @@ def _load():
     lib.orc_stokes_fgmres.argtypes = [vp, ctypes.c_int, _f64p, _f64p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), _f64p]
     lib.orc_stokes_apply_operator.argtypes = [vp, _f64p, _f64p]
+    lib.orc_stokes_np.restype = ctypes.c_int
+    lib.orc_stokes_np.argtypes = [vp]
+    lib.orc_pressure_keys.restype = ctypes.c_int
+    lib.orc_pressure_keys.argtypes = [vp, _i32p]
+    lib.orc_pressure_l2_error.restype = ctypes.c_double
+    lib.orc_pressure_l2_error.argtypes = [vp, ctypes.c_int, _f64p, _f64p]
     lib.orc_stokes_apply_qt.restype = ctypes.c_int
     lib.orc_stokes_apply_qt.argtypes = [vp, ctypes.c_int, _f64p, _f64p]
     lib.orc_block_pcg.restype = ctypes.c_int
@@ -320,12 +326,28 @@ class Problem:
 
     # ---- Stokes (Sec. 5), Hood-Taylor P^2-P^1
     def stokes_setup(self):
-        """Divergence B (n_p x 3 n_h, -div) and pressure mass matrix M_p
-        (pressure P^1 on every vertex); needs order 2."""
+        """Hood-Taylor P^k - P^{k-1} (k = 2, 3, 4): divergence B (n_p x 3 n_h,
+        -div) and pressure mass matrix M_p, the pressure on every node of
+        order k-1 (vertex order for P^1)."""
         if _load().orc_stokes_setup(self._h):
-            raise ValueError("Stokes needs the P^2 velocity space")
-        self.np = self.xyz.shape[0]
+            raise ValueError("Stokes needs a velocity order of 2, 3 or 4")
+        self.np = _load().orc_stokes_np(self._h)
         return self
+
+    def pressure_keys(self) -> np.ndarray:
+        """Node key of each pressure unknown: [n_p][k-1] sorted vertex ids."""
+        keys = np.zeros((self.np, self.k - 1), dtype=np.int32)
+        _load().orc_pressure_keys(self._h, keys)
+        return keys
+
+    def pressure_xyz(self) -> np.ndarray:
+        """Position of each pressure node (the mean of its key's vertices)."""
+        return self.xyz[self.pressure_keys()].mean(axis=1)
+
+    def pressure_l2_error(self, p_exact, ph, m: int | None = None) -> float:
+        m = self.k + 3 if m is None else m
+        pq = np.ascontiguousarray(p_exact(self.qpoints(m)), dtype=np.float64)
+        return _load().orc_pressure_l2_error(self._h, m, pq, np.ascontiguousarray(ph, dtype=np.float64))
 
     def stokes_operator(self, x) -> np.ndarray:
         out = np.zeros(3 * self.n + self.np)

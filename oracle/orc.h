@@ -64,8 +64,12 @@ typedef struct {
     double *chol;    /* dense Cholesky factor of the coarsest operator (lower, row-major) */
     int ncoarse;
 
-    /* Stokes (Sec. 5), Hood-Taylor P^2-P^1: pressure on every vertex */
-    int np;          /* pressure unknowns (vertices); 0 until orc_stokes_setup */
+    /* Stokes (Sec. 5), Hood-Taylor P^k-P^{k-1}: pressure on every node of
+       order k-1, node keys of k-1 sorted vertex ids in lexicographic order */
+    int np;          /* pressure unknowns; 0 until orc_stokes_setup */
+    int nlp;         /* local pressure nodes per tet */
+    int *pnode_key;  /* [np][k-1] */
+    int *ptet_node;  /* [nt][nlp] pressure node of each local pressure node */
     ocsr Bdiv;       /* np x 3 ndof discrete divergence, columns component-major */
     ocsr BdivT;
     ocsr Mp;         /* np x np pressure mass matrix */
@@ -96,6 +100,7 @@ int orc_amg_setup(orc *o);
 
 /* Stokes: divergence and pressure mass matrix (orc_fem.c) */
 int orc_stokes_assemble(orc *o);
+double orc_pressure_l2_error(const orc *o, int m, const double *pq, const double *ph);
 
 /* flexible GMRES(m) on vectors of length n with an operator and a
    preconditioner given as callbacks (orc_solve.c) */

@@ -37,6 +37,7 @@ void orc_free(orc *o)
     }
     free(o->chol);
     ocsr_free(&o->Bdiv); ocsr_free(&o->BdivT); ocsr_free(&o->Mp);
+    free(o->pnode_key); free(o->ptet_node);
     free(o);
 }
 
@@ -70,6 +71,15 @@ int orc_setup_amg(orc *o, double theta, int nu, int coarse_max, int max_levels, 
 }
 
 int orc_stokes_setup(orc *o) { return o->np ? 0 : orc_stokes_assemble(o); }
+
+/* pressure count and node keys [np][k-1] (after orc_stokes_setup) */
+int orc_stokes_np(const orc *o) { return o->np; }
+int orc_pressure_keys(const orc *o, int *keys)
+{
+    if (!o->np) return -1;
+    memcpy(keys, o->pnode_key, (size_t)o->np * (o->k - 1) * sizeof(int));
+    return 0;
+}
 
 /* sizes: [n_h, n_H, nnode, nlev, nnz(A_h), nnz(A_H), nnz(I_P), ncoarse, nloc] */
 void orc_sizes(const orc *o, long long *s)

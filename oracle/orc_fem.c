@@ -507,50 +507,92 @@ int orc_element_matrix(const orc *o, int t, double *K)
      (M_p)_{q,r}   =   int psi_q psi_r
    by quadrature (both integrands have degree 2; the rule with m = 2 points
    per direction is exact to degree 3). */
+/* Hood-Taylor P^k - P^{k-1} (Sec. 5), k = 2, 3, 4: pressure in the
+   continuous P^{k-1} space on every node of that order (no boundary
+   condition), numbered like the velocity nodes by sorted vertex multisets
+   (k - 1 vertex ids) in lexicographic order, so P^1 pressures are in vertex
+   order.  B_{q,(c,i)} = -int psi_q dphi_i/dx_c and M_p = int psi_q psi_r by
+   the conical-product rule with k points per direction, exact for these
+   integrands of degree 2k - 2. */
 int orc_stokes_assemble(orc *o)
 {
-    if (o->k != 2) return -1;
-    int k = o->k, nloc = o->nloc, m = 2, nq = m * m * m, n = o->ndof, np = o->nv;
-    int alpha[35 * 4];
+    if (o->k < 2 || o->k > 4) return -1;
+    const int k = o->k, kp = k - 1, nloc = o->nloc, n = o->ndof, m = k, nq = m * m * m;
+    int alpha[35 * 4], beta[20 * 4];
     orc_local_multi_indices(k, alpha);
-    double lam[4 * 512], w[512], grad[4][3];
+    const int nlp = orc_local_multi_indices(kp, beta);
+    /* pressure nodes */
+    const size_t N = (size_t)o->nt * nlp;
+    int *keys = malloc(N * kp * sizeof(int));
+    size_t *idx = malloc(N * sizeof(size_t));
+    o->ptet_node = malloc(N * sizeof(int));
+    o->pnode_key = malloc(N * kp * sizeof(int));
+    if (!keys || !idx || !o->ptet_node || !o->pnode_key) return -2;
+    for (int t = 0; t < o->nt; t++)
+        for (int a = 0; a < nlp; a++) {
+            int *key = keys + ((size_t)t * nlp + a) * kp, c = 0;
+            for (int p = 0; p < 4; p++)
+                for (int r = 0; r < beta[4 * a + p]; r++) key[c++] = o->tets[4 * t + p];
+            sort_small(key, kp);
+            idx[(size_t)t * nlp + a] = (size_t)t * nlp + a;
+        }
+    g_k = kp;
+    g_keys = keys;
+    qsort(idx, N, sizeof(size_t), cmp_key_idx);
+    int np = -1;
+    for (size_t s2 = 0; s2 < N; s2++) {
+        const int *key = keys + idx[s2] * kp;
+        if (np < 0 || memcmp(key, o->pnode_key + (size_t)np * kp, kp * sizeof(int)) != 0) {
+            np++;
+            memcpy(o->pnode_key + (size_t)np * kp, key, kp * sizeof(int));
+        }
+        o->ptet_node[idx[s2]] = np;
+    }
+    np++;
+    free(keys);
+    free(idx);
+    o->nlp = nlp;
+
+    double *lam = malloc((size_t)nq * 4 * sizeof(double)), *w = malloc((size_t)nq * sizeof(double));
+    double grad[4][3];
     orc_tet_rule(m, lam, w);
-    size_t capB = (size_t)o->nt * 4 * 3 * nloc, capM = (size_t)o->nt * 16, cb = 0, cm = 0;
+    size_t capB = (size_t)o->nt * nlp * 3 * nloc, capM = (size_t)o->nt * nlp * nlp, cb = 0, cm = 0;
     int *bri = malloc(capB * sizeof(int)), *bci = malloc(capB * sizeof(int));
     double *bv = malloc(capB * sizeof(double));
     int *mri = malloc(capM * sizeof(int)), *mci = malloc(capM * sizeof(int));
     double *mv = malloc(capM * sizeof(double));
-    if (!bri || !bci || !bv || !mri || !mci || !mv) return -2;
-    double dl[35][4];
+    double (*Bt)[3][35] = malloc(20 * sizeof(*Bt)), (*Mt)[20] = malloc(20 * sizeof(*Mt));
+    if (!lam || !w || !bri || !bci || !bv || !mri || !mci || !mv || !Bt || !Mt) return -2;
+    double dl[35][4], psi[20];
     for (int t = 0; t < o->nt; t++) {
         double det = tet_geometry(o, t, grad);
-        const int *vt = o->tets + 4 * (size_t)t;
-        double Bt[4][3][35], Mt[4][4];
-        memset(Bt, 0, sizeof(Bt));
-        memset(Mt, 0, sizeof(Mt));
+        memset(Bt, 0, 20 * sizeof(*Bt));
+        memset(Mt, 0, 20 * sizeof(*Mt));
         for (int q = 0; q < nq; q++) {
             const double *lq = lam + 4 * q;
             for (int a = 0; a < nloc; a++) orc_basis_dlam(k, alpha + 4 * a, lq, dl[a]);
-            for (int p = 0; p < 4; p++) {
-                for (int r = 0; r < 4; r++) Mt[p][r] += w[q] * lq[p] * lq[r];
+            for (int p = 0; p < nlp; p++) psi[p] = orc_basis(kp, beta + 4 * p, lq);
+            for (int p = 0; p < nlp; p++) {
+                for (int r = 0; r < nlp; r++) Mt[p][r] += w[q] * psi[p] * psi[r];
                 for (int c = 0; c < 3; c++)
                     for (int a = 0; a < nloc; a++) {
                         /* dphi_a/dx_c = sum_s dphi_a/dlam_s dlam_s/dx_c */
                         double d = dl[a][0] * grad[0][c] + dl[a][1] * grad[1][c] + dl[a][2] * grad[2][c] +
                                    dl[a][3] * grad[3][c];
-                        Bt[p][c][a] += w[q] * lq[p] * d;
+                        Bt[p][c][a] += w[q] * psi[p] * d;
                     }
             }
         }
-        for (int p = 0; p < 4; p++) {
-            for (int r = 0; r < 4; r++) {
-                mri[cm] = vt[p]; mci[cm] = vt[r]; mv[cm] = det * Mt[p][r]; cm++;
+        for (int p = 0; p < nlp; p++) {
+            const int row = o->ptet_node[(size_t)t * nlp + p];
+            for (int r = 0; r < nlp; r++) {
+                mri[cm] = row; mci[cm] = o->ptet_node[(size_t)t * nlp + r]; mv[cm] = det * Mt[p][r]; cm++;
             }
             for (int c = 0; c < 3; c++)
                 for (int a = 0; a < nloc; a++) {
                     int i = o->node_dof[o->tet_node[(size_t)t * nloc + a]];
                     if (i < 0) continue;
-                    bri[cb] = vt[p]; bci[cb] = c * n + i; bv[cb] = -det * Bt[p][c][a]; cb++;
+                    bri[cb] = row; bci[cb] = c * n + i; bv[cb] = -det * Bt[p][c][a]; cb++;
                 }
         }
     }
@@ -558,8 +600,34 @@ int orc_stokes_assemble(orc *o)
     ocsr_from_triplets(np, 3 * n, cb, bri, bci, bv, &o->Bdiv);
     ocsr_from_triplets(np, np, cm, mri, mci, mv, &o->Mp);
     ocsr_transpose(&o->Bdiv, &o->BdivT);
+    free(lam); free(w); free(Bt); free(Mt);
     free(bri); free(bci); free(bv); free(mri); free(mci); free(mv);
     return 0;
+}
+
+/* ||p - p_h||_{L2} of a pressure field (after orc_stokes_assemble): pq = exact
+   p at the points of the m-point rule [nt*m^3], ph [np] */
+double orc_pressure_l2_error(const orc *o, int m, const double *pq, const double *ph)
+{
+    int nq = m * m * m, kp = o->k - 1, nlp = o->nlp;
+    int beta[20 * 4];
+    orc_local_multi_indices(kp, beta);
+    double *lam = malloc((size_t)nq * 4 * sizeof(double)), *w = malloc((size_t)nq * sizeof(double));
+    orc_tet_rule(m, lam, w);
+    double err = 0.0;
+    for (int t = 0; t < o->nt; t++) {
+        double grad[4][3];
+        double det = tet_geometry(o, t, grad);
+        for (int q = 0; q < nq; q++) {
+            double v = 0.0;
+            for (int a = 0; a < nlp; a++)
+                v += ph[o->ptet_node[(size_t)t * nlp + a]] * orc_basis(kp, beta + 4 * a, lam + 4 * q);
+            double d = pq[(size_t)t * nq + q] - v;
+            err += det * w[q] * d * d;
+        }
+    }
+    free(lam); free(w);
+    return sqrt(err);
 }
 
 /* A_h, A_H, l1 norms and I_P */
