@@ -341,25 +341,31 @@ int pcg_solve_block(aux_handle *h, const double *F, double *U, int nrhs, double 
 int fgmres_solve(aux_handle *h, const double *b, double *x, double tol, int restart, int maxit, double *history,
                  aux_solve_info *info);
 
-/* Stokes system of the Hood-Taylor P^2-P^1 pair (Sec. 5, the paper's second
- * test problem) on the handle's mesh, order-2 handles only:
+/* Stokes system of the Hood-Taylor pair P^k - P^{k-1} (Sec. 5, the paper's
+ * second test problem; k = the handle's order, 2, 3 or 4) on the handle's
+ * mesh:
  *     [A  B^T] [u]   [f]
  *     [B   0 ] [p] = [g],   A = diag(A_h, A_h, A_h),
  * velocity u = (u_0, u_1, u_2) on the handle's dofs (zero on the boundary;
- * A_h with the handle's kappa as viscosity), pressure p in P^1 on every mesh
- * vertex (no boundary condition; constants are the null space of B^T),
- * B_{q,(c,i)} = -int lam_q dphi_i/dx_c (the discrete -div) and M_p the P^1
- * pressure mass matrix (int lam_q lam_r), both integrated exactly.  A Stokes
- * vector is a device double array [3 n_h + n_v]: u_0, u_1, u_2 in the dof
- * order of aux_dof_keys, then p in vertex order.
+ * A_h with the handle's kappa as viscosity), pressure p in the continuous
+ * P^{k-1} space on every node of order k-1 (no boundary condition; constants
+ * are the null space of B^T), B_{q,(c,i)} = -int psi_q dphi_i/dx_c (the
+ * discrete -div) and M_p the pressure mass matrix (int psi_q psi_r), both
+ * integrated exactly.  A Stokes vector is a device double array
+ * [3 n_h + n_p]: u_0, u_1, u_2 in the dof order of aux_dof_keys, then p in
+ * the order of its node keys (k-1 sorted vertex ids, lexicographic; for
+ * P^1 the vertex order, n_p = n_v).
  *
  * aux_stokes_setup builds B and M_p (host assembly, then a device copy of B,
- * B^T and M_p, about 24 nnz(A_h) bytes) and writes n_v to *n_p (may be NULL);
+ * B^T and M_p, about 24 nnz(B) bytes) and writes n_p to *n_p (may be NULL);
  * on a host-only handle it builds the host matrices only (aux_export_csr
  * which = 5 is B, 6 is M_p afterwards).  The other calls run it on first
- * use.  Errors: AUX_EINVAL (order other than 2), AUX_ENOMEM, AUX_EHIP. */
+ * use.  Errors: AUX_ENOMEM, AUX_EHIP. */
 int aux_stokes_setup(aux_handle *h, int32_t *n_p);
-/* y = [A B^T; B 0] x in FP64 (device x, y [3 n_h + n_v]; the handle's
+/* Node key of each pressure unknown: host int32 [n_p][k-1] (after
+ * aux_stokes_setup; AUX_ESTATE before). */
+int aux_stokes_pressure_keys(const aux_handle *h, int32_t *keys);
+/* y = [A B^T; B 0] x in FP64 (device x, y [3 n_h + n_p]; the handle's
  * operator form for A_h). */
 int stokes_apply_operator(aux_handle *h, const double *x, double *y);
 /* z = Q_t r, the block triangular preconditioner of Sec. 5 with the Schur
@@ -368,13 +374,13 @@ int stokes_apply_operator(aux_handle *h, const double *x, double *y);
  *     z_p = -M_p^{-1} r_p,   z_c = B (r_c - (B^T z_p)_c),
  * with M_p^{-1} r_p computed by diagonally preconditioned CG from zero until
  * ||r_p - M_p x|| <= 1e-6 ||r_p|| (at most 200 steps).  Device r, z
- * [3 n_h + n_v], not aliased.  mass_steps (host, may be NULL) receives the CG
+ * [3 n_h + n_p], not aliased.  mass_steps (host, may be NULL) receives the CG
  * step count.  Synchronises the stream (the mass CG's stop test). */
 int stokes_apply_qt(aux_handle *h, const double *r, double *z, int32_t *mass_steps);
 /* Flexible GMRES(restart) on the Stokes system with Q_t as the right
  * preconditioner (the paper's Stokes solver: FGMRES with Q_t).  Arguments,
  * stopping rule, history and statuses as fgmres_solve, on vectors
- * [3 n_h + n_v]; the basis takes (2 restart + 1) (3 n_h + n_v) doubles of
+ * [3 n_h + n_p]; the basis takes (2 restart + 1) (3 n_h + n_p) doubles of
  * device memory, kept until the handle is destroyed.  A right-hand side
  * with a pressure part orthogonal to the constants and a compatible
  * velocity part has solutions unique up to a constant pressure. */

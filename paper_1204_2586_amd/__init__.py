@@ -140,6 +140,7 @@ def load_library():
         "pcg_solve_batched": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, dbl, ctypes.c_int, P(_SolveInfo)]),
         "fgmres_solve": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int, vp, P(_SolveInfo)]),
         "aux_stokes_setup": (ctypes.c_int, [vp, P(i32)]),
+        "aux_stokes_pressure_keys": (ctypes.c_int, [vp, vp]),
         "stokes_apply_operator": (ctypes.c_int, [vp, vp, vp]),
         "stokes_apply_qt": (ctypes.c_int, [vp, vp, vp, P(i32)]),
         "stokes_fgmres_solve": (ctypes.c_int, [vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int, vp, P(_SolveInfo)]),
@@ -466,13 +467,22 @@ class Solver:
 
     # ------------------------------------------------------------ Stokes
     def stokes_setup(self) -> int:
-        """Build the Hood-Taylor P2-P1 Stokes blocks B and M_p (order 2);
-        returns the pressure count n_p (the vertex count).  Stokes vectors have
-        3 n_h + n_p entries: u_0, u_1, u_2 in dof order, then p per vertex."""
+        """Build the Hood-Taylor P^k-P^{k-1} Stokes blocks B and M_p (k = the
+        order); returns the pressure count n_p (the vertex count for P^1).
+        Stokes vectors have 3 n_h + n_p entries: u_0, u_1, u_2 in dof order,
+        then p in the order of stokes_pressure_keys()."""
         n_p = ctypes.c_int32(0)
         _check(load_library().aux_stokes_setup(self._h, ctypes.byref(n_p)))
         self.n_p = int(n_p.value)
         return self.n_p
+
+    def stokes_pressure_keys(self) -> np.ndarray:
+        """Node key of each pressure unknown: [n_p][order-1] sorted vertex ids."""
+        if self.n_p is None:
+            self.stokes_setup()
+        keys = np.zeros((self.n_p, self.order - 1), dtype=np.int32)
+        _check(load_library().aux_stokes_pressure_keys(self._h, _np_ptr(keys)))
+        return keys
 
     def _stokes_len(self):
         if self.n_p is None:

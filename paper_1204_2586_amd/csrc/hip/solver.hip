@@ -1313,7 +1313,7 @@ struct aux_handle {
     }
 
     // ------------------------------------------------------------ Stokes
-    // Hood-Taylor P^2-P^1 Stokes system (Sec. 5) on the handle's mesh,
+    // Hood-Taylor P^k-P^{k-1} Stokes system (Sec. 5) on the handle's mesh,
     //   F = [A  B^T; B  0],  A = diag(A_h, A_h, A_h),
     // with the block triangular preconditioner (Sec. 5, Q_t)
     //   Q_t = [A  B^T; 0  -S]^{-1},  S replaced by the pressure mass matrix
@@ -1321,13 +1321,14 @@ struct aux_handle {
     //   y_p = -M_p^{-1} r_p  (diagonal PCG from zero to a relative 1e-6, at
     //   most 200 steps),  y_c = B (r_c - (B^T y_p)_c).
     // Internal layout of a Stokes vector: the three velocity components, each
-    // in the internal dof order, then the pressure in vertex order.
+    // in the internal dof order, then the pressure in its key order.
     static constexpr double kMassTol = 1e-6;
     static constexpr int kMassMaxit = 200;
     struct StokesData {
         bool host_ready = false, ready = false;
         int np = 0;
         Csr B, Mp;                   // host, external numbering
+        std::vector<int32_t> pkeys;  // [np][k-1] pressure node keys
         DevOp Bi, BTi, M;            // FP64 device operators, internal velocity order
         double *mdinv = nullptr;     // 1 / diag(M_p)
         double *mx = nullptr, *mr = nullptr, *mz = nullptr, *mp = nullptr, *mq = nullptr;
@@ -1344,11 +1345,11 @@ struct aux_handle {
     {
         if (sk.host_ready) return;
         try {
-            build_stokes(disc, sk.B, sk.Mp);
+            build_stokes(disc, sk.B, sk.Mp, sk.pkeys);
         } catch (const std::invalid_argument &e) {
             throw AuxError(AUX_EINVAL, e.what());
         }
-        sk.np = disc.nv;
+        sk.np = sk.B.n;
         sk.host_ready = true;
     }
 
@@ -2944,6 +2945,16 @@ int aux_stokes_setup(aux_handle *h, int32_t *n_p)
         h->stokes_setup();
         if (!h->host_only) HIPCHECK(hipGetLastError());
         if (n_p) *n_p = h->sk.np;
+        return AUX_OK;
+    });
+}
+
+int aux_stokes_pressure_keys(const aux_handle *h, int32_t *keys)
+{
+    return guarded([&]() {
+        if (!h || !keys) throw AuxError(AUX_EINVAL, "null argument");
+        if (!h->sk.host_ready) throw AuxError(AUX_ESTATE, "call aux_stokes_setup first");
+        std::memcpy(keys, h->sk.pkeys.data(), h->sk.pkeys.size() * sizeof(int32_t));
         return AUX_OK;
     });
 }

@@ -98,6 +98,22 @@ std::vector<Term> dphi(int k, const int *alpha, int p)
     return out;
 }
 
+// phi_alpha as a list of barycentric monomials
+std::vector<Term> phi(int k, const int *alpha)
+{
+    std::vector<double> f[4];
+    for (int q = 0; q < 4; q++) f[q] = lagrange_factor(k, alpha[q]);
+    std::vector<Term> out;
+    for (size_t i0 = 0; i0 < f[0].size(); i0++)
+        for (size_t i1 = 0; i1 < f[1].size(); i1++)
+            for (size_t i2 = 0; i2 < f[2].size(); i2++)
+                for (size_t i3 = 0; i3 < f[3].size(); i3++) {
+                    double c = f[0][i0] * f[1][i1] * f[2][i2] * f[3][i3];
+                    if (c != 0.0) out.push_back({{(int)i0, (int)i1, (int)i2, (int)i3}, c});
+                }
+    return out;
+}
+
 // (1/|T|) int_T lam^e = 3! e0! e1! e2! e3! / (|e|+3)!
 double simplex_moment(const int *e)
 {
@@ -144,25 +160,37 @@ const Tables &tables(int k)
 
 const std::vector<double> &stiffness_tables(int k) { return tables(k).M; }
 
-std::vector<double> coupling_tables(int k)
+void stokes_tables(int k, std::vector<double> &C, std::vector<double> &Mp)
 {
-    std::vector<int> al = multi_indices(k);
-    const int n = (int)al.size() / 4;
-    std::vector<double> C((size_t)4 * n * 4, 0.0);
+    const std::vector<int> al = multi_indices(k), be = multi_indices(k - 1);
+    const int n = (int)al.size() / 4, np = (int)be.size() / 4;
+    std::vector<std::vector<Term>> ps(np);
+    for (int p = 0; p < np; p++) ps[p] = phi(k - 1, &be[4 * p]);
+    C.assign((size_t)4 * n * np, 0.0);
     for (int q = 0; q < 4; q++)
         for (int a = 0; a < n; a++) {
             const std::vector<Term> d = dphi(k, &al[4 * a], q);
-            for (int p = 0; p < 4; p++) {
+            for (int p = 0; p < np; p++) {
                 double s = 0.0;
-                for (const Term &x : d) {
-                    int e[4] = {x.e[0], x.e[1], x.e[2], x.e[3]};
-                    e[p]++;
-                    s += x.c * simplex_moment(e);
-                }
-                C[((size_t)q * n + a) * 4 + p] = s;
+                for (const Term &x : d)
+                    for (const Term &y : ps[p]) {
+                        int e[4] = {x.e[0] + y.e[0], x.e[1] + y.e[1], x.e[2] + y.e[2], x.e[3] + y.e[3]};
+                        s += x.c * y.c * simplex_moment(e);
+                    }
+                C[((size_t)q * n + a) * np + p] = s;
             }
         }
-    return C;
+    Mp.assign((size_t)np * np, 0.0);
+    for (int p = 0; p < np; p++)
+        for (int r = 0; r < np; r++) {
+            double s = 0.0;
+            for (const Term &x : ps[p])
+                for (const Term &y : ps[r]) {
+                    int e[4] = {x.e[0] + y.e[0], x.e[1] + y.e[1], x.e[2] + y.e[2], x.e[3] + y.e[3]};
+                    s += x.c * y.c * simplex_moment(e);
+                }
+            Mp[(size_t)p * np + r] = s;
+        }
 }
 
 double tet_gradients(const double *X0, const double *X1, const double *X2, const double *X3, double g[4][3])

@@ -81,17 +81,21 @@ double tet_metric(const double *X0, const double *X1, const double *X2, const do
                   double G[4][4]);
 // barycentric gradients g[p] = grad lam_p of a tet, returns the signed det J
 double tet_gradients(const double *X0, const double *X1, const double *X2, const double *X3, double g[4][3]);
-// C[q][a][p] = (1/|T|) int_T lam_p dphi_a/dlam_q for the P^k basis
-// ([4][nloc][4], exact integration of barycentric monomials)
-std::vector<double> coupling_tables(int k);
+// Reference tables of the Hood-Taylor pair P^k - P^{k-1} (psi_p the P^{k-1}
+// basis, phi_a the P^k basis, exact integration of barycentric monomials):
+//   C[q][a][p] = (1/|T|) int_T psi_p dphi_a/dlam_q   ([4][nloc][nlp])
+//   Mp[p][r]   = (1/|T|) int_T psi_p psi_r           ([nlp][nlp])
+void stokes_tables(int k, std::vector<double> &C, std::vector<double> &Mp);
 
-// Hood-Taylor P^2-P^1 Stokes blocks (stokes.cpp), pressure on every mesh
-// vertex (vertex id order), velocity on the interior P^2 dofs, component
-// blocks c = 0, 1, 2 of n_h columns each:
-//   B   (n_v x 3 n_h):  B_{p, c n_h + i} = -int lam_p dphi_i/dx_c  (-div)
-//   M_p (n_v x n_v):    (M_p)_pq = int lam_p lam_q
-// Entries are summed in tet order.  Throws std::invalid_argument unless k = 2.
-void build_stokes(const Discretization &d, Csr &B, Csr &Mp);
+// Hood-Taylor P^k - P^{k-1} Stokes blocks (stokes.cpp), k = 2, 3, 4: the
+// pressure on every node of order k-1 (no boundary condition), numbered by
+// its key (k-1 sorted vertex ids) in lexicographic order (vertex order for
+// P^1), keys returned in pkeys [np][k-1]; velocity on the interior P^k dofs,
+// component blocks c = 0, 1, 2 of n_h columns each:
+//   B   (n_p x 3 n_h):  B_{p, c n_h + i} = -int psi_p dphi_i/dx_c  (-div)
+//   M_p (n_p x n_p):    (M_p)_pq = int psi_p psi_q
+// Entries are summed in tet order.  Throws std::invalid_argument for other k.
+void build_stokes(const Discretization &d, Csr &B, Csr &Mp, std::vector<int32_t> &pkeys);
 
 // load vector by the conical-product rule with k+2 points per direction
 int load_rule_points(int k);                               // points per tet

@@ -1,9 +1,10 @@
-"""Host assembly of the library's Stokes blocks (Hood-Taylor P2-P1, Sec. 5)
-against the oracle's, on host-only handles (no GPU).
+"""Host assembly of the library's Stokes blocks (Hood-Taylor P^k-P^{k-1},
+Sec. 5) against the oracle's, on host-only handles (no GPU).
 
 The library integrates B = -div and the pressure mass matrix M_p exactly by
-barycentric moments; the oracle by a degree-2 quadrature rule, exact for
-these integrands.  Same patterns, values within 1e-14 of the largest entry.
+barycentric moments; the oracle by a conical-product rule exact for these
+integrands.  Same pressure keys, same patterns, values within 1e-14 of the
+largest entry.
 """
 import numpy as np
 import pytest
@@ -12,15 +13,19 @@ import oracle
 import paper_1204_2586_amd as aux
 import workloads as W
 
+CASES = [(2, 3, 0.2, True), (2, 5, 0.2, False), (2, 4, 0.0, True), (3, 3, 0.2, True), (3, 4, 0.0, False),
+         (4, 2, 0.2, True), (4, 3, 0.0, False)]
 
-@pytest.mark.parametrize("n,jitter,rand", [(3, 0.2, True), (5, 0.2, False), (4, 0.0, True)])
-def test_blocks_match_oracle(n, jitter, rand):
+
+@pytest.mark.parametrize("k,n,jitter,rand", CASES)
+def test_blocks_match_oracle(k, n, jitter, rand):
     xyz, tets = W.kuhn_mesh(n, jitter=jitter, seed=2)
     kap = np.exp(np.random.default_rng(1).normal(size=len(tets))) if rand else None
-    s = aux.Solver(xyz, tets, 2, kap, host_only=True)
-    assert s.stokes_setup() == xyz.shape[0]
-    P = oracle.Problem(xyz, tets, 2, kap).stokes_setup()
+    s = aux.Solver(xyz, tets, k, kap, host_only=True)
+    P = oracle.Problem(xyz, tets, k, kap).stokes_setup()
+    assert s.stokes_setup() == P.np
     assert np.array_equal(s.dof_keys(), P.dof_keys())
+    assert np.array_equal(s.stokes_pressure_keys(), P.pressure_keys())
     for which in ("B", "Mp"):
         a, b = s.export_csr(which), P.csr(which)
         assert a.shape == b.shape
@@ -28,27 +33,27 @@ def test_blocks_match_oracle(n, jitter, rand):
         assert np.max(np.abs(a.data - b.data)) <= 1e-14 * np.max(np.abs(b.data)), which
 
 
-def test_blocks_properties():
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_blocks_properties(k):
     """Independent of the oracle: B^T 1 = 0 (constants are the pressure null
-    space), the mass matrix integrates 1 and x exactly (1 and 1/3)."""
-    xyz, tets = W.kuhn_mesh(4, jitter=0.2, seed=3)
-    s = aux.Solver(xyz, tets, 2, host_only=True)
-    s.stokes_setup()
+    space); the mass matrix integrates 1 and x^2 exactly (1 and 1/3, the
+    nodal values of x at the pressure nodes)."""
+    xyz, tets = W.kuhn_mesh(3, jitter=0.2, seed=3)
+    s = aux.Solver(xyz, tets, k, host_only=True)
+    npr = s.stokes_setup()
     B, M = s.export_csr("B"), s.export_csr("Mp")
-    assert B.shape == (xyz.shape[0], 3 * s.n)
-    assert np.max(np.abs(B.T @ np.ones(B.shape[0]))) <= 1e-14 * np.abs(B).max()
-    one = np.ones(M.shape[0])
+    assert B.shape == (npr, 3 * s.n)
+    assert npr == (3 * (k - 1) + 1) ** 3
+    assert np.max(np.abs(B.T @ np.ones(npr))) <= 1e-14 * np.abs(B).max()
+    one = np.ones(npr)
     assert abs(one @ M @ one - 1.0) <= 1e-14
+    X = xyz[s.stokes_pressure_keys()].mean(axis=1)
     for c in range(3):
-        assert abs(xyz[:, c] @ M @ xyz[:, c] - 1.0 / 3.0) <= 1e-14
+        assert abs(X[:, c] @ M @ X[:, c] - 1.0 / 3.0) <= 1e-14
 
 
-@pytest.mark.parametrize("order", [3, 4])
-def test_other_orders_rejected(order):
+def test_keys_before_setup():
     xyz, tets = W.kuhn_mesh(2)
-    s = aux.Solver(xyz, tets, order, host_only=True)
-    with pytest.raises(aux.AuxError) as e:
-        s.stokes_setup()
-    assert e.value.code == aux.EINVAL
+    s = aux.Solver(xyz, tets, 2, host_only=True)
     with pytest.raises(aux.AuxError):
         s.export_csr("B")
