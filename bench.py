@@ -373,12 +373,12 @@ def run_extra_p3(args):
     return out
 
 
-def run_stokes(args):
-    """Stokes, Hood-Taylor P2-P1 (Sec. 5) on the jittered P2 48^3 mesh:
-    FGMRES(30) with the block triangular preconditioner Q_t to 1e-8 from
-    zero, body force of a smooth manufactured solution; one step is one
-    solve.  The oracle solves the 16^3 system of the same family (the CPU
-    sample, and the GPU's error against it at that size)."""
+def run_stokes(args, k=2, n=48, n_oracle=16):
+    """Stokes, Hood-Taylor P^k-P^{k-1} (Sec. 5) on a jittered mesh of n^3
+    cubes: FGMRES(30) with the block triangular preconditioner Q_t to 1e-8
+    from zero, body force of a smooth manufactured solution; one step is one
+    solve.  The oracle solves the n_oracle^3 system of the same family (the
+    CPU sample, and the GPU's error against it at that size)."""
     import numpy as np
     import torch
 
@@ -387,16 +387,16 @@ def run_stokes(args):
     import workloads as W
     dev = torch.device("cuda:0")
 
-    def system(n):
-        xyz, tets = W.kuhn_mesh(n, jitter=0.2, seed=0)
+    def system(m):
+        xyz, tets = W.kuhn_mesh(m, jitter=0.2, seed=0)
         t0 = time.time()
-        s = aux.Solver(xyz, tets, 2, nu=args.nu, precision="mixed", device=dev)
+        s = aux.Solver(xyz, tets, k, nu=args.nu, precision="mixed", device=dev)
         npr = s.stokes_setup()
         setup_s = time.time() - t0
         b = np.concatenate([s.load(W.stokes_f(c)) for c in range(3)] + [np.zeros(npr)])
         return xyz, tets, s, b, setup_s
 
-    xyz, tets, s, b, setup_s = system(48)
+    xyz, tets, s, b, setup_s = system(n)
     bt = torch.tensor(b, dtype=torch.float64, device=dev)
     N = 3 * s.n + s.n_p
     reps = max(1, min(args.steps, 5))
@@ -412,13 +412,16 @@ def run_stokes(args):
         ms = (time.perf_counter() - t) * 1e3 / reps
         true_res = float(torch.linalg.norm(bt - s.stokes_operator(x)) / torch.linalg.norm(bt))
         res[mode] = dict(ms=ms, iterations=info.iterations, true_rel_residual=true_res)
+    s.set_precision("mixed")
     r = torch.zeros(N, dtype=torch.float64, device=dev)
     r[3 * s.n:] = torch.tensor(np.random.default_rng(3).standard_normal(s.n_p), dtype=torch.float64, device=dev)
     _, mass_steps = s.stokes_qt(r)
-    out = {"metric": "Stokes FGMRES(30) + Q_t solve throughput to 1e-8", "unit": "unknowns/s",
-           "value": N / (res["mixed"]["ms"] * 1e-3), "ms_per_solve": round(res["mixed"]["ms"], 3),
+    pair = f"p{k}p{k - 1}"
+    out = {"metric": f"Stokes (Hood-Taylor P{k}-P{k - 1}) FGMRES(30) + Q_t solve throughput to 1e-8",
+           "unit": "unknowns/s", "value": N / (res["mixed"]["ms"] * 1e-3),
+           "ms_per_solve": round(res["mixed"]["ms"], 3),
            "dtype": "f64 FGMRES / f32 velocity preconditioner / f64 pressure mass CG",
-           "config": {"workload": "stokes_p2p1_n48_jitter", "cubes_per_side": 48, "jitter": 0.2,
+           "config": {"workload": f"stokes_{pair}_n{n}_jitter", "cubes_per_side": n, "jitter": 0.2,
                       "n_velocity": 3 * s.n, "n_pressure": s.n_p, "unknowns": N,
                       "iterations": res["mixed"]["iterations"],
                       "true_rel_residual": res["mixed"]["true_rel_residual"],
@@ -429,10 +432,10 @@ def run_stokes(args):
     del s, bt
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        xyz, tets, s, b, _ = system(16)
+        xyz, tets, s, b, _ = system(n_oracle)
         x, info, _ = s.stokes_fgmres(torch.tensor(b, dtype=torch.float64, device=dev), tol=1e-8, restart=30)
         x = x.cpu().numpy()
-        P = oracle.Problem(xyz, tets, 2).setup_amg(nu=args.nu).stokes_setup()
+        P = oracle.Problem(xyz, tets, k).setup_amg(nu=args.nu).stokes_setup()
         t0 = time.perf_counter()
         xo, it, rr, st, _ = P.stokes_fgmres(b, tol=1e-8, restart=30, fp32=True)
         dt = time.perf_counter() - t0
@@ -440,13 +443,22 @@ def run_stokes(args):
         pm = lambda v: v[3 * m:] - v[3 * m:].mean()
         out["cpu_baseline"] = {"value": len(b) / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
                                "sample": f"one FGMRES(30) + Q_t solve (FP32 velocity preconditioner) of the "
-                                         f"jittered P2-P1 16^3 system ({len(b)} unknowns) to 1e-8, {it} steps, "
-                                         f"{dt:.1f} s"}
-        out["oracle_error_16"] = {"gpu_steps": info.iterations, "oracle_steps": it,
-                                  "velocity_rel_diff": float(np.linalg.norm(x[:3 * m] - xo[:3 * m])
-                                                             / np.linalg.norm(xo[:3 * m])),
-                                  "pressure_rel_diff_mod_const": float(np.linalg.norm(pm(x) - pm(xo))
-                                                                       / np.linalg.norm(pm(xo)))}
+                                         f"jittered P{k}-P{k - 1} {n_oracle}^3 system ({len(b)} unknowns) to "
+                                         f"1e-8, {it} steps, {dt:.1f} s"}
+        out[f"oracle_error_{n_oracle}"] = {"gpu_steps": info.iterations, "oracle_steps": it,
+                                           "velocity_rel_diff": float(np.linalg.norm(x[:3 * m] - xo[:3 * m])
+                                                                      / np.linalg.norm(xo[:3 * m])),
+                                           "pressure_rel_diff_mod_const": float(np.linalg.norm(pm(x) - pm(xo))
+                                                                                / np.linalg.norm(pm(xo)))}
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
+def run_stokes_pairs(args):
+    """P2-P1 on 48^3 cubes and P3-P2 on 32^3 cubes (2.69M and 2.85M unknowns)."""
+    out = run_stokes(args, k=2, n=48, n_oracle=16)
+    out["p3p2_n32_jitter"] = run_stokes(args, k=3, n=32, n_oracle=8)
     return out
 
 
@@ -527,6 +539,8 @@ def run(args):
         out["workloads"]["p2_n64_32rhs"] = summarize_batched(run_batched(a))
         torch.cuda.empty_cache()
         out["workloads"]["stokes_p2p1_n48_jitter"] = run_stokes(args)
+        torch.cuda.empty_cache()
+        out["workloads"]["stokes_p3p2_n32_jitter"] = run_stokes(args, k=3, n=32, n_oracle=8)
     return out
 
 
@@ -986,7 +1000,7 @@ def main():
         sys.exit(2)
     wl = WORKLOADS[args.workload]
     if args.krylov == "stokes":
-        fn = run_stokes
+        fn = run_stokes_pairs
     elif "nrhs" in wl:
         fn = run_batched
     elif wl.get("adjoint"):

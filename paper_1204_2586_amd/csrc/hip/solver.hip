@@ -408,18 +408,23 @@ struct aux_handle {
     // lanes per row and row-split ELL with 1-32 lanes per row, and keep the
     // fastest.  In the solve the operator's data has been evicted by the P^k
     // passes, so each timed launch follows a write of `flush` bytes that
-    // clears the caches.
+    // clears the caches.  (T = double: the same for an FP64-only operator.)
     void tune_op(DevOp &op, const Csr &host, int split, void *flush, size_t flush_bytes)
     {
-        if (!op.v32 || op.n == 0) return;
-        float *x = dnew<float>(std::max(op.m, 1)), *y = dnew<float>(op.n);
-        HIPCHECK(hipMemsetAsync(x, 0, (size_t)std::max(op.m, 1) * sizeof(float), stream));
+        tune_op_t<float>(op, host, split, flush, flush_bytes);
+    }
+    template <typename T>
+    void tune_op_t(DevOp &op, const Csr &host, int split, void *flush, size_t flush_bytes)
+    {
+        if (!(std::is_same<T, float>::value ? (void *)op.v32 : (void *)op.v64) || op.n == 0) return;
+        T *x = dnew<T>(std::max(op.m, 1)), *y = dnew<T>(op.n);
+        HIPCHECK(hipMemsetAsync(x, 0, (size_t)std::max(op.m, 1) * sizeof(T), stream));
         const double avg = (double)op.nnz / op.n;
         hipEvent_t a = take_event(), b = take_event();
         auto measure = [&]() {
             auto run = [&]() {
-                if (split > 0) csr_matvec2<float>(stream, op.view<float>(), x, x + split, split, y, nullptr);
-                else csr_matvec<float>(stream, op.view<float>(), x, y, nullptr);
+                if (split > 0) csr_matvec2<T>(stream, op.view<T>(), x, x + split, split, y, nullptr);
+                else csr_matvec<T>(stream, op.view<T>(), x, y, nullptr);
             };
             run();
             double total = 0.0;
@@ -1361,10 +1366,18 @@ struct aux_handle {
         std::vector<int> map3((size_t)3 * n);
         for (int c = 0; c < 3; c++)
             for (int i = 0; i < n; i++) map3[(size_t)c * n + i] = c * n + sell.iperm[i];
-        Csr Bi = renumber_cols(sk.B, map3, 3 * n);
+        Csr Bi = renumber_cols(sk.B, map3, 3 * n), BTi = transpose(Bi);
         sk.Bi = upload_op(Bi);
-        sk.BTi = upload_op(transpose(Bi));
+        sk.BTi = upload_op(BTi);
         sk.M = upload_op(sk.Mp);
+        // storage of B and B^T (FP64 products), timed as the V-cycle's
+        if (opt.sell_window <= 0) {
+            const size_t fb = (size_t)512 << 20;
+            void *flush = dalloc(fb);
+            tune_op_t<double>(sk.Bi, Bi, 0, flush, fb);
+            tune_op_t<double>(sk.BTi, BTi, 0, flush, fb);
+            dfree(flush);
+        }
         std::vector<double> dinv(np, 0.0);
         for (int i = 0; i < np; i++)
             for (int e = sk.Mp.ptr[i]; e < sk.Mp.ptr[i + 1]; e++)
@@ -1387,7 +1400,8 @@ struct aux_handle {
 
     // sk.mx = M_p^{-1} b (device b [n_p]) by diagonal PCG from zero, stopped
     // at ||r|| <= 1e-6 ||b|| or 200 steps.  The steps run with their state in
-    // device memory; the host enqueues as many as the last solve took (plus
+    // device memory, five launches each (product, p.q, update, r.r and r.z,
+    // direction); the host enqueues as many as the last solve took (plus
     // one) and then two at a time until the stop flag is set.  Returns the
     // step count.
     int mass_solve(const double *b)
@@ -1409,8 +1423,7 @@ struct aux_handle {
                 g = mass_product(s, Mv, sk.mp, sk.mq, sk.part, st);
                 finish(s, sk.part, g, FIN_PQ, nullptr, st);
                 g = mass_update(s, np, sk.mx, sk.mr, sk.mp, sk.mq, sk.mdinv, sk.mz, sk.part, st);
-                finish(s, sk.part, g, FIN_RR, nullptr, st);
-                finish(s, part_rz, g, FIN_RZ, nullptr, st);
+                mass_finish(s, sk.part, g, st);
                 cg_direction(s, np, sk.mz, sk.mp, st);
             }
             HIPCHECK(hipMemcpyAsync(sk.host_state, sk.istate, 2 * sizeof(int), hipMemcpyDeviceToHost, s));

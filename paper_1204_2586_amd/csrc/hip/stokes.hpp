@@ -16,10 +16,13 @@ namespace auxp {
 // r.z.  Returns g.
 int mass_start(hipStream_t s, int n, const double *b, const double *dinv, double *x, double *r, double *z,
                double *partials);
-// q = M p (CSR, one thread per row) with the shares of p.q in partials;
+// q = M p (CSR, a few lanes per row) with the shares of p.q in partials;
 // returns the grid size (skipped once the solve stopped).
 int mass_product(hipStream_t s, const DevCsrView &M, const double *p, double *q, double *partials,
                  const CgState &st);
+// one workgroup: r.r (partials[0 ..)) closes the step (iteration count, stop
+// test), then r.z (partials[kMaxBlocks ..)) is recorded for the next step
+void mass_finish(hipStream_t s, const double *partials, int nparts, const CgState &st);
 // alpha = rz[k] / pq[k]: x += alpha p, r -= alpha q, z = D^-1 r; shares of
 // r.r in partials[0 .. g) and of r.z in partials[kMaxBlocks ..).  Returns g.
 int mass_update(hipStream_t s, int n, double *x, double *r, const double *p, const double *q, const double *dinv,
