@@ -238,9 +238,18 @@ void mf_apply(hipStream_t s, const MfView<T> &op, const T *x, T *Yel, const int 
     // (the element kernel's clamped loads read X[0]: nothing to do without unknowns)
     if (op.n == 0 || op.nt == 0) return;
     // persistent waves, a few tiles each (the operand tables are staged once
-    // per workgroup); up to 8 workgroups per compute unit
+    // per workgroup): up to 8 workgroups per compute unit at P2, 4 at P3 and
+    // P4.  Each wave loads its tile's map, weights, slots and gathers, waits,
+    // then runs its matrix-core chain (60 MFMA of 32 cycles at P3), so the
+    // waves of a SIMD overlap one another's phases; measured (P3 32^3, P4
+    // 24^3, P2 48^3 mixed solves): 1024 workgroups beat 2048 at P3 (8.77 ->
+    // 8.33 ms) and P4 (15.04 -> 14.29 ms) and lose at P2 (8.82 -> 8.97 ms);
+    // 512, 768 and 1536 were no better.  A software pipeline over each
+    // wave's tiles (the next tile's loads and gathers issued before the
+    // current contraction) was measured no faster.
     const long long tiles = ((long long)op.nt + kTetsPerWave - 1) / kTetsPerWave;
-    int g = (int)std::min<long long>((tiles + kWaves - 1) / kWaves, 2048);
+    const int cap = op.nloc == 10 ? 2048 : 1024;
+    int g = (int)std::min<long long>((tiles + kWaves - 1) / kWaves, cap);
     if (g < 1) g = 1;
     if (op.nloc == 10)
         hipLaunchKernelGGL((k_mf_element<T, 10>), dim3(g), dim3(kBlock), 0, s, op, x, Yel, done);
