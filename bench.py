@@ -29,6 +29,14 @@ sys.path.insert(0, ROOT)
 METRIC = "P2/P3 Poisson time-to-1e-8 residual, DOF/s, precond HBM GB/s; mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
 
+
+_T0 = time.time()
+
+
+def progress(msg):
+    """One line per finished stage on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench {time.time() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
 WORKLOADS = {
     "p2_n48_jitter": dict(k=2, n=48, jitter=0.2, seed=0, kappa=None),
     "p2_n8": dict(k=2, n=8, jitter=0.0, seed=0, kappa=None),
@@ -235,6 +243,7 @@ def timed_solves(s, f, u, args, mode):
         s.solve(f, tol=args.tol, out=u)
     torch.cuda.synchronize()
     prof_apply = s.profile_read()["apply"]
+    progress(f"{mode} solves: {ms:.3f} ms each, {its[-1]} iterations")
     s.profile(False)
     return dict(ms=ms, ms_profiled=ms_prof, iterations=its, true_rel_residual=true_res, prof=prof, u=sol,
                 prof_apply=prof_apply)
@@ -292,6 +301,7 @@ def oracle_reference(xyz, tets, wl, kappa, args, reps):
     P = oracle.Problem(xyz, tets, wl["k"], kappa).setup_amg(nu=args.nu)
     b = P.load(W.manufactured_f)
     setup = time.time() - t0
+    progress(f"oracle setup ({P.n} unknowns): {setup:.1f} s")
     model, ncpu = host_cpu()
     keep = os.sched_getaffinity(0)
     one = {min(keep)}
@@ -302,7 +312,9 @@ def oracle_reference(xyz, tets, wl, kappa, args, reps):
             t0 = time.perf_counter()
             x, it, rr, st = P.pcg(b, tol=args.tol)
             times.append(time.perf_counter() - t0)
+            progress(f"oracle timed solve {len(times)}/{reps}: {times[-1]:.1f} s")
         x_tight, it_tight, _, _ = P.pcg(b, tol=1e-13)
+        progress(f"oracle 1e-13 reference solve: {it_tight} iterations")
     finally:
         os.sched_setaffinity(0, keep)
     dt = statistics.median(times)
@@ -356,6 +368,7 @@ def run_extra_p3(args):
     t0 = time.time()
     s = aux.Solver(xyz, tets, wl["k"], kappa, nu=args.nu, precision="mixed", device=dev)
     setup_s = time.time() - t0
+    progress(f"GPU setup: {setup_s:.2f} s")
     b = s.load(W.manufactured_f)
     f = torch.tensor(b, dtype=torch.float64, device=dev)
     out = {"order": wl["k"], "cubes_per_side": wl["n"], "kappa": "exp(GRF seed 1)", "n_h": s.n,
@@ -393,6 +406,7 @@ def run_stokes(args, k=2, n=48, n_oracle=16):
         s = aux.Solver(xyz, tets, k, nu=args.nu, precision="mixed", device=dev)
         npr = s.stokes_setup()
         setup_s = time.time() - t0
+        progress(f"GPU setup: {setup_s:.2f} s")
         b = np.concatenate([s.load(W.stokes_f(c)) for c in range(3)] + [np.zeros(npr)])
         return xyz, tets, s, b, setup_s
 
@@ -412,6 +426,7 @@ def run_stokes(args, k=2, n=48, n_oracle=16):
         ms = (time.perf_counter() - t) * 1e3 / reps
         true_res = float(torch.linalg.norm(bt - s.stokes_operator(x)) / torch.linalg.norm(bt))
         res[mode] = dict(ms=ms, iterations=info.iterations, true_rel_residual=true_res)
+        progress(f"Stokes P{k}-P{k - 1} {mode}: {ms:.1f} ms per solve, {info.iterations} steps")
     s.set_precision("mixed")
     r = torch.zeros(N, dtype=torch.float64, device=dev)
     r[3 * s.n:] = torch.tensor(np.random.default_rng(3).standard_normal(s.n_p), dtype=torch.float64, device=dev)
@@ -439,6 +454,7 @@ def run_stokes(args, k=2, n=48, n_oracle=16):
         t0 = time.perf_counter()
         xo, it, rr, st, _ = P.stokes_fgmres(b, tol=1e-8, restart=30, fp32=True)
         dt = time.perf_counter() - t0
+        progress(f"oracle Stokes solve ({len(b)} unknowns): {dt:.1f} s, {it} steps")
         m = s.n
         pm = lambda v: v[3 * m:] - v[3 * m:].mean()
         out["cpu_baseline"] = {"value": len(b) / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
@@ -479,6 +495,7 @@ def run(args):
     t0 = time.time()
     s = aux.Solver(xyz, tets, wl["k"], kappa, nu=args.nu, precision="mixed", device=dev, operator=args.operator)
     setup_s = time.time() - t0
+    progress(f"GPU setup: {setup_s:.2f} s")
     b = s.load(W.manufactured_f)
     f = torch.tensor(b, dtype=torch.float64, device=dev)
     n, nnz = s.n, int(s.info.nnz_A)
@@ -585,6 +602,7 @@ def run_batched(args):
     s = aux.Solver(xyz, tets, wl["k"], None, nu=args.nu, precision="mixed", device=dev,
                    batch_order=getattr(args, "batch_order", 0))
     setup_s = time.time() - t0
+    progress(f"GPU setup: {setup_s:.2f} s")
     t0 = time.time()
     B = s.load_many(W.fourier_fields(range(nrhs)), nrhs, threads=args.threads)
     load_s = time.time() - t0
@@ -610,7 +628,9 @@ def run_batched(args):
         return dict(ms=ms, its=[i.iterations for i in infos], true_res=float(res.max()), prof=prof, U=U)
 
     mixed = timed("mixed")
+    progress(f"batched mixed: {mixed['ms']:.2f} ms per batch")
     fp64 = timed("fp64")
+    progress(f"batched fp64: {fp64['ms']:.2f} ms per batch")
     # the same sources one at a time (mixed), for the lock-step gain
     s.set_precision("mixed")
     u = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -624,6 +644,7 @@ def run_batched(args):
         single_its.append(info.iterations)
     torch.cuda.synchronize()
     single_ms = (time.perf_counter() - t) * 1e3
+    progress(f"sequential single-source solves: {single_ms:.1f} ms")
     diff = float(torch.linalg.norm(mixed["U"] - fp64["U"]) / torch.linalg.norm(fp64["U"]))
     # O'Leary's block CG on the same sources (FP32 preconditioner)
     s.set_precision("mixed")
@@ -635,6 +656,7 @@ def run_batched(args):
         Ub, binfos = s.solve_block(F, tol=args.tol)
     torch.cuda.synchronize()
     block_ms = (time.perf_counter() - t) * 1e3 / args.steps
+    progress(f"block CG: {block_ms:.2f} ms per batch")
     block_res = max(float(torch.linalg.norm(F[:, c] - s.matvec(Ub[:, c].contiguous())) / torch.linalg.norm(F[:, c]))
                     for c in range(nrhs))
     block_diff = float(torch.linalg.norm(Ub - fp64["U"]) / torch.linalg.norm(fp64["U"]))
@@ -733,6 +755,7 @@ def cpu_baseline_single(xyz, tets, wl, args):
         return out
 
     b = P.load(f)
+    progress(f"oracle setup and load vector ({P.n} unknowns) done")
     model, ncpu = host_cpu()
     keep = os.sched_getaffinity(0)
     os.sched_setaffinity(0, {min(keep)})
@@ -740,6 +763,7 @@ def cpu_baseline_single(xyz, tets, wl, args):
         t0 = time.perf_counter()
         x, it, rr, st = P.pcg(b, tol=args.tol)
         dt = time.perf_counter() - t0
+        progress(f"oracle solve: {dt:.1f} s, {it} iterations")
     finally:
         os.sched_setaffinity(0, keep)
     entry = {"value": P.n / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle", "cpu_model": model,
@@ -769,6 +793,7 @@ def run_fgmres(args):
     t0 = time.time()
     s = aux.Solver(xyz, tets, wl["k"], kappa, nu=args.nu, precision="mixed", device=dev, operator=args.operator)
     setup_s = time.time() - t0
+    progress(f"GPU setup: {setup_s:.2f} s")
     n = s.n
     x0 = torch.tensor(np.random.default_rng(7).uniform(-1.0, 1.0, n), dtype=torch.float64, device=dev)
     zero = torch.zeros_like(x0)
@@ -794,7 +819,9 @@ def run_fgmres(args):
         return dict(ms=ms, iterations=info.iterations, true_rel_residual=true_res, prof=prof)
 
     mixed = timed("mixed")
+    progress(f"FGMRES mixed: {mixed['ms']:.2f} ms per solve")
     fp64 = timed("fp64")
+    progress(f"FGMRES fp64: {fp64['ms']:.2f} ms per solve")
     kernels = kernel_table(mixed["prof"], args, s, wl, len(tets))
     dom = max(kernels, key=lambda c: kernels[c]["total_ms"])
     kd = kernels[dom]
@@ -827,16 +854,35 @@ def run_fgmres(args):
                      "bytes_per_launch": kd["bytes"], "avg_us": kd["avg_us"]},
     }
     if not args.no_cpu_baseline:
+        import statistics
+
         import oracle
         P = oracle.Problem(xyz, tets, wl["k"], kappa).setup_amg(nu=args.nu)
         x0h = x0.cpu().numpy()
-        t0 = time.perf_counter()
-        _, it, rr, st, _ = P.fgmres(np.zeros(P.n), tol=args.tol, restart=args.restart, x0=x0h)
-        dt = time.perf_counter() - t0
+        model, ncpu = host_cpu()
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            xo, it, rr, st, _ = P.fgmres(np.zeros(P.n), tol=args.tol, restart=args.restart, x0=x0h)
+            times.append(time.perf_counter() - t0)
+            progress(f"oracle timed solve {len(times)}/{reps}: {times[-1]:.1f} s")
+        dt = statistics.median(times)
         out["cpu_baseline"] = {"value": P.n / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-                               "sample": f"one FP64 FGMRES({args.restart}) solve of the full {args.workload} "
+                               "cpu_model": model, "host_cpus": ncpu, "repeats": 3,
+                               "sample": f"median of 3 FP64 FGMRES({args.restart}) solves of the full {args.workload} "
                                          f"system (n_h={P.n}) by the paper's protocol to {args.tol:g}, {it} "
-                                         f"steps, {dt:.1f} s"}
+                                         f"steps, {dt:.1f} s each"}
+        # both sides from the same random initial guess: the iterates after the
+        # same number of steps are the same up to rounding
+        s.set_precision("fp64")
+        x64, i64, _ = s.fgmres(zero, tol=args.tol, x0=x0, restart=args.restart)
+        s.set_precision("mixed")
+        xm, im, _ = s.fgmres(zero, tol=args.tol, x0=x0, restart=args.restart)
+        out["oracle_error"] = {"oracle_steps": it, "fp64_steps": i64.iterations, "mixed_steps": im.iterations,
+                               "fp64_iterate_vs_oracle_rel_diff": rel_err(x64, xo),
+                               "mixed_iterate_vs_oracle_rel_diff": rel_err(xm, xo),
+                               "note": "zero right-hand side: the iterate is the remaining error after the "
+                                       "steps, compared at the step counts shown"}
     return out
 
 
@@ -877,6 +923,7 @@ def run_adjoint(args):
         t0 = time.time()
         step()                                    # the host setup for this kappa
         setup_s = time.time() - t0
+        progress(f"GPU setup: {setup_s:.2f} s")
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -947,15 +994,25 @@ def run_adjoint(args):
         Pt = oracle.Problem(xyz, tets, wl["k"], np.exp(logk_t)).setup_amg(nu=args.nu)
         b = f.cpu().numpy()
         u_t, _, _, _ = Pt.pcg(b, tol=args.tol)
-        t0 = time.perf_counter()
-        uo, it1, _, _ = P.pcg(b, tol=args.tol)
-        lo, it2, _, _ = P.pcg(uo - u_t, tol=args.tol)
-        P.kappa_grad(uo, lo)
-        dt = time.perf_counter() - t0
+        import statistics
+        model, ncpu = host_cpu()
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            uo, it1, _, _ = P.pcg(b, tol=args.tol)
+            lo, it2, _, _ = P.pcg(uo - u_t, tol=args.tol)
+            go = P.kappa_grad(uo, lo)
+            times.append(time.perf_counter() - t0)
+            progress(f"oracle timed solve {len(times)}/{reps}: {times[-1]:.1f} s")
+        dt = statistics.median(times)
         out["cpu_baseline"] = {"value": P.n / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-                               "sample": f"one FP64 forward solve ({it1} iterations), adjoint solve ({it2}) and "
-                                         f"per-tet gradient of the full {args.workload} system (n_h={P.n}), "
-                                         f"{dt:.1f} s"}
+                               "cpu_model": model, "host_cpus": ncpu, "repeats": 3,
+                               "sample": f"median of 3: one FP64 forward solve ({it1} iterations), adjoint solve "
+                                         f"({it2}) and per-tet gradient of the full {args.workload} system "
+                                         f"(n_h={P.n}), {dt:.1f} s each"}
+        out["oracle_error"] = {"mixed_grad_vs_oracle_rel_err": rel_err(res["mixed"]["gk"], go),
+                               "fp64_grad_vs_oracle_rel_err": rel_err(res["fp64"]["gk"], go),
+                               "note": "oracle gradient from its own FP64 solves to the same tolerance"}
     return out
 
 
