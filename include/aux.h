@@ -129,6 +129,13 @@ typedef struct aux_options {
                                 the GPU taking a contiguous range of A_h's slices (gathered
                                 block rows stay in one die's cache: fewer bytes fetched past L2,
                                 measured no faster).  Results agree to rounding */
+    int amg_setup;           /* where the AMG hierarchy of A_H (strength, PMIS, extended+i,
+                                Galerkin products), the composite level operators, the dense
+                                cycle and the coarsest inverse are built, at setup and on every
+                                aux_set_kappa: 1 (default) on the device, 0 on the host.  Both
+                                follow the same definitions with the same arithmetic in the same
+                                order, so the hierarchies are bitwise equal; host_only handles
+                                always build on the host */
 } aux_options;
 
 typedef struct aux_device {
@@ -177,6 +184,8 @@ typedef struct aux_info {
     int32_t lanes_prolong;   /* I_P */
     int32_t lanes_down[32];  /* fused down operator of level l */
     int32_t lanes_up[32];    /* fused up operator of level l */
+    double amg_setup_seconds; /* wall time of the last build of the AMG hierarchy and the
+                                composite operators (at setup or by aux_set_kappa) */
 } aux_info;
 
 typedef struct aux_solve_info {
@@ -189,8 +198,9 @@ typedef struct aux_solve_info {
 /* Fill opt with the defaults listed above. */
 void aux_default_options(aux_options *opt);
 
-/* Build the discretisation, transfer and AMG hierarchy on the host and copy
- * the solve-phase data to the device.  mesh: host arrays as described; order
+/* Build the discretisation and transfer on the host, the AMG hierarchy and
+ * the composite operators on the device (or on the host: amg_setup, host_only),
+ * and copy the solve-phase data to the device.  mesh: host arrays as described; order
  * 2, 3 or 4; kappa: host [n_tets]
  * positive values, or NULL for kappa = 1; opt: NULL for defaults; dev: NULL
  * for hipMalloc on the current device and the default stream.  On success *out owns all buffers; release it with
@@ -205,9 +215,11 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
  * A_h into its existing sliced-ELL slots (FP64 and FP32), its l1 norms, the
  * P^1 stiffness A_H and the matrix-free weights, repeating the host
  * assembly's arithmetic in its order (the operators equal those of a new
- * aux_setup bit for bit); the host builds the AMG hierarchy of the new A_H
- * (strength, PMIS, extended+i, Galerkin products) and the coefficient-
- * dependent device data are rebuilt.  The dof numbering, patterns, layouts,
+ * aux_setup bit for bit); the AMG hierarchy of the new A_H (strength, PMIS,
+ * extended+i, Galerkin products), the composite level operators and the
+ * dense cycle are built on the device from the device A_H (amg_setup = 1;
+ * on the host from a copy with amg_setup = 0, bitwise the same), and the
+ * coefficient-dependent device data are rebuilt.  The dof numbering, patterns, layouts,
  * I_P and tet metrics are kept.  The first call also builds the mesh-only
  * assembly maps (each entry's list of element-matrix contributions, about
  * nnz(A_h) * 3 int32 of device memory).  aux_info.setup_seconds then reports
@@ -257,7 +269,10 @@ int aux_load_accumulate(const aux_handle *h, int32_t t0, int32_t t1, const doubl
 
 /* Export a host copy of a matrix for inspection.  which: 0 = A_h, 1 = A_H,
  * 2 = I_P, 3 = AMG level operator A_level, 4 = AMG interpolation P_level,
- * 5 = Stokes B, 6 = pressure mass matrix M_p (after aux_stokes_setup).
+ * 5 = Stokes B, 6 = pressure mass matrix M_p (after aux_stokes_setup),
+ * 7 = composite down operator P^T (I - A D^-1) of level `level`, 8 = composite
+ * up operator [2 D^-1 - D^-1 A D^-1, P - D^-1 A P] of level `level` (fuse_cycle;
+ * device handles).
  * With ptr == NULL only shape[3] = {rows, cols, nnz} is written; otherwise
  * ptr host int32 [rows+1], col int32 [nnz], val double [nnz] receive the CSR. */
 int aux_export_csr(const aux_handle *h, int which, int level, int64_t *shape, int32_t *ptr,

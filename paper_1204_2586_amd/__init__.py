@@ -52,7 +52,7 @@ class _Options(ctypes.Structure):
                 ("sell_window", ctypes.c_int), ("graph", ctypes.c_int),
                 ("sell_index16", ctypes.c_int), ("fuse_cycle", ctypes.c_int),
                 ("batch_tiles", ctypes.c_int), ("cycle_lanes", ctypes.c_int), ("dense_cycle_rows", ctypes.c_int),
-                ("batch_order", ctypes.c_int)]
+                ("batch_order", ctypes.c_int), ("amg_setup", ctypes.c_int)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -79,7 +79,7 @@ class _Info(ctypes.Structure):
                 ("sell_split", ctypes.c_int32),
                 ("lanes_restrict", ctypes.c_int32),
                 ("lanes_prolong", ctypes.c_int32), ("lanes_down", ctypes.c_int32 * 32),
-                ("lanes_up", ctypes.c_int32 * 32)]
+                ("lanes_up", ctypes.c_int32 * 32), ("amg_setup_seconds", ctypes.c_double)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -175,7 +175,8 @@ class Solver:
     (smoothing sweeps ``nu``, strength threshold ``theta``, coarsest size,
     precision, operator, layout window, graph replay, 16-bit columns, composite
     cycle, batched layout, V-cycle operator storage ``cycle_lanes``, dense
-    sub-cycle threshold ``dense_cycle_rows``, batched dof order ``batch_order``); the defaults are the timed
+    sub-cycle threshold ``dense_cycle_rows``, batched dof order ``batch_order``, where the AMG
+    hierarchy is built ``amg_setup`` = "device" or "host"); the defaults are the timed
     configuration.  ``host_only=True`` runs only the host setup (no GPU
     needed); the matrices and AMG hierarchy can then be inspected with
     ``export_csr``/``export_cf``.
@@ -186,7 +187,7 @@ class Solver:
                  maxit: int = 1000, host_only: bool = False, device=None, use_torch_allocator: bool = True,
                  operator: str = "assembled", sell_window: int = 0, graph: bool = True, sell_index16: bool = True,
                  fuse_cycle: bool = True, batch_tiles: int = 1, cycle_lanes: int = 0,
-                 dense_cycle_rows: int = 2048, batch_order: int = 0):
+                 dense_cycle_rows: int = 2048, batch_order: int = 0, amg_setup: str = "device"):
         lib = load_library()
         self._h = ctypes.c_void_p()
         self.order = order
@@ -209,6 +210,7 @@ class Solver:
         opt.cycle_lanes = int(cycle_lanes)
         opt.dense_cycle_rows = int(dense_cycle_rows)
         opt.batch_order = int(batch_order)
+        opt.amg_setup = {"host": 0, "device": 1}[amg_setup]
         kap = None
         if kappa is not None:
             self._kappa = np.ascontiguousarray(kappa, dtype=np.float64)
@@ -353,7 +355,7 @@ class Solver:
 
     def export_csr(self, which: str, level: int = 0):
         import scipy.sparse as sp
-        code = {"A": 0, "AH": 1, "IP": 2, "Alev": 3, "P": 4, "B": 5, "Mp": 6}[which]
+        code = {"A": 0, "AH": 1, "IP": 2, "Alev": 3, "P": 4, "B": 5, "Mp": 6, "down": 7, "up": 8}[which]
         shape = (ctypes.c_int64 * 3)()
         lib = load_library()
         _check(lib.aux_export_csr(self._h, code, level, shape, None, None, None))

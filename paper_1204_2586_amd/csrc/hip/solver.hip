@@ -22,6 +22,7 @@
 
 #include "../host/setup.hpp"
 #include "aux.h"
+#include "amgsetup.hpp"
 #include "assemble.hpp"
 #include "batched.hpp"
 #include "blockcg.hpp"
@@ -193,6 +194,13 @@ struct aux_handle {
     double *dcyc64 = nullptr;
     float *dcyc32 = nullptr;
     std::vector<FusedLevel> fused_host;
+    // built on the device (amg_setup): fused_host already holds the
+    // composite operators, and the dense cycle from level dense_pre_first
+    // waits in dense_pre for upload_coefficient_part
+    bool fused_pre = false;
+    double *dense_pre = nullptr;
+    int dense_pre_first = -1;
+    double amg_seconds = 0.0;
     Csr RF_host;
     std::vector<Lev> lev;
     double *cinv64 = nullptr;
@@ -628,9 +636,9 @@ struct aux_handle {
         }
         cinv64 = upload(hier.coarse_inv);
         if (opt.fuse_cycle && !hier.levels.empty()) {
-            fused_host.resize(hier.levels.size());
+            if (!fused_pre) fused_host.resize(hier.levels.size());
             for (size_t l = 0; l + 1 < hier.levels.size(); l++) {
-                fused_host[l] = fuse_level(hier.levels[l]);
+                if (!fused_pre) fused_host[l] = fuse_level(hier.levels[l]);
                 lev[l].down = upload_op2(fused_host[l].down);
                 lev[l].up = upload_op2(fused_host[l].up);
             }
@@ -638,7 +646,16 @@ struct aux_handle {
             // of dependent-load latency (about 5 us each) for well under a
             // microsecond of traffic; below the first level of at most
             // dense_cycle_rows rows the cycle is one dense product instead
-            if (opt.dense_cycle_rows > 0)
+            if (fused_pre) {
+                if (dense_pre) {                   // formed on the device by the same rule
+                    const size_t nd = (size_t)lev[dense_pre_first].A.n;
+                    dcyc64 = dense_pre;
+                    dcyc32 = dnew<float>(nd * nd);
+                    to_f32_device(stream, (long long)(nd * nd), dcyc64, dcyc32);
+                    dense_first = (size_t)dense_pre_first;
+                    dense_pre = nullptr;
+                }
+            } else if (opt.dense_cycle_rows > 0)
                 for (size_t l = 0; l + 1 < lev.size(); l++)
                     if (lev[l].A.n <= opt.dense_cycle_rows) {
                         const std::vector<double> T = dense_cycle(fused_host, hier, l);
@@ -701,6 +718,58 @@ struct aux_handle {
                 }
             }
         }
+        fused_pre = false;
+    }
+
+    SetupOptions amg_options() const
+    {
+        SetupOptions so;
+        so.theta = opt.theta;
+        so.coarse_max = opt.coarse_max;
+        so.max_levels = opt.max_levels;
+        so.seed = opt.pmis_seed;
+        return so;
+    }
+
+    // The hierarchy of A_H (a device CSR in A_H's pattern) built on the
+    // device with the host setup's arithmetic; host copies of the levels and
+    // of the composite operators go to hier and fused_host (the host-side
+    // consumers: uploads, layout choices, batched forms), and the dense
+    // cycle stays on the device for upload_coefficient_part.
+    void device_hierarchy(const DCsr &AH)
+    {
+        auto t0 = std::chrono::steady_clock::now();
+        DevMem mem{[this](size_t b) { return dalloc(b); }, [this](void *p) { dfree(p); }};
+        DevAmg d;
+        try {
+            device_amg(stream, AH, amg_options(), opt.fuse_cycle != 0, opt.dense_cycle_rows, mem, d);
+            hier = Hierarchy();
+            fused_host.clear();
+            download_amg(stream, d, hier, opt.fuse_cycle ? &fused_host : nullptr);
+        } catch (...) {
+            free_amg(mem, d);
+            throw;
+        }
+        dfree(dense_pre);
+        dense_pre = d.dense;
+        dense_pre_first = d.dense_first;
+        d.dense = nullptr;
+        fused_pre = opt.fuse_cycle != 0;
+        free_amg(mem, d);
+        amg_seconds = seconds_since(t0);
+    }
+
+    // at setup: the host-assembled A_H through the device build
+    void device_hierarchy_from_host()
+    {
+        DCsr AH;
+        AH.n = AH.m = disc.AH.n;
+        AH.nnz = (int)disc.AH.nnz();
+        AH.ptr = upload(disc.AH.ptr);
+        AH.col = upload(disc.AH.col);
+        AH.val = upload(disc.AH.val);
+        device_hierarchy(AH);
+        for (void *b : {(void *)AH.ptr, (void *)AH.col, (void *)AH.val}) dfree(b);
     }
 
     void ensure_hist(int maxit)
@@ -2333,6 +2402,7 @@ struct aux_handle {
         bool ready = false;
         int *a_ptr = nullptr, *a_idx = nullptr, *a_pos = nullptr, *a_rowptr = nullptr, *a_col = nullptr;
         int *h_ptr = nullptr, *h_idx = nullptr;
+        int *h_rowptr = nullptr, *h_col = nullptr;   // A_H's pattern
     } asmd;
 
     void ensure_assembly_maps()
@@ -2358,6 +2428,8 @@ struct aux_handle {
         assembly_map(disc.AH, nt, 4, vmap.data(), ptr, idx);
         asmd.h_ptr = upload(ptr);
         asmd.h_idx = upload(idx);
+        asmd.h_rowptr = upload(disc.AH.ptr);
+        asmd.h_col = upload(disc.AH.col);
         asmd.ready = true;
     }
 
@@ -2387,6 +2459,9 @@ struct aux_handle {
         cinv32 = dcyc32 = nullptr;
         dense_first = SIZE_MAX;
         fused_host.clear();
+        dfree(dense_pre);
+        dense_pre = nullptr;
+        fused_pre = false;
         release_work(w64);
         release_work(w32);
         // batched forms: rebuilt on their next use
@@ -2447,17 +2522,27 @@ struct aux_handle {
             HIPCHECK(hipMemcpyAsync(RF_host.val.data(), RF.v64, RF_host.val.size() * sizeof(double),
                                     hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
-        for (void *b : {(void *)Ke, (void *)aval, (void *)l1e, (void *)hval}) dfree(b);
+        for (void *b : {(void *)Ke, (void *)aval, (void *)l1e}) dfree(b);
         disc.kappa.assign(kap, kap + nt);
         // the hierarchy of the new A_H and everything built from it
         release_coefficient_part();
         hier = Hierarchy();
-        SetupOptions so;
-        so.theta = opt.theta;
-        so.coarse_max = opt.coarse_max;
-        so.max_levels = opt.max_levels;
-        so.seed = opt.pmis_seed;
-        if (disc.nH > 0) build_hierarchy(disc.AH, so, hier);
+        if (disc.nH > 0) {
+            if (opt.amg_setup) {
+                DCsr AH;
+                AH.n = AH.m = disc.nH;
+                AH.nnz = (int)nnzH;
+                AH.ptr = asmd.h_rowptr;
+                AH.col = asmd.h_col;
+                AH.val = hval;
+                device_hierarchy(AH);
+            } else {
+                auto t0 = std::chrono::steady_clock::now();
+                build_hierarchy(disc.AH, amg_options(), hier);
+                amg_seconds = seconds_since(t0);
+            }
+        }
+        dfree(hval);
         upload_coefficient_part(false);
         if (fp32_ready) fp32_coefficient_part();
         work<double>();
@@ -2582,6 +2667,7 @@ void aux_default_options(aux_options *o)
     o->cycle_lanes = 0;
     o->dense_cycle_rows = 2048;
     o->batch_order = 0;
+    o->amg_setup = 1;
 }
 
 int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt, const aux_device *dev,
@@ -2601,7 +2687,7 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
         if (o.precision != AUX_FP64 && o.precision != AUX_MIXED) throw AuxError(AUX_EINVAL, "bad precision");
         if (o.op != AUX_OP_ASSEMBLED && o.op != AUX_OP_MATFREE) throw AuxError(AUX_EINVAL, "bad operator kind");
         if (o.sell_window < 0) throw AuxError(AUX_EINVAL, "sell_window must be >= 0");
-        for (int flag : {o.graph, o.sell_index16, o.fuse_cycle, o.host_only, o.batch_order})
+        for (int flag : {o.graph, o.sell_index16, o.fuse_cycle, o.host_only, o.batch_order, o.amg_setup})
             if (flag != 0 && flag != 1) throw AuxError(AUX_EINVAL, "a boolean option is not 0 or 1");
         if (o.batch_tiles < 0 || o.batch_tiles > 2) throw AuxError(AUX_EINVAL, "batch_tiles must be 0, 1 or 2");
         if (o.dense_cycle_rows < 0 || o.dense_cycle_rows > 8192)
@@ -2620,15 +2706,16 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
             h->stream = (hipStream_t)h->dev.stream;
             build_discretization(h->disc, mesh->n_vertices, mesh->xyz, mesh->n_tets, mesh->tets, order, kappa);
             if (h->disc.ndof == 0) throw AuxError(AUX_EINVAL, "mesh has no interior degrees of freedom");
-            SetupOptions so;
-            so.theta = o.theta;
-            so.coarse_max = o.coarse_max;
-            so.max_levels = o.max_levels;
-            so.seed = o.pmis_seed;
-            if (h->disc.nH > 0) build_hierarchy(h->disc.AH, so, h->hier);
+            const bool dev_amg = !h->host_only && o.amg_setup == 1 && h->disc.nH > 0;
+            if (h->disc.nH > 0 && !dev_amg) {
+                auto t1 = std::chrono::steady_clock::now();
+                build_hierarchy(h->disc.AH, h->amg_options(), h->hier);
+                h->amg_seconds = seconds_since(t1);
+            }
             if (!h->host_only) {
                 HIPCHECK(hipGetDevice(&h->device));
                 scratch_address(h->device);
+                if (dev_amg) h->device_hierarchy_from_host();
                 h->upload_all();
                 if (o.precision == AUX_MIXED) h->ensure_fp32();
                 h->work<double>();
@@ -2735,6 +2822,7 @@ int aux_get_info(const aux_handle *h, aux_info *info)
             info->level_nnz_up[l] = h->fused_host[l].up.nnz();
         }
         info->dense_cycle_level = h->dense_first == SIZE_MAX ? -1 : (int32_t)h->dense_first;
+        info->amg_setup_seconds = h->amg_seconds;
         info->sell_split = h->A.split() ? 1 : 0;
         info->lanes_restrict = h->RF.n ? h->RF.lanes_code() : 0;
         info->lanes_prolong = h->IP.lanes_code();
@@ -2804,6 +2892,12 @@ int aux_export_csr(const aux_handle *h, int which, int level, int64_t *shape, in
         case 4: if (level >= 0 && level + 1 < nl) c = &h->hier.levels[level].P; break;
         case 5: if (h->sk.host_ready) c = &h->sk.B; break;
         case 6: if (h->sk.host_ready) c = &h->sk.Mp; break;
+        case 7:
+            if (level >= 0 && level + 1 < nl && (size_t)level < h->fused_host.size()) c = &h->fused_host[level].down;
+            break;
+        case 8:
+            if (level >= 0 && level + 1 < nl && (size_t)level < h->fused_host.size()) c = &h->fused_host[level].up;
+            break;
         default: break;
         }
         if (!c) throw AuxError(AUX_EINVAL, "no such matrix");

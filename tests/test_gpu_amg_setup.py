@@ -1,0 +1,137 @@
+"""AMG setup on the device against the host setup and the oracle.
+
+The device build (amg_setup="device", the default) and the host build
+(amg_setup="host") follow the same definitions (strength rule of Sec. 6.2,
+PMIS and extended+i of Sec. 6.1, Galerkin products, the composite level
+operators and the dense cycle of the fused V-cycle) with the same arithmetic
+in the same order, so every level, every C/F split, every interpolation and
+composite operator and the dense cycle agree bit for bit, and with them the
+preconditioner and the CG iterates.  The host build itself is pinned to the
+oracle (tests/test_host_setup.py); the splits are checked against the oracle
+here too.  Both paths are checked at setup and after aux_set_kappa (the
+device-assembled A_H going straight into the device build).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1204_2586_amd as aux
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+# (name, order, cubes per side, jitter, kappa, options)
+CASES = [
+    ("p2_n6_jitter", 2, 6, 0.2, None, {}),
+    ("p3_n5_grf", 3, 5, 0.15, "grf", {}),
+    ("p2_n10_cmax20", 2, 10, 0.2, None, dict(coarse_max=20)),
+    ("p2_n10_theta025_seed7", 2, 10, 0.2, "rand", dict(theta=0.25, seed=7)),
+    ("p4_n4_rand", 4, 4, 0.2, "rand", {}),
+    ("p2_n12_no_dense", 2, 12, 0.0, None, dict(dense_cycle_rows=0)),
+    ("p2_n10_unfused", 2, 10, 0.2, None, dict(fuse_cycle=False)),
+    ("p2_n9_two_levels", 2, 9, 0.2, "rand", dict(max_levels=2)),
+]
+
+
+def _kappa(kind, xyz, tets, seed=1):
+    if kind == "grf":
+        return np.exp(W.grf_log_kappa(xyz, tets, seed=seed))
+    if kind == "rand":
+        return np.exp(np.random.default_rng(seed + 1).normal(size=len(tets)))
+    return None
+
+
+def _bits(a):
+    return np.ascontiguousarray(a).view(np.uint64 if a.dtype == np.float64 else a.dtype)
+
+
+def _same_csr(a, b):
+    return (a.shape == b.shape and np.array_equal(a.indptr, b.indptr) and np.array_equal(a.indices, b.indices)
+            and np.array_equal(_bits(a.data), _bits(b.data)))
+
+
+def _assert_same_hierarchy(dv, hs, fused):
+    assert dv.info.levels == hs.info.levels and dv.info.ncoarse == hs.info.ncoarse
+    assert dv.info.dense_cycle_level == hs.info.dense_cycle_level
+    L = dv.info.levels
+    for l in range(L):
+        assert _same_csr(dv.export_csr("Alev", l), hs.export_csr("Alev", l)), f"A level {l}"
+    for l in range(L - 1):
+        assert np.array_equal(dv.export_cf(l), hs.export_cf(l)), f"C/F split level {l}"
+        assert _same_csr(dv.export_csr("P", l), hs.export_csr("P", l)), f"P level {l}"
+        if fused:
+            assert _same_csr(dv.export_csr("down", l), hs.export_csr("down", l)), f"down level {l}"
+            assert _same_csr(dv.export_csr("up", l), hs.export_csr("up", l)), f"up level {l}"
+
+
+def _assert_same_preconditioner(dv, hs, f):
+    g = torch.Generator(device="cpu").manual_seed(5)
+    r = torch.randn(dv.n, generator=g, dtype=torch.float64).to(DEV)
+    for mode in ("fp64", "mixed"):
+        dv.set_precision(mode)
+        hs.set_precision(mode)
+        assert torch.equal(dv.apply(r), hs.apply(r)), mode
+    ud, infd = dv.solve(f, tol=1e-8)
+    uh, infh = hs.solve(f, tol=1e-8)
+    assert infd.iterations == infh.iterations
+    assert torch.equal(ud, uh)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_device_hierarchy_bitwise_equals_host(case):
+    name, k, n, jit, kap, extra = case
+    print(f"[amg setup] {name}", flush=True)
+    xyz, tets = W.kuhn_mesh(n, jitter=jit, seed=0)
+    kappa = _kappa(kap, xyz, tets)
+    opts = dict(sell_window=4096, precision="mixed", device=DEV, **extra)
+    dv = aux.Solver(xyz, tets, k, kappa, amg_setup="device", **opts)
+    hs = aux.Solver(xyz, tets, k, kappa, amg_setup="host", **opts)
+    fused = extra.get("fuse_cycle", True)
+    _assert_same_hierarchy(dv, hs, fused)
+    assert dv.info.amg_setup_seconds > 0 and hs.info.amg_setup_seconds > 0
+    f = torch.tensor(dv.load(W.manufactured_f), dtype=torch.float64, device=DEV)
+    _assert_same_preconditioner(dv, hs, f)
+    # a new coefficient: the device-assembled A_H into each build
+    kappa2 = np.exp(np.random.default_rng(11).normal(size=len(tets)))
+    dv.set_kappa(kappa2)
+    hs.set_kappa(kappa2)
+    _assert_same_hierarchy(dv, hs, fused)
+    _assert_same_preconditioner(dv, hs, f)
+
+
+@pytest.mark.parametrize("k,n,kap", [(2, 6, None), (3, 5, "grf"), (2, 8, "rand")])
+def test_device_splits_equal_oracle(k, n, kap):
+    """The device hierarchy against the oracle directly: identical C/F splits
+    on every level, interpolation and coarse operators to rounding."""
+    xyz, tets = W.kuhn_mesh(n, jitter=0.2, seed=0)
+    kappa = _kappa(kap, xyz, tets)
+    dv = aux.Solver(xyz, tets, k, kappa, device=DEV, coarse_max=8)
+    orc = oracle.Problem(xyz, tets, k, kappa).setup_amg(coarse_max=8)
+    assert dv.info.levels == orc.nlev >= 3
+    for l in range(orc.nlev - 1):
+        assert np.array_equal(dv.export_cf(l), orc.level_cf(l)), l
+        P, Po = dv.export_csr("P", l), orc.csr("P", l)
+        assert abs(P - Po).max() <= 1e-12 * abs(Po).max()
+        A, Ao = dv.export_csr("Alev", l + 1), orc.csr("Alev", l + 1)
+        assert abs(A - Ao).max() <= 1e-12 * abs(Ao).max()
+
+
+def test_device_hierarchy_full_size_set_kappa():
+    """P2 on 48^3 cubes (857,375 unknowns, seven AMG levels): a new
+    coefficient through the device build equals the host build bit for bit,
+    and the device build is the faster."""
+    xyz, tets = W.kuhn_mesh(48, jitter=0.2, seed=0)
+    kappa = np.exp(W.grf_log_kappa(xyz, tets, seed=1))
+    opts = dict(sell_window=4096, precision="mixed", device=DEV)
+    dv = aux.Solver(xyz, tets, 2, amg_setup="device", **opts)
+    hs = aux.Solver(xyz, tets, 2, amg_setup="host", **opts)
+    dv.set_kappa(kappa)
+    hs.set_kappa(kappa)
+    print(f"[amg setup] P2 48^3 set_kappa: device build {dv.info.amg_setup_seconds * 1e3:.1f} ms, "
+          f"host build {hs.info.amg_setup_seconds * 1e3:.1f} ms, levels {dv.info.levels}", flush=True)
+    _assert_same_hierarchy(dv, hs, True)
+    f = torch.tensor(dv.load(W.manufactured_f), dtype=torch.float64, device=DEV)
+    _assert_same_preconditioner(dv, hs, f)
