@@ -80,6 +80,13 @@ def _load():
     lib.orc_kappa_grad.argtypes = [vp, _f64p, _f64p, _f64p]
     lib.orc_stokes_setup.restype = ctypes.c_int
     lib.orc_stokes_setup.argtypes = [vp]
+    lib.orc_setup_nested.restype = ctypes.c_int
+    lib.orc_setup_nested.argtypes = [vp, vp, ctypes.c_int]
+    lib.orc_apply_nested.restype = ctypes.c_int
+    lib.orc_apply_nested.argtypes = [vp, ctypes.c_int, _f64p, _f64p]
+    lib.orc_pcg_nested.restype = ctypes.c_int
+    lib.orc_pcg_nested.argtypes = [vp, ctypes.c_int, _f64p, _f64p, ctypes.c_double, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
     lib.orc_stokes_fgmres.restype = ctypes.c_int
     lib.orc_stokes_fgmres.argtypes = [vp, ctypes.c_int, _f64p, _f64p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), _f64p]
@@ -219,9 +226,10 @@ class Problem:
     # ---- matrices
     def csr(self, which: str, level: int = 0):
         """'A' (A_h), 'AH', 'IP', 'Alev' (level operator), 'P' (level interpolation),
-        'B' (Stokes divergence, after stokes_setup), 'Mp' (pressure mass matrix)."""
+        'B' (Stokes divergence, after stokes_setup), 'Mp' (pressure mass matrix),
+        'I2' (P^k <- P^2 transfer, after setup_nested)."""
         import scipy.sparse as sp
-        code = {"A": 0, "AH": 1, "IP": 2, "Alev": 3, "P": 4, "B": 5, "Mp": 6}[which]
+        code = {"A": 0, "AH": 1, "IP": 2, "Alev": 3, "P": 4, "B": 5, "Mp": 6, "I2": 7}[which]
         shp = np.zeros(3, dtype=np.int64)
         if _load().orc_csr_shape(self._h, code, level, shp):
             raise IndexError("no such matrix")
@@ -322,6 +330,39 @@ class Problem:
         rr = ctypes.c_double(0.0)
         st = _load().orc_pcg(self._h, int(fp32), np.ascontiguousarray(b, dtype=np.float64), x, tol,
                              maxit, ctypes.byref(it), ctypes.byref(rr))
+        return x, it.value, rr.value, st
+
+    # ---- intermediate auxiliary space (Remark 6.2)
+    def setup_nested(self, theta=0.8, nu=2, coarse_max=100, max_levels=25, seed=0):
+        """P^2 on the same mesh as the auxiliary space of this P^k problem
+        (k >= 2), its own problem solved by one application of its
+        auxiliary-space preconditioner (P^2 smoothing around the P^1 AMG
+        cycle, with these AMG options).  Keeps the P^2 problem as ``aux2``."""
+        kap = getattr(self, "_kappa", None)
+        self.aux2 = Problem(self.xyz, self.tets, 2, kap).setup_amg(theta=theta, nu=nu, coarse_max=coarse_max,
+                                                                  max_levels=max_levels, seed=seed)
+        if _load().orc_setup_nested(self._h, self.aux2._h, nu):
+            raise RuntimeError("oracle: nested transfer failed")
+        self.nu = nu
+        return self
+
+    def apply_nested(self, r, fp32: bool = False) -> np.ndarray:
+        """z = B r with the intermediate P^2 space (after setup_nested)."""
+        z = np.zeros(self.n)
+        if _load().orc_apply_nested(self._h, int(fp32), np.ascontiguousarray(r, dtype=np.float64), z):
+            raise RuntimeError("call setup_nested first")
+        return z
+
+    def pcg_nested(self, b, tol=1e-8, maxit=1000, x0=None, fp32: bool = False):
+        """PCG with the intermediate-space preconditioner: (x, iterations,
+        relative recursive residual, status)."""
+        x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64)
+        it = ctypes.c_int(0)
+        rr = ctypes.c_double(0.0)
+        st = _load().orc_pcg_nested(self._h, int(fp32), np.ascontiguousarray(b, dtype=np.float64), x, tol,
+                                    maxit, ctypes.byref(it), ctypes.byref(rr))
+        if st < 0:
+            raise RuntimeError("call setup_nested first")
         return x, it.value, rr.value, st
 
     # ---- Stokes (Sec. 5), Hood-Taylor P^2-P^1

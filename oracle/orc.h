@@ -33,7 +33,7 @@ typedef struct {
 
 #define ORC_MAX_LEVELS 32
 
-typedef struct {
+typedef struct orc_s {
     /* mesh (copied) */
     int k, nloc, nv, nt;
     double *xyz;     /* [nv][3] */
@@ -74,6 +74,13 @@ typedef struct {
     ocsr BdivT;
     ocsr Mp;         /* np x np pressure mass matrix */
 
+    /* intermediate auxiliary space (Remark 6.2), after orc_nested_transfer:
+       the P^2 problem on the same mesh (not owned, its AMG set up) in place
+       of P^1, and the transfer I_2 (n_h x n_2, the embedding of P^2 in P^k)
+       with its transpose */
+    const struct orc_s *aux2;
+    ocsr I2, I2T;
+
     /* options */
     double theta;
     int nu, coarse_max, max_levels;
@@ -100,6 +107,9 @@ int orc_amg_setup(orc *o);
 
 /* Stokes: divergence and pressure mass matrix (orc_fem.c) */
 int orc_stokes_assemble(orc *o);
+
+/* intermediate auxiliary space: I_2 from the P^2 problem o2 on the same mesh (orc_fem.c) */
+int orc_nested_transfer(orc *o, const orc *o2);
 double orc_pressure_l2_error(const orc *o, int m, const double *pq, const double *ph);
 
 /* flexible GMRES(m) on vectors of length n with an operator and a

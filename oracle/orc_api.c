@@ -38,6 +38,7 @@ void orc_free(orc *o)
     free(o->chol);
     ocsr_free(&o->Bdiv); ocsr_free(&o->BdivT); ocsr_free(&o->Mp);
     free(o->pnode_key); free(o->ptet_node);
+    ocsr_free(&o->I2); ocsr_free(&o->I2T);
     free(o);
 }
 
@@ -72,6 +73,15 @@ int orc_setup_amg(orc *o, double theta, int nu, int coarse_max, int max_levels, 
 
 int orc_stokes_setup(orc *o) { return o->np ? 0 : orc_stokes_assemble(o); }
 
+/* intermediate auxiliary space (Remark 6.2): o2 is the P^2 problem on the same
+   mesh with its AMG set up (kept alive by the caller); nu sweeps on P^k */
+int orc_setup_nested(orc *o, const orc *o2, int nu)
+{
+    if (!o2 || !o2->nlev) return -1;
+    o->nu = nu;
+    return orc_nested_transfer(o, o2);
+}
+
 /* pressure count and node keys [np][k-1] (after orc_stokes_setup) */
 int orc_stokes_np(const orc *o) { return o->np; }
 int orc_pressure_keys(const orc *o, int *keys)
@@ -99,6 +109,7 @@ static const ocsr *pick(const orc *o, int which, int level)
     case 4: return level + 1 < o->nlev ? &o->lev[level].P : NULL;
     case 5: return o->np ? &o->Bdiv : NULL;
     case 6: return o->np ? &o->Mp : NULL;
+    case 7: return o->aux2 ? &o->I2 : NULL;
     default: return NULL;
     }
 }

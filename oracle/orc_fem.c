@@ -823,3 +823,72 @@ double orc_h1_error(const orc *o, int m, const double *gq, const double *u)
     free(lam); free(w);
     return sqrt(err);
 }
+
+
+/* ------------------------------------------------------------------------
+ * Intermediate auxiliary space (Remark 6.2).  The P^2 space of the same mesh
+ * is a subspace of P^k (k >= 2), so a P^2 function has exact P^k nodal
+ * values.  At a P^k node with key multiplicities alpha_p (barycentric
+ * coordinates lam_p = alpha_p / k in any tet holding it) the P^2 basis
+ * functions that do not vanish belong to the vertices and edges of the key:
+ * vertex functions lam_p (2 lam_p - 1) and edge functions 4 lam_p lam_q.
+ * Rows: interior P^k dofs; columns: interior P^2 dofs (the Dirichlet nodes'
+ * functions vanish on the boundary, so they drop out).  Exact zeros (lam_p =
+ * 1/2) are not stored.
+ * ------------------------------------------------------------------------ */
+
+/* node of the P^2 problem with key (a, b), a <= b, or -1 */
+static int p2_node(const orc *o2, int a, int b)
+{
+    int lo = 0, hi = o2->nnode;
+    while (lo < hi) {
+        int mid = lo + (hi - lo) / 2;
+        const int *kk = o2->node_key + 2 * (size_t)mid;
+        if (kk[0] < a || (kk[0] == a && kk[1] < b)) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < o2->nnode && o2->node_key[2 * (size_t)lo] == a && o2->node_key[2 * (size_t)lo + 1] == b) return lo;
+    return -1;
+}
+
+int orc_nested_transfer(orc *o, const orc *o2)
+{
+    if (!o2 || o2->k != 2 || o->k < 2 || o2->nv != o->nv || o2->nt != o->nt) return -1;
+    if (memcmp(o2->tets, o->tets, (size_t)o->nt * 4 * sizeof(int)) != 0) return -1;
+    int k = o->k;
+    size_t cap = (size_t)o->ndof * 10 + 1, cnt = 0;
+    int *ri = malloc(cap * sizeof(int)), *ci = malloc(cap * sizeof(int));
+    double *v = malloc(cap * sizeof(double));
+    for (int g = 0; g < o->nnode; g++) {
+        int i = o->node_dof[g];
+        if (i < 0) continue;
+        const int *key = o->node_key + (size_t)g * k;
+        int vert[4], mult[4], nd = 0;
+        for (int q = 0; q < k; q++) {
+            if (nd > 0 && vert[nd - 1] == key[q]) mult[nd - 1]++;
+            else { vert[nd] = key[q]; mult[nd] = 1; nd++; }
+        }
+        double lam[4];
+        for (int p = 0; p < nd; p++) lam[p] = (double)mult[p] / k;
+        for (int p = 0; p < nd; p++) {
+            double w = lam[p] * (2.0 * lam[p] - 1.0);
+            int node = p2_node(o2, vert[p], vert[p]);
+            int j = node >= 0 ? o2->node_dof[node] : -1;
+            if (w != 0.0 && j >= 0) { ri[cnt] = i; ci[cnt] = j; v[cnt] = w; cnt++; }
+        }
+        for (int p = 0; p < nd; p++)
+            for (int q = p + 1; q < nd; q++) {
+                double w = 4.0 * lam[p] * lam[q];
+                int node = p2_node(o2, vert[p], vert[q]);
+                int j = node >= 0 ? o2->node_dof[node] : -1;
+                if (j >= 0) { ri[cnt] = i; ci[cnt] = j; v[cnt] = w; cnt++; }
+            }
+    }
+    ocsr_free(&o->I2);
+    ocsr_free(&o->I2T);
+    int rc = ocsr_from_triplets(o->ndof, o2->ndof, cnt, ri, ci, v, &o->I2);
+    if (!rc) rc = ocsr_transpose(&o->I2, &o->I2T);
+    free(ri); free(ci); free(v);
+    if (!rc) o->aux2 = o2;
+    return rc;
+}

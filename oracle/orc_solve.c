@@ -225,12 +225,12 @@ static void spmv(const ocsr *A, const double *x, double *y)
 /* Preconditioned CG on A_h x = b from the given x.  Stops when
    ||r_k||_2 <= tol ||b||_2 (recursive residual).  Returns 0 converged,
    1 not converged in maxit, 2 breakdown (p.Ap <= 0 or r.z <= 0), 3 NaN. */
-int orc_pcg(const orc *o, int fp32, const double *b, double *x, double tol, int maxit,
-            int *iters, double *relres)
+typedef void (*precfn)(void *ctx, const double *r, double *z);
+
+static int pcg_core(const orc *o, precfn prec, void *ctx, const double *b, double *x, double tol, int maxit,
+                    int *iters, double *relres)
 {
     int n = o->ndof, status = 1, it = 0;
-    bops B;
-    bops_init(o, fp32, &B);
     double *r = malloc((size_t)n * sizeof(double)), *z = malloc((size_t)n * sizeof(double));
     double *p = malloc((size_t)n * sizeof(double)), *q = malloc((size_t)n * sizeof(double));
     spmv(&o->A, x, q);
@@ -244,7 +244,7 @@ int orc_pcg(const orc *o, int fp32, const double *b, double *x, double tol, int 
         goto done;
     }
     if (rn <= tol * bn) { status = 0; goto done; }
-    apply_B(o, &B, r, z);
+    prec(ctx, r, z);
     double rho = dot(n, r, z);
     if (!(rho > 0.0)) { status = isnan(rho) ? 3 : 2; goto done; }
     memcpy(p, z, (size_t)n * sizeof(double));
@@ -261,7 +261,7 @@ int orc_pcg(const orc *o, int fp32, const double *b, double *x, double tol, int 
         rn = sqrt(dot(n, r, r));
         if (isnan(rn)) { status = 3; break; }
         if (rn <= tol * bn) { status = 0; break; }
-        apply_B(o, &B, r, z);
+        prec(ctx, r, z);
         double rho_new = dot(n, r, z);
         if (!(rho_new > 0.0)) { status = isnan(rho_new) ? 3 : 2; break; }
         double beta = rho_new / rho;
@@ -272,7 +272,120 @@ done:
     if (iters) *iters = it;
     if (relres) *relres = rn / bn;
     free(r); free(z); free(p); free(q);
+    return status;
+}
+
+struct bctx { const orc *o; const bops *B; };
+static void prec_B(void *c, const double *r, double *z)
+{
+    const struct bctx *b = c;
+    apply_B(b->o, b->B, r, z);
+}
+
+int orc_pcg(const orc *o, int fp32, const double *b, double *x, double tol, int maxit,
+            int *iters, double *relres)
+{
+    bops B;
+    bops_init(o, fp32, &B);
+    struct bctx c = {o, &B};
+    int status = pcg_core(o, prec_B, &c, b, x, tol, maxit, iters, relres);
     bops_free(&B);
+    return status;
+}
+
+/* ------------------------------------------------------------------------
+ * Intermediate auxiliary space (Remark 6.2): the two-level method of
+ * Algorithm 2.1 on P^k with the P^2 space of the same mesh in place of P^1,
+ * made symmetric as above -- presmoothing, the residual restricted by I_2^T,
+ * the P^2 problem solved approximately by one application of its own
+ * auxiliary-space preconditioner B_2 (P^2 smoothing around the P^1 AMG
+ * cycle), the correction prolonged by I_2 (Step 2), postsmoothing (Step 3).
+ * B_2 is symmetric positive definite, so B stays symmetric; in the fp32 mode
+ * B_2 runs in single precision too.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    const double *I2val, *I2Tval;
+    double *own[2];
+} nops;
+
+static void nops_init(const orc *o, rfun R, nops *N)
+{
+    size_t a = (size_t)o->I2.ptr[o->I2.n], b = (size_t)o->I2T.ptr[o->I2T.n];
+    N->own[0] = malloc((a ? a : 1) * sizeof(double));
+    N->own[1] = malloc((b ? b : 1) * sizeof(double));
+    for (size_t e = 0; e < a; e++) N->own[0][e] = R(o->I2.val[e]);
+    for (size_t e = 0; e < b; e++) N->own[1][e] = R(o->I2T.val[e]);
+    N->I2val = N->own[0];
+    N->I2Tval = N->own[1];
+}
+
+static void apply_B_nested(const orc *o, const bops *B, const bops *B2, const nops *N, const double *rin,
+                           double *z)
+{
+    rfun R = B->R;
+    const orc *o2 = o->aux2;
+    int n = o->ndof, n2 = o2->ndof;
+    double *r = calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *t = malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *b2 = malloc((size_t)(n2 > 0 ? n2 : 1) * sizeof(double));
+    double *e2 = malloc((size_t)(n2 > 0 ? n2 : 1) * sizeof(double));
+    for (int i = 0; i < n; i++) r[i] = R(rin[i]);
+    /* presmoothing: nu l1-Jacobi sweeps from z = 0 */
+    for (int i = 0; i < n; i++) z[i] = R(B->dinv[i] * r[i]);
+    for (int s = 1; s < o->nu; s++) {
+        sweep(&o->A, B->Aval, B->dinv, r, z, t, R);
+        memcpy(z, t, (size_t)n * sizeof(double));
+    }
+    /* the P^2 equation A_2 w = I_2^T (f - A_h u), by one application of B_2 */
+    residual(&o->A, B->Aval, r, z, t, R);
+    matvec(&o->I2T, N->I2Tval, t, b2, R);
+    if (n2 > 0) apply_B(o2, B2, b2, e2);
+    /* correction u += I_2 w */
+    matvec_add(&o->I2, N->I2val, e2, z, R);
+    /* postsmoothing */
+    for (int s = 0; s < o->nu; s++) {
+        sweep(&o->A, B->Aval, B->dinv, r, z, t, R);
+        memcpy(z, t, (size_t)n * sizeof(double));
+    }
+    free(r); free(t); free(b2); free(e2);
+}
+
+struct nctx { const orc *o; const bops *B, *B2; const nops *N; };
+static void prec_nested(void *c, const double *r, double *z)
+{
+    const struct nctx *x = c;
+    apply_B_nested(x->o, x->B, x->B2, x->N, r, z);
+}
+
+int orc_apply_nested(const orc *o, int fp32, const double *r, double *z)
+{
+    if (!o->aux2) return -1;
+    bops B, B2;
+    nops N;
+    bops_init(o, fp32, &B);
+    bops_init(o->aux2, fp32, &B2);
+    nops_init(o, B.R, &N);
+    apply_B_nested(o, &B, &B2, &N, r, z);
+    bops_free(&B);
+    bops_free(&B2);
+    free(N.own[0]); free(N.own[1]);
+    return 0;
+}
+
+int orc_pcg_nested(const orc *o, int fp32, const double *b, double *x, double tol, int maxit, int *iters,
+                   double *relres)
+{
+    if (!o->aux2) return -1;
+    bops B, B2;
+    nops N;
+    bops_init(o, fp32, &B);
+    bops_init(o->aux2, fp32, &B2);
+    nops_init(o, B.R, &N);
+    struct nctx c = {o, &B, &B2, &N};
+    int status = pcg_core(o, prec_nested, &c, b, x, tol, maxit, iters, relres);
+    bops_free(&B);
+    bops_free(&B2);
+    free(N.own[0]); free(N.own[1]);
     return status;
 }
 

@@ -94,6 +94,26 @@ PLANTS = {
         ["test_oracle_fgmres.py::test_gmres_minimises_residual_over_krylov_space",
          "test_oracle_fgmres.py::test_flexible_gmres_minimises_over_preconditioned_space",
          "test_oracle_fgmres.py::test_restart_one_is_minimal_residual_iteration"]),
+    # intermediate space: the P^2 vertex function taken as lam^2 (not lam (2 lam - 1))
+    "nested_vertex_function": (
+        [("orc_fem.c", "double w = lam[p] * (2.0 * lam[p] - 1.0);", "double w = lam[p] * lam[p];")],
+        ["test_oracle_nested.py::test_transfer_reproduces_quadratics",
+         "test_oracle_nested.py::test_galerkin_product_is_the_p2_stiffness"]),
+    # intermediate space: the P^2 edge function without its factor 4
+    "nested_edge_function_scale": (
+        [("orc_fem.c", "double w = 4.0 * lam[p] * lam[q];", "double w = 2.0 * lam[p] * lam[q];")],
+        ["test_oracle_nested.py::test_transfer_reproduces_quadratics",
+         "test_oracle_nested.py::test_galerkin_product_is_the_p2_stiffness"]),
+    # intermediate space: the postsmoothing left out (B no longer symmetric)
+    "nested_no_postsmoothing": (
+        [("orc_solve.c",
+          "    matvec_add(&o->I2, N->I2val, e2, z, R);\n"
+          "    /* postsmoothing */\n"
+          "    for (int s = 0; s < o->nu; s++) {\n",
+          "    matvec_add(&o->I2, N->I2val, e2, z, R);\n"
+          "    /* postsmoothing */\n"
+          "    for (int s = 0; s < 0; s++) {\n")],
+        ["test_oracle_nested.py::test_nested_preconditioner_spd"]),
 }
 
 _RUNNER = r"""
