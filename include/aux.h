@@ -136,6 +136,13 @@ typedef struct aux_options {
                                 follow the same definitions with the same arithmetic in the same
                                 order, so the hierarchies are bitwise equal; host_only handles
                                 always build on the host */
+    int aux_space;           /* auxiliary space of the two-level method: 1 (default) P^1 with its
+                                AMG hierarchy (Algorithm 2.1); 2 (orders 3 and 4) the intermediate
+                                space of Remark 6.2: P^2 on the same mesh, its problem solved by
+                                one application of its own auxiliary-space preconditioner (P^2
+                                l1-Jacobi around the P^1 AMG cycle, with these options), the
+                                transfer the embedding of P^2 in P^k.  Batched and block solves
+                                need 1 */
 } aux_options;
 
 typedef struct aux_device {
@@ -186,6 +193,8 @@ typedef struct aux_info {
     int32_t lanes_up[32];    /* fused up operator of level l */
     double amg_setup_seconds; /* wall time of the last build of the AMG hierarchy and the
                                 composite operators (at setup or by aux_set_kappa) */
+    int32_t aux_space;       /* 1: P^1 auxiliary space; 2: intermediate P^2 space (the hierarchy
+                                fields above are then empty: the P^2 handle holds it) */
 } aux_info;
 
 typedef struct aux_solve_info {
@@ -272,7 +281,7 @@ int aux_load_accumulate(const aux_handle *h, int32_t t0, int32_t t1, const doubl
  * 5 = Stokes B, 6 = pressure mass matrix M_p (after aux_stokes_setup),
  * 7 = composite down operator P^T (I - A D^-1) of level `level`, 8 = composite
  * up operator [2 D^-1 - D^-1 A D^-1, P - D^-1 A P] of level `level` (fuse_cycle;
- * device handles).
+ * device handles), 9 = the P^k <- P^2 transfer I_2 (aux_space 2).
  * With ptr == NULL only shape[3] = {rows, cols, nnz} is written; otherwise
  * ptr host int32 [rows+1], col int32 [nnz], val double [nnz] receive the CSR. */
 int aux_export_csr(const aux_handle *h, int which, int level, int64_t *shape, int32_t *ptr,

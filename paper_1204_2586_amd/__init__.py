@@ -52,7 +52,7 @@ class _Options(ctypes.Structure):
                 ("sell_window", ctypes.c_int), ("graph", ctypes.c_int),
                 ("sell_index16", ctypes.c_int), ("fuse_cycle", ctypes.c_int),
                 ("batch_tiles", ctypes.c_int), ("cycle_lanes", ctypes.c_int), ("dense_cycle_rows", ctypes.c_int),
-                ("batch_order", ctypes.c_int), ("amg_setup", ctypes.c_int)]
+                ("batch_order", ctypes.c_int), ("amg_setup", ctypes.c_int), ("aux_space", ctypes.c_int)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -79,7 +79,8 @@ class _Info(ctypes.Structure):
                 ("sell_split", ctypes.c_int32),
                 ("lanes_restrict", ctypes.c_int32),
                 ("lanes_prolong", ctypes.c_int32), ("lanes_down", ctypes.c_int32 * 32),
-                ("lanes_up", ctypes.c_int32 * 32), ("amg_setup_seconds", ctypes.c_double)]
+                ("lanes_up", ctypes.c_int32 * 32), ("amg_setup_seconds", ctypes.c_double),
+                ("aux_space", ctypes.c_int32)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -158,9 +159,11 @@ def load_library():
     return lib
 
 
-def _check(rc, allow=()):
+def _check(rc, allow=(), msg=None):
+    """Raise for a failed call; msg is the error text taken right after it
+    (any later library call clears the text)."""
     if rc != 0 and rc not in allow:
-        raise AuxError(rc, load_library().aux_last_error().decode())
+        raise AuxError(rc, msg if msg is not None else load_library().aux_last_error().decode())
     return rc
 
 
@@ -176,7 +179,8 @@ class Solver:
     precision, operator, layout window, graph replay, 16-bit columns, composite
     cycle, batched layout, V-cycle operator storage ``cycle_lanes``, dense
     sub-cycle threshold ``dense_cycle_rows``, batched dof order ``batch_order``, where the AMG
-    hierarchy is built ``amg_setup`` = "device" or "host"); the defaults are the timed
+    hierarchy is built ``amg_setup`` = "device" or "host", auxiliary space ``aux_space`` = 1 (P^1)
+    or 2 (the intermediate P^2 space of Remark 6.2, orders 3 and 4)); the defaults are the timed
     configuration.  ``host_only=True`` runs only the host setup (no GPU
     needed); the matrices and AMG hierarchy can then be inspected with
     ``export_csr``/``export_cf``.
@@ -187,7 +191,8 @@ class Solver:
                  maxit: int = 1000, host_only: bool = False, device=None, use_torch_allocator: bool = True,
                  operator: str = "assembled", sell_window: int = 0, graph: bool = True, sell_index16: bool = True,
                  fuse_cycle: bool = True, batch_tiles: int = 1, cycle_lanes: int = 0,
-                 dense_cycle_rows: int = 2048, batch_order: int = 0, amg_setup: str = "device"):
+                 dense_cycle_rows: int = 2048, batch_order: int = 0, amg_setup: str = "device",
+                 aux_space: int = 1):
         lib = load_library()
         self._h = ctypes.c_void_p()
         self.order = order
@@ -211,6 +216,7 @@ class Solver:
         opt.dense_cycle_rows = int(dense_cycle_rows)
         opt.batch_order = int(batch_order)
         opt.amg_setup = {"host": 0, "device": 1}[amg_setup]
+        opt.aux_space = int(aux_space)
         kap = None
         if kappa is not None:
             self._kappa = np.ascontiguousarray(kappa, dtype=np.float64)
@@ -355,7 +361,8 @@ class Solver:
 
     def export_csr(self, which: str, level: int = 0):
         import scipy.sparse as sp
-        code = {"A": 0, "AH": 1, "IP": 2, "Alev": 3, "P": 4, "B": 5, "Mp": 6, "down": 7, "up": 8}[which]
+        code = {"A": 0, "AH": 1, "IP": 2, "Alev": 3, "P": 4, "B": 5, "Mp": 6, "down": 7, "up": 8,
+                "I2": 9}[which]
         shape = (ctypes.c_int64 * 3)()
         lib = load_library()
         _check(lib.aux_export_csr(self._h, code, level, shape, None, None, None))
@@ -550,9 +557,10 @@ class Solver:
         self._sync_stream()
         rc = load_library().pcg_solve_batched(self._h, ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(U.data_ptr()),
                                               nrhs, tol, int(maxit), infos)
+        msg = load_library().aux_last_error().decode()
         self.info = self._info()                  # the layout chosen for this block width
         if check:
-            _check(rc)
+            _check(rc, msg=msg)
         return U, [SolveInfo(i.iterations, i.status, i.rel_residual, i.seconds) for i in infos]
 
     def solve_block(self, F, tol: float = 1e-8, U0=None, maxit: int = 0, check: bool = True):
@@ -568,11 +576,12 @@ class Solver:
         self._sync_stream()
         rc = load_library().pcg_solve_block(self._h, ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(U.data_ptr()),
                                             nrhs, tol, int(maxit), infos)
+        msg = load_library().aux_last_error().decode()
         self.info = self._info()
         if check:
-            _check(rc)
+            _check(rc, msg=msg)
         elif rc not in (0, -4, -5, -6):
-            _check(rc)
+            _check(rc, msg=msg)
         return U, [SolveInfo(i.iterations, i.status, i.rel_residual, i.seconds) for i in infos]
 
     PROF = {"pk_first": 0, "pk_sweep": 1, "pk_last": 2, "pk_resid": 3, "coarse": 4, "cg_spmv": 5, "apply": 6}

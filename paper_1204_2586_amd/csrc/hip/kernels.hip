@@ -220,8 +220,8 @@ __global__ __launch_bounds__(kBlock) void k_sell_residual64(DevSellView A, const
     sell_rows<double, F>(A, [&](int j) { return u[j]; }, [&](int row, double s) { r[row] = f[row] - s; });
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_jacobi0(int n, const T *__restrict__ dinv, const double *__restrict__ r,
+template <typename T, typename TR>
+__global__ __launch_bounds__(kBlock) void k_jacobi0(int n, const T *__restrict__ dinv, const TR *__restrict__ r,
                                                     T *__restrict__ z, T *__restrict__ rT, const int *done)
 {
     if (stop(done)) return;
@@ -564,8 +564,14 @@ template <typename T>
 int vec_jacobi0(hipStream_t s, int n, const T *dinv, const double *r, T *z, T *rT, const int *done)
 {
     int g = vec_grid(n);
-    hipLaunchKernelGGL(k_jacobi0<T>, dim3(g), dim3(kBlock), 0, s, n, dinv, r, z, rT, done);
+    hipLaunchKernelGGL((k_jacobi0<T, double>), dim3(g), dim3(kBlock), 0, s, n, dinv, r, z, rT, done);
     return g;
+}
+
+template <typename T>
+void vec_jacobi0_t(hipStream_t s, int n, const T *dinv, const T *r, T *z, const int *done)
+{
+    hipLaunchKernelGGL((k_jacobi0<T, T>), dim3(vec_grid(n)), dim3(kBlock), 0, s, n, dinv, r, z, nullptr, done);
 }
 
 template <typename T, typename TR, typename TZ>
@@ -740,6 +746,7 @@ void kappa_grad(hipStream_t s, int nt, int nloc, const int *tet_dof, const doubl
 
 #define INST(T)                                                                                              \
     template int vec_jacobi0<T>(hipStream_t, int, const T *, const double *, T *, T *, const int *);         \
+    template void vec_jacobi0_t<T>(hipStream_t, int, const T *, const T *, T *, const int *);               \
     template int sell_resid<T>(hipStream_t, const DevSellView &, const T *, const T *, T *, const int *);    \
     template int sell_sweep<T, T, T>(hipStream_t, const DevSellView &, const T *, const T *, const T *, T *, \
                                      const double *, double *, const int *);                                 \

@@ -84,6 +84,9 @@ enum FinishMode { FIN_PLAIN = 0, FIN_PQ = 1, FIN_RZ = 2, FIN_RR = 3 };
 // z = D^{-1} r (one sweep from zero); rT = (T) r if rT
 template <typename T>
 int vec_jacobi0(hipStream_t s, int n, const T *dinv, const double *r, T *z, T *rT, const int *done);
+// z = D^{-1} r for r in the working precision
+template <typename T>
+void vec_jacobi0_t(hipStream_t s, int n, const T *dinv, const T *r, T *z, const int *done);
 // zout = zin + D^{-1} (rhs - A zin); with partials, also sum_i rdot_i zout_i
 template <typename T, typename TR, typename TZ>
 int sell_sweep(hipStream_t s, const DevSellView &A, const T *dinv, const TR *rhs, const T *zin, TZ *zout,

@@ -111,6 +111,7 @@ template <typename T>
 struct Work {
     bool ready = false;
     T *za = nullptr, *zb = nullptr, *res = nullptr, *rT = nullptr;
+    T *nb = nullptr, *ne = nullptr;   // intermediate-space right-hand side and correction
     std::vector<T *> b, x, r, y;
 };
 
@@ -201,6 +202,13 @@ struct aux_handle {
     double *dense_pre = nullptr;
     int dense_pre_first = -1;
     double amg_seconds = 0.0;
+    // intermediate auxiliary space (aux_space = 2, Remark 6.2): the P^2
+    // handle on the same mesh and stream, the transfer I_2 (external orders
+    // for export; internal orders on the device) and the composite
+    // restriction [I_2^T, -I_2^T A_h]
+    aux_handle *child = nullptr;
+    Csr I2host, I2i, I2Ti, RF2_host;
+    DevOp I2d, I2Td, RF2;
     Csr RF_host;
     std::vector<Lev> lev;
     double *cinv64 = nullptr;
@@ -781,6 +789,7 @@ struct aux_handle {
 
     void ensure_fp32()
     {
+        if (child) child->ensure_fp32();
         if (fp32_ready) return;
         A.v32 = upload(to_f32(sell.val));
         if (!IP.v32) IP.v32 = upload(to_f32(IPi.val));
@@ -821,6 +830,11 @@ struct aux_handle {
                 w->x.push_back(dnew<T>(L.A.n));
                 w->r.push_back(dnew<T>(L.A.n));
                 w->y.push_back(dnew<T>(L.A.n));
+            }
+            if (child) {
+                w->nb = dnew<T>(child->disc.ndof);
+                w->ne = dnew<T>(child->disc.ndof);
+                child->work<T>();
             }
             w->ready = true;
         }
@@ -954,24 +968,7 @@ struct aux_handle {
             pend(pk);
             std::swap(zc, zn);
         }
-        // Step 1: r_H = I_R (r - A z), one AMG V-cycle; Step 2: z += I_P e_H
-        if (!lev.empty()) {
-            pk = pbeg(AUX_PROF_PK_RESID);
-            if (opt.fuse_cycle) {
-                // r_H = I_R r - (I_R A_h) z in one pass
-                csr_matvec2<T>(s, RF.view<T>(), rT, zc, disc.ndof, w.b[0], done);
-                pend(pk);
-                pk = pbeg(AUX_PROF_COARSE);
-            } else {
-                pk_resid<T>(rT, zc, w.res, done);
-                pend(pk);
-                pk = pbeg(AUX_PROF_COARSE);
-                csr_matvec<T>(s, IR.view<T>(), w.res, w.b[0], done);
-            }
-            const T *e0 = vcycle<T>(0, done);
-            csr_matvec_add<T>(s, IP.view<T>(), e0, zc, done);
-            pend(pk);
-        }
+        coarse_correction<T>(rT, zc, done);
         // Step 3: nu postsmoothing sweeps; the last one writes the FP64 result
         for (int k = 1; k < nu; k++) {
             pk = pbeg(AUX_PROF_PK_SWEEP);
@@ -984,6 +981,83 @@ struct aux_handle {
         pend(pk);
         pend(pb);
         return g;
+    }
+
+    // Steps 1 and 2 of Algorithm 2.1 on z (rT the right-hand side in T):
+    // r_H = I_R (r - A z), one AMG V-cycle, z += I_P e_H; with the
+    // intermediate space (Remark 6.2) r_2 = I_2^T (r - A z), one application
+    // of the P^2 handle's own preconditioner, z += I_2 e_2
+    template <typename T>
+    void coarse_correction(const T *rT, T *zc, const int *done)
+    {
+        Work<T> &w = work<T>();
+        hipStream_t s = stream;
+        if (child) {
+            int pk = pbeg(AUX_PROF_PK_RESID);
+            if (opt.fuse_cycle) {
+                csr_matvec2<T>(s, RF2.view<T>(), rT, zc, disc.ndof, w.nb, done);
+            } else {
+                pk_resid<T>(rT, zc, w.res, done);
+                csr_matvec<T>(s, I2Td.view<T>(), w.res, w.nb, done);
+            }
+            pend(pk);
+            pk = pbeg(AUX_PROF_COARSE);
+            child->stream = s;
+            child->apply_inner<T>(w.nb, w.ne, done);
+            csr_matvec_add<T>(s, I2d.view<T>(), w.ne, zc, done);
+            pend(pk);
+            return;
+        }
+        if (lev.empty()) return;
+        int pk = pbeg(AUX_PROF_PK_RESID);
+        if (opt.fuse_cycle) {
+            // r_H = I_R r - (I_R A_h) z in one pass
+            csr_matvec2<T>(s, RF.view<T>(), rT, zc, disc.ndof, w.b[0], done);
+            pend(pk);
+            pk = pbeg(AUX_PROF_COARSE);
+        } else {
+            pk_resid<T>(rT, zc, w.res, done);
+            pend(pk);
+            pk = pbeg(AUX_PROF_COARSE);
+            csr_matvec<T>(s, IR.view<T>(), w.res, w.b[0], done);
+        }
+        const T *e0 = vcycle<T>(0, done);
+        csr_matvec_add<T>(s, IP.view<T>(), e0, zc, done);
+        pend(pk);
+    }
+
+    // zout = B rin with both vectors in the working precision T and no
+    // inner-product partials: this handle as the intermediate space of a
+    // higher-order one (its stream set by the caller)
+    template <typename T>
+    void apply_inner(const T *rin, T *zout, const int *done)
+    {
+        Work<T> &w = work<T>();
+        hipStream_t s = stream;
+        const T *d = dinv<T>();
+        T *zc = w.za, *zn = w.zb;
+        vec_jacobi0_t<T>(s, disc.ndof, d, rin, zc, done);
+        for (int k = 1; k < opt.nu; k++) {
+            pk_sweep<T, T, T>(d, rin, zc, zn, nullptr, nullptr, done);
+            std::swap(zc, zn);
+        }
+        coarse_correction<T>(rin, zc, done);
+        for (int k = 1; k < opt.nu; k++) {
+            pk_sweep<T, T, T>(d, rin, zc, zn, nullptr, nullptr, done);
+            std::swap(zc, zn);
+        }
+        pk_sweep<T, T, T>(d, rin, zc, zout, nullptr, nullptr, done);
+    }
+
+    // the intermediate space's device data (after upload_all)
+    void setup_nested()
+    {
+        I2i = renumber_cols(permute_rows(I2host, sell.perm), child->sell.iperm, child->disc.ndof);
+        I2Ti = transpose(I2i);
+        RF2_host = fuse_restriction(I2Ti, permute_symmetric(disc.A, sell.perm, sell.iperm));
+        I2d = upload_op2(I2i);
+        I2Td = upload_op2(I2Ti);
+        RF2 = upload_op2(RF2_host);
     }
 
     int apply(const double *rin, double *zout, double *rz_partials, const int *done, bool prepped = false)
@@ -1815,7 +1889,7 @@ struct aux_handle {
     template <typename T>
     void release_work(Work<T> &w)
     {
-        for (T *b : {w.za, w.zb, w.res, w.rT}) dfree(b);
+        for (T *b : {w.za, w.zb, w.res, w.rT, w.nb, w.ne}) dfree(b);
         for (auto *v : {&w.b, &w.x, &w.r, &w.y})
             for (T *b : *v) dfree(b);
         w = Work<T>();
@@ -2513,6 +2587,9 @@ struct aux_handle {
         if (RF.ptr)
             restrict_values(s, RF.n, n, RF.ptr, RF.col, IR.ptr, IR.col, IR.v64, asmd.a_rowptr, asmd.a_col, aval, perm,
                             RF.v64, RF.v32, RF.ell_lanes, RF.ell_off, RF.ell_v64, RF.ell_v32);
+        if (RF2.ptr)
+            restrict_values(s, RF2.n, n, RF2.ptr, RF2.col, I2Td.ptr, I2Td.col, I2Td.v64, asmd.a_rowptr, asmd.a_col,
+                            aval, perm, RF2.v64, RF2.v32, RF2.ell_lanes, RF2.ell_off, RF2.ell_v64, RF2.ell_v32);
         // host copies of the new values
         HIPCHECK(hipMemcpyAsync(disc.A.val.data(), aval, nnzA * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipMemcpyAsync(sell.val.data(), A.v64, sell.val.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -2527,7 +2604,8 @@ struct aux_handle {
         // the hierarchy of the new A_H and everything built from it
         release_coefficient_part();
         hier = Hierarchy();
-        if (disc.nH > 0) {
+        if (child) child->set_kappa(kap);
+        if (disc.nH > 0 && !child) {
             if (opt.amg_setup) {
                 DCsr AH;
                 AH.n = AH.m = disc.nH;
@@ -2586,6 +2664,11 @@ struct aux_handle {
 
     void release()
     {
+        if (child) {
+            child->release();
+            delete child;
+            child = nullptr;
+        }
         if (!host_only) {
             if (stream) hipStreamSynchronize(stream);
             else hipDeviceSynchronize();
@@ -2668,6 +2751,7 @@ void aux_default_options(aux_options *o)
     o->dense_cycle_rows = 2048;
     o->batch_order = 0;
     o->amg_setup = 1;
+    o->aux_space = 1;
 }
 
 int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt, const aux_device *dev,
@@ -2690,6 +2774,7 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
         for (int flag : {o.graph, o.sell_index16, o.fuse_cycle, o.host_only, o.batch_order, o.amg_setup})
             if (flag != 0 && flag != 1) throw AuxError(AUX_EINVAL, "a boolean option is not 0 or 1");
         if (o.batch_tiles < 0 || o.batch_tiles > 2) throw AuxError(AUX_EINVAL, "batch_tiles must be 0, 1 or 2");
+        if (o.aux_space != 1 && o.aux_space != 2) throw AuxError(AUX_EINVAL, "aux_space must be 1 or 2");
         if (o.dense_cycle_rows < 0 || o.dense_cycle_rows > 8192)
             throw AuxError(AUX_EINVAL, "dense_cycle_rows must be in [0, 8192]");
         {
@@ -2706,8 +2791,19 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
             h->stream = (hipStream_t)h->dev.stream;
             build_discretization(h->disc, mesh->n_vertices, mesh->xyz, mesh->n_tets, mesh->tets, order, kappa);
             if (h->disc.ndof == 0) throw AuxError(AUX_EINVAL, "mesh has no interior degrees of freedom");
-            const bool dev_amg = !h->host_only && o.amg_setup == 1 && h->disc.nH > 0;
-            if (h->disc.nH > 0 && !dev_amg) {
+            if (o.aux_space == 2) {
+                // the intermediate space: the P^2 problem on the same mesh,
+                // with the P^1 auxiliary space and the assembled operator
+                if (order < 3) throw AuxError(AUX_EINVAL, "aux_space 2 needs order 3 or 4");
+                aux_options co = o;
+                co.aux_space = 1;
+                co.op = AUX_OP_ASSEMBLED;
+                const int rc = aux_setup(mesh, 2, kappa, &co, dev, &h->child);
+                if (rc != AUX_OK) throw AuxError(rc, "intermediate P2 space: " + g_error);
+                h->I2host = p2_transfer(h->disc, h->child->disc);
+            }
+            const bool dev_amg = !h->host_only && o.amg_setup == 1 && h->disc.nH > 0 && !h->child;
+            if (h->disc.nH > 0 && !dev_amg && !h->child) {
                 auto t1 = std::chrono::steady_clock::now();
                 build_hierarchy(h->disc.AH, h->amg_options(), h->hier);
                 h->amg_seconds = seconds_since(t1);
@@ -2717,6 +2813,7 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
                 scratch_address(h->device);
                 if (dev_amg) h->device_hierarchy_from_host();
                 h->upload_all();
+                if (h->child) h->setup_nested();
                 if (o.precision == AUX_MIXED) h->ensure_fp32();
                 h->work<double>();
                 if (o.precision == AUX_MIXED) h->work<float>();
@@ -2750,6 +2847,7 @@ int aux_set_stream(aux_handle *h, void *stream)
     return guarded([&]() {
         need_device(h);
         h->stream = (hipStream_t)stream;
+        if (h->child) h->child->stream = (hipStream_t)stream;
         return AUX_OK;
     });
 }
@@ -2761,6 +2859,7 @@ int aux_set_precision(aux_handle *h, int precision)
         if (precision != AUX_FP64 && precision != AUX_MIXED) throw AuxError(AUX_EINVAL, "bad precision");
         set_dev(h);
         h->opt.precision = precision;
+        if (h->child) h->child->opt.precision = precision;
         if (precision == AUX_MIXED) {
             h->ensure_fp32();
             h->work<float>();
@@ -2823,6 +2922,7 @@ int aux_get_info(const aux_handle *h, aux_info *info)
         }
         info->dense_cycle_level = h->dense_first == SIZE_MAX ? -1 : (int32_t)h->dense_first;
         info->amg_setup_seconds = h->amg_seconds;
+        info->aux_space = h->child ? 2 : 1;
         info->sell_split = h->A.split() ? 1 : 0;
         info->lanes_restrict = h->RF.n ? h->RF.lanes_code() : 0;
         info->lanes_prolong = h->IP.lanes_code();
@@ -2898,6 +2998,7 @@ int aux_export_csr(const aux_handle *h, int which, int level, int64_t *shape, in
         case 8:
             if (level >= 0 && level + 1 < nl && (size_t)level < h->fused_host.size()) c = &h->fused_host[level].up;
             break;
+        case 9: if (h->child) c = &h->I2host; break;
         default: break;
         }
         if (!c) throw AuxError(AUX_EINVAL, "no such matrix");
@@ -3007,6 +3108,7 @@ int pcg_solve_block(aux_handle *h, const double *F, double *U, int nrhs, double 
         if (!F || !U) throw AuxError(AUX_EINVAL, "null block");
         if (nrhs < 1 || nrhs > 64) throw AuxError(AUX_EINVAL, "nrhs must be in [1, 64]");
         if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
+        if (h->child) throw AuxError(AUX_EINVAL, "block solves use the P^1 auxiliary space (aux_space 1)");
         set_dev(h);
         int st = h->block_pcg(F, U, nrhs, tol, maxit, infos);
         HIPCHECK(hipGetLastError());
@@ -3022,6 +3124,7 @@ int pcg_solve_batched(aux_handle *h, const double *F, double *U, int nrhs, doubl
         if (!F || !U) throw AuxError(AUX_EINVAL, "null block");
         if (nrhs < 1 || nrhs > 64) throw AuxError(AUX_EINVAL, "nrhs must be in [1, 64]");
         if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
+        if (h->child) throw AuxError(AUX_EINVAL, "batched solves use the P^1 auxiliary space (aux_space 1)");
         set_dev(h);
         int st = h->pcg_batched(F, U, nrhs, tol, maxit, infos);
         HIPCHECK(hipGetLastError());

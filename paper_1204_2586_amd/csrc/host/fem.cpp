@@ -560,6 +560,69 @@ void build_discretization(Discretization &d, int nv, const double *xyz, int nt, 
     d.IR = transpose(d.IP);
 }
 
+// ------------------------------------------------------------ P^k <- P^2
+
+// P^2 on the same mesh is a subspace of P^k: at a node whose key has
+// multiplicities m_p (barycentric coordinates lam_p = m_p / k) the nonzero
+// P^2 basis values are those of the key's vertices, lam_p (2 lam_p - 1), and
+// of its vertex pairs, 4 lam_p lam_q.  P^2 unknowns are found by their keys
+// ((p, p) for a vertex, (p, q) for an edge) among d2's interior dofs;
+// boundary ones drop out.  Zero weights (lam_p = 1/2) are not stored.
+Csr p2_transfer(const Discretization &d, const Discretization &d2)
+{
+    if (d2.k != 2 || d.nv != d2.nv || d.nt != d2.nt || d.tets != d2.tets)
+        throw std::invalid_argument("p2_transfer: the P^2 discretisation must be on the same mesh");
+    const int k = d.k;
+    auto find2 = [&](int a, int b) {
+        int lo = 0, hi = d2.ndof;
+        while (lo < hi) {
+            const int mid = lo + (hi - lo) / 2;
+            const int32_t *q = &d2.keys[(size_t)mid * 2];
+            if (q[0] < a || (q[0] == a && q[1] < b)) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo < d2.ndof && d2.keys[(size_t)lo * 2] == a && d2.keys[(size_t)lo * 2 + 1] == b ? lo : -1;
+    };
+    Csr T;
+    T.n = d.ndof;
+    T.m = d2.ndof;
+    T.ptr.assign((size_t)d.ndof + 1, 0);
+    std::vector<std::pair<int, double>> row;
+    for (int i = 0; i < d.ndof; i++) {
+        const int32_t *key = &d.keys[(size_t)i * k];
+        int vert[4], mult[4], nd = 0;
+        for (int q = 0; q < k; q++) {
+            if (nd > 0 && vert[nd - 1] == key[q]) {
+                mult[nd - 1]++;
+            } else {
+                vert[nd] = key[q];
+                mult[nd] = 1;
+                nd++;
+            }
+        }
+        row.clear();
+        for (int p = 0; p < nd; p++) {
+            const double lam = (double)mult[p] / k;
+            const double w = lam * (2.0 * lam - 1.0);
+            const int j = find2(vert[p], vert[p]);
+            if (w != 0.0 && j >= 0) row.push_back({j, w});
+        }
+        for (int p = 0; p < nd; p++)
+            for (int q = p + 1; q < nd; q++) {
+                const double w = 4.0 * ((double)mult[p] / k) * ((double)mult[q] / k);
+                const int j = find2(vert[p], vert[q]);
+                if (j >= 0) row.push_back({j, w});
+            }
+        std::sort(row.begin(), row.end());
+        for (auto &e : row) {
+            T.col.push_back(e.first);
+            T.val.push_back(e.second);
+        }
+        T.ptr[i + 1] = (int)T.col.size();
+    }
+    return T;
+}
+
 // ------------------------------------------------------------ assembly maps
 
 void assembly_map(const Csr &A, int nt, int nl, const int *emap, std::vector<int> &ptr, std::vector<int> &idx)

@@ -104,6 +104,12 @@ void accumulate_load(const Discretization &d, int t0, int t1, const double *fq, 
 
 Csr transpose(const Csr &a);
 
+// The embedding of P^2 in P^k on one mesh (the intermediate auxiliary space
+// of Remark 6.2): n_h(k) x n_h(2), rows and columns in the two
+// discretisations' dof orders.  Throws std::invalid_argument if d2 is not
+// the order-2 discretisation of the same mesh.
+Csr p2_transfer(const Discretization &d, const Discretization &d2);
+
 // Composite operators of the preconditioner (fuse.cpp).  For an AMG level
 // with D = diag(l1):  down = P^T (I - A D^-1)  (n_{l+1} x n_l);
 // up = [2 D^-1 - D^-1 A D^-1,  P - D^-1 A P]  (n_l x (n_l + n_{l+1})), so
