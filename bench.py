@@ -43,6 +43,8 @@ WORKLOADS = {
     "p3_n32_grf": dict(k=3, n=32, jitter=0.0, seed=0, kappa=1),
     # P4 (35 nodes per tet) at the same 857,375 unknowns, kappa = 1
     "p4_n24": dict(k=4, n=24, jitter=0.0, seed=0, kappa=None),
+    # the same with kappa = exp(GRF seed 1): P^1 against the intermediate P^2 auxiliary space
+    "p4_n24_grf": dict(k=4, n=24, jitter=0.0, seed=0, kappa=1),
     # 32 right-hand sides solved in lock-step (sources fourier_f(0..31))
     "p2_n64_32rhs": dict(k=2, n=64, jitter=0.0, seed=0, kappa=None, nrhs=32),
     # gradient of L = |u - u_t|^2 / 2 with respect to f and log kappa: forward
@@ -386,6 +388,48 @@ def run_extra_p3(args):
     return out
 
 
+def run_extra_nested(args):
+    """P4 on 24^3 cubes with kappa = exp(GRF seed 1): the P^1 auxiliary
+    space against the intermediate P^2 space (Remark 6.2), mixed and FP64;
+    one step is one solve to 1e-8.  Parity with the oracle's nested
+    preconditioner is tested at small sizes; here the two spaces' solutions
+    are compared with each other."""
+    import numpy as np
+    import torch
+
+    import paper_1204_2586_amd as aux
+    import workloads as W
+    name = "p4_n24_grf"
+    wl = WORKLOADS[name]
+    xyz, tets = W.kuhn_mesh(wl["n"], jitter=wl["jitter"], seed=wl["seed"])
+    kappa = np.exp(W.grf_log_kappa(xyz, tets, seed=wl["kappa"]))
+    dev = torch.device("cuda:0")
+    out = {"order": 4, "cubes_per_side": wl["n"], "kappa": "exp(GRF seed 1)"}
+    sol = {}
+    for space in (1, 2):
+        t0 = time.time()
+        s = aux.Solver(xyz, tets, 4, kappa, nu=args.nu, precision="mixed", device=dev, aux_space=space)
+        setup_s = time.time() - t0
+        progress(f"GPU setup (aux_space {space}): {setup_s:.2f} s")
+        f = torch.tensor(s.load(W.manufactured_f), dtype=torch.float64, device=dev)
+        u = torch.zeros_like(f)
+        e = {"setup_s": round(setup_s, 2), "n_h": s.n}
+        for mode in ("mixed", "fp64"):
+            r = timed_solves(s, f, u, args, mode)
+            cnt, tot = r["prof_apply"]
+            e[mode] = {"ms": round(r["ms"], 3), "dof_per_s": s.n / (r["ms"] * 1e-3),
+                       "iterations": r["iterations"][-1], "true_rel_residual": r["true_rel_residual"],
+                       "precond_apply_us": round(tot / max(cnt, 1) * 1e3, 2)}
+            if mode == "mixed":
+                sol[space] = r["u"]
+        out["p1_space" if space == 1 else "p2_space"] = e
+        del s
+        torch.cuda.empty_cache()
+    out["p2_vs_p1_solution_rel_diff"] = float(torch.linalg.norm(sol[2] - sol[1]) / torch.linalg.norm(sol[1]))
+    out["speedup_p2_space_mixed"] = out["p1_space"]["mixed"]["ms"] / out["p2_space"]["mixed"]["ms"]
+    return out
+
+
 def run_stokes(args, k=2, n=48, n_oracle=16):
     """Stokes, Hood-Taylor P^k-P^{k-1} (Sec. 5) on a jittered mesh of n^3
     cubes: FGMRES(30) with the block triangular preconditioner Q_t to 1e-8
@@ -558,6 +602,8 @@ def run(args):
         out["workloads"]["stokes_p2p1_n48_jitter"] = run_stokes(args)
         torch.cuda.empty_cache()
         out["workloads"]["stokes_p3p2_n32_jitter"] = run_stokes(args, k=3, n=32, n_oracle=8)
+        torch.cuda.empty_cache()
+        out["workloads"]["p4_n24_grf_aux_spaces"] = run_extra_nested(args)
     return out
 
 
