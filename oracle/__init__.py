@@ -80,6 +80,7 @@ def _load():
     lib.orc_kappa_grad.argtypes = [vp, _f64p, _f64p, _f64p]
     lib.orc_stokes_setup.restype = ctypes.c_int
     lib.orc_stokes_setup.argtypes = [vp]
+    lib.orc_set_smoother_weight.argtypes = [vp, ctypes.c_double]
     lib.orc_setup_nested.restype = ctypes.c_int
     lib.orc_setup_nested.argtypes = [vp, vp, ctypes.c_int]
     lib.orc_apply_nested.restype = ctypes.c_int
@@ -200,6 +201,7 @@ class Problem:
         if not self._h:
             raise ValueError("oracle: discretisation failed")
         self._amg = False
+        self.omega = 1.0
         self._refresh()
 
     def _refresh(self):
@@ -332,6 +334,13 @@ class Problem:
                              maxit, ctypes.byref(it), ctypes.byref(rr))
         return x, it.value, rr.value, st
 
+    def set_smoother_weight(self, omega: float):
+        """The P^k smoother G_h = omega D_l1^{-1} (1 = plain l1-Jacobi); also used
+        by the intermediate space's P^2 problem set up afterwards."""
+        _load().orc_set_smoother_weight(self._h, float(omega))
+        self.omega = float(omega)
+        return self
+
     # ---- intermediate auxiliary space (Remark 6.2)
     def setup_nested(self, theta=0.8, nu=2, coarse_max=100, max_levels=25, seed=0):
         """P^2 on the same mesh as the auxiliary space of this P^k problem
@@ -341,6 +350,7 @@ class Problem:
         kap = getattr(self, "_kappa", None)
         self.aux2 = Problem(self.xyz, self.tets, 2, kap).setup_amg(theta=theta, nu=nu, coarse_max=coarse_max,
                                                                   max_levels=max_levels, seed=seed)
+        self.aux2.set_smoother_weight(self.omega)
         if _load().orc_setup_nested(self._h, self.aux2._h, nu):
             raise RuntimeError("oracle: nested transfer failed")
         self.nu = nu

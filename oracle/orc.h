@@ -82,6 +82,7 @@ typedef struct orc_s {
     ocsr I2, I2T;
 
     /* options */
+    double omega;    /* weight of the P^k smoother G_h = omega D_l1^{-1} (1 unless set) */
     double theta;
     int nu, coarse_max, max_levels;
     uint64_t seed;

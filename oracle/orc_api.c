@@ -57,6 +57,7 @@ orc *orc_create(int nv, const double *xyz, int nt, const int *tets, int k, const
     memcpy(o->tets, tets, (size_t)nt * 4 * sizeof(int));
     o->kappa = malloc((size_t)nt * sizeof(double));
     for (int t = 0; t < nt; t++) o->kappa[t] = kappa ? kappa[t] : 1.0;
+    o->omega = 1.0;
     if (orc_build_mesh_dofs(o) || orc_assemble(o)) { orc_free(o); return NULL; }
     return o;
 }
@@ -72,6 +73,9 @@ int orc_setup_amg(orc *o, double theta, int nu, int coarse_max, int max_levels, 
 }
 
 int orc_stokes_setup(orc *o) { return o->np ? 0 : orc_stokes_assemble(o); }
+
+/* weight of the P^k smoother: G_h = omega D_l1^{-1} */
+void orc_set_smoother_weight(orc *o, double omega) { o->omega = omega; }
 
 /* intermediate auxiliary space (Remark 6.2): o2 is the P^2 problem on the same
    mesh with its AMG set up (kept alive by the caller); nu sweeps on P^k */

@@ -52,6 +52,10 @@ static void bops_init(const orc *o, int fp32, bops *b)
     b->R = R;
     b->Aval = keep(b, o->A.val, (size_t)o->A.ptr[o->A.n], R, 0);
     b->dinv = keep(b, o->dl1, (size_t)o->ndof, R, 1);
+    if (o->omega != 1.0) {
+        double *d = (double *)b->dinv;
+        for (int i = 0; i < o->ndof; i++) d[i] = R(o->omega / o->dl1[i]);
+    }
     b->IPval = keep(b, o->IP.val, (size_t)o->IP.ptr[o->IP.n], R, 0);
     b->IRval = keep(b, o->IR.val, (size_t)o->IR.ptr[o->IR.n], R, 0);
     for (int l = 0; l < o->nlev; l++) {
