@@ -143,6 +143,13 @@ typedef struct aux_options {
                                 l1-Jacobi around the P^1 AMG cycle, with these options), the
                                 transfer the embedding of P^2 in P^k.  Batched and block solves
                                 need 1 */
+    double smoother_weight;  /* omega of the P^k smoother G_h = omega D_l1^-1 (1: plain l1-Jacobi,
+                                the default; the AMG levels keep omega = 1).  Finite and nonzero;
+                                a negative weight makes B indefinite (CG then reports
+                                AUX_EBREAKDOWN), which is how the breakdown path is exercised */
+    int true_residual;       /* 1: pcg_solve and pcg_solve_noalloc also compute the true
+                                ||f - A_h u||_2 / ||f||_2 of the returned iterate (one more
+                                product); 0 (default) leaves aux_solve_info.true_rel_residual -1 */
 } aux_options;
 
 typedef struct aux_device {
@@ -202,6 +209,8 @@ typedef struct aux_solve_info {
     int32_t status;          /* AUX_OK, AUX_ENOTCONV, AUX_EBREAKDOWN or AUX_ENAN */
     double rel_residual;     /* ||r_k||_2 / ||f||_2 of the recursive residual at exit */
     double seconds;          /* wall time of the solve (host clock, includes the final sync) */
+    double true_rel_residual; /* ||f - A_h u||_2 / ||f||_2 of the returned iterate when the
+                                option true_residual is set (single-vector CG), else -1 */
 } aux_solve_info;
 
 /* Fill opt with the defaults listed above. */
@@ -235,6 +244,15 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
  * this call's time.  Synchronises the stream.  Errors: AUX_EINVAL (kappa <= 0
  * or not finite), AUX_ENOMEM, AUX_EHIP. */
 int aux_set_kappa(aux_handle *h, const double *kappa);
+
+/* Residual history of the handle's last single-vector CG solve (pcg_solve or
+ * pcg_solve_noalloc): hist host double [max_len] receives ||r_k||_2 / ||f||_2 for
+ * k = 0 .. iterations (the recursive residual the stopping test reads), at most
+ * max_len values; *len = iterations + 1.  hist may be NULL to query the length.
+ * After pcg_solve_noalloc the history lives in the GPU's shared scratch array and
+ * is valid until the next such call on that GPU.  Errors: AUX_ESTATE before the
+ * first solve. */
+int aux_residual_history(aux_handle *h, double *hist, int32_t max_len, int32_t *len);
 
 /* Release everything the handle owns (waits for its stream).  NULL is a no-op. */
 int aux_destroy(aux_handle *h);

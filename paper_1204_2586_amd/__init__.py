@@ -52,7 +52,8 @@ class _Options(ctypes.Structure):
                 ("sell_window", ctypes.c_int), ("graph", ctypes.c_int),
                 ("sell_index16", ctypes.c_int), ("fuse_cycle", ctypes.c_int),
                 ("batch_tiles", ctypes.c_int), ("cycle_lanes", ctypes.c_int), ("dense_cycle_rows", ctypes.c_int),
-                ("batch_order", ctypes.c_int), ("amg_setup", ctypes.c_int), ("aux_space", ctypes.c_int)]
+                ("batch_order", ctypes.c_int), ("amg_setup", ctypes.c_int), ("aux_space", ctypes.c_int),
+                ("smoother_weight", ctypes.c_double), ("true_residual", ctypes.c_int)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -85,7 +86,7 @@ class _Info(ctypes.Structure):
 
 class _SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("true_rel_residual", ctypes.c_double)]
 
 
 @dataclass
@@ -94,6 +95,7 @@ class SolveInfo:
     status: int
     rel_residual: float
     seconds: float
+    true_rel_residual: float = -1.0      # with the option true_residual (single-vector CG)
 
     @property
     def converged(self) -> bool:
@@ -150,6 +152,7 @@ def load_library():
         "aux_profile": (ctypes.c_int, [vp, ctypes.c_int]),
         "aux_profile_read": (ctypes.c_int, [vp, ctypes.c_int, P(i64), P(dbl)]),
         "aux_last_error": (ctypes.c_char_p, []),
+        "aux_residual_history": (ctypes.c_int, [vp, vp, ctypes.c_int32, P(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -192,7 +195,7 @@ class Solver:
                  operator: str = "assembled", sell_window: int = 0, graph: bool = True, sell_index16: bool = True,
                  fuse_cycle: bool = True, batch_tiles: int = 1, cycle_lanes: int = 0,
                  dense_cycle_rows: int = 2048, batch_order: int = 0, amg_setup: str = "device",
-                 aux_space: int = 1):
+                 aux_space: int = 1, smoother_weight: float = 1.0, true_residual: bool = False):
         lib = load_library()
         self._h = ctypes.c_void_p()
         self.order = order
@@ -217,6 +220,8 @@ class Solver:
         opt.batch_order = int(batch_order)
         opt.amg_setup = {"host": 0, "device": 1}[amg_setup]
         opt.aux_space = int(aux_space)
+        opt.smoother_weight = float(smoother_weight)
+        opt.true_residual = int(true_residual)
         kap = None
         if kappa is not None:
             self._kappa = np.ascontiguousarray(kappa, dtype=np.float64)
@@ -427,7 +432,16 @@ class Solver:
             _check(rc)
         elif rc not in (0, -4, -5, -6):
             _check(rc)
-        return u, SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds)
+        return u, SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds, info.true_rel_residual)
+
+    def residual_history(self) -> np.ndarray:
+        """||r_k|| / ||f|| for k = 0 .. iterations of the last single-vector CG solve."""
+        lib = load_library()
+        n = ctypes.c_int32(0)
+        _check(lib.aux_residual_history(self._h, None, 0, ctypes.byref(n)))
+        out = np.zeros(max(n.value, 1))
+        _check(lib.aux_residual_history(self._h, _np_ptr(out), n.value, ctypes.byref(n)))
+        return out[:n.value]
 
     def solve_noalloc(self, f, u, tol: float = 1e-8, maxit: int = 0, check: bool = True):
         """CG on A_h u = f through pcg_solve_noalloc (no allocation in the
@@ -446,7 +460,7 @@ class Solver:
             _check(rc)
         elif rc not in (0, -4, -5, -6):
             _check(rc)
-        return SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds)
+        return SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds, info.true_rel_residual)
 
     def fgmres(self, b, tol: float = 1e-6, x0=None, restart: int = 30, maxit: int = 0, check: bool = True):
         """Flexible GMRES(restart) on A_h x = b with the same preconditioner,
@@ -471,7 +485,7 @@ class Solver:
             _check(rc)
         elif rc not in (0, -4, -6):
             _check(rc)
-        return x, SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds), \
+        return x, SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds, info.true_rel_residual), \
             hist[: info.iterations + 1]
 
     # ------------------------------------------------------------ Stokes
@@ -542,7 +556,7 @@ class Solver:
             _check(rc)
         elif rc not in (0, -4, -6):
             _check(rc)
-        return x, SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds), \
+        return x, SolveInfo(info.iterations, info.status, info.rel_residual, info.seconds, info.true_rel_residual), \
             hist[: info.iterations + 1]
 
     def solve_batched(self, F, tol: float = 1e-8, U0=None, maxit: int = 0, check: bool = True):

@@ -226,7 +226,12 @@ struct aux_handle {
     double *hist = nullptr;          // rz, pq, rr each [hist_cap]
     int hist_cap = 0;
     int *host_state = nullptr;       // pinned: iter, done
-    double *host_scal = nullptr;     // pinned: r.r window of the chunk prediction, target, final r.r and f.f
+    double *host_scal = nullptr;     // pinned: r.r window of the chunk prediction, target, final r.r and f.f,
+                                     // true residual r.r
+    // the last single-vector CG solve: its r_k.r_k history (device), count and f.f
+    const double *last_rr = nullptr;
+    int last_iters = -1;
+    double last_ff = 0.0;
     std::vector<void *> host_bufs;   // other pinned buffers
 
     // adjoint data (external dof numbering)
@@ -390,6 +395,13 @@ struct aux_handle {
         return upload(v.data(), v.size());
     }
     static std::vector<float> to_f32(const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); }
+    // the P^k smoother's diagonal: omega / l1 (omega = 1: plain l1-Jacobi)
+    std::vector<double> smoother_inv(const std::vector<double> &l1) const
+    {
+        std::vector<double> o(l1.size());
+        for (size_t i = 0; i < l1.size(); i++) o[i] = opt.smoother_weight / l1[i];
+        return o;
+    }
     static std::vector<double> inverse(const std::vector<double> &v)
     {
         std::vector<double> o(v.size());
@@ -631,7 +643,7 @@ struct aux_handle {
     {
         l1i.resize(disc.ndof);
         for (int i = 0; i < disc.ndof; i++) l1i[i] = disc.l1[sell.perm[i]];
-        dinv64 = upload(inverse(l1i));
+        dinv64 = upload(smoother_inv(l1i));
         lev.resize(hier.levels.size());
         for (size_t l = 0; l < hier.levels.size(); l++) {
             const AmgLevel &hl = hier.levels[l];
@@ -800,7 +812,7 @@ struct aux_handle {
     // FP32 copies of the coefficient-dependent operators
     void fp32_coefficient_part()
     {
-        dinv32 = upload(to_f32(inverse(l1i)));
+        dinv32 = upload(to_f32(smoother_inv(l1i)));
         for (size_t l = 0; l < hier.levels.size(); l++) {
             const AmgLevel &hl = hier.levels[l];
             lev[l].A.v32 = upload(to_f32(hl.A.val));
@@ -1266,10 +1278,20 @@ struct aux_handle {
         vec_scatter(s, n, perm, xi, u);
         prof_tag = -1;
         prof_collect(iter);
+        if (opt.true_residual) {
+            // ||f - A_h u||_2 of the returned iterate (one more product)
+            sell_residual64(s, A.view<double>(), fi, xi, r);
+            const int g2 = vec_dot(s, n, r, r, partials);
+            finish(s, partials, g2, FIN_PLAIN, scal + 3, st);
+            HIPCHECK(hipMemcpyAsync(host_scal + 6, scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+        }
         HIPCHECK(hipMemcpyAsync(host_scal + 4, st.rr + iter, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipMemcpyAsync(host_scal + 5, scal + 0, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         const double rrv = host_scal[4], ffv = host_scal[5];
+        last_rr = st.rr;
+        last_iters = iter;
+        last_ff = ffv;
         int status = AUX_OK;
         if (done == 2 || (done == 0 && issued >= maxit)) status = AUX_ENOTCONV;
         else if (done == 3) status = AUX_EBREAKDOWN;
@@ -1279,6 +1301,7 @@ struct aux_handle {
             info->status = status;
             info->rel_residual = ffv > 0 ? std::sqrt(rrv / ffv) : 0.0;
             info->seconds = seconds_since(t0);
+            info->true_rel_residual = !opt.true_residual ? -1.0 : ffv > 0 ? std::sqrt(host_scal[6] / ffv) : 0.0;
         }
         return status;
     }
@@ -1741,8 +1764,8 @@ struct aux_handle {
         bo.perm_d = upload(bo.perm);
         std::vector<double> l1b(n);
         for (int r = 0; r < n; r++) l1b[r] = disc.l1[bo.perm[r]];
-        bo.dinv64 = upload(inverse(l1b));
-        bo.dinv32 = upload(to_f32(inverse(l1b)));
+        bo.dinv64 = upload(smoother_inv(l1b));
+        bo.dinv32 = upload(to_f32(smoother_inv(l1b)));
         if (!opt.batch_tiles) {
             bo.Am = Csr();
             bo.m2b.clear();
@@ -2718,6 +2741,13 @@ int guarded(F &&f)
     }
 }
 
+// fields a solve fills only when asked for
+void init_infos(aux_solve_info *info, int n)
+{
+    if (info)
+        for (int i = 0; i < n; i++) info[i].true_rel_residual = -1.0;
+}
+
 void need_device(const aux_handle *h)
 {
     if (!h) throw AuxError(AUX_EINVAL, "null handle");
@@ -2752,6 +2782,8 @@ void aux_default_options(aux_options *o)
     o->batch_order = 0;
     o->amg_setup = 1;
     o->aux_space = 1;
+    o->smoother_weight = 1.0;
+    o->true_residual = 0;
 }
 
 int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt, const aux_device *dev,
@@ -2771,10 +2803,13 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
         if (o.precision != AUX_FP64 && o.precision != AUX_MIXED) throw AuxError(AUX_EINVAL, "bad precision");
         if (o.op != AUX_OP_ASSEMBLED && o.op != AUX_OP_MATFREE) throw AuxError(AUX_EINVAL, "bad operator kind");
         if (o.sell_window < 0) throw AuxError(AUX_EINVAL, "sell_window must be >= 0");
-        for (int flag : {o.graph, o.sell_index16, o.fuse_cycle, o.host_only, o.batch_order, o.amg_setup})
+        for (int flag : {o.graph, o.sell_index16, o.fuse_cycle, o.host_only, o.batch_order, o.amg_setup,
+                         o.true_residual})
             if (flag != 0 && flag != 1) throw AuxError(AUX_EINVAL, "a boolean option is not 0 or 1");
         if (o.batch_tiles < 0 || o.batch_tiles > 2) throw AuxError(AUX_EINVAL, "batch_tiles must be 0, 1 or 2");
         if (o.aux_space != 1 && o.aux_space != 2) throw AuxError(AUX_EINVAL, "aux_space must be 1 or 2");
+        if (!std::isfinite(o.smoother_weight) || o.smoother_weight == 0.0)
+            throw AuxError(AUX_EINVAL, "smoother_weight must be finite and nonzero");
         if (o.dense_cycle_rows < 0 || o.dense_cycle_rows > 8192)
             throw AuxError(AUX_EINVAL, "dense_cycle_rows must be in [0, 8192]");
         {
@@ -3057,6 +3092,7 @@ int pcg_solve(aux_handle *h, const double *f, double *u, double tol, int maxit, 
         need_device(h);
         if (!f || !u) throw AuxError(AUX_EINVAL, "null vector");
         if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
+        init_infos(info, 1);
         set_dev(h);
         int st = h->pcg(f, u, tol, maxit, info);
         HIPCHECK(hipGetLastError());
@@ -3074,6 +3110,7 @@ int pcg_solve_noalloc(aux_handle *h, const double *f, double *u, double tol, int
         if (maxit + 2 > kNoAllocHist)
             throw AuxError(AUX_EINVAL, "maxit exceeds the limit of the allocation-free solve (" +
                                            std::to_string(kNoAllocHist - 2) + ")");
+        init_infos(info, 1);
         set_dev(h);
         // everything the solve reads must already exist (built by aux_setup,
         // aux_set_precision and aux_set_operator): nothing is allocated here
@@ -3109,6 +3146,7 @@ int pcg_solve_block(aux_handle *h, const double *F, double *U, int nrhs, double 
         if (nrhs < 1 || nrhs > 64) throw AuxError(AUX_EINVAL, "nrhs must be in [1, 64]");
         if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
         if (h->child) throw AuxError(AUX_EINVAL, "block solves use the P^1 auxiliary space (aux_space 1)");
+        init_infos(infos, nrhs);
         set_dev(h);
         int st = h->block_pcg(F, U, nrhs, tol, maxit, infos);
         HIPCHECK(hipGetLastError());
@@ -3125,6 +3163,7 @@ int pcg_solve_batched(aux_handle *h, const double *F, double *U, int nrhs, doubl
         if (nrhs < 1 || nrhs > 64) throw AuxError(AUX_EINVAL, "nrhs must be in [1, 64]");
         if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
         if (h->child) throw AuxError(AUX_EINVAL, "batched solves use the P^1 auxiliary space (aux_space 1)");
+        init_infos(infos, nrhs);
         set_dev(h);
         int st = h->pcg_batched(F, U, nrhs, tol, maxit, infos);
         HIPCHECK(hipGetLastError());
@@ -3140,6 +3179,7 @@ int fgmres_solve(aux_handle *h, const double *b, double *x, double tol, int rest
         if (!b || !x) throw AuxError(AUX_EINVAL, "null vector");
         if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
         if (restart < 1 || restart > auxp::kMaxRestart) throw AuxError(AUX_EINVAL, "restart must be in [1, 128]");
+        init_infos(info, 1);
         set_dev(h);
         int st = h->fgmres(b, x, tol, restart, maxit, history, info);
         HIPCHECK(hipGetLastError());
@@ -3203,6 +3243,7 @@ int stokes_fgmres_solve(aux_handle *h, const double *b, double *x, double tol, i
         if (!b || !x) throw AuxError(AUX_EINVAL, "null vector");
         if (!(tol >= 0.0)) throw AuxError(AUX_EINVAL, "tol must be >= 0");
         if (restart < 1 || restart > auxp::kMaxRestart) throw AuxError(AUX_EINVAL, "restart must be in [1, 128]");
+        init_infos(info, 1);
         set_dev(h);
         int st = h->stokes_fgmres(b, x, tol, restart, maxit, history, info);
         HIPCHECK(hipGetLastError());
@@ -3267,5 +3308,26 @@ int aux_profile_read(aux_handle *h, int category, int64_t *launches, double *ms)
 }
 
 const char *aux_last_error(void) { return g_error.c_str(); }
+
+int aux_residual_history(aux_handle *h, double *hist, int32_t max_len, int32_t *len)
+{
+    return guarded([&]() {
+        need_device(h);
+        if (!len) throw AuxError(AUX_EINVAL, "null length");
+        if (h->last_iters < 0 || !h->last_rr) throw AuxError(AUX_ESTATE, "no single-vector CG solve yet");
+        const int n = h->last_iters + 1;
+        *len = n;
+        if (hist && max_len > 0) {
+            const int m = std::min(n, (int)max_len);
+            std::vector<double> rr((size_t)m);
+            set_dev(h);
+            HIPCHECK(hipMemcpyAsync(rr.data(), h->last_rr, (size_t)m * sizeof(double), hipMemcpyDeviceToHost,
+                                    h->stream));
+            HIPCHECK(hipStreamSynchronize(h->stream));
+            for (int k = 0; k < m; k++) hist[k] = h->last_ff > 0 ? std::sqrt(rr[k] / h->last_ff) : 0.0;
+        }
+        return AUX_OK;
+    });
+}
 
 }  // extern "C"
