@@ -803,6 +803,7 @@ struct aux_handle {
     {
         if (child) child->ensure_fp32();
         if (fp32_ready) return;
+        ensure_host_values();
         A.v32 = upload(to_f32(sell.val));
         if (!IP.v32) IP.v32 = upload(to_f32(IPi.val));
         IR.v32 = upload(to_f32(IRi.val));
@@ -1570,6 +1571,20 @@ struct aux_handle {
     // direction); the host enqueues as many as the last solve took (plus
     // one) and then two at a time until the stop flag is set.  Returns the
     // step count.
+    // count steps of the mass-matrix CG, enqueued on the handle's stream
+    void mass_steps(int count, const CgState &st)
+    {
+        hipStream_t s = stream;
+        const DevCsrView Mv = sk.M.view<double>();
+        for (int c = 0; c < count; c++) {
+            int g = mass_product(s, Mv, sk.mp, sk.mq, sk.part, st);
+            finish(s, sk.part, g, FIN_PQ, nullptr, st);
+            g = mass_update(s, sk.np, sk.mx, sk.mr, sk.mp, sk.mq, sk.mdinv, sk.mz, sk.part, st);
+            mass_finish(s, sk.part, g, st);
+            cg_direction(s, sk.np, sk.mz, sk.mp, st);
+        }
+    }
+
     int mass_solve(const double *b)
     {
         hipStream_t s = stream;
@@ -1582,16 +1597,11 @@ struct aux_handle {
         cg_init(s, st, kMassTol * kMassTol);
         finish(s, part_rz, g, FIN_RZ, nullptr, st);
         cg_direction(s, np, sk.mz, sk.mp, st);
-        const DevCsrView Mv = sk.M.view<double>();
         int issued = 0, chunk = sk.mass_chunk;
         while (true) {
-            for (int c = 0; c < chunk && issued < kMassMaxit; c++, issued++) {
-                g = mass_product(s, Mv, sk.mp, sk.mq, sk.part, st);
-                finish(s, sk.part, g, FIN_PQ, nullptr, st);
-                g = mass_update(s, np, sk.mx, sk.mr, sk.mp, sk.mq, sk.mdinv, sk.mz, sk.part, st);
-                mass_finish(s, sk.part, g, st);
-                cg_direction(s, np, sk.mz, sk.mp, st);
-            }
+            const int cnt = std::min(chunk, kMassMaxit - issued);
+            mass_steps(cnt, st);
+            issued += cnt;
             HIPCHECK(hipMemcpyAsync(sk.host_state, sk.istate, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
             if (sk.host_state[1] || issued >= kMassMaxit) break;
@@ -1714,6 +1724,7 @@ struct aux_handle {
 
     void ensure_border()
     {
+        ensure_host_values();
         if (bo.ready) return;
         ensure_fp32();
         const int n = disc.ndof;
@@ -2038,6 +2049,7 @@ struct aux_handle {
 
     void ensure_bops()
     {
+        ensure_host_values();
         if (bops_ready) return;
         const size_t L = hier.levels.size();
         bA.resize(L);
@@ -2501,6 +2513,23 @@ struct aux_handle {
         int *h_ptr = nullptr, *h_idx = nullptr;
         int *h_rowptr = nullptr, *h_col = nullptr;   // A_H's pattern
     } asmd;
+    // after a coefficient update the host copies of A_h (CSR and sliced-ELL
+    // values) and of the composite restriction's values are fetched from
+    // the device only when a host-side consumer needs them
+    std::vector<int> a_pos_host;     // sliced-ELL slot of each CSR entry of A_h
+    bool host_vals_stale = false;
+    void ensure_host_values()
+    {
+        if (!host_vals_stale) return;
+        HIPCHECK(hipMemcpyAsync(sell.val.data(), A.v64, sell.val.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                stream));
+        if (RF.ptr)
+            HIPCHECK(hipMemcpyAsync(RF_host.val.data(), RF.v64, RF_host.val.size() * sizeof(double),
+                                    hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        for (size_t e = 0; e < disc.A.val.size(); e++) disc.A.val[e] = sell.val[a_pos_host[e]];
+        host_vals_stale = false;
+    }
 
     void ensure_assembly_maps()
     {
@@ -2518,6 +2547,7 @@ struct aux_handle {
                 pos[e] = sell.slice_off[sl] + j * kSlice + lane;
         }
         asmd.a_pos = upload(pos);
+        a_pos_host = std::move(pos);
         asmd.a_rowptr = upload(disc.A.ptr);
         asmd.a_col = upload(disc.A.col);
         std::vector<int> vmap((size_t)nt * 4);
@@ -2613,15 +2643,12 @@ struct aux_handle {
         if (RF2.ptr)
             restrict_values(s, RF2.n, n, RF2.ptr, RF2.col, I2Td.ptr, I2Td.col, I2Td.v64, asmd.a_rowptr, asmd.a_col,
                             aval, perm, RF2.v64, RF2.v32, RF2.ell_lanes, RF2.ell_off, RF2.ell_v64, RF2.ell_v32);
-        // host copies of the new values
-        HIPCHECK(hipMemcpyAsync(disc.A.val.data(), aval, nnzA * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipMemcpyAsync(sell.val.data(), A.v64, sell.val.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        // host copies of the l1 norms and A_H now; those of A_h and of the
+        // composite restriction when a host-side consumer needs them
         HIPCHECK(hipMemcpyAsync(disc.l1.data(), l1e, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
         if (nnzH) HIPCHECK(hipMemcpyAsync(disc.AH.val.data(), hval, nnzH * sizeof(double), hipMemcpyDeviceToHost, s));
-        if (RF.ptr)
-            HIPCHECK(hipMemcpyAsync(RF_host.val.data(), RF.v64, RF_host.val.size() * sizeof(double),
-                                    hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
+        host_vals_stale = true;
         for (void *b : {(void *)Ke, (void *)aval, (void *)l1e}) dfree(b);
         disc.kappa.assign(kap, kap + nt);
         // the hierarchy of the new A_H and everything built from it
@@ -3020,7 +3047,13 @@ int aux_export_csr(const aux_handle *h, int which, int level, int64_t *shape, in
         const Csr *c = nullptr;
         int nl = (int)h->hier.levels.size();
         switch (which) {
-        case 0: c = &h->disc.A; break;
+        case 0:
+            if (!h->host_only) {
+                set_dev(h);
+                const_cast<aux_handle *>(h)->ensure_host_values();
+            }
+            c = &h->disc.A;
+            break;
         case 1: c = &h->disc.AH; break;
         case 2: c = &h->disc.IP; break;
         case 3: if (level >= 0 && level < nl) c = &h->hier.levels[level].A; break;
