@@ -269,7 +269,7 @@ def measure_single(s, f, args, wl, nt, operator):
         us = tot / max(cnt, 1) * 1e3
         c1, t1 = res["prof"]["apply"]
         entry = {"us": us, "us_with_launch_events": t1 / max(c1, 1) * 1e3}
-        if operator == "assembled":
+        if operator == "assembled" and int(s.info.aux_space) == 1:
             ab = apply_bytes(s.info, sz, args.nu, first=res["prof"].get("pk_first", (0, 0))[0] > 0)
             entry.update(bytes=ab, gbs=ab / (us * 1e-6) / 1e9, frac=ab / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
         precond[name] = entry
@@ -576,7 +576,8 @@ def run(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
-    s = aux.Solver(xyz, tets, wl["k"], kappa, nu=args.nu, precision="mixed", device=dev, operator=args.operator)
+    s = aux.Solver(xyz, tets, wl["k"], kappa, nu=args.nu, precision="mixed", device=dev, operator=args.operator,
+                   aux_space=args.aux_space)
     setup_s = time.time() - t0
     progress(f"GPU setup: {setup_s:.2f} s")
     b = s.load(W.manufactured_f)
@@ -601,6 +602,7 @@ def run(args):
         "dtype": "f64 CG / f32 preconditioner",
         "data": "synthetic",
         "config": {"workload": args.workload, "operator": args.operator, "nu": args.nu, "order": wl["k"],
+                   "aux_space": args.aux_space,
                    "cubes_per_side": wl["n"],
                    "jitter": wl["jitter"], "n_h": n, "nnz_A": nnz, "tol": args.tol,
                    "iterations": mixed["iterations"][-1], "true_rel_residual": mixed["true_rel_residual"],
@@ -880,7 +882,8 @@ def run_fgmres(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
-    s = aux.Solver(xyz, tets, wl["k"], kappa, nu=args.nu, precision="mixed", device=dev, operator=args.operator)
+    s = aux.Solver(xyz, tets, wl["k"], kappa, nu=args.nu, precision="mixed", device=dev, operator=args.operator,
+                   aux_space=args.aux_space)
     setup_s = time.time() - t0
     progress(f"GPU setup: {setup_s:.2f} s")
     n = s.n
@@ -1121,12 +1124,18 @@ def main():
                     help="l1-Jacobi sweeps before and after the coarse correction (the workloads are defined with 2)")
     ap.add_argument("--operator", default="assembled", choices=["assembled", "matfree"],
                     help="P^k products inside the preconditioner: sliced-ELL A_h or the MFMA element operator")
+    ap.add_argument("--aux-space", type=int, default=1, choices=[1, 2],
+                    help="auxiliary space of a single-vector workload: 1 P^1 (the paper's), 2 the intermediate "
+                         "P^2 space of Remark 6.2 (orders 3 and 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="with the default workload, skip the P3 32^3 and 32-source P2 64^3 entries of the line")
     ap.add_argument("--threads", type=int, default=16, help="host threads for the load vectors of the batch")
     ap.add_argument("--batch-order", type=int, default=0, choices=[0, 1],
                     help="dof order of the batched solve: 0 the single-vector order, 1 Morton curve with die ranges")
+    ap.add_argument("--coefficient-update", action="store_true",
+                    help="only time new coefficients through aux_set_kappa at P2 48^3 (AMG built on the device "
+                         "and on the host)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 1 GiB device-to-device copies (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -1137,10 +1146,15 @@ def main():
     if args.calibrate_copy:
         print(json.dumps(calibrate_copy()), flush=True)
         return
+    if args.coefficient_update:
+        if args.tol is None:
+            args.tol = 1e-8
+        print(json.dumps(run_kappa_update(args)), flush=True)
+        return
     if args.tol is None:
         args.tol = 1e-6 if args.krylov == "fgmres" else 1e-8
     args.extras = (not args.no_extras and args.workload == "p2_n48_jitter" and args.krylov == "cg"
-                   and args.operator == "assembled")
+                   and args.operator == "assembled" and args.aux_space == 1)
     if args.krylov == "fgmres" and ("nrhs" in WORKLOADS[args.workload] or WORKLOADS[args.workload].get("adjoint")):
         print(json.dumps({"error": "FGMRES runs the single-vector solve workloads only"}))
         sys.exit(2)
