@@ -518,16 +518,126 @@ __global__ __launch_bounds__(kB) void k_product_bound(int n, const int *__restri
     ub[i] = b;
 }
 
-// Row i of C = A B: the products a_ik b_kj in the order of A's row, then
-// of B's rows, each added to its column's sum (the first one to zero when
+// rows whose products fit one wavefront's LDS (at most kWaveProducts
+// products from at most kWaveEntries entries of A) go to k_product_rows_wave
+constexpr int kWaveProducts = 2048, kWaveEntries = 256;
+
+__device__ __forceinline__ bool wave_row(long long ub, int na) { return ub <= kWaveProducts && na <= kWaveEntries; }
+
+// Row i of C = A B, one wavefront: the row's products a_ik b_kj are laid
+// out in LDS in the order of A's row, then of B's rows (their sequence
+// number), sorted by (column, sequence number) with a bitonic network, and
+// each column's products are summed in sequence order by the lane that
+// holds the column's first one (the first product added to zero when
 // zero_init, as the composite-operator product does; taken as the sum
-// otherwise, as the Galerkin product does), columns found through an
-// open-addressing table of 2 ub slots; the distinct columns are then
-// sorted.  The row goes to the workspace at woff[i].
+// otherwise, as the Galerkin product does).  The same sums in the same order
+// as the host's row accumulator.  The sorted row goes to the workspace at
+// woff[i].
+__global__ __launch_bounds__(64) void k_product_rows_wave(int n, const int *__restrict__ aptr,
+                                                          const int *__restrict__ acol, const double *__restrict__ aval,
+                                                          const int *__restrict__ bptr, const int *__restrict__ bcol,
+                                                          const double *__restrict__ bval,
+                                                          const long long *__restrict__ woff, int *__restrict__ ocol,
+                                                          double *__restrict__ oacc, int *__restrict__ cnt, int zero_init)
+{
+#pragma clang fp contract(off)
+    __shared__ unsigned long long keys[kWaveProducts];
+    __shared__ double vals[kWaveProducts];
+    __shared__ int off[kWaveEntries + 1];
+    const int i = blockIdx.x, lane = threadIdx.x;
+    if (i >= n) return;
+    const int a0 = aptr[i], na = aptr[i + 1] - a0;
+    const long long ub = woff[i + 1] - woff[i];
+    if (!wave_row(ub, na)) return;                 // a row of k_product_rows
+    if (ub == 0) {
+        if (lane == 0) cnt[i] = 0;
+        return;
+    }
+    if (lane == 0) {
+        int o = 0;
+        for (int e = 0; e < na; e++) {
+            off[e] = o;
+            const int k = acol[a0 + e];
+            o += bptr[k + 1] - bptr[k];
+        }
+        off[na] = o;
+    }
+    __syncthreads();
+    const int m = (int)ub;
+    int np2 = 1;
+    while (np2 < m) np2 <<= 1;
+    for (int p = lane; p < np2; p += 64) {
+        if (p < m) {
+            int lo = 0, hi = na;                   // off[lo] <= p < off[lo + 1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (off[mid] <= p) lo = mid;
+                else hi = mid;
+            }
+            const int f = bptr[acol[a0 + lo]] + (p - off[lo]);
+            keys[p] = ((unsigned long long)(unsigned)bcol[f] << 32) | (unsigned)p;
+            vals[p] = aval[a0 + lo] * bval[f];
+        } else {
+            keys[p] = ~0ULL;
+        }
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= np2; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < np2 / 2; t += 64) {
+                const int i1 = 2 * j * (t / j) + (t % j), i2 = i1 + j;
+                const bool up = (i1 & kk) == 0;
+                const unsigned long long x = keys[i1], y = keys[i2];
+                if ((x > y) == up) {
+                    keys[i1] = y;
+                    keys[i2] = x;
+                }
+            }
+            __syncthreads();
+        }
+    int base = 0;
+    for (int q0 = 0; q0 < m; q0 += 64) {
+        const int q = q0 + lane;
+        bool head = false;
+        int col = 0;
+        if (q < m) {
+            col = (int)(keys[q] >> 32);
+            head = q == 0 || (int)(keys[q - 1] >> 32) != col;
+        }
+        const unsigned long long mask = __ballot(head);
+        if (head) {
+            const int rank = base + __popcll(mask & ((1ULL << lane) - 1ULL));
+            double acc = vals[(unsigned)keys[q]];
+            if (zero_init) acc = 0.0 + acc;
+            for (int r = q + 1; r < m && (int)(keys[r] >> 32) == col; r++) acc += vals[(unsigned)keys[r]];
+            ocol[woff[i] + rank] = col;
+            oacc[woff[i] + rank] = acc;
+        }
+        base += __popcll(mask);
+    }
+    if (lane == 0) cnt[i] = base;
+}
+
+// table slots of the rows k_product_rows handles (2 per product)
+__global__ __launch_bounds__(kB) void k_long_rows(int n, const int *__restrict__ aptr,
+                                                  const long long *__restrict__ woff, long long *__restrict__ hub)
+{
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= n) return;
+    const long long ub = woff[i + 1] - woff[i];
+    hub[i] = wave_row(ub, aptr[i + 1] - aptr[i]) ? 0 : 2 * ub;
+}
+
+// Row i of C = A B for rows too long for k_product_rows_wave: the products
+// a_ik b_kj in the order of A's row, then of B's rows, each added to its
+// column's sum (the first one as in k_product_rows_wave), columns found
+// through an open-addressing table of 2 ub slots at hoff[i]; the distinct
+// columns are then sorted.  The row goes to the workspace at woff[i].
 __global__ __launch_bounds__(kB) void k_product_rows(int n, const int *__restrict__ aptr, const int *__restrict__ acol,
                                                      const double *__restrict__ aval, const int *__restrict__ bptr,
                                                      const int *__restrict__ bcol, const double *__restrict__ bval,
-                                                     const long long *__restrict__ woff, int *__restrict__ hkey,
+                                                     const long long *__restrict__ woff,
+                                                     const long long *__restrict__ hoff, int *__restrict__ hkey,
                                                      int *__restrict__ hslot, int *__restrict__ ocol,
                                                      double *__restrict__ oacc, int *__restrict__ cnt, int zero_init)
 {
@@ -535,13 +645,10 @@ __global__ __launch_bounds__(kB) void k_product_rows(int n, const int *__restric
     const int i = blockIdx.x * kB + threadIdx.x;
     if (i >= n) return;
     const long long ub = woff[i + 1] - woff[i];
-    if (ub == 0) {
-        cnt[i] = 0;
-        return;
-    }
+    if (wave_row(ub, aptr[i + 1] - aptr[i])) return;   // a row of k_product_rows_wave
     const long long cap = 2 * ub;
-    int *keys = hkey + 2 * woff[i];
-    int *slots = hslot + 2 * woff[i];
+    int *keys = hkey + hoff[i];
+    int *slots = hslot + hoff[i];
     int *oc = ocol + woff[i];
     double *oa = oacc + woff[i];
     for (long long q = 0; q < cap; q++) keys[q] = -1;
@@ -611,15 +718,22 @@ DCsr product(hipStream_t s, const DCsr &A, const DCsr &B, bool zero_init, DevMem
     long long *woff = dnew<long long>(mem, (size_t)A.n + 1);
     hipLaunchKernelGGL(k_product_bound, dim3(rows_grid(A.n)), dim3(kB), 0, s, A.n, A.ptr, A.col, B.ptr, ub);
     const long long total = scan(s, A.n, ub, woff, mem);
+    // hash tables only for the rows too long for one wavefront's LDS
+    hipLaunchKernelGGL(k_long_rows, dim3(rows_grid(A.n)), dim3(kB), 0, s, A.n, A.ptr, woff, ub);
+    long long *hoff = dnew<long long>(mem, (size_t)A.n + 1);
+    const long long htotal = scan(s, A.n, ub, hoff, mem);
     dfree(mem, ub);
-    int *hkey = dnew<int>(mem, (size_t)(2 * total)), *hslot = dnew<int>(mem, (size_t)(2 * total));
+    int *hkey = dnew<int>(mem, (size_t)htotal), *hslot = dnew<int>(mem, (size_t)htotal);
     int *ocol = dnew<int>(mem, (size_t)total);
     double *oacc = dnew<double>(mem, (size_t)total);
     int *cnt = dnew<int>(mem, (size_t)A.n);
-    hipLaunchKernelGGL(k_product_rows, dim3(rows_grid(A.n)), dim3(kB), 0, s, A.n, A.ptr, A.col, A.val, B.ptr, B.col,
-                       B.val, woff, hkey, hslot, ocol, oacc, cnt, zero_init ? 1 : 0);
-    dfree(mem, hkey);
-    dfree(mem, hslot);
+    if (A.n > 0)
+        hipLaunchKernelGGL(k_product_rows_wave, dim3(A.n), dim3(64), 0, s, A.n, A.ptr, A.col, A.val, B.ptr, B.col,
+                           B.val, woff, ocol, oacc, cnt, zero_init ? 1 : 0);
+    if (htotal > 0)
+        hipLaunchKernelGGL(k_product_rows, dim3(rows_grid(A.n)), dim3(kB), 0, s, A.n, A.ptr, A.col, A.val, B.ptr,
+                           B.col, B.val, woff, hoff, hkey, hslot, ocol, oacc, cnt, zero_init ? 1 : 0);
+    for (void *p : {(void *)hkey, (void *)hslot, (void *)hoff}) dfree(mem, p);
     C.ptr = dnew<int>(mem, (size_t)A.n + 1);
     C.nnz = checked_int(scan(s, A.n, cnt, C.ptr, mem), "product entries");
     C.col = dnew<int>(mem, (size_t)C.nnz);
