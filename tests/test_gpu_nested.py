@@ -150,7 +150,7 @@ def test_set_kappa(pair):
 
 @pytest.mark.parametrize("k,n", [(4, 24), (3, 32)])
 def test_full_size_fewer_iterations(k, n):
-    """P4 on 24^3 and P3 on 32^3 cubes (857,375 and 912,673 unknowns),
+    """P4 on 24^3 and P3 on 32^3 cubes (857,375 unknowns each),
     kappa = exp(GRF): the intermediate space converges to the same solution
     in fewer CG iterations than the P^1 space (timings printed)."""
     xyz, tets = W.kuhn_mesh(n, jitter=0.0, seed=0)
