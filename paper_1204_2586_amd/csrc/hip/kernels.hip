@@ -348,27 +348,35 @@ __global__ __launch_bounds__(kBlock) void k_csr_sweep(int n, const int *__restri
     }
 }
 
+// One workgroup per row: each lane's few loads of the row are all in flight
+// at once (at most n / 256 per lane), then a workgroup sum; the rows of the
+// dense cycle (at most 8192) are short enough that one wavefront per row
+// leaves each lane a chain of dependent load rounds.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const T *__restrict__ Ainv, const T *__restrict__ b,
                                                        T *__restrict__ x, const int *done)
 {
     if (stop(done)) return;
+    __shared__ T red[kBlock / 64];
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-    for (int i = blockIdx.x * (kBlock / 64) + w; i < n; i += gridDim.x * (kBlock / 64)) {
-        // four accumulators, loads unrolled: a lane's loads of the row in flight together
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const T *__restrict__ row = Ainv + (size_t)i * n;
-        T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-        int j = l;
-#pragma unroll 4
-        for (; j + 192 < n; j += 256) {
+        T s0 = T(0), s1 = T(0);
+        int j = threadIdx.x;
+        for (; j + kBlock < n; j += 2 * kBlock) {
             s0 += row[j] * b[j];
-            s1 += row[j + 64] * b[j + 64];
-            s2 += row[j + 128] * b[j + 128];
-            s3 += row[j + 192] * b[j + 192];
+            s1 += row[j + kBlock] * b[j + kBlock];
         }
-        for (; j < n; j += 64) s0 += row[j] * b[j];
-        T s = group_sum<64>((s0 + s1) + (s2 + s3));
-        if (l == 0) x[i] = s;
+        if (j < n) s0 += row[j] * b[j];
+        T s = group_sum<64>(s0 + s1);
+        __syncthreads();                           // red of the previous row is consumed
+        if (l == 0) red[w] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            T t = T(0);
+            for (int q = 0; q < kBlock / 64; q++) t += red[q];
+            x[i] = t;
+        }
     }
 }
 
@@ -668,9 +676,8 @@ void csr_sweep(hipStream_t s, const DevCsrView &A, const T *dinv, const T *b, co
 template <typename T>
 void dense_gemv(hipStream_t s, int n, const T *Ainv, const T *b, T *x, const int *done)
 {
-    // one wavefront per row
-    hipLaunchKernelGGL(k_dense_gemv<T>, dim3(grid_cap((n + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, s, n,
-                       Ainv, b, x, done);
+    // one workgroup per row
+    hipLaunchKernelGGL(k_dense_gemv<T>, dim3(grid_cap(n)), dim3(kBlock), 0, s, n, Ainv, b, x, done);
 }
 
 int vec_dot(hipStream_t s, int n, const double *a, const double *b, double *partials)
