@@ -150,6 +150,9 @@ typedef struct aux_options {
     int true_residual;       /* 1: pcg_solve and pcg_solve_noalloc also compute the true
                                 ||f - A_h u||_2 / ||f||_2 of the returned iterate (one more
                                 product); 0 (default) leaves aux_solve_info.true_rel_residual -1 */
+    int gram_schmidt;        /* passes of classical Gram-Schmidt per FGMRES step (fgmres_solve,
+                                stokes_fgmres_solve): 1 (default, as PETSc's GMRES by default) or
+                                2 (reorthogonalised; two more passes over the basis) */
 } aux_options;
 
 typedef struct aux_device {

@@ -53,7 +53,8 @@ class _Options(ctypes.Structure):
                 ("sell_index16", ctypes.c_int), ("fuse_cycle", ctypes.c_int),
                 ("batch_tiles", ctypes.c_int), ("cycle_lanes", ctypes.c_int), ("dense_cycle_rows", ctypes.c_int),
                 ("batch_order", ctypes.c_int), ("amg_setup", ctypes.c_int), ("aux_space", ctypes.c_int),
-                ("smoother_weight", ctypes.c_double), ("true_residual", ctypes.c_int)]
+                ("smoother_weight", ctypes.c_double), ("true_residual", ctypes.c_int),
+                ("gram_schmidt", ctypes.c_int)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -195,7 +196,8 @@ class Solver:
                  operator: str = "assembled", sell_window: int = 0, graph: bool = True, sell_index16: bool = True,
                  fuse_cycle: bool = True, batch_tiles: int = 1, cycle_lanes: int = 0,
                  dense_cycle_rows: int = 2048, batch_order: int = 0, amg_setup: str = "device",
-                 aux_space: int = 1, smoother_weight: float = 1.0, true_residual: bool = False):
+                 aux_space: int = 1, smoother_weight: float = 1.0, true_residual: bool = False,
+                 gram_schmidt: int = 1):
         lib = load_library()
         self._h = ctypes.c_void_p()
         self.order = order
@@ -222,6 +224,7 @@ class Solver:
         opt.aux_space = int(aux_space)
         opt.smoother_weight = float(smoother_weight)
         opt.true_residual = int(true_residual)
+        opt.gram_schmidt = int(gram_schmidt)
         kap = None
         if kappa is not None:
             self._kappa = np.ascontiguousarray(kappa, dtype=np.float64)

@@ -1418,14 +1418,22 @@ struct aux_handle {
                 double *vj = V + j * ld, *zj = Z + j * ld, *w = V + (j + 1) * ld;
                 K.prec(vj, zj);
                 K.op(zj, w);
-                // classical Gram-Schmidt, twice
+                // classical Gram-Schmidt, once (PETSc's default for its
+                // GMRES) or twice (option gram_schmidt)
                 multi_dot(s, n, j + 1, V, ld, w, fg.part, h1);
-                multi_axpy(s, n, j + 1, V, ld, h1, -1.0, w, nullptr, nullptr);
-                multi_dot(s, n, j + 1, V, ld, w, fg.part, h2);
-                multi_axpy(s, n, j + 1, V, ld, h2, -1.0, w, fg.part, nrm);
+                if (opt.gram_schmidt == 2) {
+                    multi_axpy(s, n, j + 1, V, ld, h1, -1.0, w, nullptr, nullptr);
+                    multi_dot(s, n, j + 1, V, ld, w, fg.part, h2);
+                    multi_axpy(s, n, j + 1, V, ld, h2, -1.0, w, fg.part, nrm);
+                } else {
+                    multi_axpy(s, n, j + 1, V, ld, h1, -1.0, w, fg.part, nrm);
+                }
                 scale_unit(s, n, w, nrm, w);
                 HIPCHECK(hipMemcpyAsync(hh, h1, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-                HIPCHECK(hipMemcpyAsync(hh + kHs, h2, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+                if (opt.gram_schmidt == 2)
+                    HIPCHECK(hipMemcpyAsync(hh + kHs, h2, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+                else
+                    for (int i = 0; i <= j; i++) hh[kHs + i] = 0.0;
                 HIPCHECK(hipMemcpyAsync(hh + 2 * kHs, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
                 HIPCHECK(hipStreamSynchronize(s));
                 for (int i = 0; i <= j; i++) Hc(i, j) = hh[i] + hh[kHs + i];
@@ -2811,6 +2819,7 @@ void aux_default_options(aux_options *o)
     o->aux_space = 1;
     o->smoother_weight = 1.0;
     o->true_residual = 0;
+    o->gram_schmidt = 1;
 }
 
 int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_options *opt, const aux_device *dev,
@@ -2835,6 +2844,7 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
             if (flag != 0 && flag != 1) throw AuxError(AUX_EINVAL, "a boolean option is not 0 or 1");
         if (o.batch_tiles < 0 || o.batch_tiles > 2) throw AuxError(AUX_EINVAL, "batch_tiles must be 0, 1 or 2");
         if (o.aux_space != 1 && o.aux_space != 2) throw AuxError(AUX_EINVAL, "aux_space must be 1 or 2");
+        if (o.gram_schmidt != 1 && o.gram_schmidt != 2) throw AuxError(AUX_EINVAL, "gram_schmidt must be 1 or 2");
         if (!std::isfinite(o.smoother_weight) || o.smoother_weight == 0.0)
             throw AuxError(AUX_EINVAL, "smoother_weight must be finite and nonzero");
         if (o.dense_cycle_rows < 0 || o.dense_cycle_rows > 8192)

@@ -64,6 +64,25 @@ def test_fixed_steps_fp64(pair, restart, steps):
     np.testing.assert_allclose(h, ho, rtol=0, atol=1e-9 * ho[0])
 
 
+def test_two_pass_gram_schmidt():
+    """The reorthogonalised Arnoldi step (gram_schmidt = 2) against the
+    oracle at a fixed step count, and the default single pass beside it:
+    both are the same Arnoldi process in exact arithmetic."""
+    xyz, tets = W.kuhn_mesh(6, jitter=0.2, seed=0)
+    orc = oracle.Problem(xyz, tets, 2).setup_amg()
+    b = orc.load(W.manufactured_f)
+    x0 = W.random_vector(orc.n, 11)
+    xo, ito, _, _, ho = orc.fgmres(b, tol=0.0, restart=30, maxit=20, x0=x0)
+    for gs in (2, 1):
+        lib = aux.Solver(xyz, tets, 2, device=DEV, gram_schmidt=gs)
+        x, info, h = lib.fgmres(_t(b), tol=0.0, x0=_t(x0), restart=30, maxit=20, check=False)
+        assert info.iterations == ito == 20
+        assert _rel(x.cpu().numpy(), xo) <= 1e-10, gs
+        np.testing.assert_allclose(h, ho, rtol=0, atol=1e-9 * ho[0])
+    with pytest.raises(aux.AuxError, match="gram_schmidt"):
+        aux.Solver(xyz, tets, 2, device=DEV, gram_schmidt=3)
+
+
 def test_free_running_fp64(pair):
     lib, orc, b = pair
     lib.set_precision("fp64")
