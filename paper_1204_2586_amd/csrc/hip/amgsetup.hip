@@ -8,10 +8,12 @@
 // Every step repeats the host setup's definitions and its arithmetic in its
 // order, with contraction into fused multiply-adds off, so that the device
 // hierarchy is bitwise the host one (identical C/F splits on every level):
-//  * strength, l1 norms, extended+i weights, sparse products, scaling and
-//    merging of operators: one thread per row, each sum in the host's order
-//    (sparse products accumulate in the order of the factors' entries, then
-//    the row is sorted by column);
+//  * strength, l1 norms, extended+i weights, scaling and merging of
+//    operators: one thread per row, each sum in the host's order;
+//  * sparse products: one wavefront per row (one workgroup for long rows),
+//    the row's products sorted by (column, order of the factors' entries)
+//    and each column summed in that order, as the host's row accumulator
+//    adds them;
 //  * PMIS: synchronous rounds, a selection pass (an undecided point whose
 //    measure beats every undecided strong neighbour, in S or S^T, becomes C)
 //    then a marking pass (undecided points that depend strongly on a new C
@@ -21,7 +23,7 @@
 //    cycle T_l = N_l + Q_l T_{l+1} M_l: one workgroup or one workgroup per
 //    row, each entry's sum in the host's order.
 // Variable-length row work (distance-two interpolation sets, product rows
-// and their hash tables) lives in workspaces sized by a first pass's upper
+// and their sort keys) lives in workspaces sized by a first pass's upper
 // bounds (prefix sums on the device).
 #include <hip/hip_runtime.h>
 
@@ -548,7 +550,7 @@ __global__ __launch_bounds__(64) void k_product_rows_wave(int n, const int *__re
     if (i >= n) return;
     const int a0 = aptr[i], na = aptr[i + 1] - a0;
     const long long ub = woff[i + 1] - woff[i];
-    if (!wave_row(ub, na)) return;                 // a row of k_product_rows
+    if (!wave_row(ub, na)) return;                 // a row of k_product_rows_long
     if (ub == 0) {
         if (lane == 0) cnt[i] = 0;
         return;
@@ -618,79 +620,158 @@ __global__ __launch_bounds__(64) void k_product_rows_wave(int n, const int *__re
     if (lane == 0) cnt[i] = base;
 }
 
-// table slots of the rows k_product_rows handles (2 per product)
+// workspace slots of the rows k_product_rows_long handles (one per product)
 __global__ __launch_bounds__(kB) void k_long_rows(int n, const int *__restrict__ aptr,
                                                   const long long *__restrict__ woff, long long *__restrict__ hub)
 {
     const int i = blockIdx.x * kB + threadIdx.x;
     if (i >= n) return;
     const long long ub = woff[i + 1] - woff[i];
-    hub[i] = wave_row(ub, aptr[i + 1] - aptr[i]) ? 0 : 2 * ub;
+    hub[i] = wave_row(ub, aptr[i + 1] - aptr[i]) ? 0 : ub;
 }
 
-// Row i of C = A B for rows too long for k_product_rows_wave: the products
-// a_ik b_kj in the order of A's row, then of B's rows, each added to its
-// column's sum (the first one as in k_product_rows_wave), columns found
-// through an open-addressing table of 2 ub slots at hoff[i]; the distinct
-// columns are then sorted.  The row goes to the workspace at woff[i].
-__global__ __launch_bounds__(kB) void k_product_rows(int n, const int *__restrict__ aptr, const int *__restrict__ acol,
-                                                     const double *__restrict__ aval, const int *__restrict__ bptr,
-                                                     const int *__restrict__ bcol, const double *__restrict__ bval,
-                                                     const long long *__restrict__ woff,
-                                                     const long long *__restrict__ hoff, int *__restrict__ hkey,
-                                                     int *__restrict__ hslot, int *__restrict__ ocol,
-                                                     double *__restrict__ oacc, int *__restrict__ cnt, int zero_init)
+// Exclusive prefix sum of v over a workgroup of kB threads (every thread
+// calls it); total receives the sum over the workgroup.
+__device__ __forceinline__ int block_scan(int v, int *wsum, int &total)
+{
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kB / 64; q++) {
+        const int t = wsum[q];
+        if (q < w) pre += t;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + x - v;
+}
+
+// keys sorted in LDS at once by k_product_rows_long
+constexpr int kLongChunk = 4096;
+
+// Row i of C = A B for the rows k_product_rows_wave leaves, one workgroup
+// per row.  The products a_ik b_kj, numbered in the order of A's row, then
+// of B's rows, go to the workspace at hoff[i] with their keys (column << 32
+// | number); runs of kLongChunk keys are sorted in LDS (bitonic), then runs
+// are merged pairwise (each key's place is its index in its run plus the
+// number of keys of the other run below it; keys are distinct); each
+// column's products are then summed in number order by the thread holding
+// its first one, exactly as in k_product_rows_wave, and the columns written
+// in order to the workspace at woff[i].
+__global__ __launch_bounds__(kB) void k_product_rows_long(
+    int n, const int *__restrict__ aptr, const int *__restrict__ acol, const double *__restrict__ aval,
+    const int *__restrict__ bptr, const int *__restrict__ bcol, const double *__restrict__ bval,
+    const long long *__restrict__ woff, const long long *__restrict__ hoff, unsigned long long *__restrict__ keya,
+    unsigned long long *__restrict__ keyb, double *__restrict__ pval, int *__restrict__ ocol,
+    double *__restrict__ oacc, int *__restrict__ cnt, int zero_init)
 {
 #pragma clang fp contract(off)
-    const int i = blockIdx.x * kB + threadIdx.x;
+    __shared__ unsigned long long sk[kLongChunk];
+    __shared__ int wsum[kB / 64];
+    const int i = blockIdx.x;
     if (i >= n) return;
+    const int a0 = aptr[i], na = aptr[i + 1] - a0;
     const long long ub = woff[i + 1] - woff[i];
-    if (wave_row(ub, aptr[i + 1] - aptr[i])) return;   // a row of k_product_rows_wave
-    const long long cap = 2 * ub;
-    int *keys = hkey + hoff[i];
-    int *slots = hslot + hoff[i];
-    int *oc = ocol + woff[i];
-    double *oa = oacc + woff[i];
-    for (long long q = 0; q < cap; q++) keys[q] = -1;
-    int d = 0;
-    for (int e = aptr[i]; e < aptr[i + 1]; e++) {
-        const int k = acol[e];
-        const double a = aval[e];
-        for (int f = bptr[k]; f < bptr[k + 1]; f++) {
-            const int j = bcol[f];
-            const double prod = a * bval[f];
-            long long q = (long long)(((unsigned long long)(unsigned)j * 2654435761ULL) % (unsigned long long)cap);
-            for (;;) {
-                const int key = keys[q];
-                if (key == j) {
-                    oa[slots[q]] += prod;
-                    break;
-                }
-                if (key < 0) {
-                    keys[q] = j;
-                    slots[q] = d;
-                    oc[d] = j;
-                    oa[d] = zero_init ? 0.0 + prod : prod;
-                    d++;
-                    break;
-                }
-                q = q + 1 == cap ? 0 : q + 1;
+    if (wave_row(ub, na)) return;                  // a row of k_product_rows_wave
+    const int m = (int)ub;
+    unsigned long long *src = keya + hoff[i], *dst = keyb + hoff[i];
+    double *pv = pval + hoff[i];
+    // the products, numbered in order
+    int base = 0;
+    for (int e0 = 0; e0 < na; e0 += kB) {
+        const int e = e0 + (int)threadIdx.x;
+        int k = 0, len = 0;
+        if (e < na) {
+            k = acol[a0 + e];
+            len = bptr[k + 1] - bptr[k];
+        }
+        int tot;
+        const int off = base + block_scan(len, wsum, tot);
+        if (e < na) {
+            const double a = aval[a0 + e];
+            const int f0 = bptr[k];
+            for (int f = 0; f < len; f++) {
+                src[off + f] = ((unsigned long long)(unsigned)bcol[f0 + f] << 32) | (unsigned)(off + f);
+                pv[off + f] = a * bval[f0 + f];
             }
         }
+        base += tot;
     }
-    for (int p = 1; p < d; p++) {
-        const int c = oc[p];
-        const double v = oa[p];
-        int q = p - 1;
-        while (q >= 0 && oc[q] > c) {
-            oc[q + 1] = oc[q];
-            oa[q + 1] = oa[q];
-            q--;
+    __syncthreads();
+    // sorted runs
+    for (int c0 = 0; c0 < m; c0 += kLongChunk) {
+        const int len = std::min(kLongChunk, m - c0);
+        int np2 = 1;
+        while (np2 < len) np2 <<= 1;
+        for (int t = threadIdx.x; t < np2; t += kB) sk[t] = t < len ? src[c0 + t] : ~0ULL;
+        __syncthreads();
+        for (int kk = 2; kk <= np2; kk <<= 1)
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int t = threadIdx.x; t < np2 / 2; t += kB) {
+                    const int i1 = 2 * j * (t / j) + (t % j), i2 = i1 + j;
+                    const bool up = (i1 & kk) == 0;
+                    const unsigned long long x = sk[i1], y = sk[i2];
+                    if ((x > y) == up) {
+                        sk[i1] = y;
+                        sk[i2] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        for (int t = threadIdx.x; t < len; t += kB) src[c0 + t] = sk[t];
+        __syncthreads();
+    }
+    // pairwise merges of runs of w keys
+    for (int w = kLongChunk; w < m; w <<= 1) {
+        for (int t = threadIdx.x; t < m; t += kB) {
+            const int lo = t / (2 * w) * (2 * w);
+            const int mid = std::min(lo + w, m), hi = std::min(lo + 2 * w, m);
+            const unsigned long long x = src[t];
+            const bool first = t < mid;
+            int l = first ? mid : lo, r = first ? hi : mid;
+            const int ob = l;
+            while (l < r) {
+                const int md = (l + r) >> 1;
+                if (src[md] < x) l = md + 1;
+                else r = md;
+            }
+            dst[lo + (t - (first ? lo : mid)) + (l - ob)] = x;
         }
-        oc[q + 1] = c;
-        oa[q + 1] = v;
+        __syncthreads();
+        unsigned long long *t = src;
+        src = dst;
+        dst = t;
     }
-    cnt[i] = d;
+    // column sums in number order, columns in order
+    int ncols = 0;
+    for (int q0 = 0; q0 < m; q0 += kB) {
+        const int q = q0 + (int)threadIdx.x;
+        int head = 0, col = 0;
+        if (q < m) {
+            col = (int)(src[q] >> 32);
+            head = q == 0 || (int)(src[q - 1] >> 32) != col;
+        }
+        int tot;
+        const int rank = ncols + block_scan(head, wsum, tot);
+        if (head) {
+            double acc = pv[(unsigned)src[q]];
+            if (zero_init) acc = 0.0 + acc;
+            for (int r = q + 1; r < m && (int)(src[r] >> 32) == col; r++) acc += pv[(unsigned)src[r]];
+            ocol[woff[i] + rank] = col;
+            oacc[woff[i] + rank] = acc;
+        }
+        ncols += tot;
+    }
+    if (threadIdx.x == 0) cnt[i] = ncols;
 }
 
 __global__ __launch_bounds__(kB) void k_compact_rows(int n, const long long *__restrict__ woff,
@@ -718,12 +799,15 @@ DCsr product(hipStream_t s, const DCsr &A, const DCsr &B, bool zero_init, DevMem
     long long *woff = dnew<long long>(mem, (size_t)A.n + 1);
     hipLaunchKernelGGL(k_product_bound, dim3(rows_grid(A.n)), dim3(kB), 0, s, A.n, A.ptr, A.col, B.ptr, ub);
     const long long total = scan(s, A.n, ub, woff, mem);
-    // hash tables only for the rows too long for one wavefront's LDS
+    checked_int(total, "products of a sparse product");   // numbers in 32-bit keys
+    // sort workspaces only for the rows too long for one wavefront's LDS
     hipLaunchKernelGGL(k_long_rows, dim3(rows_grid(A.n)), dim3(kB), 0, s, A.n, A.ptr, woff, ub);
     long long *hoff = dnew<long long>(mem, (size_t)A.n + 1);
     const long long htotal = scan(s, A.n, ub, hoff, mem);
     dfree(mem, ub);
-    int *hkey = dnew<int>(mem, (size_t)htotal), *hslot = dnew<int>(mem, (size_t)htotal);
+    unsigned long long *keya = dnew<unsigned long long>(mem, (size_t)htotal);
+    unsigned long long *keyb = dnew<unsigned long long>(mem, (size_t)htotal);
+    double *pval = dnew<double>(mem, (size_t)htotal);
     int *ocol = dnew<int>(mem, (size_t)total);
     double *oacc = dnew<double>(mem, (size_t)total);
     int *cnt = dnew<int>(mem, (size_t)A.n);
@@ -731,9 +815,9 @@ DCsr product(hipStream_t s, const DCsr &A, const DCsr &B, bool zero_init, DevMem
         hipLaunchKernelGGL(k_product_rows_wave, dim3(A.n), dim3(64), 0, s, A.n, A.ptr, A.col, A.val, B.ptr, B.col,
                            B.val, woff, ocol, oacc, cnt, zero_init ? 1 : 0);
     if (htotal > 0)
-        hipLaunchKernelGGL(k_product_rows, dim3(rows_grid(A.n)), dim3(kB), 0, s, A.n, A.ptr, A.col, A.val, B.ptr,
-                           B.col, B.val, woff, hoff, hkey, hslot, ocol, oacc, cnt, zero_init ? 1 : 0);
-    for (void *p : {(void *)hkey, (void *)hslot, (void *)hoff}) dfree(mem, p);
+        hipLaunchKernelGGL(k_product_rows_long, dim3(A.n), dim3(kB), 0, s, A.n, A.ptr, A.col, A.val, B.ptr, B.col,
+                           B.val, woff, hoff, keya, keyb, pval, ocol, oacc, cnt, zero_init ? 1 : 0);
+    for (void *p : {(void *)keya, (void *)keyb, (void *)pval, (void *)hoff}) dfree(mem, p);
     C.ptr = dnew<int>(mem, (size_t)A.n + 1);
     C.nnz = checked_int(scan(s, A.n, cnt, C.ptr, mem), "product entries");
     C.col = dnew<int>(mem, (size_t)C.nnz);
@@ -1027,6 +1111,45 @@ __global__ __launch_bounds__(kB) void k_to_f32(long long n, const double *__rest
     if (i < n) b[i] = (float)a[i];
 }
 
+__global__ __launch_bounds__(kB) void k_reciprocal(int n, const double *__restrict__ a, double *__restrict__ b)
+{
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i < n) b[i] = 1.0 / a[i];
+}
+
+// ------------------------------------------------------------ row-split sliced ELL
+
+// slots[s] = 64 x the widest row of slice s in groups of `lanes` entries
+__global__ __launch_bounds__(kB) void k_ell_width(int nsl, int n, int rows, int lanes, const int *__restrict__ ptr,
+                                                  int *__restrict__ slots)
+{
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s >= nsl) return;
+    int w = 0;
+    for (int q = 0; q < rows && s * rows + q < n; q++) {
+        const int i = s * rows + q;
+        w = max(w, (ptr[i + 1] - ptr[i] + lanes - 1) / lanes);
+    }
+    slots[s] = 64 * w;
+}
+
+// entry k of row i (slice s = i / rows, row q = i % rows of it) goes to slot
+// k / lanes of its slice, lane q * lanes + k % lanes
+__global__ __launch_bounds__(kB) void k_ell_fill(int n, int rows, int lanes, const int *__restrict__ ptr,
+                                                 const int *__restrict__ col, const double *__restrict__ val,
+                                                 const int *__restrict__ off, int *__restrict__ ecol,
+                                                 double *__restrict__ eval)
+{
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= n) return;
+    const int s = i / rows, q = i % rows;
+    for (int e = ptr[i], k = 0; e < ptr[i + 1]; e++, k++) {
+        const size_t at = (size_t)off[s] + (size_t)(k / lanes) * 64 + q * lanes + k % lanes;
+        ecol[at] = col[e];
+        eval[at] = val[e];
+    }
+}
+
 }  // namespace
 
 void device_amg(hipStream_t s, const DCsr &AH, const SetupOptions &opt, bool fuse, int dense_rows, DevMem &mem,
@@ -1227,6 +1350,35 @@ void download_amg(hipStream_t s, const DevAmg &d, Hierarchy &h, std::vector<Fuse
 void to_f32_device(hipStream_t s, long long n, const double *a, float *b)
 {
     if (n > 0) hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + kB - 1) / kB)), dim3(kB), 0, s, n, a, b);
+    AMG_CHECK(hipGetLastError());
+}
+
+void reciprocal_device(hipStream_t s, int n, const double *a, double *b)
+{
+    if (n > 0) hipLaunchKernelGGL(k_reciprocal, dim3(rows_grid(n)), dim3(kB), 0, s, n, a, b);
+    AMG_CHECK(hipGetLastError());
+}
+
+void ell_from_csr(hipStream_t s, const DCsr &A, int lanes, DevMem &mem, DevEll &out)
+{
+    if (lanes < 1 || lanes > 64 || (64 % lanes) != 0) throw std::invalid_argument("ell_from_csr: lanes must divide 64");
+    out = DevEll();
+    const int rows = 64 / lanes, nsl = (A.n + rows - 1) / rows;
+    int *slots = dnew<int>(mem, (size_t)nsl);
+    if (nsl > 0)
+        hipLaunchKernelGGL(k_ell_width, dim3(rows_grid(nsl)), dim3(kB), 0, s, nsl, A.n, rows, lanes, A.ptr, slots);
+    out.off = dnew<int>(mem, (size_t)nsl + 1);
+    out.stored = checked_int(scan(s, nsl, slots, out.off, mem), "ELL slots");
+    dfree(mem, slots);
+    out.col = dnew<int>(mem, (size_t)out.stored);
+    out.val = dnew<double>(mem, (size_t)out.stored);
+    if (out.stored > 0) {
+        AMG_CHECK(hipMemsetAsync(out.col, 0, sizeof(int) * (size_t)out.stored, s));
+        AMG_CHECK(hipMemsetAsync(out.val, 0, sizeof(double) * (size_t)out.stored, s));
+    }
+    if (A.n > 0)
+        hipLaunchKernelGGL(k_ell_fill, dim3(rows_grid(A.n)), dim3(kB), 0, s, A.n, rows, lanes, A.ptr, A.col, A.val,
+                           out.off, out.col, out.val);
     AMG_CHECK(hipGetLastError());
 }
 

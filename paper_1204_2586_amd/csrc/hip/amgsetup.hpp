@@ -53,5 +53,20 @@ void download_amg(hipStream_t s, const DevAmg &d, Hierarchy &h, std::vector<Fuse
 void free_amg(DevMem &mem, DevAmg &d);
 // b = (float) a, n entries
 void to_f32_device(hipStream_t s, long long n, const double *a, float *b);
+// b = 1 / a, n entries
+void reciprocal_device(hipStream_t s, int n, const double *a, double *b);
+
+// Row-split sliced ELL of a device CSR matrix, the host build_ell layout:
+// slices of 64 / lanes rows, each row's entries dealt in order to its lanes
+// (entry k to slot k / lanes, lane q * lanes + k % lanes of row q), a slice
+// as wide as its longest row, padding (column 0, value 0).  off has one
+// entry per slice plus one (slot offsets); stored = off[last].
+struct DevEll {
+    int *off = nullptr, *col = nullptr;
+    double *val = nullptr;
+    int stored = 0;
+};
+// lanes divides 64 (std::invalid_argument otherwise); synchronises the stream
+void ell_from_csr(hipStream_t s, const DCsr &A, int lanes, DevMem &mem, DevEll &out);
 
 }  // namespace auxp

@@ -188,6 +188,10 @@ struct aux_handle {
         DevOp down, up;              // composite operators (fuse_cycle)
         double *dinv64 = nullptr;
         float *dinv32 = nullptr;
+        // levels taken over from the device build: its l1 norms and C/F
+        // split, kept for the host copies made on demand
+        double *l1 = nullptr;
+        int *cf = nullptr;
     };
     DevOp RF;                        // composite restriction [I_R, -I_R A_h] (fuse_cycle)
     // the cycle from level dense_first down, as one dense matrix (fuse_cycle)
@@ -200,6 +204,12 @@ struct aux_handle {
     // waits in dense_pre for upload_coefficient_part
     bool fused_pre = false;
     double *dense_pre = nullptr;
+    // a device build whose operators upload_coefficient_part takes over as
+    // they are (no host round trip); hier and fused_host then stay empty
+    // until a host consumer asks (host_hier_stale)
+    DevAmg dev_built;
+    bool dev_built_ready = false;
+    bool host_hier_stale = false;
     int dense_pre_first = -1;
     double amg_seconds = 0.0;
     // intermediate auxiliary space (aux_space = 2, Remark 6.2): the P^2
@@ -634,6 +644,126 @@ struct aux_handle {
         ensure_hist(std::max(opt.maxit, 16));
     }
 
+    // Storage of one operator by lanes code (> 0: row-split ELL with that
+    // many lanes per row, built from the host copy if given, else from the
+    // operator's own device CSR; <= 0: CSR with -code lanes per row)
+    void set_storage(DevOp &op, const Csr *host, int code)
+    {
+        if (code > 0) {
+            if (host) set_ell(op, *host, code);
+            else set_ell_dev(op, code);
+        } else {
+            drop_ell(op);
+            op.lpr = -code;
+        }
+    }
+    void set_ell_dev(DevOp &op, int lanes)
+    {
+        drop_ell(op);
+        DevMem mem{[this](size_t b) { return dalloc(b); }, [this](void *p) { dfree(p); }};
+        DCsr c;
+        c.n = op.n;
+        c.m = op.m;
+        c.nnz = (int)op.nnz;
+        c.ptr = op.ptr;
+        c.col = op.col;
+        c.val = op.v64;
+        DevEll e;
+        ell_from_csr(stream, c, lanes, mem, e);
+        op.ell_off = e.off;
+        op.ell_col = e.col;
+        op.ell_v64 = e.val;
+        op.ell_v32 = dnew<float>((size_t)e.stored);
+        to_f32_device(stream, e.stored, e.val, op.ell_v32);
+        op.ell_stored = e.stored;
+        op.ell_lanes = lanes;
+    }
+
+    // The levels, composite operators and coarse inverse of the pending
+    // device build, taken over as they are (same arrays, CSR with the
+    // rule-based lanes; FP32 copies of the composite operators made on the
+    // device); the host copies are made when a host consumer needs them.
+    void adopt_device_levels()
+    {
+        DevAmg &d = dev_built;
+        const size_t L = d.A.size();
+        auto take = [&](const DCsr &c) {
+            DevOp o;
+            o.n = c.n;
+            o.m = c.m;
+            o.nnz = c.nnz;
+            o.ptr = c.ptr;
+            o.col = c.col;
+            o.v64 = c.val;
+            o.lpr = pick_lpr(c.n ? (double)c.nnz / c.n : 1.0);
+            return o;
+        };
+        auto with_f32 = [&](DevOp o) {
+            o.v32 = dnew<float>((size_t)o.nnz);
+            to_f32_device(stream, o.nnz, o.v64, o.v32);
+            return o;
+        };
+        lev.assign(L, Lev());
+        for (size_t l = 0; l < L; l++) {
+            Lev &lv = lev[l];
+            lv.A = take(d.A[l]);
+            lv.l1 = d.l1[l];
+            lv.dinv64 = dnew<double>((size_t)lv.A.n);
+            reciprocal_device(stream, lv.A.n, lv.l1, lv.dinv64);
+            if (l + 1 < L) {
+                lv.P = take(d.P[l]);
+                lv.R = take(d.R[l]);
+                lv.cf = d.cf[l];
+                if (opt.fuse_cycle) {
+                    lv.down = with_f32(take(d.down[l]));
+                    lv.up = with_f32(take(d.up[l]));
+                }
+            }
+        }
+        cinv64 = d.coarse_inv;
+        dev_built = DevAmg();
+        dev_built_ready = false;
+        hier = Hierarchy();
+        fused_host.clear();
+        host_hier_stale = true;
+    }
+
+    // host copies of the levels and composite operators taken over from a
+    // device build (exports, the batched forms)
+    void ensure_host_hierarchy()
+    {
+        if (!host_hier_stale) return;
+        DevAmg v;
+        auto view = [](const DevOp &o) {
+            DCsr c;
+            c.n = o.n;
+            c.m = o.m;
+            c.nnz = (int)o.nnz;
+            c.ptr = o.ptr;
+            c.col = o.col;
+            c.val = o.v64;
+            return c;
+        };
+        const size_t L = lev.size();
+        for (size_t l = 0; l < L; l++) {
+            v.A.push_back(view(lev[l].A));
+            v.l1.push_back(lev[l].l1);
+            if (l + 1 < L) {
+                v.P.push_back(view(lev[l].P));
+                v.R.push_back(view(lev[l].R));
+                v.cf.push_back(lev[l].cf);
+                if (opt.fuse_cycle) {
+                    v.down.push_back(view(lev[l].down));
+                    v.up.push_back(view(lev[l].up));
+                }
+            }
+        }
+        v.coarse_inv = cinv64;
+        v.ncoarse = L ? lev[L - 1].A.n : 0;
+        download_amg(stream, v, hier, opt.fuse_cycle ? &fused_host : nullptr);
+        host_hier_stale = false;
+    }
+
     // Everything on the device that depends on the coefficient beyond A_h's
     // values, built from the host discretisation and hierarchy: the l1
     // diagonal, the AMG levels and coarse inverse, the composite cycle
@@ -644,23 +774,30 @@ struct aux_handle {
         l1i.resize(disc.ndof);
         for (int i = 0; i < disc.ndof; i++) l1i[i] = disc.l1[sell.perm[i]];
         dinv64 = upload(smoother_inv(l1i));
-        lev.resize(hier.levels.size());
-        for (size_t l = 0; l < hier.levels.size(); l++) {
-            const AmgLevel &hl = hier.levels[l];
-            lev[l].A = upload_op(hl.A);
-            lev[l].dinv64 = upload(inverse(hl.l1));
-            if (l + 1 < hier.levels.size()) {
-                lev[l].P = upload_op(hl.P);
-                lev[l].R = upload_op(hl.R);
+        const bool adopted = dev_built_ready;
+        if (adopted) {
+            adopt_device_levels();
+        } else {
+            lev.resize(hier.levels.size());
+            for (size_t l = 0; l < hier.levels.size(); l++) {
+                const AmgLevel &hl = hier.levels[l];
+                lev[l].A = upload_op(hl.A);
+                lev[l].dinv64 = upload(inverse(hl.l1));
+                if (l + 1 < hier.levels.size()) {
+                    lev[l].P = upload_op(hl.P);
+                    lev[l].R = upload_op(hl.R);
+                }
             }
+            cinv64 = upload(hier.coarse_inv);
         }
-        cinv64 = upload(hier.coarse_inv);
-        if (opt.fuse_cycle && !hier.levels.empty()) {
-            if (!fused_pre) fused_host.resize(hier.levels.size());
-            for (size_t l = 0; l + 1 < hier.levels.size(); l++) {
-                if (!fused_pre) fused_host[l] = fuse_level(hier.levels[l]);
-                lev[l].down = upload_op2(fused_host[l].down);
-                lev[l].up = upload_op2(fused_host[l].up);
+        if (opt.fuse_cycle && !lev.empty()) {
+            if (!adopted) {
+                if (!fused_pre) fused_host.resize(hier.levels.size());
+                for (size_t l = 0; l + 1 < hier.levels.size(); l++) {
+                    if (!fused_pre) fused_host[l] = fuse_level(hier.levels[l]);
+                    lev[l].down = upload_op2(fused_host[l].down);
+                    lev[l].up = upload_op2(fused_host[l].up);
+                }
             }
             // the bottom of the cycle: each small level costs two launches
             // of dependent-load latency (about 5 us each) for well under a
@@ -697,21 +834,14 @@ struct aux_handle {
             // per row measured best in the solve).  A new coefficient keeps
             // the storage chosen at setup for each level index.
             if (opt.cycle_lanes != 0) {                // one storage for all of them
-                auto force = [&](DevOp &op, const Csr &host) {
-                    if (opt.cycle_lanes > 0) {
-                        set_ell(op, host, opt.cycle_lanes);
-                    } else {
-                        drop_ell(op);
-                        op.lpr = -opt.cycle_lanes;
-                    }
-                };
+                const int code = opt.cycle_lanes;
                 if (first) {
-                    force(RF, RF_host);
-                    force(IP, IPi);
+                    set_storage(RF, &RF_host, code);
+                    set_storage(IP, &IPi, code);
                 }
                 for (size_t l = 0; l + 1 < lev.size(); l++) {
-                    force(lev[l].down, fused_host[l].down);
-                    force(lev[l].up, fused_host[l].up);
+                    set_storage(lev[l].down, adopted ? nullptr : &fused_host[l].down, code);
+                    set_storage(lev[l].up, adopted ? nullptr : &fused_host[l].up, code);
                 }
             } else if (opt.sell_window <= 0 && first) {
                 const size_t fb = (size_t)512 << 20;    // twice the last-level cache
@@ -727,14 +857,10 @@ struct aux_handle {
                 }
                 dfree(flush);
             } else if (opt.sell_window <= 0) {
-                auto restore = [&](DevOp &op, const Csr &host, int code) {
-                    if (code > 0) set_ell(op, host, code);
-                    else op.lpr = -code;
-                };
                 for (size_t l = 0; l + 1 < lev.size() && l < tuned_lanes.size(); l++) {
                     if (lev[l].A.n < 8192) break;
-                    restore(lev[l].down, fused_host[l].down, tuned_lanes[l][0]);
-                    restore(lev[l].up, fused_host[l].up, tuned_lanes[l][1]);
+                    set_storage(lev[l].down, adopted ? nullptr : &fused_host[l].down, tuned_lanes[l][0]);
+                    set_storage(lev[l].up, adopted ? nullptr : &fused_host[l].up, tuned_lanes[l][1]);
                 }
             }
         }
@@ -756,7 +882,9 @@ struct aux_handle {
     // of the composite operators go to hier and fused_host (the host-side
     // consumers: uploads, layout choices, batched forms), and the dense
     // cycle stays on the device for upload_coefficient_part.
-    void device_hierarchy(const DCsr &AH)
+    // With adopt, the device arrays are kept for upload_coefficient_part to
+    // take over and nothing is copied to the host.
+    void device_hierarchy(const DCsr &AH, bool adopt = false)
     {
         auto t0 = std::chrono::steady_clock::now();
         DevMem mem{[this](size_t b) { return dalloc(b); }, [this](void *p) { dfree(p); }};
@@ -765,7 +893,7 @@ struct aux_handle {
             device_amg(stream, AH, amg_options(), opt.fuse_cycle != 0, opt.dense_cycle_rows, mem, d);
             hier = Hierarchy();
             fused_host.clear();
-            download_amg(stream, d, hier, opt.fuse_cycle ? &fused_host : nullptr);
+            if (!adopt) download_amg(stream, d, hier, opt.fuse_cycle ? &fused_host : nullptr);
         } catch (...) {
             free_amg(mem, d);
             throw;
@@ -775,7 +903,12 @@ struct aux_handle {
         dense_pre_first = d.dense_first;
         d.dense = nullptr;
         fused_pre = opt.fuse_cycle != 0;
-        free_amg(mem, d);
+        if (adopt) {
+            dev_built = d;
+            dev_built_ready = true;
+        } else {
+            free_amg(mem, d);
+        }
         amg_seconds = seconds_since(t0);
     }
 
@@ -811,19 +944,25 @@ struct aux_handle {
         fp32_ready = true;
     }
     // FP32 copies of the coefficient-dependent operators
+    // (each the rounding of the FP64 array on the device)
     void fp32_coefficient_part()
     {
-        dinv32 = upload(to_f32(smoother_inv(l1i)));
-        for (size_t l = 0; l < hier.levels.size(); l++) {
-            const AmgLevel &hl = hier.levels[l];
-            lev[l].A.v32 = upload(to_f32(hl.A.val));
-            lev[l].dinv32 = upload(to_f32(inverse(hl.l1)));
-            if (l + 1 < hier.levels.size()) {
-                lev[l].P.v32 = upload(to_f32(hl.P.val));
-                lev[l].R.v32 = upload(to_f32(hl.R.val));
+        auto f32 = [&](const double *a, size_t n) {
+            float *b = dnew<float>(n);
+            to_f32_device(stream, (long long)n, a, b);
+            return b;
+        };
+        dinv32 = f32(dinv64, (size_t)disc.ndof);
+        for (size_t l = 0; l < lev.size(); l++) {
+            Lev &lv = lev[l];
+            lv.A.v32 = f32(lv.A.v64, (size_t)lv.A.nnz);
+            lv.dinv32 = f32(lv.dinv64, (size_t)lv.A.n);
+            if (l + 1 < lev.size()) {
+                lv.P.v32 = f32(lv.P.v64, (size_t)lv.P.nnz);
+                lv.R.v32 = f32(lv.R.v64, (size_t)lv.R.nnz);
             }
         }
-        cinv32 = upload(to_f32(hier.coarse_inv));
+        if (!lev.empty()) cinv32 = f32(cinv64, (size_t)lev.back().A.n * lev.back().A.n);
     }
 
     template <typename T>
@@ -2058,6 +2197,7 @@ struct aux_handle {
     void ensure_bops()
     {
         ensure_host_values();
+        ensure_host_hierarchy();
         if (bops_ready) return;
         const size_t L = hier.levels.size();
         bA.resize(L);
@@ -2585,10 +2725,10 @@ struct aux_handle {
         dinv32 = nullptr;
         for (Lev &L : lev) {
             for (DevOp *op : {&L.A, &L.P, &L.R, &L.down, &L.up}) free_op(*op);
-            dfree(L.dinv64);
-            dfree(L.dinv32);
+            for (void *b : {(void *)L.dinv64, (void *)L.dinv32, (void *)L.l1, (void *)L.cf}) dfree(b);
         }
         lev.clear();
+        host_hier_stale = false;
         for (void *b : {(void *)cinv64, (void *)cinv32, (void *)dcyc64, (void *)dcyc32}) dfree(b);
         cinv64 = dcyc64 = nullptr;
         cinv32 = dcyc32 = nullptr;
@@ -2671,7 +2811,7 @@ struct aux_handle {
                 AH.ptr = asmd.h_rowptr;
                 AH.col = asmd.h_col;
                 AH.val = hval;
-                device_hierarchy(AH);
+                device_hierarchy(AH, true);
             } else {
                 auto t0 = std::chrono::steady_clock::now();
                 build_hierarchy(disc.AH, amg_options(), hier);
@@ -2965,15 +3105,19 @@ int aux_get_info(const aux_handle *h, aux_info *info)
         info->nnz_AH = d.AH.nnz();
         info->nnz_IP = d.IP.nnz();
         info->order = d.k;
-        info->levels = (int)h->hier.levels.size();
-        info->ncoarse = h->hier.ncoarse;
+        // sizes from the device levels when their host copies are not made
+        const bool dev = h->host_hier_stale;
+        const size_t L = dev ? h->lev.size() : h->hier.levels.size();
+        info->levels = (int)L;
+        info->ncoarse = dev ? (L ? h->lev[L - 1].A.n : 0) : h->hier.ncoarse;
         info->precision = h->opt.precision;
         double tot = 0.0;
-        for (size_t l = 0; l < h->hier.levels.size() && l < 32; l++) {
-            info->level_rows[l] = h->hier.levels[l].A.n;
-            info->level_nnz[l] = h->hier.levels[l].A.nnz();
-            info->level_nnz_P[l] = l + 1 < h->hier.levels.size() ? h->hier.levels[l].P.nnz() : 0;
-            tot += (double)h->hier.levels[l].A.nnz();
+        for (size_t l = 0; l < L && l < 32; l++) {
+            const int64_t nnz = dev ? h->lev[l].A.nnz : h->hier.levels[l].A.nnz();
+            info->level_rows[l] = dev ? h->lev[l].A.n : h->hier.levels[l].A.n;
+            info->level_nnz[l] = nnz;
+            info->level_nnz_P[l] = l + 1 < L ? (dev ? h->lev[l].P.nnz : h->hier.levels[l].P.nnz()) : 0;
+            tot += (double)nnz;
         }
         info->op_complexity = d.A.nnz() ? (d.A.nnz() + tot) / (double)d.A.nnz() : 0.0;
         info->amg_complexity = d.AH.nnz() ? tot / (double)d.AH.nnz() : 0.0;
@@ -2988,9 +3132,16 @@ int aux_get_info(const aux_handle *h, aux_info *info)
         info->nnz_restrict = h->RF_host.nnz();
         info->batch_tile_rows[0] = h->bt.layout32 >= 0 ? h->tiles[h->bt.layout32].tile : 0;
         info->batch_tile_rows[1] = h->bt.layout64 >= 0 ? h->tiles[h->bt.layout64].tile : 0;
-        for (size_t l = 0; l < h->fused_host.size() && l < 32; l++) {
-            info->level_nnz_down[l] = h->fused_host[l].down.nnz();
-            info->level_nnz_up[l] = h->fused_host[l].up.nnz();
+        if (dev) {
+            for (size_t l = 0; l + 1 < L && l < 32; l++) {
+                info->level_nnz_down[l] = h->lev[l].down.nnz;
+                info->level_nnz_up[l] = h->lev[l].up.nnz;
+            }
+        } else {
+            for (size_t l = 0; l < h->fused_host.size() && l < 32; l++) {
+                info->level_nnz_down[l] = h->fused_host[l].down.nnz();
+                info->level_nnz_up[l] = h->fused_host[l].up.nnz();
+            }
         }
         info->dense_cycle_level = h->dense_first == SIZE_MAX ? -1 : (int32_t)h->dense_first;
         info->amg_setup_seconds = h->amg_seconds;
@@ -3054,6 +3205,10 @@ int aux_export_csr(const aux_handle *h, int which, int level, int64_t *shape, in
 {
     return guarded([&]() {
         if (!h || !shape) throw AuxError(AUX_EINVAL, "null argument");
+        if ((which == 3 || which == 4 || which == 7 || which == 8) && h->host_hier_stale) {
+            set_dev(h);
+            const_cast<aux_handle *>(h)->ensure_host_hierarchy();
+        }
         const Csr *c = nullptr;
         int nl = (int)h->hier.levels.size();
         switch (which) {
@@ -3095,6 +3250,10 @@ int aux_export_csr(const aux_handle *h, int which, int level, int64_t *shape, in
 int aux_export_cf(const aux_handle *h, int level, int32_t *cf)
 {
     return guarded([&]() {
+        if (h && h->host_hier_stale) {
+            set_dev(h);
+            const_cast<aux_handle *>(h)->ensure_host_hierarchy();
+        }
         if (!h || !cf || level < 0 || level + 1 >= (int)h->hier.levels.size())
             throw AuxError(AUX_EINVAL, "no splitting on this level");
         const auto &v = h->hier.levels[level].cf;

@@ -33,6 +33,11 @@ CASES = [
     ("p2_n12_no_dense", 2, 12, 0.0, None, dict(dense_cycle_rows=0)),
     ("p2_n10_unfused", 2, 10, 0.2, None, dict(fuse_cycle=False)),
     ("p2_n9_two_levels", 2, 9, 0.2, "rand", dict(max_levels=2)),
+    # theta = 0.1: dense coarse levels whose composite-operator products have
+    # rows of up to 13,480 products (several sorted runs merged in the
+    # workspace); the theta = 0.25 and no-dense cases have rows of 2,550 and
+    # 4,146 (one run, two runs)
+    ("p2_n16_theta01", 2, 16, 0.2, None, dict(theta=0.1)),
 ]
 
 

@@ -67,6 +67,38 @@ def test_set_kappa_equals_new_setup(k, n):
         assert torch.equal(a.apply(r), b.apply(r))
 
 
+@pytest.mark.parametrize("lanes", [4, -8])
+def test_set_kappa_forced_storage(lanes):
+    """The V-cycle's level operators in a forced storage (row-split ELL with
+    4 lanes per row, built again on the device from the new device-built
+    operators; or CSR with 8 lanes), no dense sub-cycle: the update equals a
+    new setup bitwise (composite operators, applications in both
+    precisions, CG)."""
+    print(f"[set_kappa forced storage {lanes}]", flush=True)
+    xyz, tets = W.kuhn_mesh(10, jitter=0.2, seed=0)
+    k1, k2 = _kappas(xyz, tets, (1, 2))
+    kw = dict(device=DEV, sell_window=1 << 30, cycle_lanes=lanes, coarse_max=20, dense_cycle_rows=0)
+    a = aux.Solver(xyz, tets, 2, k1, **kw)
+    a.set_kappa(k2)
+    b = aux.Solver(xyz, tets, 2, k2, **kw)
+    assert a.info.levels == b.info.levels >= 3
+    assert list(a.info.level_nnz_up[:a.info.levels]) == list(b.info.level_nnz_up[:b.info.levels])
+    for l in range(a.info.levels - 1):
+        for which in ("down", "up"):
+            ma, mb = a.export_csr(which, l), b.export_csr(which, l)
+            assert np.array_equal(ma.indptr, mb.indptr) and np.array_equal(ma.indices, mb.indices)
+            assert np.array_equal(ma.data, mb.data), (which, l)
+    r = _t(W.random_vector(a.n, 5))
+    for prec in ("fp64", "mixed"):
+        a.set_precision(prec)
+        b.set_precision(prec)
+        assert torch.equal(a.apply(r), b.apply(r)), prec
+    f = _t(W.random_vector(a.n, 6))
+    ua, ia = a.solve(f, tol=1e-9)
+    ub, ib = b.solve(f, tol=1e-9)
+    assert ia.iterations == ib.iterations and torch.equal(ua, ub)
+
+
 def test_set_kappa_against_oracle_and_forms():
     print("[set_kappa against the oracle]", flush=True)
     xyz, tets = W.kuhn_mesh(8, jitter=0.2, seed=1)
