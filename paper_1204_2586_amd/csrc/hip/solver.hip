@@ -374,11 +374,12 @@ struct aux_handle {
         device_bytes += (int64_t)bytes;
         return ptr;
     }
-    void dfree(void *ptr)
+    // (wait: first wait for the stream, which may still use the buffer)
+    void dfree(void *ptr, bool wait = true)
     {
         for (size_t i = 0; i < allocs.size(); i++)
             if (allocs[i] == ptr) {
-                HIPCHECK(hipStreamSynchronize(stream));
+                if (wait) HIPCHECK(hipStreamSynchronize(stream));
                 if (dev.free) dev.free(ptr, dev.ctx);
                 else HIPCHECK(hipFree(ptr));
                 device_bytes -= (int64_t)alloc_size[i];
@@ -884,18 +885,29 @@ struct aux_handle {
     // cycle stays on the device for upload_coefficient_part.
     // With adopt, the device arrays are kept for upload_coefficient_part to
     // take over and nothing is copied to the host.
+    // The build's workspaces are released together at its end: a release
+    // waits for the stream (the allocator need not be stream-ordered), and
+    // one wait instead of one per workspace keeps the device busy.
     void device_hierarchy(const DCsr &AH, bool adopt = false)
     {
         auto t0 = std::chrono::steady_clock::now();
-        DevMem mem{[this](size_t b) { return dalloc(b); }, [this](void *p) { dfree(p); }};
+        std::vector<void *> spent;
+        DevMem mem{[this](size_t b) { return dalloc(b); }, [&spent](void *p) { spent.push_back(p); }};
+        auto release_spent = [&]() {
+            if (!spent.empty()) HIPCHECK(hipStreamSynchronize(stream));
+            for (void *p : spent) dfree(p, false);
+            spent.clear();
+        };
         DevAmg d;
         try {
             device_amg(stream, AH, amg_options(), opt.fuse_cycle != 0, opt.dense_cycle_rows, mem, d);
+            release_spent();
             hier = Hierarchy();
             fused_host.clear();
             if (!adopt) download_amg(stream, d, hier, opt.fuse_cycle ? &fused_host : nullptr);
         } catch (...) {
             free_amg(mem, d);
+            release_spent();
             throw;
         }
         dfree(dense_pre);
@@ -908,6 +920,7 @@ struct aux_handle {
             dev_built_ready = true;
         } else {
             free_amg(mem, d);
+            release_spent();
         }
         amg_seconds = seconds_since(t0);
     }
