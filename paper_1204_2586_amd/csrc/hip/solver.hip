@@ -2742,6 +2742,11 @@ struct aux_handle {
         }
         lev.clear();
         host_hier_stale = false;
+        if (dev_built_ready) {                     // a build never taken over (an error in between)
+            DevMem mem{[this](size_t b) { return dalloc(b); }, [this](void *p) { dfree(p); }};
+            free_amg(mem, dev_built);
+            dev_built_ready = false;
+        }
         for (void *b : {(void *)cinv64, (void *)cinv32, (void *)dcyc64, (void *)dcyc32}) dfree(b);
         cinv64 = dcyc64 = nullptr;
         cinv32 = dcyc32 = nullptr;
