@@ -240,7 +240,10 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
  * extended+i, Galerkin products), the composite level operators and the
  * dense cycle are built on the device from the device A_H (amg_setup = 1;
  * on the host from a copy with amg_setup = 0, bitwise the same), and the
- * coefficient-dependent device data are rebuilt.  The dof numbering, patterns, layouts,
+ * coefficient-dependent device data are rebuilt.  With amg_setup = 1 the
+ * device-built operators are used where they are; their host copies (read by
+ * aux_export_csr, aux_export_cf and the batched and block solves) are made
+ * on first use.  The dof numbering, patterns, layouts,
  * I_P and tet metrics are kept.  The first call also builds the mesh-only
  * assembly maps (each entry's list of element-matrix contributions, about
  * nnz(A_h) * 3 int32 of device memory).  aux_info.setup_seconds then reports
