@@ -429,18 +429,6 @@ struct aux_handle {
         op.ell_stored = 0;
     }
 
-    void set_ell(DevOp &op, const Csr &c, int lanes)
-    {
-        drop_ell(op);
-        Ell e;
-        build_ell(c, lanes, e);
-        op.ell_off = upload(e.slice_off);
-        op.ell_col = upload(e.col);
-        op.ell_v64 = upload(e.val);
-        op.ell_v32 = upload(to_f32(e.val));
-        op.ell_stored = (int64_t)e.val.size();
-        op.ell_lanes = lanes;
-    }
 
     // Storage and lanes of one V-cycle operator: time one FP32 product
     // (two-source form when split > 0) for each candidate, CSR with 2-32
@@ -448,12 +436,12 @@ struct aux_handle {
     // fastest.  In the solve the operator's data has been evicted by the P^k
     // passes, so each timed launch follows a write of `flush` bytes that
     // clears the caches.  (T = double: the same for an FP64-only operator.)
-    void tune_op(DevOp &op, const Csr &host, int split, void *flush, size_t flush_bytes)
+    void tune_op(DevOp &op, int split, void *flush, size_t flush_bytes)
     {
-        tune_op_t<float>(op, host, split, flush, flush_bytes);
+        tune_op_t<float>(op, split, flush, flush_bytes);
     }
     template <typename T>
-    void tune_op_t(DevOp &op, const Csr &host, int split, void *flush, size_t flush_bytes)
+    void tune_op_t(DevOp &op, int split, void *flush, size_t flush_bytes)
     {
         if (!(std::is_same<T, float>::value ? (void *)op.v32 : (void *)op.v64) || op.n == 0) return;
         T *x = dnew<T>(std::max(op.m, 1)), *y = dnew<T>(op.n);
@@ -494,14 +482,14 @@ struct aux_handle {
         op.lpr = pick;
         for (int lanes : {1, 2, 4, 8, 16, 32}) {
             if (lanes > 4 * avg + 4) break;
-            set_ell(op, host, lanes);
+            set_ell(op, lanes);
             const double t = measure();
             if (t < best) {
                 best = t;
                 pick_ell = lanes;
             }
         }
-        if (pick_ell > 0) set_ell(op, host, pick_ell);
+        if (pick_ell > 0) set_ell(op, pick_ell);
         else drop_ell(op);
         ev_used -= 2;
         dfree(x);
@@ -646,19 +634,19 @@ struct aux_handle {
     }
 
     // Storage of one operator by lanes code (> 0: row-split ELL with that
-    // many lanes per row, built from the host copy if given, else from the
-    // operator's own device CSR; <= 0: CSR with -code lanes per row)
-    void set_storage(DevOp &op, const Csr *host, int code)
+    // many lanes per row; <= 0: CSR with -code lanes per row)
+    void set_storage(DevOp &op, int code)
     {
         if (code > 0) {
-            if (host) set_ell(op, *host, code);
-            else set_ell_dev(op, code);
+            set_ell(op, code);
         } else {
             drop_ell(op);
             op.lpr = -code;
         }
     }
-    void set_ell_dev(DevOp &op, int lanes)
+    // the row-split ELL copy of an operator, built on the device from its
+    // FP64 CSR (FP32 values the rounding of the FP64 ones)
+    void set_ell(DevOp &op, int lanes)
     {
         drop_ell(op);
         DevMem mem{[this](size_t b) { return dalloc(b); }, [this](void *p) { dfree(p); }};
@@ -837,31 +825,31 @@ struct aux_handle {
             if (opt.cycle_lanes != 0) {                // one storage for all of them
                 const int code = opt.cycle_lanes;
                 if (first) {
-                    set_storage(RF, &RF_host, code);
-                    set_storage(IP, &IPi, code);
+                    set_storage(RF, code);
+                    set_storage(IP, code);
                 }
                 for (size_t l = 0; l + 1 < lev.size(); l++) {
-                    set_storage(lev[l].down, adopted ? nullptr : &fused_host[l].down, code);
-                    set_storage(lev[l].up, adopted ? nullptr : &fused_host[l].up, code);
+                    set_storage(lev[l].down, code);
+                    set_storage(lev[l].up, code);
                 }
             } else if (opt.sell_window <= 0 && first) {
                 const size_t fb = (size_t)512 << 20;    // twice the last-level cache
                 void *flush = dalloc(fb);
-                tune_op(RF, RF_host, disc.ndof, flush, fb);
-                tune_op(IP, IPi, 0, flush, fb);
+                tune_op(RF, disc.ndof, flush, fb);
+                tune_op(IP, 0, flush, fb);
                 tuned_lanes.clear();
                 for (size_t l = 0; l + 1 < lev.size(); l++) {
                     if (lev[l].A.n < 8192) break;
-                    tune_op(lev[l].down, fused_host[l].down, 0, flush, fb);
-                    tune_op(lev[l].up, fused_host[l].up, lev[l].A.n, flush, fb);
+                    tune_op(lev[l].down, 0, flush, fb);
+                    tune_op(lev[l].up, lev[l].A.n, flush, fb);
                     tuned_lanes.push_back({lev[l].down.lanes_code(), lev[l].up.lanes_code()});
                 }
                 dfree(flush);
             } else if (opt.sell_window <= 0) {
                 for (size_t l = 0; l + 1 < lev.size() && l < tuned_lanes.size(); l++) {
                     if (lev[l].A.n < 8192) break;
-                    set_storage(lev[l].down, adopted ? nullptr : &fused_host[l].down, tuned_lanes[l][0]);
-                    set_storage(lev[l].up, adopted ? nullptr : &fused_host[l].up, tuned_lanes[l][1]);
+                    set_storage(lev[l].down, tuned_lanes[l][0]);
+                    set_storage(lev[l].up, tuned_lanes[l][1]);
                 }
             }
         }
@@ -1701,8 +1689,8 @@ struct aux_handle {
         if (opt.sell_window <= 0) {
             const size_t fb = (size_t)512 << 20;
             void *flush = dalloc(fb);
-            tune_op_t<double>(sk.Bi, Bi, 0, flush, fb);
-            tune_op_t<double>(sk.BTi, BTi, 0, flush, fb);
+            tune_op_t<double>(sk.Bi, 0, flush, fb);
+            tune_op_t<double>(sk.BTi, 0, flush, fb);
             dfree(flush);
         }
         std::vector<double> dinv(np, 0.0);
