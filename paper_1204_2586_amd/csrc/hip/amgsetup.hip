@@ -378,6 +378,31 @@ __global__ __launch_bounds__(kB) void k_diag(int n, const int *__restrict__ ptr,
 }
 
 // workspace bound of an F row: |S_i| + sum over strong F neighbours j of |S_j|
+// Exclusive prefix sum of v over a workgroup of kB threads (every thread
+// calls it); total receives the sum over the workgroup.
+__device__ __forceinline__ int block_scan(int v, int *wsum, int &total)
+{
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kB / 64; q++) {
+        const int t = wsum[q];
+        if (q < w) pre += t;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + x - v;
+}
+
 __global__ __launch_bounds__(kB) void k_exti_bound(int n, const int *__restrict__ sptr, const int *__restrict__ scol,
                                                    const int *__restrict__ cf, long long *__restrict__ ub)
 {
@@ -406,6 +431,13 @@ __device__ __forceinline__ int find_sorted(const int *h, int len, int c)
     return lo < len && h[lo] == c ? lo : -1;
 }
 
+// F rows whose candidate set (at most kExtiCand entries counted with
+// repeats) and row of A (at most kExtiRow entries) fit the LDS of
+// k_exti_rows_wg; the others go to k_exti_rows
+constexpr int kExtiCand = 4096, kExtiRow = 512;
+
+__device__ __forceinline__ bool exti_wg_row(long long ub, int na) { return ub <= kExtiCand && na <= kExtiRow; }
+
 // Interpolation row of each F point: the set hat C_i of C points in S_i and
 // in S_j for strong F neighbours j (kept sorted), its weights -w_j / d_ii
 // with a_ij on hat C_i added to w_j, each strong F neighbour's a_ij spread
@@ -427,6 +459,7 @@ __global__ __launch_bounds__(kB) void k_exti_rows(int n, const int *__restrict__
         cnt[i] = 1;
         return;
     }
+    if (exti_wg_row(woff[i + 1] - woff[i], ptr[i + 1] - ptr[i])) return;   // k_exti_rows_wg's
     int *hat = hcol + woff[i];
     double *w = hw + woff[i];
     int h = 0;
@@ -486,6 +519,157 @@ __global__ __launch_bounds__(kB) void k_exti_rows(int n, const int *__restrict__
     }
     for (int q = 0; q < h; q++) w[q] = -w[q] / dii;
     cnt[i] = h;
+}
+
+// The rows of k_exti_rows that fit its LDS, one workgroup per F row, with
+// every sum in the same order.  The candidates (C points of S_i and of S_j
+// for strong F neighbours j) are sorted in LDS and made unique: hat C_i.
+// Each entry of A's row is classified (a point of hat C_i, lumped onto the
+// diagonal, or a strong F neighbour spread with scale a_ij / den, den
+// summed over row j in order by the entry's thread); then each thread owns
+// one weight (or d_ii) and walks all entries and their spread rows in the
+// host's order, adding only its own contributions, so each weight receives
+// exactly the host's sequence of additions.
+__global__ __launch_bounds__(kB) void k_exti_rows_wg(int n, const int *__restrict__ ptr, const int *__restrict__ col,
+                                                     const double *__restrict__ val,
+                                                     const unsigned char *__restrict__ strong,
+                                                     const int *__restrict__ sptr, const int *__restrict__ scol,
+                                                     const int *__restrict__ cf, const double *__restrict__ diag,
+                                                     const long long *__restrict__ woff, int *__restrict__ hcol,
+                                                     double *__restrict__ hw, int *__restrict__ cnt)
+{
+#pragma clang fp contract(off)
+    __shared__ int cand[kExtiCand];
+    __shared__ int hat[kExtiCand];
+    __shared__ int kind[kExtiRow];                 // >= 0 hat position, -1 diagonal, -2 lumped, -3 spread
+    __shared__ double escale[kExtiRow];
+    __shared__ int wsum[kB / 64];
+    __shared__ double dii_sh;
+    const int i = blockIdx.x;
+    if (i >= n || cf[i] > 0) return;
+    const long long ub = woff[i + 1] - woff[i];
+    const int a0 = ptr[i], na = ptr[i + 1] - a0;
+    if (!exti_wg_row(ub, na)) return;              // a row of k_exti_rows
+    const int t = threadIdx.x;
+    // candidates, non-C entries of the S_j as INT_MAX
+    const int s0 = sptr[i], ns = sptr[i + 1] - s0;
+    int m = 0;
+    for (int e0 = 0; e0 < ns; e0 += kB) {
+        const int e = e0 + t;
+        int j = 0, len = 0;
+        if (e < ns) {
+            j = scol[s0 + e];
+            len = cf[j] > 0 ? 1 : sptr[j + 1] - sptr[j];
+        }
+        int tot;
+        const int off = m + block_scan(len, wsum, tot);
+        if (e < ns) {
+            if (cf[j] > 0) {
+                cand[off] = j;
+            } else {
+                for (int f = 0; f < len; f++) {
+                    const int l = scol[sptr[j] + f];
+                    cand[off + f] = cf[l] > 0 ? l : INT_MAX;
+                }
+            }
+        }
+        m += tot;
+    }
+    int np2 = 1;
+    while (np2 < m) np2 <<= 1;
+    for (int q = m + t; q < np2; q += kB) cand[q] = INT_MAX;
+    __syncthreads();
+    for (int kk = 2; kk <= np2; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int q = t; q < np2 / 2; q += kB) {
+                const int i1 = 2 * j * (q / j) + (q % j), i2 = i1 + j;
+                const bool up = (i1 & kk) == 0;
+                const int x = cand[i1], y = cand[i2];
+                if ((x > y) == up) {
+                    cand[i1] = y;
+                    cand[i2] = x;
+                }
+            }
+            __syncthreads();
+        }
+    int h = 0;
+    for (int q0 = 0; q0 < m; q0 += kB) {
+        const int q = q0 + t;
+        const int head = q < m && cand[q] != INT_MAX && (q == 0 || cand[q - 1] != cand[q]) ? 1 : 0;
+        int tot;
+        const int r = h + block_scan(head, wsum, tot);
+        if (head) hat[r] = cand[q];
+        h += tot;
+    }
+    __syncthreads();
+    // the entries of row i
+    for (int e = t; e < na; e += kB) {
+        const int j = col[a0 + e];
+        int k = -1;
+        if (j != i) {
+            const int pj = find_sorted(hat, h, j);
+            if (pj >= 0) {
+                k = pj;
+            } else if (strong[a0 + e] && cf[j] <= 0) {
+                const double dj = diag[j];
+                double den = 0.0;
+                for (int f = ptr[j]; f < ptr[j + 1]; f++) {
+                    const int l = col[f];
+                    if ((l == i || find_sorted(hat, h, l) >= 0) && val[f] * dj < 0.0) den += val[f];
+                }
+                if (den == 0.0) {
+                    k = -2;
+                } else {
+                    k = -3;
+                    escale[e] = val[a0 + e] / den;
+                }
+            } else {
+                k = -2;
+            }
+        }
+        kind[e] = k;
+    }
+    __syncthreads();
+    // thread t of a pass owns weight q0 + t (q == h: d_ii)
+    int *hc = hcol + woff[i];
+    double *w = hw + woff[i];
+    for (int q0 = 0; q0 <= h; q0 += kB) {
+        const int q = q0 + t;
+        const int mine = q < h ? hat[q] : -1;
+        double acc = q == h ? diag[i] : 0.0;
+        for (int e = 0; e < na; e++) {
+            const int k = kind[e];
+            if (k == -1) continue;
+            if (k >= 0) {
+                if (q == k) acc += val[a0 + e];
+            } else if (k == -2) {
+                if (q == h) acc += val[a0 + e];
+            } else {
+                const int j = col[a0 + e];
+                const double dj = diag[j], sc = escale[e];
+                for (int f = ptr[j]; f < ptr[j + 1]; f++) {
+                    const double vf = val[f];
+                    if (vf * dj >= 0.0) continue;
+                    const int l = col[f];
+                    if (l == i) {
+                        if (q == h) acc += sc * vf;
+                    } else if (l == mine) {
+                        acc += sc * vf;
+                    }
+                }
+            }
+        }
+        if (q < h) {
+            hc[q] = mine;
+            w[q] = acc;
+        } else if (q == h) {
+            dii_sh = acc;
+        }
+    }
+    __syncthreads();
+    const double dii = dii_sh;
+    for (int q = t; q < h; q += kB) w[q] = -w[q] / dii;
+    if (t == 0) cnt[i] = h;
 }
 
 __global__ __launch_bounds__(kB) void k_exti_write(int n, const int *__restrict__ cf, const int *__restrict__ cnum,
@@ -628,31 +812,6 @@ __global__ __launch_bounds__(kB) void k_long_rows(int n, const int *__restrict__
     if (i >= n) return;
     const long long ub = woff[i + 1] - woff[i];
     hub[i] = wave_row(ub, aptr[i + 1] - aptr[i]) ? 0 : ub;
-}
-
-// Exclusive prefix sum of v over a workgroup of kB threads (every thread
-// calls it); total receives the sum over the workgroup.
-__device__ __forceinline__ int block_scan(int v, int *wsum, int &total)
-{
-    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[w] = x;
-    __syncthreads();
-    int pre = 0, tot = 0;
-#pragma unroll
-    for (int q = 0; q < kB / 64; q++) {
-        const int t = wsum[q];
-        if (q < w) pre += t;
-        tot += t;
-    }
-    __syncthreads();
-    total = tot;
-    return pre + x - v;
 }
 
 // keys sorted in LDS at once by k_product_rows_long
@@ -1217,6 +1376,8 @@ void device_amg(hipStream_t s, const DCsr &AH, const SetupOptions &opt, bool fus
         int *hcol = dnew<int>(mem, (size_t)wtot), *pcnt = dnew<int>(mem, (size_t)n);
         double *hw = dnew<double>(mem, (size_t)wtot);
         hipLaunchKernelGGL(k_exti_rows, dim3(rows_grid(n)), dim3(kB), 0, s, n, A.ptr, A.col, A.val, strong, S.ptr,
+                           S.col, cf, diag, woff, hcol, hw, pcnt);
+        hipLaunchKernelGGL(k_exti_rows_wg, dim3(std::max(n, 1)), dim3(kB), 0, s, n, A.ptr, A.col, A.val, strong, S.ptr,
                            S.col, cf, diag, woff, hcol, hw, pcnt);
         DCsr P;
         P.n = n;
