@@ -235,12 +235,53 @@ __global__ __launch_bounds__(kB) void k_scatter_transpose(int n, const int *__re
 }
 
 // each row sorted by column (columns distinct within a row; val may be null)
+// rows of at most kSortWave entries: k_sort_rows_wave; longer: k_sort_rows
+constexpr int kSortWave = 1024;
+
+// Row i sorted by column (columns distinct) by one wavefront: keys (column
+// << 32 | position) sorted in LDS (bitonic), values moved with them.
+__global__ __launch_bounds__(64) void k_sort_rows_wave(int n, const int *__restrict__ ptr, int *__restrict__ col,
+                                                       double *__restrict__ val)
+{
+    __shared__ unsigned long long keys[kSortWave];
+    __shared__ double vs[kSortWave];
+    const int i = blockIdx.x, lane = threadIdx.x;
+    if (i >= n) return;
+    const int b = ptr[i], d = ptr[i + 1] - b;
+    if (d < 2 || d > kSortWave) return;
+    int np2 = 1;
+    while (np2 < d) np2 <<= 1;
+    for (int q = lane; q < np2; q += 64) {
+        keys[q] = q < d ? ((unsigned long long)(unsigned)col[b + q] << 32) | (unsigned)q : ~0ULL;
+        if (val && q < d) vs[q] = val[b + q];
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= np2; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < np2 / 2; t += 64) {
+                const int i1 = 2 * j * (t / j) + (t % j), i2 = i1 + j;
+                const bool up = (i1 & kk) == 0;
+                const unsigned long long x = keys[i1], y = keys[i2];
+                if ((x > y) == up) {
+                    keys[i1] = y;
+                    keys[i2] = x;
+                }
+            }
+            __syncthreads();
+        }
+    for (int q = lane; q < d; q += 64) {
+        col[b + q] = (int)(keys[q] >> 32);
+        if (val) val[b + q] = vs[(unsigned)keys[q]];
+    }
+}
+
 __global__ __launch_bounds__(kB) void k_sort_rows(int n, const int *__restrict__ ptr, int *__restrict__ col,
                                                   double *__restrict__ val)
 {
     const int i = blockIdx.x * kB + threadIdx.x;
     if (i >= n) return;
     const int b = ptr[i], e = ptr[i + 1];
+    if (e - b <= kSortWave) return;                // k_sort_rows_wave's
     for (int p = b + 1; p < e; p++) {
         const int c = col[p];
         const double v = val ? val[p] : 0.0;
@@ -273,7 +314,10 @@ DCsr transpose(hipStream_t s, const DCsr &A, bool values, bool sorted_rows, DevM
     T.val = values ? dnew<double>(mem, (size_t)A.nnz) : nullptr;
     hipLaunchKernelGGL(k_scatter_transpose, dim3(rows_grid(A.n)), dim3(kB), 0, s, A.n, A.ptr, A.col,
                        values ? A.val : nullptr, T.ptr, cnt, T.col, T.val);
-    if (sorted_rows) hipLaunchKernelGGL(k_sort_rows, dim3(rows_grid(T.n)), dim3(kB), 0, s, T.n, T.ptr, T.col, T.val);
+    if (sorted_rows && T.n > 0) {
+        hipLaunchKernelGGL(k_sort_rows_wave, dim3(T.n), dim3(64), 0, s, T.n, T.ptr, T.col, T.val);
+        hipLaunchKernelGGL(k_sort_rows, dim3(rows_grid(T.n)), dim3(kB), 0, s, T.n, T.ptr, T.col, T.val);
+    }
     AMG_CHECK(hipGetLastError());
     dfree(mem, cnt);
     return T;
@@ -933,17 +977,22 @@ __global__ __launch_bounds__(kB) void k_product_rows_long(
     if (threadIdx.x == 0) cnt[i] = ncols;
 }
 
+// lanes per row of the row-wise copy and scaling passes
+constexpr int kRowLanes = 16;
+
 __global__ __launch_bounds__(kB) void k_compact_rows(int n, const long long *__restrict__ woff,
                                                      const int *__restrict__ ocol, const double *__restrict__ oacc,
                                                      const int *__restrict__ cptr, int *__restrict__ ccol,
                                                      double *__restrict__ cval)
 {
-    const int i = blockIdx.x * kB + threadIdx.x;
+    const long long g = (long long)blockIdx.x * kB + threadIdx.x;
+    const int i = (int)(g / kRowLanes), sub = (int)(g % kRowLanes);
     if (i >= n) return;
     const int p = cptr[i], d = cptr[i + 1] - p;
-    for (int q = 0; q < d; q++) {
-        ccol[p + q] = ocol[woff[i] + q];
-        cval[p + q] = oacc[woff[i] + q];
+    const long long w0 = woff[i];
+    for (int q = sub; q < d; q += kRowLanes) {
+        ccol[p + q] = ocol[w0 + q];
+        cval[p + q] = oacc[w0 + q];
     }
 }
 
@@ -981,7 +1030,7 @@ DCsr product(hipStream_t s, const DCsr &A, const DCsr &B, bool zero_init, DevMem
     C.nnz = checked_int(scan(s, A.n, cnt, C.ptr, mem), "product entries");
     C.col = dnew<int>(mem, (size_t)C.nnz);
     C.val = dnew<double>(mem, (size_t)C.nnz);
-    hipLaunchKernelGGL(k_compact_rows, dim3(rows_grid(A.n)), dim3(kB), 0, s, A.n, woff, ocol, oacc, C.ptr, C.col,
+    hipLaunchKernelGGL(k_compact_rows, dim3(rows_grid((long long)A.n * kRowLanes)), dim3(kB), 0, s, A.n, woff, ocol, oacc, C.ptr, C.col,
                        C.val);
     AMG_CHECK(hipGetLastError());
     for (void *p : {(void *)ocol, (void *)oacc, (void *)cnt, (void *)woff}) dfree(mem, p);
@@ -996,9 +1045,10 @@ __global__ __launch_bounds__(kB) void k_scale(int n, const int *__restrict__ ptr
                                               const double *__restrict__ right)
 {
 #pragma clang fp contract(off)
-    const int i = blockIdx.x * kB + threadIdx.x;
+    const long long g = (long long)blockIdx.x * kB + threadIdx.x;
+    const int i = (int)(g / kRowLanes), sub = (int)(g % kRowLanes);
     if (i >= n) return;
-    for (int e = ptr[i]; e < ptr[i + 1]; e++) {
+    for (int e = ptr[i] + sub; e < ptr[i + 1]; e += kRowLanes) {
         double v = val[e];
         if (left) v *= left[i];
         if (right) v *= right[col[e]];
@@ -1130,16 +1180,16 @@ void fuse_level_dev(hipStream_t s, const DCsr &A, const DCsr &P, const DCsr &R, 
     D.val = two;
     hipLaunchKernelGGL(k_recip, dim3(rows_grid(n + 1)), dim3(kB), 0, s, n, l1, dinv, two, D.ptr, D.col);
     DCsr RA = product(s, R, A, true, mem);
-    hipLaunchKernelGGL(k_scale, dim3(rows_grid(RA.n)), dim3(kB), 0, s, RA.n, RA.ptr, RA.col, RA.val, nullptr, dinv);
+    hipLaunchKernelGGL(k_scale, dim3(rows_grid((long long)RA.n * kRowLanes)), dim3(kB), 0, s, RA.n, RA.ptr, RA.col, RA.val, nullptr, dinv);
     down = combine(s, 1.0, R, -1.0, RA, mem);
     free_csr(mem, RA);
     DCsr SA = copy_csr(s, A, mem);
-    hipLaunchKernelGGL(k_scale, dim3(rows_grid(n)), dim3(kB), 0, s, n, SA.ptr, SA.col, SA.val, dinv, dinv);
+    hipLaunchKernelGGL(k_scale, dim3(rows_grid((long long)n * kRowLanes)), dim3(kB), 0, s, n, SA.ptr, SA.col, SA.val, dinv, dinv);
     DCsr N = combine(s, 1.0, D, -1.0, SA, mem);
     free_csr(mem, SA);
     free_csr(mem, D);                                  // frees two as D.val
     DCsr AP = product(s, A, P, true, mem);
-    hipLaunchKernelGGL(k_scale, dim3(rows_grid(n)), dim3(kB), 0, s, n, AP.ptr, AP.col, AP.val, dinv, nullptr);
+    hipLaunchKernelGGL(k_scale, dim3(rows_grid((long long)n * kRowLanes)), dim3(kB), 0, s, n, AP.ptr, AP.col, AP.val, dinv, nullptr);
     DCsr Q = combine(s, 1.0, P, -1.0, AP, mem);
     free_csr(mem, AP);
     up.n = n;
