@@ -748,11 +748,20 @@ __global__ __launch_bounds__(kB) void k_product_bound(int n, const int *__restri
     ub[i] = b;
 }
 
-// rows whose products fit one wavefront's LDS (at most kWaveProducts
-// products from at most kWaveEntries entries of A) go to k_product_rows_wave
+// Rows of a product by size: at most kSmallProducts products from at most
+// kSmallEntries entries of A (0), at most kWaveProducts from kWaveEntries
+// (1), both k_product_rows_wave with LDS of that size; longer rows (2)
+// k_product_rows_long.  The small form's LDS lets many more rows be in
+// flight per compute unit.
+constexpr int kSmallProducts = 256, kSmallEntries = 64;
 constexpr int kWaveProducts = 2048, kWaveEntries = 256;
 
-__device__ __forceinline__ bool wave_row(long long ub, int na) { return ub <= kWaveProducts && na <= kWaveEntries; }
+__device__ __forceinline__ int product_form(long long ub, int na)
+{
+    if (ub <= kSmallProducts && na <= kSmallEntries) return 0;
+    return ub <= kWaveProducts && na <= kWaveEntries ? 1 : 2;
+}
+__device__ __forceinline__ bool wave_row(long long ub, int na) { return product_form(ub, na) < 2; }
 
 // Row i of C = A B, one wavefront: the row's products a_ik b_kj are laid
 // out in LDS in the order of A's row, then of B's rows (their sequence
@@ -763,6 +772,7 @@ __device__ __forceinline__ bool wave_row(long long ub, int na) { return ub <= kW
 // otherwise, as the Galerkin product does).  The same sums in the same order
 // as the host's row accumulator.  The sorted row goes to the workspace at
 // woff[i].
+template <int CAP, int EC>
 __global__ __launch_bounds__(64) void k_product_rows_wave(int n, const int *__restrict__ aptr,
                                                           const int *__restrict__ acol, const double *__restrict__ aval,
                                                           const int *__restrict__ bptr, const int *__restrict__ bcol,
@@ -771,27 +781,37 @@ __global__ __launch_bounds__(64) void k_product_rows_wave(int n, const int *__re
                                                           double *__restrict__ oacc, int *__restrict__ cnt, int zero_init)
 {
 #pragma clang fp contract(off)
-    __shared__ unsigned long long keys[kWaveProducts];
-    __shared__ double vals[kWaveProducts];
-    __shared__ int off[kWaveEntries + 1];
+    __shared__ unsigned long long keys[CAP];
+    __shared__ double vals[CAP];
+    __shared__ int off[EC + 1];
     const int i = blockIdx.x, lane = threadIdx.x;
     if (i >= n) return;
     const int a0 = aptr[i], na = aptr[i + 1] - a0;
     const long long ub = woff[i + 1] - woff[i];
-    if (!wave_row(ub, na)) return;                 // a row of k_product_rows_long
+    if (product_form(ub, na) != (CAP == kSmallProducts ? 0 : 1)) return;   // another form's row
     if (ub == 0) {
         if (lane == 0) cnt[i] = 0;
         return;
     }
-    if (lane == 0) {
-        int o = 0;
-        for (int e = 0; e < na; e++) {
-            off[e] = o;
+    // first product of each entry of A's row: a prefix sum over the wavefront
+    int o = 0;
+    for (int e0 = 0; e0 < na; e0 += 64) {
+        const int e = e0 + lane;
+        int len = 0;
+        if (e < na) {
             const int k = acol[a0 + e];
-            o += bptr[k + 1] - bptr[k];
+            len = bptr[k + 1] - bptr[k];
         }
-        off[na] = o;
+        int x = len;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        if (e < na) off[e] = o + x - len;
+        o += __shfl(x, 63, 64);
     }
+    if (lane == 0) off[na] = o;
     __syncthreads();
     const int m = (int)ub;
     int np2 = 1;
@@ -1019,9 +1039,12 @@ DCsr product(hipStream_t s, const DCsr &A, const DCsr &B, bool zero_init, DevMem
     int *ocol = dnew<int>(mem, (size_t)total);
     double *oacc = dnew<double>(mem, (size_t)total);
     int *cnt = dnew<int>(mem, (size_t)A.n);
-    if (A.n > 0)
-        hipLaunchKernelGGL(k_product_rows_wave, dim3(A.n), dim3(64), 0, s, A.n, A.ptr, A.col, A.val, B.ptr, B.col,
-                           B.val, woff, ocol, oacc, cnt, zero_init ? 1 : 0);
+    if (A.n > 0) {
+        hipLaunchKernelGGL((k_product_rows_wave<kSmallProducts, kSmallEntries>), dim3(A.n), dim3(64), 0, s, A.n, A.ptr,
+                           A.col, A.val, B.ptr, B.col, B.val, woff, ocol, oacc, cnt, zero_init ? 1 : 0);
+        hipLaunchKernelGGL((k_product_rows_wave<kWaveProducts, kWaveEntries>), dim3(A.n), dim3(64), 0, s, A.n, A.ptr,
+                           A.col, A.val, B.ptr, B.col, B.val, woff, ocol, oacc, cnt, zero_init ? 1 : 0);
+    }
     if (htotal > 0)
         hipLaunchKernelGGL(k_product_rows_long, dim3(A.n), dim3(kB), 0, s, A.n, A.ptr, A.col, A.val, B.ptr, B.col,
                            B.val, woff, hoff, keya, keyb, pval, ocol, oacc, cnt, zero_init ? 1 : 0);
@@ -1349,10 +1372,11 @@ __global__ __launch_bounds__(kB) void k_ell_fill(int n, int rows, int lanes, con
                                                  const int *__restrict__ off, int *__restrict__ ecol,
                                                  double *__restrict__ eval)
 {
-    const int i = blockIdx.x * kB + threadIdx.x;
+    const long long g = (long long)blockIdx.x * kB + threadIdx.x;
+    const int i = (int)(g / kRowLanes), sub = (int)(g % kRowLanes);
     if (i >= n) return;
     const int s = i / rows, q = i % rows;
-    for (int e = ptr[i], k = 0; e < ptr[i + 1]; e++, k++) {
+    for (int e = ptr[i] + sub, k = sub; e < ptr[i + 1]; e += kRowLanes, k += kRowLanes) {
         const size_t at = (size_t)off[s] + (size_t)(k / lanes) * 64 + q * lanes + k % lanes;
         ecol[at] = col[e];
         eval[at] = val[e];
@@ -1588,7 +1612,7 @@ void ell_from_csr(hipStream_t s, const DCsr &A, int lanes, DevMem &mem, DevEll &
         AMG_CHECK(hipMemsetAsync(out.val, 0, sizeof(double) * (size_t)out.stored, s));
     }
     if (A.n > 0)
-        hipLaunchKernelGGL(k_ell_fill, dim3(rows_grid(A.n)), dim3(kB), 0, s, A.n, rows, lanes, A.ptr, A.col, A.val,
+        hipLaunchKernelGGL(k_ell_fill, dim3(rows_grid((long long)A.n * kRowLanes)), dim3(kB), 0, s, A.n, rows, lanes, A.ptr, A.col, A.val,
                            out.off, out.col, out.val);
     AMG_CHECK(hipGetLastError());
 }
