@@ -8,8 +8,12 @@
 // Every step repeats the host setup's definitions and its arithmetic in its
 // order, with contraction into fused multiply-adds off, so that the device
 // hierarchy is bitwise the host one (identical C/F splits on every level):
-//  * strength, l1 norms, extended+i weights, scaling and merging of
-//    operators: one thread per row, each sum in the host's order;
+//  * strength, l1 norms and merging of operators: one thread per row, each
+//    sum in the host's order; scaling, copies and row sorts: 16 lanes or a
+//    wavefront per row;
+//  * extended+i: one workgroup per F row, each thread owning one weight and
+//    adding its contributions in the host's order (one thread per row for
+//    rows beyond the workgroup's LDS);
 //  * sparse products: one wavefront per row (one workgroup for long rows),
 //    the row's products sorted by (column, order of the factors' entries)
 //    and each column summed in that order, as the host's row accumulator
