@@ -248,7 +248,11 @@ int aux_setup(const aux_mesh *mesh, int order, const double *kappa, const aux_op
  * assembly maps (each entry's list of element-matrix contributions, about
  * nnz(A_h) * 3 int32 of device memory).  aux_info.setup_seconds then reports
  * this call's time.  Synchronises the stream.  Errors: AUX_EINVAL (kappa <= 0
- * or not finite), AUX_ENOMEM, AUX_EHIP. */
+ * or not finite, checked before anything changes; or an AMG hierarchy that
+ * cannot be built), AUX_ENOMEM, AUX_EHIP.  After a failure past the check
+ * the handle's coefficient-dependent data are gone: solves, applications
+ * and precision or operator changes return AUX_ESTATE until a later
+ * aux_set_kappa succeeds. */
 int aux_set_kappa(aux_handle *h, const double *kappa);
 
 /* Residual history of the handle's last single-vector CG solve (pcg_solve or

@@ -286,13 +286,15 @@ class Solver:
 
     def set_kappa(self, kappa):
         """A new per-tet coefficient on the same mesh: the device re-assembles
-        A_h, A_H and the l1 norms (bitwise as a new setup would), the host
-        rebuilds the AMG hierarchy."""
+        A_h, A_H and the l1 norms (bitwise as a new setup would) and builds
+        the AMG hierarchy (on the host with amg_setup="host").  If the update
+        fails, the handle refuses solves until a later update succeeds."""
         kap = np.ascontiguousarray(kappa, dtype=np.float64)
         if kap.shape != (self.n_tets,):
             raise ValueError(f"kappa must have shape ({self.n_tets},)")
-        self._kappa = kap
+        self._kappa = None
         _check(load_library().aux_set_kappa(self._h, _np_ptr(kap)))
+        self._kappa = kap
         self.info = self._info()
 
     def set_precision(self, precision: str):

@@ -209,6 +209,9 @@ struct aux_handle {
     // until a host consumer asks (host_hier_stale)
     DevAmg dev_built;
     bool dev_built_ready = false;
+    // the coefficient-dependent device data exist (false from their release
+    // in set_kappa until the update completes)
+    bool coef_ready = true;
     bool host_hier_stale = false;
     int dense_pre_first = -1;
     double amg_seconds = 0.0;
@@ -2818,6 +2821,7 @@ struct aux_handle {
         for (void *b : {(void *)Ke, (void *)aval, (void *)l1e}) dfree(b);
         disc.kappa.assign(kap, kap + nt);
         // the hierarchy of the new A_H and everything built from it
+        coef_ready = false;
         release_coefficient_part();
         hier = Hierarchy();
         if (child) child->set_kappa(kap);
@@ -2842,6 +2846,7 @@ struct aux_handle {
         work<double>();
         if (opt.precision == AUX_MIXED) work<float>();
         HIPCHECK(hipStreamSynchronize(s));
+        coef_ready = true;
     }
 
     void apply_external(const double *rext, double *zext)
@@ -2941,10 +2946,14 @@ void init_infos(aux_solve_info *info, int n)
         for (int i = 0; i < n; i++) info[i].true_rel_residual = -1.0;
 }
 
-void need_device(const aux_handle *h)
+// coef: the call needs the coefficient-dependent device data, which a
+// coefficient update that failed after releasing them leaves missing
+void need_device(const aux_handle *h, bool coef = true)
 {
     if (!h) throw AuxError(AUX_EINVAL, "null handle");
     if (h->host_only) throw AuxError(AUX_ESTATE, "handle was set up host-only");
+    if (coef && !h->coef_ready)
+        throw AuxError(AUX_ESTATE, "the last aux_set_kappa failed: set a coefficient again before solving");
 }
 
 void set_dev(const aux_handle *h) { HIPCHECK(hipSetDevice(h->device)); }
@@ -3075,7 +3084,7 @@ int aux_destroy(aux_handle *h)
 int aux_set_stream(aux_handle *h, void *stream)
 {
     return guarded([&]() {
-        need_device(h);
+        need_device(h, false);
         h->stream = (hipStream_t)stream;
         if (h->child) h->child->stream = (hipStream_t)stream;
         return AUX_OK;
@@ -3283,7 +3292,7 @@ int aux_export_cf(const aux_handle *h, int level, int32_t *cf)
 int aux_set_kappa(aux_handle *h, const double *kappa)
 {
     return guarded([&]() {
-        need_device(h);
+        need_device(h, false);
         if (!kappa) throw AuxError(AUX_EINVAL, "null kappa");
         set_dev(h);
         auto t0 = std::chrono::steady_clock::now();
@@ -3499,7 +3508,7 @@ int aux_kappa_grad(aux_handle *h, const double *u, const double *lam, double *g)
 int aux_profile(aux_handle *h, int enable)
 {
     return guarded([&]() {
-        need_device(h);
+        need_device(h, false);
         set_dev(h);
         if (enable < 0 || enable > 2) throw AuxError(AUX_EINVAL, "enable must be 0, 1 or 2");
         h->prof_collect(1 << 30);
@@ -3516,7 +3525,7 @@ int aux_profile(aux_handle *h, int enable)
 int aux_profile_read(aux_handle *h, int category, int64_t *launches, double *ms)
 {
     return guarded([&]() {
-        need_device(h);
+        need_device(h, false);
         if (category < 0 || category >= AUX_PROF_NCAT || !launches || !ms)
             throw AuxError(AUX_EINVAL, "bad profile category");
         set_dev(h);
@@ -3532,7 +3541,7 @@ const char *aux_last_error(void) { return g_error.c_str(); }
 int aux_residual_history(aux_handle *h, double *hist, int32_t max_len, int32_t *len)
 {
     return guarded([&]() {
-        need_device(h);
+        need_device(h, false);
         if (!len) throw AuxError(AUX_EINVAL, "null length");
         if (h->last_iters < 0 || !h->last_rr) throw AuxError(AUX_ESTATE, "no single-vector CG solve yet");
         const int n = h->last_iters + 1;

@@ -9,6 +9,7 @@ against a new setup and against the oracle.
 * Against the oracle for kappa_2: apply 1e-12, CG at the oracle's iteration
   count 1e-10, mixed mode 1e-7; the matrix-free operator and the batched
   solve after the update; several updates in a row.
+* A failed update leaves the handle refusing solves until the next update.
 """
 import time
 
@@ -97,6 +98,40 @@ def test_set_kappa_forced_storage(lanes):
     ua, ia = a.solve(f, tol=1e-9)
     ub, ib = b.solve(f, tol=1e-9)
     assert ia.iterations == ib.iterations and torch.equal(ua, ub)
+
+
+def test_failed_update_refuses_solves(monkeypatch):
+    """An update that fails after the old coefficient's device data are
+    released (the device allocator refuses every allocation after the first
+    dozen of the update, which lands inside the AMG build) leaves the handle
+    refusing applications and solves with AUX_ESTATE instead of running on
+    missing data; the next update restores it, bitwise equal to a new setup."""
+    print("[set_kappa failure path]", flush=True)
+    xyz, tets = W.kuhn_mesh(8, jitter=0.2, seed=0)
+    k1, k2 = _kappas(xyz, tets, (1, 2))
+    kw = dict(device=DEV, sell_window=1 << 30)
+    s = aux.Solver(xyz, tets, 2, k1, **kw)
+    s.set_kappa(k2)                                          # builds the assembly maps
+    real = torch.cuda.caching_allocator_alloc
+    calls = [0]
+
+    def refusing(n, d, st):
+        calls[0] += 1
+        return 0 if calls[0] > 12 else real(n, d, st)
+
+    monkeypatch.setattr(torch.cuda, "caching_allocator_alloc", refusing)
+    with pytest.raises(aux.AuxError, match="AUX_ENOMEM"):
+        s.set_kappa(k1)
+    monkeypatch.setattr(torch.cuda, "caching_allocator_alloc", real)
+    assert calls[0] > 12
+    r = _t(W.random_vector(s.n, 3))
+    with pytest.raises(aux.AuxError, match="AUX_ESTATE"):
+        s.apply(r)
+    with pytest.raises(aux.AuxError, match="AUX_ESTATE"):
+        s.solve(_t(W.random_vector(s.n, 4)), tol=1e-8)
+    s.set_kappa(k1)
+    b = aux.Solver(xyz, tets, 2, k1, **kw)
+    assert torch.equal(s.apply(r), b.apply(r))
 
 
 def test_set_kappa_against_oracle_and_forms():
