@@ -81,11 +81,13 @@ def measured_traffic(workload, operator, category, precision):
 
 def cycle_lanes(info):
     """Storage the setup chose for the V-cycle's operators: "ell<L>" row-split
-    sliced ELL with L lanes per row, "csr<L>" CSR with L lanes per row."""
+    sliced ELL with L lanes per row, "csr<L>" CSR with L lanes per row,
+    "fixed" (I_P) fixed-width column-major slots."""
     def name(v):
         return f"ell{v}" if v > 0 else (f"csr{-v}" if v < 0 else "-")
     levels = max(int(info.levels) - 1, 0)
-    return {"restrict": name(info.lanes_restrict), "prolong": name(info.lanes_prolong),
+    return {"restrict": name(info.lanes_restrict),
+            "prolong": name(info.lanes_prolong) if info.lanes_prolong else "fixed",
             "down": [name(info.lanes_down[l]) for l in range(levels)],
             "up": [name(info.lanes_up[l]) for l in range(levels)]}
 

@@ -198,7 +198,8 @@ typedef struct aux_info {
     int32_t sell_split;      /* 1: the single-vector A_h passes give each slice two wavefronts
                                 (32-bit layout with slices of at least 56 slots on average) */
     int32_t lanes_restrict;  /* fused restriction [I_R, -I_R A_h] (0 if not fused) */
-    int32_t lanes_prolong;   /* I_P */
+    int32_t lanes_prolong;   /* I_P; 0: fixed-width column-major slots (its rows have 1 to 4
+                                entries; the default unless cycle_lanes forces a storage) */
     int32_t lanes_down[32];  /* fused down operator of level l */
     int32_t lanes_up[32];    /* fused up operator of level l */
     double amg_setup_seconds; /* wall time of the last build of the AMG hierarchy and the

@@ -104,6 +104,10 @@ template <typename T>
 void csr_matvec(hipStream_t s, const DevCsrView &M, const T *x, T *y, const int *done);
 template <typename T>
 void csr_matvec_add(hipStream_t s, const DevCsrView &M, const T *e, T *x, const int *done);
+// z += M e for M with at most w (1..4) entries per row in w column-major
+// slots (slot k of row i at k n + i, padding value 0 at column 0)
+template <typename T>
+void fixed_matvec_add(hipStream_t s, int n, int w, const int *col, const T *val, const T *e, T *z, const int *done);
 // y = M [x1; x2] (columns below split index x1, the rest x2)
 template <typename T>
 void csr_matvec2(hipStream_t s, const DevCsrView &M, const T *x1, const T *x2, int split, T *y, const int *done);

@@ -194,6 +194,14 @@ struct aux_handle {
         int *cf = nullptr;
     };
     DevOp RF;                        // composite restriction [I_R, -I_R A_h] (fuse_cycle)
+    // I_P in fixed-width column-major slots (at most 4 entries per row: one
+    // per vertex of the node's key; w = 0 when not used)
+    struct FixedOp {
+        int n = 0, w = 0;
+        int *col = nullptr;
+        double *v64 = nullptr;
+        float *v32 = nullptr;
+    } IPf;
     // the cycle from level dense_first down, as one dense matrix (fuse_cycle)
     size_t dense_first = SIZE_MAX;
     double *dcyc64 = nullptr;
@@ -632,6 +640,7 @@ struct aux_handle {
         IRi = transpose(IPi);
         IP = upload_op2(IPi);
         IR = upload_op(IRi);
+        if (opt.cycle_lanes == 0) set_fixed(IPf, IPi);
         upload_coefficient_part(true);
         int n = disc.ndof;
         r = dnew<double>(n);
@@ -646,6 +655,28 @@ struct aux_handle {
         HIPCHECK(hipHostMalloc((void **)&host_state, 4 * sizeof(int), hipHostMallocDefault));
         HIPCHECK(hipHostMalloc((void **)&host_scal, 8 * sizeof(double), hipHostMallocDefault));
         ensure_hist(std::max(opt.maxit, 16));
+    }
+
+    // the fixed-width slot form of an operator with 1 to 4 entries per row
+    // (left unused otherwise)
+    void set_fixed(FixedOp &f, const Csr &c)
+    {
+        int w = 0;
+        for (int i = 0; i < c.n; i++) w = std::max(w, c.ptr[i + 1] - c.ptr[i]);
+        if (w < 1 || w > 4) return;
+        const size_t n = (size_t)c.n;
+        std::vector<int> col(w * n, 0);
+        std::vector<double> val(w * n, 0.0);
+        for (size_t i = 0; i < n; i++)
+            for (int e = c.ptr[i], k = 0; e < c.ptr[i + 1]; e++, k++) {
+                col[k * n + i] = c.col[e];
+                val[k * n + i] = c.val[e];
+            }
+        f.n = c.n;
+        f.w = w;
+        f.col = upload(col);
+        f.v64 = upload(val);
+        f.v32 = upload(to_f32(val));
     }
 
     // Storage of one operator by lanes code (> 0: row-split ELL with that
@@ -851,7 +882,7 @@ struct aux_handle {
                 const size_t fb = (size_t)512 << 20;    // twice the last-level cache
                 void *flush = dalloc(fb);
                 tune_op(RF, disc.ndof, flush, fb);
-                tune_op(IP, 0, flush, fb);
+                if (!IPf.w) tune_op(IP, 0, flush, fb);
                 tuned_lanes.clear();
                 for (size_t l = 0; l + 1 < lev.size(); l++) {
                     if (lev[l].A.n < 8192) break;
@@ -1190,7 +1221,14 @@ struct aux_handle {
             csr_matvec<T>(s, IR.view<T>(), w.res, w.b[0], done);
         }
         const T *e0 = vcycle<T>(0, done);
-        csr_matvec_add<T>(s, IP.view<T>(), e0, zc, done);
+        if (IPf.w) {
+            const T *v;
+            if constexpr (std::is_same<T, float>::value) v = IPf.v32;
+            else v = IPf.v64;
+            fixed_matvec_add<T>(s, IPf.n, IPf.w, IPf.col, v, e0, zc, done);
+        } else {
+            csr_matvec_add<T>(s, IP.view<T>(), e0, zc, done);
+        }
         pend(pk);
     }
 
@@ -3175,7 +3213,7 @@ int aux_get_info(const aux_handle *h, aux_info *info)
         info->aux_space = h->child ? 2 : 1;
         info->sell_split = h->A.split() ? 1 : 0;
         info->lanes_restrict = h->RF.n ? h->RF.lanes_code() : 0;
-        info->lanes_prolong = h->IP.lanes_code();
+        info->lanes_prolong = h->IPf.w ? 0 : h->IP.lanes_code();
         for (size_t l = 0; l + 1 < h->lev.size() && l < 32; l++) {
             info->lanes_down[l] = h->lev[l].down.n ? h->lev[l].down.lanes_code() : 0;
             info->lanes_up[l] = h->lev[l].up.n ? h->lev[l].up.lanes_code() : 0;
