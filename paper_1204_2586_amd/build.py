@@ -11,7 +11,7 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libauxprec.so")
 
 HOST_SOURCES = ["host/fem.cpp", "host/amg.cpp", "host/formats.cpp", "host/fuse.cpp", "host/stokes.cpp"]
-HIP_SOURCES = ["hip/kernels.hip", "hip/batched.hip", "hip/mfree.hip", "hip/krylov.hip", "hip/blockcg.hip",
+HIP_SOURCES = ["hip/kernels.hip", "hip/prolong.hip", "hip/batched.hip", "hip/mfree.hip", "hip/krylov.hip", "hip/blockcg.hip",
                "hip/assemble.hip", "hip/amgsetup.hip", "hip/stokes.hip", "hip/solver.hip"]
 ARCH = os.environ.get("AUXPREC_ARCH", "gfx950")
 

@@ -265,23 +265,6 @@ __global__ __launch_bounds__(kBlock) void k_csr_matvec(int n, const int *__restr
     }
 }
 
-// z += M e for an operator of at most W entries per row kept in W
-// column-major slots (slot k of row i at k n + i; padding value 0 at column
-// 0): a row's loads depend on nothing but its index, so the chain per row
-// is slots, then the gathered e, then z.
-template <typename T, int W>
-__global__ __launch_bounds__(kBlock) void k_fixed_add(int n, const int *__restrict__ col, const T *__restrict__ val,
-                                                      const T *__restrict__ e, T *__restrict__ z, const int *done)
-{
-    if (stop(done)) return;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        T acc = T(0);
-#pragma unroll
-        for (int k = 0; k < W; k++) acc += val[(size_t)k * n + i] * e[col[(size_t)k * n + i]];
-        z[i] += acc;
-    }
-}
-
 // Row-split sliced ELL product, one wavefront per slice of 64 / L rows.
 // MODE 0: y = M x1; 1: y += M x1; 2: y = M [x1; x2] (columns below split
 // index x1).  Every slot is one coalesced load of 64 values and 64 columns;
@@ -669,19 +652,6 @@ void csr_matvec_add(hipStream_t s, const DevCsrView &M, const T *e, T *x, const 
 }
 
 template <typename T>
-void fixed_matvec_add(hipStream_t s, int n, int w, const int *col, const T *val, const T *e, T *z, const int *done)
-{
-    const int g = vec_grid(n);
-    switch (w) {
-    case 1: hipLaunchKernelGGL((k_fixed_add<T, 1>), dim3(g), dim3(kBlock), 0, s, n, col, val, e, z, done); break;
-    case 2: hipLaunchKernelGGL((k_fixed_add<T, 2>), dim3(g), dim3(kBlock), 0, s, n, col, val, e, z, done); break;
-    case 3: hipLaunchKernelGGL((k_fixed_add<T, 3>), dim3(g), dim3(kBlock), 0, s, n, col, val, e, z, done); break;
-    case 4: hipLaunchKernelGGL((k_fixed_add<T, 4>), dim3(g), dim3(kBlock), 0, s, n, col, val, e, z, done); break;
-    default: throw std::invalid_argument("fixed_matvec_add: 1 to 4 entries per row");
-    }
-}
-
-template <typename T>
 void csr_matvec2(hipStream_t s, const DevCsrView &M, const T *x1, const T *x2, int split, T *y, const int *done)
 {
     if (M.ell_lanes > 0) return ell_matvec<T, 2>(s, M, x1, x2, split, y, done);
@@ -789,7 +759,6 @@ void kappa_grad(hipStream_t s, int nt, int nloc, const int *tet_dof, const doubl
                                      const double *, double *, const int *);                                 \
     template void csr_matvec<T>(hipStream_t, const DevCsrView &, const T *, T *, const int *);               \
     template void csr_matvec_add<T>(hipStream_t, const DevCsrView &, const T *, T *, const int *);           \
-    template void fixed_matvec_add<T>(hipStream_t, int, int, const int *, const T *, const T *, T *, const int *); \
     template void csr_matvec2<T>(hipStream_t, const DevCsrView &, const T *, const T *, int, T *, const int *); \
     template void csr_vpre<T>(hipStream_t, const DevCsrView &, const T *, const T *, T *, T *, const int *); \
     template void csr_sweep<T>(hipStream_t, const DevCsrView &, const T *, const T *, const T *, T *,        \
